@@ -1,0 +1,245 @@
+/*
+ * FP64 time stepping of the oracle.  TEST INFRASTRUCTURE ONLY: loaded by the
+ * oracle's Python driver through ctypes; never linked into the GPU library.
+ *
+ * One Runge-Kutta stage follows the six coupling steps of Sec. 3.2 literally,
+ * ghost by ghost:
+ *   1. least-squares read-out of p, u, v at P_0..P_4 (W from the Python side);
+ *      p_BP = p(P_0);
+ *   2. ADE derivative dPsi/dt = A Psi^(l-1) + f p_BP (Sec. 2.5 / eq. ADEgeneral);
+ *   3. u_n,BP = c.Psi^(l-1) and du_n,BP/dt = c.dPsi/dt (eqs. ADE-un, ADE-dpdn);
+ *   4. boundary data in the frame of the immersed-boundary normal n (wall to
+ *      fluid): u.n = -u_n,BP (u_n counts positive into the wall) and
+ *      dp/dn = +du_n,BP/dt (momentum eq. momentum-normal with the normal
+ *      reversed); tangential velocity free;
+ *   5. 1-D extrapolation to s = -r (eq. ns-ghost): Dirichlet for u.n, Neumann
+ *      for p (Q'(0) = h dp/dn in the reduced coordinate), free for u.t;
+ *   6. right-hand side of the LEE (eq. LEE, rho0 = c0 = 1) at every fluid node
+ *      with the DRP first derivative (eq. DRP_s), plus the selective-filter
+ *      damping term, the outer sponge and the monopole source, and the stage
+ *      update q^(l) = q^n + alpha_l dt RHS(q^(l-1)).
+ * The auxiliary states follow the same stage update,
+ * Psi^(l) = Psi^n + alpha_l dt dPsi/dt.
+ *
+ * Fields are (ny + 2F) x (nx + 2F) row-major arrays: the domain plus a frame of
+ * F = 5 nodes held at zero on every side.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef struct {
+    int nx, ny, F, H;
+    double h, dt, x0, y0;
+    double a[5];            /* DRP a_1..a_H */
+    double sigma_d;         /* filter strength, 0 = off */
+    double d[6];            /* filter d_0..d_5 */
+    int sponge_w;
+    double sponge_smax;
+    int has_src;
+    double src_x, src_y, src_a, src_b, src_omega;
+    const unsigned char *fluid; /* ny*nx */
+    int G;
+    const long long *gidx;      /* G, linear j*nx+i */
+    const double *gnx, *gny;    /* G */
+    const long long *cptr;      /* G+1 */
+    const long long *cidx;      /* nnz, linear */
+    const double *W;            /* nnz*5 */
+    const double *lag;          /* G*5  Lagrange l_i(-r) */
+    const double *bir;          /* G*5  Birkhoff mu_i(-r) */
+    int ade_kind;               /* 0 rigid, 1 complex pair, 2 real poles */
+    double ade[4];              /* complex: a, b, B1, C1; real: l1, l2, A1, A2 */
+} oc_case;
+
+static const double RK_ALPHA[4] = {0.25, 1.0 / 3.0, 0.5, 1.0};
+static const double RK_C[4] = {0.0, 0.25, 1.0 / 3.0, 0.5};
+
+static long long pad_index(const oc_case *c, long long lin)
+{
+    long long i = lin % c->nx, j = lin / c->nx;
+    return (j + c->F) * (long long)(c->nx + 2 * c->F) + (i + c->F);
+}
+
+/* steps 1-5 for every ghost; writes ghost values into (p, u, v) and the
+ * stage value of the auxiliary states into psi_out */
+static void fill_ghosts(const oc_case *c, double *p, double *u, double *v,
+                        const double *psi_in, const double *psi_n, double *psi_out,
+                        double alpha)
+{
+    int g;
+#pragma omp parallel for schedule(static)
+    for (g = 0; g < c->G; ++g) {
+        double fp[5] = {0}, fu[5] = {0}, fv[5] = {0}, un[5], ut[5];
+        double nx = c->gnx[g], ny = c->gny[g];
+        long long e;
+        int i;
+        /* step 1: least-squares read-out at P_0..P_4 */
+        for (e = c->cptr[g]; e < c->cptr[g + 1]; ++e) {
+            long long q = pad_index(c, c->cidx[e]);
+            for (i = 0; i < 5; ++i) {
+                double w = c->W[e * 5 + i];
+                fp[i] += w * p[q];
+                fu[i] += w * u[q];
+                fv[i] += w * v[q];
+            }
+        }
+        for (i = 0; i < 5; ++i) {
+            un[i] = nx * fu[i] + ny * fv[i];
+            ut[i] = -ny * fu[i] + nx * fv[i];
+        }
+        double pBP = fp[0];
+        /* steps 2-3: ADE derivative, wall velocity and its time derivative */
+        double s1 = psi_in[2 * g], s2 = psi_in[2 * g + 1];
+        double d1 = 0.0, d2 = 0.0, U = 0.0, Ud = 0.0;
+        if (c->ade_kind == 1) {
+            double a = c->ade[0], b = c->ade[1], B1 = c->ade[2], C1 = c->ade[3];
+            d1 = -a * s1 - b * s2 + pBP;
+            d2 = -a * s2 + b * s1;
+            U = 2.0 * B1 * s1 - 2.0 * C1 * s2;
+            Ud = 2.0 * B1 * d1 - 2.0 * C1 * d2;
+        } else if (c->ade_kind == 2) {
+            double l1 = c->ade[0], l2 = c->ade[1], A1 = c->ade[2], A2 = c->ade[3];
+            d1 = l1 * s1 + pBP;
+            d2 = l2 * s2 + pBP;
+            U = A1 * s1 + A2 * s2;
+            Ud = A1 * d1 + A2 * d2;
+        }
+        /* steps 4-5: boundary data in the IBM frame and 1-D extrapolation */
+        const double *L = c->lag + 5 * g, *B = c->bir + 5 * g;
+        double pg = B[0] * (c->h * Ud);
+        double ung = L[0] * (-U);
+        double utg = L[0] * ut[0];
+        for (i = 1; i < 5; ++i) {
+            pg += B[i] * fp[i];
+            ung += L[i] * un[i];
+            utg += L[i] * ut[i];
+        }
+        long long q = pad_index(c, c->gidx[g]);
+        p[q] = pg;
+        u[q] = nx * ung - ny * utg;
+        v[q] = ny * ung + nx * utg;
+        psi_out[2 * g] = psi_n[2 * g] + alpha * c->dt * d1;
+        psi_out[2 * g + 1] = psi_n[2 * g + 1] + alpha * c->dt * d2;
+    }
+}
+
+static double sponge(const oc_case *c, int i, int j)
+{
+    if (c->sponge_w <= 0) return 0.0;
+    int e = i;
+    if (j < e) e = j;
+    if (c->nx - 1 - i < e) e = c->nx - 1 - i;
+    if (c->ny - 1 - j < e) e = c->ny - 1 - j;
+    if (e >= c->sponge_w) return 0.0;
+    double f = (double)(c->sponge_w - e) / (double)c->sponge_w;
+    return c->sponge_smax * f * f;
+}
+
+/* step 6: RHS at fluid nodes of the stage input (ps, us, vs) and the update */
+static void sweep(const oc_case *c, const double *p, const double *u, const double *v,
+                  const double *ps, const double *us, const double *vs,
+                  double *po, double *uo, double *vo, double alpha, double t)
+{
+    const long long sy = c->nx + 2 * c->F;
+    const double amp = c->has_src ? sin(c->src_omega * t) : 0.0;
+    int j;
+#pragma omp parallel for schedule(static)
+    for (j = 0; j < c->ny; ++j) {
+        int i, k;
+        for (i = 0; i < c->nx; ++i) {
+            long long q = (j + c->F) * sy + (i + c->F);
+            if (!c->fluid[(long long)j * c->nx + i]) {
+                po[q] = 0.0; uo[q] = 0.0; vo[q] = 0.0;
+                continue;
+            }
+            double dpdx = 0, dudx = 0, dpdy = 0, dvdy = 0;
+            for (k = 1; k <= c->H; ++k) {
+                dpdx += c->a[k - 1] * (ps[q + k] - ps[q - k]);
+                dudx += c->a[k - 1] * (us[q + k] - us[q - k]);
+                dpdy += c->a[k - 1] * (ps[q + k * sy] - ps[q - k * sy]);
+                dvdy += c->a[k - 1] * (vs[q + k * sy] - vs[q - k * sy]);
+            }
+            dpdx /= c->h; dudx /= c->h; dpdy /= c->h; dvdy /= c->h;
+            double rp = -(dudx + dvdy);
+            double ru = -dpdx;
+            double rv = -dpdy;
+            if (c->sigma_d > 0.0) {
+                double fp = 2.0 * c->d[0] * ps[q];
+                double fu = 2.0 * c->d[0] * us[q];
+                double fv = 2.0 * c->d[0] * vs[q];
+                for (k = 1; k <= 5; ++k) {
+                    fp += c->d[k] * (ps[q + k] + ps[q - k] + ps[q + k * sy] + ps[q - k * sy]);
+                    fu += c->d[k] * (us[q + k] + us[q - k] + us[q + k * sy] + us[q - k * sy]);
+                    fv += c->d[k] * (vs[q + k] + vs[q - k] + vs[q + k * sy] + vs[q - k * sy]);
+                }
+                double s = c->sigma_d / c->dt;
+                rp -= s * fp; ru -= s * fu; rv -= s * fv;
+            }
+            double ss = sponge(c, i, j);
+            if (ss != 0.0) {
+                rp -= ss * ps[q]; ru -= ss * us[q]; rv -= ss * vs[q];
+            }
+            if (c->has_src) {
+                double x = c->x0 + (double)i * c->h, y = c->y0 + (double)j * c->h;
+                double r2 = (x - c->src_x) * (x - c->src_x) + (y - c->src_y) * (y - c->src_y);
+                rp += c->src_a * exp(-c->src_b * r2) * amp;
+            }
+            po[q] = p[q] + alpha * c->dt * rp;
+            uo[q] = u[q] + alpha * c->dt * ru;
+            vo[q] = v[q] + alpha * c->dt * rv;
+        }
+    }
+}
+
+/*
+ * Advance nsteps full steps from step counter step0.  After every step the
+ * probes are sampled from q^{n+1}: trace[(s*np + k)*3 + {0,1,2}] = p, u, v at
+ * probe k, with 4x4 interpolation weights probe_w[k*16 + b*4 + a] applied to
+ * node (probe_ij[2k] + a, probe_ij[2k+1] + b).
+ */
+int oc_run(const oc_case *c, double *p, double *u, double *v, double *psi,
+           long long step0, int nsteps, int np, const long long *probe_ij,
+           const double *probe_w, double *trace)
+{
+    const long long sy = c->nx + 2 * c->F;
+    const long long n = sy * (long long)(c->ny + 2 * c->F);
+    double *buf = (double *)calloc((size_t)(6 * n), sizeof(double));
+    double *psb = (double *)calloc((size_t)(4 * (c->G > 0 ? c->G : 1)), sizeof(double));
+    if (!buf || !psb) { free(buf); free(psb); return -1; }
+    double *S[3] = {buf, buf + n, buf + 2 * n};      /* stage value q^(l-1) */
+    double *T[3] = {buf + 3 * n, buf + 4 * n, buf + 5 * n}; /* stage output */
+    double *psS = psb, *psT = psb + 2 * (c->G > 0 ? c->G : 1);
+    int s, l, k;
+    for (s = 0; s < nsteps; ++s) {
+        for (l = 0; l < 4; ++l) {
+            double *ps = l == 0 ? p : S[0], *us = l == 0 ? u : S[1], *vs = l == 0 ? v : S[2];
+            const double *psi_in = l == 0 ? psi : psS;
+            double t = ((double)(step0 + s) + RK_C[l]) * c->dt;
+            fill_ghosts(c, ps, us, vs, psi_in, psi, psT, RK_ALPHA[l]);
+            sweep(c, p, u, v, ps, us, vs, T[0], T[1], T[2], RK_ALPHA[l], t);
+            for (k = 0; k < 3; ++k) { double *x = S[k]; S[k] = T[k]; T[k] = x; }
+            { double *x = psS; psS = psT; psT = x; }
+        }
+        memcpy(p, S[0], (size_t)n * sizeof(double));
+        memcpy(u, S[1], (size_t)n * sizeof(double));
+        memcpy(v, S[2], (size_t)n * sizeof(double));
+        if (c->G > 0) memcpy(psi, psS, (size_t)(2 * c->G) * sizeof(double));
+        for (k = 0; k < np; ++k) {
+            double acc[3] = {0, 0, 0};
+            int a, b;
+            for (b = 0; b < 4; ++b)
+                for (a = 0; a < 4; ++a) {
+                    long long lin = (probe_ij[2 * k + 1] + b) * (long long)c->nx + probe_ij[2 * k] + a;
+                    long long q = pad_index(c, lin);
+                    double w = probe_w[k * 16 + b * 4 + a];
+                    acc[0] += w * p[q]; acc[1] += w * u[q]; acc[2] += w * v[q];
+                }
+            trace[((long long)s * np + k) * 3 + 0] = acc[0];
+            trace[((long long)s * np + k) * 3 + 1] = acc[1];
+            trace[((long long)s * np + k) * 3 + 2] = acc[2];
+        }
+    }
+    free(buf);
+    free(psb);
+    return 0;
+}

@@ -1,0 +1,67 @@
+"""Difference, filter and time-integration coefficients (oracle, FP64).
+
+* DRP7: the 7-point DRP first derivative printed in Sec. 2.2 (eq. DRP_s):
+  a_1..a_3, antisymmetric, a_0 = 0.
+* DRP11: the 11-point first derivative.  The paper prints only the 7-point
+  set; the 11-point set used here is the optimised 11-point scheme of Bogey &
+  Bailly (2004), which is in the paper's bibliography.  Pinned by the
+  consistency condition sum 2 k a_k = 1, the fourth-order conditions and the
+  dispersion error bound (tests).
+* FILTER11: the 11-point selective filter of the same reference, as the
+  symmetric stencil D f_i = d_0 f_i + sum_j d_j (f_{i+j} + f_{i-j}).  It is
+  applied inside every stage as the damping term -(sigma_d/dt)(D_x + D_y) q.
+  Pinned by D(0) = 0 (no damping of a constant) and D(pi) = 1 (full removal
+  of the grid-scale mode).
+* RK: the four-stage low-storage Runge-Kutta (Sec. 2.2 cites a low-storage
+  fourth-order scheme without printing it).  Reading: the two-register form
+  q^(l) = q^n + alpha_l dt RHS(q^(l-1)), alpha = (1/4, 1/3, 1/2, 1), whose
+  amplification on a linear system is the fourth-order Taylor polynomial
+  (pinned in tests); stage l evaluates the right-hand side at
+  t^n + c_l dt with c = (0, 1/4, 1/3, 1/2).
+"""
+import numpy as np
+
+# Sec. 2.2, eq. DRP_s: a_1, a_2, a_3 of the 7-point scheme.
+DRP7 = np.array([0.770882380518, -0.166705904415, 0.020843142770])
+
+# 11-point optimised first derivative (Bogey & Bailly 2004), a_1 .. a_5.
+DRP11 = np.array([0.872756993962, -0.286511173973, 0.090320001280,
+                  -0.020779405824, 0.002484594688])
+
+# 11-point selective filter (Bogey & Bailly 2004), d_0 .. d_5.
+FILTER11 = np.array([0.215044884112, -0.187772883589, 0.123755948787,
+                     -0.059227575576, 0.018721609157, -0.002999540835])
+
+RK_ALPHA = np.array([0.25, 1.0 / 3.0, 0.5, 1.0])
+RK_C = np.array([0.0, 0.25, 1.0 / 3.0, 0.5])
+
+
+def drp(H: int) -> np.ndarray:
+    """a_1..a_H of the central first-derivative stencil of half-width H."""
+    if H == 3:
+        return DRP7.copy()
+    if H == 5:
+        return DRP11.copy()
+    raise ValueError("H must be 3 or 5")
+
+
+def drp_wavenumber(a: np.ndarray, kdx: np.ndarray) -> np.ndarray:
+    """Effective wavenumber k* dx = 2 sum_k a_k sin(k kdx) of the stencil."""
+    k = np.arange(1, len(a) + 1)
+    return 2.0 * np.sum(a[None, :] * np.sin(np.outer(kdx, k)), axis=1)
+
+
+def filter_response(d: np.ndarray, kdx: np.ndarray) -> np.ndarray:
+    """Damping function D(k dx) = d_0 + 2 sum_j d_j cos(j k dx)."""
+    j = np.arange(1, len(d))
+    return d[0] + 2.0 * np.sum(d[None, 1:] * np.cos(np.outer(kdx, j)), axis=1)
+
+
+def rk_amplification(z: complex) -> complex:
+    """Amplification of one step of the two-register scheme on dq/dt = z q/dt,
+    applying the stages literally."""
+    q = 1.0 + 0j
+    qs = q
+    for a in RK_ALPHA:
+        qs = q + a * z * qs
+    return qs

@@ -1,0 +1,176 @@
+"""Whole-solver pins of the oracle against exact and semi-analytic solutions.
+
+* free Gaussian pulse (Hankel-transform closed form): LEE signs, DRP, RK;
+* harmonic monopole switched on from rest: the source term;
+* rigid straight wall at 30 deg against the method of images: the ghost fill
+  (Dirichlet u.n = 0, Neumann dp/dn = 0, free tangential velocity, rotation);
+* impedance wall hit by a plane packet against App. A (R_c = (Z-1)/(Z+1)):
+  the ADE coupling, its signs and the Neumann scaling;
+* grid convergence of the rigid-wall case in the paper's own set-up (7-point
+  DRP, no filter), compared with the paper's reported order of about 4;
+* the selective filter's grid-scale damping and the sponge's sign.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import lee_cases as lc
+from oracle.solver import OracleSolver
+from tests import refsol
+
+
+def _probe_series(case, nsteps):
+    s = OracleSolver(case)
+    tr = s.run(nsteps)
+    return s, tr
+
+
+def test_free_pulse_matches_closed_form():
+    w = 4.0
+    pts = ((0.0, 0.0), (10.0, 0.0), (14.0, 14.0), (-25.0, 3.0))
+    case = lc.Case(nx=121, ny=121, x0=-60.0, y0=-60.0, h=1.0, H=5, filter_sigma=0.0,
+                   ic=lc.Pulse(0.0, 0.0, 1.0, w), probes=pts)
+    s, tr = _probe_series(case, 60)            # t = 30
+    r = np.array([math.hypot(*p) for p in pts])
+    ref = refsol.free_pulse(r, 30.0, 1.0, w)
+    assert np.max(np.abs(tr[-1, :, 0] - ref)) < 1e-3 * np.abs(ref).max()
+    # with the filter the well-resolved pulse is barely touched
+    s2, tr2 = _probe_series(case.replace(filter_sigma=0.2), 60)
+    assert np.max(np.abs(tr2[-1, :, 0] - ref)) < 2e-3 * np.abs(ref).max()
+    # the 7-point scheme of Sec. 2.2 too
+    s3, tr3 = _probe_series(case.replace(H=3), 60)
+    assert np.max(np.abs(tr3[-1, :, 0] - ref)) < 2e-3 * np.abs(ref).max()
+
+
+def test_monopole_from_rest_matches_quadrature():
+    w, om = 4.0, 2 * math.pi / 20.0
+    pts = ((0.0, 0.0), (8.0, 0.0), (0.0, -16.0))
+    case = lc.Case(nx=121, ny=121, x0=-60.0, y0=-60.0, h=1.0, H=5, filter_sigma=0.0,
+                   source=lc.Monopole(0.0, 0.0, 1.0, w, om), probes=pts)
+    r = np.array([math.hypot(*p) for p in pts])
+    ref = refsol.monopole_from_rest(r, 30.0, 1.0, w, om)
+    errs = []
+    for cfl in (0.5, 0.25):
+        c = case.replace(cfl=cfl)
+        s, tr = _probe_series(c, int(round(30.0 / c.dt)))
+        errs.append(np.max(np.abs(tr[-1, :, 0] - ref)) / np.abs(ref).max())
+        assert np.sign(tr[-1, 0, 0]) == np.sign(ref[0])
+    # the two-register RK is second order for an explicit time dependence
+    assert errs[1] < 4e-4 and errs[0] / errs[1] > 3.0, errs
+
+
+def _rigid_line_case(h, H=5, filt=0.0, t_end=None, scale=1.0):
+    """Rigid wall at 30 deg through (0.13, -0.07) (physical units of w = 1)."""
+    nxw, nyw = lc.line_normal(30.0)
+    c = (0.13, -0.07)
+    L = 10.0 * scale
+    n = int(round(2 * L / h)) + 1
+    src = (c[0] + 3.0 * nxw, c[1] + 3.0 * nyw)
+    mic = ((c[0] + 1.0 * nxw, c[1] + 1.0 * nyw), (c[0] + 1.5 * nxw + 1.0, c[1] + 1.5 * nyw))
+    return lc.Case(nx=n, ny=n, x0=-L, y0=-L, h=h, H=H, filter_sigma=filt,
+                   wall=lc.Wall("line", c[0], c[1], nxw, nyw), impedance=lc.Impedance("rigid"),
+                   ic=lc.Pulse(src[0], src[1], 1.0, 1.0), probes=mic)
+
+
+def _image_ref(case, t):
+    w = case.wall
+    return np.array([refsol.image_rigid(x, y, case.ic.xs, case.ic.ys, w.nx, w.ny, w.cx, w.cy, t, 1.0, 1.0)[0]
+                     for (x, y) in case.probes])
+
+
+def test_rigid_wall_images_30deg():
+    case = _rigid_line_case(h=1.0 / 12.0, H=5, filt=0.2)
+    steps = int(round(4.0 / case.dt))
+    s, tr = _probe_series(case, steps)
+    ref = _image_ref(case, steps * case.dt)
+    assert np.max(np.abs(tr[-1, :, 0] - ref)) < 1e-3 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("H", [3, 5])
+def test_rigid_wall_convergence_order(H):
+    """Paper set-up (Sec. 4.1/4.2: no filter); the paper reports about 4."""
+    errs = []
+    hs = (1.0 / 4.0, 1.0 / 6.0, 1.0 / 8.0)
+    for h in hs:
+        case = _rigid_line_case(h=h, H=H)
+        steps = int(round(4.0 / case.dt))
+        s, tr = _probe_series(case, steps)
+        ref = _image_ref(case, steps * case.dt)
+        errs.append(np.max(np.abs(tr[-1, :, 0] - ref)))
+    order = np.polyfit(np.log(hs), np.log(errs), 1)[0]
+    assert order > 3.3, (errs, order)
+
+
+def _packet_case(imp, h=0.5, ang=30.0):
+    """Plane packet of wavelength 16 h travelling along -n onto the wall through
+    the domain centre; microphone 10 h in front of the wall."""
+    nxw, nyw = lc.line_normal(ang)
+    lam = 16.0 * h
+    k = 1.0 / lam
+    alpha = k / math.sqrt(0.8)               # envelope of Sec. 4.1
+    Ds = 40.0 * h
+    src = (Ds * nxw, Ds * nyw)
+    mic = (10.0 * h * nxw + 0.3 * h, 10.0 * h * nyw)
+    return lc.Case(nx=201, ny=201, x0=-100.0 * h, y0=-100.0 * h, h=h, H=5, filter_sigma=0.0,
+                   wall=lc.Wall("line", 0.0, 0.0, nxw, nyw), impedance=imp,
+                   ic=lc.Packet(src[0], src[1], -nxw, -nyw, 1.0, alpha, k), probes=(mic,))
+
+
+@pytest.mark.parametrize("imp", [lc.Impedance("msd", R=0.5, M=1.0, K=1.0 * (2 * math.pi / 8.0) ** 2),
+                                 lc.Impedance("msd", R=2.0, M=0.5, K=0.2),
+                                 lc.Impedance("rigid")], ids=["resonant", "real-poles", "rigid"])
+def test_impedance_wall_plane_packet(imp):
+    """App. A: p(s_m, t) = F(s_m - t) + r(t - (s_w - s_m)), r = R_c * signal at the wall."""
+    case = _packet_case(imp)
+    steps = int(round(80.0 * case.h / case.dt))
+    s, tr = _probe_series(case, steps)
+    n_w = (-case.wall.nx, -case.wall.ny)              # u_n direction (into the wall)
+    sm = case.probes[0][0] * n_w[0] + case.probes[0][1] * n_w[1]
+    ss = case.ic.xs * n_w[0] + case.ic.ys * n_w[1]
+    pk = case.ic
+
+    def F(xi):
+        d = np.asarray(xi) - ss
+        return 0.5 * pk.a * np.exp(-(pk.alpha ** 2) * d * d) * np.cos(2 * math.pi * pk.k * d)
+
+    t = (np.arange(steps) + 1) * case.dt
+    R, M, K = (imp.R, imp.M, imp.K) if imp.kind == "msd" else (0.0, 0.0, 0.0)
+    ref = refsol.flat_reflection(F, 0.0, sm, t, R, M, K, dt_fft=0.05)
+    win = t > 30.0 * case.h                            # incident and reflected parts
+    err = np.sqrt(np.mean((tr[win, 0, 0] - ref[win]) ** 2)) / np.sqrt(np.mean(ref[win] ** 2))
+    assert err < 2e-2, err
+    # and the reflected part really differs from a rigid wall unless rigid
+    if imp.kind == "msd":
+        rig = refsol.flat_reflection(F, 0.0, sm, t, 0.0, 0.0, 0.0, dt_fft=0.05)
+        far = np.sqrt(np.mean((rig[win] - ref[win]) ** 2)) / np.sqrt(np.mean(ref[win] ** 2))
+        assert far > 10 * err
+
+
+def test_filter_removes_checkerboard_at_rk4_rate():
+    """(-1)^(i+j) is the grid-scale mode: D_x + D_y gives 2 (D(pi) = 1) and
+    its DRP derivative vanishes, so away from the frame one step multiplies it
+    by R4(-2 sigma_d)."""
+    n = 61
+    case = lc.Case(nx=n, ny=n, x0=0.0, y0=0.0, h=1.0, H=5, filter_sigma=0.2, probes=((30.0, 30.0),))
+    s = OracleSolver(case)
+    ii, jj = np.meshgrid(np.arange(n), np.arange(n))
+    s.p[5:5 + n, 5:5 + n] = 1e-3 * (-1.0) ** (ii + jj)
+    s.run(1)
+    p, u, v = s.fields()
+    z = -2 * 0.2
+    r4 = 1 + z + z ** 2 / 2 + z ** 3 / 6 + z ** 4 / 24
+    assert abs(p[30, 30] / 1e-3 - r4) < 1e-12
+    assert abs(u[30, 30]) < 1e-15 and abs(v[30, 30]) < 1e-15
+
+
+def test_sponge_absorbs():
+    base = lc.Case(nx=81, ny=81, x0=-40.0, y0=-40.0, h=1.0, H=5, filter_sigma=0.0,
+                   ic=lc.Pulse(0.0, 0.0, 1.0, 3.0))
+    e = []
+    for cells, sig in ((0, 0.0), (16, 0.5)):
+        s = OracleSolver(base.replace(sponge_cells=cells, sponge_sigma=sig))
+        s.run(160)
+        p, u, v = s.fields()
+        e.append(np.sum(p * p + u * u + v * v))
+    assert e[1] < 0.2 * e[0]
