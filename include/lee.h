@@ -1,0 +1,272 @@
+/*
+ * lee.h -- C ABI of the MI355X library for one Runge-Kutta stage of the 2-D
+ * linearized Euler equations with a ghost-point immersed boundary and a
+ * mass-spring-damper impedance wall advanced by auxiliary differential
+ * equations (ADE).
+ *
+ * The problem (paper Sec. 2.1, eq. LEE): dq/dt + dE/dx + dF/dy = S with
+ * q = [p, u, v], rho0 = c0 = 1, S = [s, 0, 0]; advanced on a uniform grid
+ * x_i = x0 + i h, y_j = y0 + j h (0 <= i < nx, 0 <= j < ny) at fluid nodes
+ * only (Sec. 3.1).  Each stage fills the ghost points from a least-squares
+ * fit on an elliptical cloud of fluid nodes extrapolated along the wall
+ * normal (Sec. 3.1, eqs. ns-ellipse .. ns-ghost), coupled to the two-state
+ * ADE of the impedance Z = M s + R + K/s (Sec. 2.5) through the six steps
+ * of Sec. 3.2, then evaluates the DRP right-hand side (Sec. 2.2, eq. DRP_s)
+ * and the low-storage RK4 stage update.
+ *
+ * Conventions common to every call:
+ *   - every call returns a lee_status; nothing aborts or throws across the
+ *     ABI; lee_last_error() returns a thread-local message for the last
+ *     failing call on this thread;
+ *   - host pointers are plain C arrays owned by the caller; device memory is
+ *     owned by the caller (lee_bind) and never freed by the library;
+ *   - all device work is asynchronous on the stream given to lee_bind,
+ *     except the calls documented as synchronising;
+ *   - an instance is not thread-safe: one thread at a time per instance.
+ */
+#ifndef LEE_H
+#define LEE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t lee_status;
+#define LEE_OK 0
+#define LEE_E_ARG (-1)               /* invalid argument or unsupported option */
+#define LEE_E_GEOMETRY (-2)          /* wall/grid combination cannot be handled */
+#define LEE_E_CRITICAL_DAMPING (-3)  /* R = 2 sqrt(KM): double pole (Sec. 2.5) */
+#define LEE_E_ADE_STIFF (-4)         /* ADE or wall coupling unstable at this dt */
+#define LEE_E_RANK (-5)              /* reserved: least-squares rank failure */
+#define LEE_E_NOMEM (-6)             /* host allocation or device buffer too small */
+#define LEE_E_DEVICE (-7)            /* a HIP runtime call failed */
+#define LEE_E_STATE (-8)             /* call out of order (e.g. stage sequence) */
+#define LEE_E_PROBE (-9)             /* probe stencil leaves the fluid */
+
+#define LEE_F32 0
+#define LEE_F64 1
+
+#define LEE_WALL_NONE 0
+#define LEE_WALL_LINE 1     /* through (cx, cy), unit normal (nx, ny) into the fluid */
+#define LEE_WALL_CIRCLE 2   /* centre (cx, cy), radius rc, fluid outside */
+
+#define LEE_IC_NONE 0
+#define LEE_IC_PULSE 1      /* ic = {xs, ys, a, w}: p0 = a exp(-ln2 r^2 / w^2) (Sec. 4.2) */
+#define LEE_IC_PACKET 2     /* ic = {xs, ys, dx, dy, a, alpha, k}: plane packet of Sec. 4.1
+                               along (dx, dy): p0 = a/2 exp(-alpha^2 s^2) cos(2 pi k s),
+                               s = (x - xs) dx + (y - ys) dy, (u0, v0) = p0 (dx, dy) */
+
+#define LEE_SRC_NONE 0
+#define LEE_SRC_MONOPOLE 1  /* src = {xs, ys, a, w, omega}:
+                               s = a exp(-ln2 r^2 / w^2) sin(omega t) (Sec. 4.3) */
+
+#define LEE_Z_RIGID 0       /* Y -> 0: u_n = 0, dp/dn = 0 (Sec. 2.4) */
+#define LEE_Z_MSD 1         /* Z = M s + R + K / s (Sec. 2.5) */
+
+/* Problem description (Sec. 2.1-2.2, 3.1, 4).  dt = cfl * h (c0 = 1). */
+typedef struct {
+    int32_t nx, ny;          /* grid nodes, each >= 16 */
+    double x0, y0, h;        /* node (i, j) sits at (x0 + i h, y0 + j h) */
+    int32_t stencil_half;    /* DRP half-width: 5 (11-point) or 3 (7-point, eq. DRP_s) */
+    double cfl;              /* dt = cfl * h */
+    double filter_sigma;     /* 11-point selective filter strength; 0 disables it
+                                (requires stencil_half = 5 when > 0) */
+    int32_t sponge_cells;    /* outer damping layer width in cells (0 = none) */
+    double sponge_sigma;     /* its peak rate; sigma(e) = sigma ((W - e)/W)^2 */
+    int32_t precision;       /* LEE_F32 or LEE_F64 field arithmetic */
+    int32_t wall_kind;       /* LEE_WALL_* */
+    double wall_cx, wall_cy, wall_nx, wall_ny, wall_rc;
+    int32_t ic_kind;         /* LEE_IC_* */
+    double ic[7];
+    int32_t src_kind;        /* LEE_SRC_* */
+    double src[5];
+} lee_case_desc;
+
+typedef struct {
+    int32_t kind;            /* LEE_Z_RIGID or LEE_Z_MSD */
+    double R, M, K;          /* resistance, mass, stiffness per unit area (all > 0) */
+} lee_impedance;
+
+typedef struct {
+    int32_t G;               /* ghost points */
+    int64_t nnz;             /* total cloud entries */
+    int32_t n_degraded;      /* ghosts fitted below degree 4 (or not at all) */
+    int32_t n_cut;           /* ghosts whose ellipse leaves the domain (value 0) */
+    double r_min, r_max;     /* range of r = d / h */
+    double w_l1_max;         /* largest 1-norm of a composite weight row */
+    int64_t fluid_nodes;     /* nodes advanced per stage */
+    int32_t ade_kind;        /* 0 rigid, 1 complex pole pair, 2 two real poles */
+    double poles[4];         /* re s1, im s1, re s2, im s2 */
+} lee_ghost_summary;
+
+typedef struct lee_instance lee_instance;
+typedef struct lee_batch lee_batch;
+
+/* Thread-local message describing the last failing call on this thread. */
+const char *lee_last_error(void);
+
+/*
+ * Grid set-up (host only, no device call): fluid mask (phi > 0, a node on the
+ * wall is solid; Sec. 3.1), ghost list (solid nodes reached by a fluid
+ * node's stencil along x or y), dt.  *out belongs to the library until
+ * lee_destroy.  Unsupported descriptions -> LEE_E_ARG; a wall the kernels
+ * cannot represent (more than two fluid intervals in a row, a ghost at a
+ * circle centre) -> LEE_E_GEOMETRY.
+ */
+lee_status lee_setup_grid(const lee_case_desc *d, lee_instance **out);
+
+/*
+ * Ghost weights and ADE coefficients (host only, FP64).  For every ghost:
+ * boundary point, normal and r (eq. ns-rotation), elliptical cloud
+ * (eq. ns-ellipse, R_n = 2k, R_t = k/2 + 1), least-squares read-out at
+ * P_0..P_4 by Householder QR (eqs. ns-vandermonde .. ns-readout), composed
+ * with the 1-D Lagrange / Birkhoff extrapolation (eq. ns-ghost) into four
+ * weights per cloud entry (p_BP, free, Dirichlet, Neumann).  degree must be
+ * 4 (k = m = 4, Sec. 3.1); clouds that are too small or rank-deficient fall
+ * back to degree 3, 2, 1, else zero; clouds cut by the domain edge are zero.
+ * ADE: poles and residues of Y = 1/Z (Sec. 2.5); critical damping ->
+ * LEE_E_CRITICAL_DAMPING; a pole outside the RK4 stability region or a wall
+ * coupling gain h/M > 2 -> LEE_E_ADE_STIFF.  opt_out may be NULL.
+ * Must be called once, after lee_setup_grid and before lee_bind.
+ */
+lee_status lee_build_ghosts(lee_instance *inst, const lee_impedance *z, int32_t degree,
+                            lee_ghost_summary *opt_out);
+
+/* Device bytes lee_bind needs (fields: 3 register sets x 3 planes, ADE
+ * states, ghost lists, probe buffers); valid after lee_build_ghosts and
+ * after lee_set_probes. */
+lee_status lee_required_bytes(const lee_instance *inst, size_t *dev_bytes);
+
+/*
+ * Bind caller-owned device memory (at least lee_required_bytes, 256-byte
+ * aligned) and a HIP stream (hipStream_t, may be NULL for the default
+ * stream) on the current device.  Uploads the lists and zeroes the state
+ * asynchronously; lee_init_fields then applies the initial condition.  The
+ * library never frees dev_ptr.
+ */
+lee_status lee_bind(lee_instance *inst, void *dev_ptr, size_t bytes, void *hip_stream);
+
+/* Initial state (Sec. 2.1): q0 at fluid nodes, zero elsewhere, ADE states
+ * zero, step counter 0, traces cleared.  Asynchronous. */
+lee_status lee_init_fields(lee_instance *inst);
+
+/*
+ * One Runge-Kutta stage (stage = 0..3) on the bound stream, asynchronous:
+ * ghost fill + ADE (Sec. 3.2 steps 1-5) then the stage sweep (step 6).  The
+ * stages of a step must be issued in order 0, 1, 2, 3 (else LEE_E_STATE);
+ * after stage 3 the step counter advances and the probes are sampled.  Four
+ * calls give bit-identical results to lee_step_n(inst, 1).
+ */
+lee_status lee_rk_stage(lee_instance *inst, int32_t stage);
+
+/* n full steps by replaying a captured hipGraph of the step; asynchronous.
+ * Requires that no partial step is pending (else LEE_E_STATE). */
+lee_status lee_step_n(lee_instance *inst, int64_t n);
+
+/*
+ * Register recorded probes before lee_bind: np points (xy[2k], xy[2k+1]),
+ * sampled after every step by 4 x 4 cubic Lagrange interpolation into a
+ * device ring of `capacity` steps.  A stencil leaving the fluid ->
+ * LEE_E_PROBE.  Optionally a running DFT of p at each probe over steps
+ * [dft_start, dft_start + dft_count): P = (2i/N) sum p(t_n) exp(-i omega t_n)
+ * (pass dft_count = 0 for none).
+ */
+lee_status lee_set_probes(lee_instance *inst, int32_t np, const double *xy, int64_t capacity,
+                          double dft_omega, int64_t dft_start, int64_t dft_count);
+
+/* Synchronising: sample q^n (after a full step) at np <= 256 arbitrary points;
+ * out[3k + {0,1,2}] = p, u, v.  LEE_E_PROBE if a stencil leaves the fluid. */
+lee_status lee_probe(lee_instance *inst, int32_t np, const double *xy, double *out);
+
+/* Synchronising: copy recorded traces, oldest first, out[(s np + k) 3 + f];
+ * *n receives the number of steps copied (at most cap and the ring size). */
+lee_status lee_probe_traces(lee_instance *inst, double *out, int64_t cap, int64_t *n);
+
+/* Synchronising: running DFT amplitudes, out[2k] = Re P_k, out[2k+1] = Im P_k. */
+lee_status lee_probe_dft(lee_instance *inst, double *out);
+
+/* Synchronising: copy q^n at the domain nodes into caller arrays of
+ * ny * nx doubles (row-major, x fastest); any pointer may be NULL. */
+lee_status lee_get_fields(lee_instance *inst, double *p, double *u, double *v);
+
+/* Synchronising: overwrite q^n at fluid nodes from ny * nx doubles. */
+lee_status lee_set_fields(lee_instance *inst, const double *p, const double *u, const double *v);
+
+/* Synchronising: ADE states after the last full step, out[2g + {0,1}]. */
+lee_status lee_get_ade_states(lee_instance *inst, double *out);
+
+/* Completed steps (host-side count of issued steps). */
+lee_status lee_get_step(const lee_instance *inst, int64_t *step);
+
+/*
+ * Copy the set-up lists into caller arrays sized from the summary:
+ * ghost_idx[G] (j nx + i, ascending), cloud_ptr[G+1], cloud_idx[nnz]
+ * (j nx + i, ascending within a ghost), degree[G] (0 = zero ghost),
+ * weights[4 nnz] as (w_BP, w_free, w_Dirichlet, w_Neumann) per entry and
+ * beta[2 G] as (beta_D, beta_N) per ghost, geom[5 G] as (x_BP, y_BP, n_x,
+ * n_y, r) per ghost.  Any pointer may be NULL.
+ */
+lee_status lee_export_lists(const lee_instance *inst, int32_t *ghost_idx, int32_t *cloud_ptr,
+                            int32_t *cloud_idx, int8_t *degree, double *weights, double *beta,
+                            double *geom);
+
+/*
+ * Sweep tiling: vec = columns per lane (FP32: 2 or 4; FP64: 2), rows = rows
+ * per marching tile (>= 1), waves = waves per workgroup (1, 2 or 4).
+ * Invalidates the captured graph.  Defaults come from the built-in tuned
+ * table.
+ */
+lee_status lee_set_tiling(lee_instance *inst, int32_t vec, int32_t rows, int32_t waves);
+
+/*
+ * Measurement: run n steps eagerly with HIP events around every sweep
+ * launch on the bound stream and return the mean sweep and ghost-kernel
+ * durations in microseconds (synchronising).
+ */
+lee_status lee_time_kernels(lee_instance *inst, int64_t n, double *sweep_us, double *ghost_us,
+                            double *step_us);
+
+/* Free host structures and device-side objects the library created (graph,
+ * events); the bound device memory stays the caller's. */
+void lee_destroy(lee_instance *inst);
+
+/* ---------------- batches: many instances in one launch per phase -------- */
+
+typedef struct {
+    int32_t vec, rows, waves;   /* sweep tiling for the whole batch (0 = tuned default) */
+    int32_t persistent_blocks;  /* 0 = one workgroup per work item */
+} lee_batch_opts;
+
+/*
+ * Group n bound instances of the same precision and stencil into a batch
+ * advanced by one launch per phase (ghost fill, sweep, step end) over a
+ * flat work list spanning all members, captured as one hipGraph per step on
+ * the stream of the first member.  The instance table lives in device memory
+ * owned by the batch (allocated by the library).  Members keep their own
+ * step counters; lee_batch_set_budget lets finished members idle without
+ * re-capturing.
+ */
+lee_status lee_batch_create(lee_instance *const *v, int32_t n, const lee_batch_opts *opts,
+                            lee_batch **out);
+
+/* Per-member remaining step budget: a member advances only while its budget
+ * is positive (budget decremented on device every step).  n entries. */
+lee_status lee_batch_set_budget(lee_batch *b, const int64_t *steps);
+
+/* n steps of every member with a positive budget; asynchronous. */
+lee_status lee_batch_step_n(lee_batch *b, int64_t n);
+
+/* Synchronising: mean per-launch sweep and ghost durations over n eager steps. */
+lee_status lee_batch_time_kernels(lee_batch *b, int64_t n, double *sweep_us, double *ghost_us,
+                                  double *step_us);
+
+void lee_batch_destroy(lee_batch *b);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LEE_H */

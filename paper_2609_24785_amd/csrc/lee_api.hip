@@ -1,0 +1,969 @@
+// C ABI of the library: instance life cycle, device memory layout, work lists,
+// stage sequencing, hipGraph capture of a step, probes and timing.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "lee_device.h"
+
+using namespace lee;
+
+struct lee_instance {
+    Host host;
+    int vec = 0, rows = 0, waves = 1;
+    // device
+    bool bound = false;
+    int device = -1;
+    hipStream_t stream = nullptr;
+    char *base = nullptr;
+    size_t bytes = 0;
+    DevInst dev{};
+    DevInst *d_inst = nullptr;
+    int4 *d_work1 = nullptr;
+    size_t work1_cap = 0;
+    int nwork1 = 0;
+    int2 *d_work2 = nullptr;
+    int nwork2 = 0;
+    int *d_sij = nullptr;
+    double *d_sw = nullptr, *d_sout = nullptr;
+    // host staging kept alive for asynchronous uploads
+    std::vector<char> up_w4, up_gd;
+    std::vector<int> up_goff, up_coff;
+    std::vector<int4> up_work1, up_iv;
+    std::vector<int2> up_work2;
+    long long up_counters[3] = {0, LLONG_MAX, 1};
+    // sequencing
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int next_stage = 0;
+    int64_t steps_issued = 0;
+};
+
+namespace {
+
+constexpr int SAMPLE_MAX = 256;
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int esize(const Host &h) { return h.d.precision == LEE_F32 ? 4 : 8; }
+
+int pitch_of(const Host &h)
+{
+    int p = LPAD + h.d.nx + RPAD_MIN;
+    return (p + 63) / 64 * 64;
+}
+
+size_t plane_elems(const Host &h) { return (size_t)(h.d.ny + 2 * FRAME) * pitch_of(h); }
+
+size_t work1_capacity(const Host &h)
+{
+    const int ow_min = 64 * 2 - 16;
+    const size_t strips = (h.d.nx + ow_min - 1) / ow_min;
+    const size_t tiles = (h.d.ny + 3) / 4;
+    return strips * tiles + 64;
+}
+
+struct Layout {
+    size_t inst, planes[9], psi[3], iv, goff, cptr, coff, w4, gd, counters, pij, pw, trace, dft, work1, work2,
+        sij, sw, sout, total;
+};
+
+Layout layout(const Host &h)
+{
+    Layout L{};
+    size_t o = 0;
+    auto take = [&](size_t n) {
+        size_t at = o;
+        o = align256(o + n);
+        return at;
+    };
+    const size_t es = esize(h);
+    const size_t G = h.gidx.size(), nnz = h.cidx.size();
+    L.inst = take(sizeof(DevInst));
+    for (int k = 0; k < 9; ++k) L.planes[k] = take(plane_elems(h) * es);
+    for (int k = 0; k < 3; ++k) L.psi[k] = take(2 * std::max<size_t>(G, 1) * es);
+    L.iv = take((size_t)h.d.ny * sizeof(int4));
+    L.goff = take(std::max<size_t>(G, 1) * 4);
+    L.cptr = take((G + 1) * 4);
+    L.coff = take(std::max<size_t>(nnz, 1) * 4);
+    L.w4 = take(4 * std::max<size_t>(nnz, 1) * es);
+    L.gd = take(4 * std::max<size_t>(G, 1) * es);
+    L.counters = take(3 * 8);
+    L.pij = take(2 * std::max(h.np, 1) * 4);
+    L.pw = take(16 * std::max(h.np, 1) * 8);
+    L.trace = take(std::max<size_t>((size_t)h.trace_cap * h.np * 3, 1) * 8);
+    L.dft = take(2 * std::max(h.np, 1) * 8);
+    L.work1 = take(work1_capacity(h) * sizeof(int4));
+    L.work2 = take(std::max<size_t>(G, 1) * sizeof(int2));
+    L.sij = take(2 * SAMPLE_MAX * 4);
+    L.sw = take(16 * SAMPLE_MAX * 8);
+    L.sout = take(3 * SAMPLE_MAX * 8);
+    L.total = o;
+    return L;
+}
+
+lee_status hip_fail(hipError_t e, const char *what)
+{
+    return fail(LEE_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(x)                                   \
+    do {                                            \
+        hipError_t e_ = (x);                        \
+        if (e_ != hipSuccess) return hip_fail(e_, #x); \
+    } while (0)
+
+void default_tiling(lee_instance *I)
+{
+    const Host &h = I->host;
+    if (h.d.precision == LEE_F32)
+        I->vec = 4;
+    else
+        I->vec = 2;
+    // enough rows per tile to amortise the 10 halo rows, enough tiles to fill
+    // 256 CUs: aim at >= 2048 waves
+    const int ow = 64 * I->vec - 16;
+    const long strips = (h.d.nx + ow - 1) / ow;
+    int rows = 64;
+    while (rows > 8 && strips * ((h.d.ny + rows - 1) / rows) < 2048) rows /= 2;
+    I->rows = rows;
+    I->waves = 1;
+}
+
+// Sweep work list: one item per (strip, row tile) holding fluid nodes;
+// alternate row tiles march in opposite directions; items are grouped so that
+// consecutive workgroups of one XCD (workgroup id mod 8) cover neighbouring
+// tiles.
+void build_work1(const Host &h, int inst_id, int vec, int rows, int waves, std::vector<int4> &out, bool xcd)
+{
+    const int ow = 64 * vec - 16;
+    const int strips = (h.d.nx + ow - 1) / ow;
+    const int tiles = (h.d.ny + rows - 1) / rows;
+    std::vector<int4> items;
+    for (int t = 0; t < tiles; ++t) {
+        const int r0 = t * rows, r1 = std::min(r0 + rows, h.d.ny);
+        for (int s = 0; s < strips; ++s) {
+            const int c0 = s * ow, c1 = std::min(c0 + ow, h.d.nx);
+            bool any = false;
+            for (int j = r0; j < r1 && !any; ++j) {
+                const int *iv = &h.iv[(size_t)j * 4];
+                for (int q = 0; q < 2; ++q)
+                    if (iv[2 * q] < iv[2 * q + 1] && iv[2 * q] < c1 && iv[2 * q + 1] > c0) any = true;
+            }
+            if (!any) continue;
+            items.push_back(make_int4(inst_id, c0, r0, (t & 1) ? -r1 : r1));
+        }
+    }
+    if (!xcd) {
+        out.insert(out.end(), items.begin(), items.end());
+        return;
+    }
+    const int units = (int)((items.size() + waves - 1) / waves);
+    const int per = (units + 7) / 8;
+    for (int b = 0; b < 8 * per; ++b) {
+        const int su = (b % 8) * per + b / 8;
+        for (int w = 0; w < waves; ++w) {
+            const size_t k = (size_t)su * waves + w;
+            if (su < units && k < items.size())
+                out.push_back(items[k]);
+            else
+                out.push_back(make_int4(-1, 0, 0, 1));   // idle slot keeps the XCD pattern
+        }
+    }
+}
+
+lee_status upload_work1(lee_instance *I)
+{
+    I->up_work1.clear();
+    build_work1(I->host, 0, I->vec, I->rows, I->waves, I->up_work1, true);
+    if (I->up_work1.size() > I->work1_cap) return fail(LEE_E_ARG, "tiling produces too many work items");
+    I->nwork1 = (int)I->up_work1.size();
+    HIPCHK(hipMemcpyAsync(I->d_work1, I->up_work1.data(), I->up_work1.size() * sizeof(int4),
+                          hipMemcpyHostToDevice, I->stream));
+    return LEE_OK;
+}
+
+void drop_graph(lee_instance *I)
+{
+    if (I->exec) hipGraphExecDestroy(I->exec);
+    if (I->graph) hipGraphDestroy(I->graph);
+    I->exec = nullptr;
+    I->graph = nullptr;
+}
+
+hipError_t issue_stage(lee_instance *I, int stage)
+{
+    const int prec = I->host.d.precision;
+    hipError_t e = launch_ghost(prec, I->d_inst, I->d_work2, I->nwork2, stage, I->stream);
+    if (e != hipSuccess) return e;
+    e = launch_sweep(prec, I->vec, I->host.d.filter_sigma > 0.0, I->waves, I->d_inst, I->d_work1, I->nwork1,
+                     stage, 0, I->stream);
+    if (e != hipSuccess) return e;
+    if (stage == 3) e = launch_step_end(prec, I->d_inst, 1, I->stream);
+    return e;
+}
+
+template <typename T>
+void pack_lists(lee_instance *I)
+{
+    const Host &h = I->host;
+    const int pitch = pitch_of(h);
+    const size_t G = h.gidx.size(), nnz = h.cidx.size();
+    I->up_w4.assign(4 * nnz * sizeof(T), 0);
+    T *w = (T *)I->up_w4.data();
+    for (size_t k = 0; k < 4 * nnz; ++k) w[k] = (T)h.w4[k];
+    I->up_gd.assign(4 * G * sizeof(T), 0);
+    T *gd = (T *)I->up_gd.data();
+    for (size_t g = 0; g < G; ++g) {
+        gd[4 * g + 0] = (T)h.gnx[g];
+        gd[4 * g + 1] = (T)h.gny[g];
+        gd[4 * g + 2] = (T)h.beta[2 * g];
+        gd[4 * g + 3] = (T)h.beta[2 * g + 1];
+    }
+    I->up_goff.resize(G);
+    for (size_t g = 0; g < G; ++g) I->up_goff[g] = (h.gidx[g] / h.d.nx) * pitch + h.gidx[g] % h.d.nx;
+    I->up_coff.resize(nnz);
+    for (size_t e = 0; e < nnz; ++e) I->up_coff[e] = (h.cidx[e] / h.d.nx) * pitch + h.cidx[e] % h.d.nx;
+}
+
+}  // namespace
+
+extern "C" {
+
+lee_status lee_setup_grid(const lee_case_desc *d, lee_instance **out)
+{
+    if (!out) return fail(LEE_E_ARG, "null output pointer");
+    *out = nullptr;
+    lee_instance *I = new (std::nothrow) lee_instance();
+    if (!I) return fail(LEE_E_NOMEM, "host allocation");
+    lee_status s = host_setup(d, &I->host);
+    if (s != LEE_OK) {
+        delete I;
+        return s;
+    }
+    default_tiling(I);
+    *out = I;
+    return LEE_OK;
+}
+
+lee_status lee_build_ghosts(lee_instance *I, const lee_impedance *z, int32_t degree, lee_ghost_summary *out)
+{
+    if (!I) return fail(LEE_E_ARG, "null instance");
+    if (I->bound) return fail(LEE_E_STATE, "lee_build_ghosts after lee_bind");
+    return host_build(&I->host, z, degree, out);
+}
+
+lee_status lee_set_probes(lee_instance *I, int32_t np, const double *xy, int64_t capacity, double dft_omega,
+                          int64_t dft_start, int64_t dft_count)
+{
+    if (!I) return fail(LEE_E_ARG, "null instance");
+    if (I->bound) return fail(LEE_E_STATE, "lee_set_probes after lee_bind");
+    if (np < 0 || (np > 0 && !xy) || capacity < 0 || dft_count < 0 || dft_start < 0)
+        return fail(LEE_E_ARG, "probe arguments");
+    Host &h = I->host;
+    h.probe_ij.assign(2 * (size_t)np, 0);
+    h.probe_w.assign(16 * (size_t)np, 0.0);
+    for (int k = 0; k < np; ++k) {
+        lee_status s = host_probe_stencil(&h, xy[2 * k], xy[2 * k + 1], &h.probe_ij[2 * k], &h.probe_ij[2 * k + 1],
+                                          &h.probe_w[16 * k]);
+        if (s != LEE_OK) return s;
+    }
+    h.np = np;
+    h.trace_cap = np > 0 ? capacity : 0;
+    h.dft_omega = dft_omega;
+    h.dft_start = dft_start;
+    h.dft_count = np > 0 ? dft_count : 0;
+    return LEE_OK;
+}
+
+lee_status lee_required_bytes(const lee_instance *I, size_t *dev_bytes)
+{
+    if (!I || !dev_bytes) return fail(LEE_E_ARG, "null argument");
+    if (!I->host.built) return fail(LEE_E_STATE, "lee_build_ghosts first");
+    *dev_bytes = layout(I->host).total;
+    return LEE_OK;
+}
+
+lee_status lee_bind(lee_instance *I, void *dev_ptr, size_t bytes, void *hip_stream)
+{
+    if (!I || !dev_ptr) return fail(LEE_E_ARG, "null argument");
+    if (I->bound) return fail(LEE_E_STATE, "already bound");
+    if (!I->host.built) return fail(LEE_E_STATE, "lee_build_ghosts first");
+    if (((uintptr_t)dev_ptr & 255) != 0) return fail(LEE_E_ARG, "device buffer must be 256-byte aligned");
+    const Host &h = I->host;
+    const Layout L = layout(h);
+    if (bytes < L.total) return fail(LEE_E_NOMEM, "device buffer smaller than lee_required_bytes");
+    HIPCHK(hipGetDevice(&I->device));
+    I->stream = (hipStream_t)hip_stream;
+    I->base = (char *)dev_ptr;
+    I->bytes = bytes;
+    char *b = I->base;
+    const int pitch = pitch_of(h);
+    const size_t es = esize(h);
+    const size_t origin = ((size_t)FRAME * pitch + LPAD) * es;
+    DevInst &D = I->dev;
+    std::memset(&D, 0, sizeof(D));
+    for (int r = 0; r < 3; ++r)
+        for (int f = 0; f < 3; ++f) D.f[r][f] = b + L.planes[3 * r + f] + origin;
+    for (int r = 0; r < 3; ++r) D.psi[r] = b + L.psi[r];
+    D.iv = (const int4 *)(b + L.iv);
+    D.goff = (const int *)(b + L.goff);
+    D.cptr = (const int *)(b + L.cptr);
+    D.coff = (const int *)(b + L.coff);
+    D.w4 = b + L.w4;
+    D.gd = b + L.gd;
+    D.step = (long long *)(b + L.counters);
+    D.budget = D.step + 1;
+    D.active = (int *)(D.step + 2);
+    D.pij = (const int *)(b + L.pij);
+    D.pw = (const double *)(b + L.pw);
+    D.trace = (double *)(b + L.trace);
+    D.dft = (double *)(b + L.dft);
+    D.trace_cap = h.trace_cap;
+    D.dft_start = h.dft_start;
+    D.dft_count = h.dft_count;
+    D.dft_omega = h.dft_omega;
+    D.np = h.np;
+    D.nx = h.d.nx;
+    D.ny = h.d.ny;
+    D.pitch = pitch;
+    D.G = (int)h.gidx.size();
+    D.x0 = h.d.x0;
+    D.y0 = h.d.y0;
+    D.h = h.d.h;
+    D.dt = h.dt;
+    static const double A5[5] = {0.872756993962, -0.286511173973, 0.090320001280, -0.020779405824, 0.002484594688};
+    static const double A3[3] = {0.770882380518, -0.166705904415, 0.020843142770};
+    static const double FD[6] = {0.215044884112, -0.187772883589, 0.123755948787, -0.059227575576, 0.018721609157,
+                                 -0.002999540835};
+    for (int k = 0; k < 5; ++k) {
+        const double a = h.d.stencil_half == 5 ? A5[k] : (k < 3 ? A3[k] : 0.0);
+        D.ax[k] = a / h.d.h;
+    }
+    const double sd = h.d.filter_sigma / h.dt;
+    D.fd[0] = sd * 2.0 * FD[0];
+    for (int k = 1; k < 6; ++k) D.fd[k] = sd * FD[k];
+    static const double ALPHA[4] = {0.25, 1.0 / 3.0, 0.5, 1.0};
+    static const double CST[4] = {0.0, 0.25, 1.0 / 3.0, 0.5};
+    for (int l = 0; l < 4; ++l) {
+        D.alpha_dt[l] = ALPHA[l] * h.dt;
+        D.c_stage[l] = CST[l];
+    }
+    D.sponge_w = h.d.sponge_cells;
+    D.sponge_s = h.d.sponge_sigma;
+    D.has_src = h.d.src_kind == LEE_SRC_MONOPOLE ? 1 : 0;
+    if (D.has_src) {
+        const double xs = h.d.src[0], ys = h.d.src[1], w = h.d.src[3];
+        D.src_a = h.d.src[2];
+        D.src_b = 0.6931471805599453 / (w * w);
+        D.src_om = h.d.src[4];
+        D.src_ic = (int)std::lround((xs - h.d.x0) / h.d.h);
+        D.src_jc = (int)std::lround((ys - h.d.y0) / h.d.h);
+        D.src_fx = xs - (h.d.x0 + D.src_ic * h.d.h);
+        D.src_fy = ys - (h.d.y0 + D.src_jc * h.d.h);
+        // exp(-b r^2) < 1e-45 beyond r^2 > 104 / b
+        const int rad = (int)std::ceil(std::sqrt(104.0 / D.src_b) / h.d.h) + 1;
+        D.src_i0 = D.src_ic - rad;
+        D.src_i1 = D.src_ic + rad;
+        D.src_j0 = D.src_jc - rad;
+        D.src_j1 = D.src_jc + rad;
+    }
+    D.ade_kind = h.ade_kind;
+    for (int k = 0; k < 4; ++k) D.ade[k] = h.ade[k];
+
+    // uploads
+    if (h.d.precision == LEE_F32)
+        pack_lists<float>(I);
+    else
+        pack_lists<double>(I);
+    I->up_iv.resize(h.d.ny);
+    for (int j = 0; j < h.d.ny; ++j)
+        I->up_iv[j] = make_int4(h.iv[4 * j], h.iv[4 * j + 1], h.iv[4 * j + 2], h.iv[4 * j + 3]);
+    const size_t G = h.gidx.size(), nnz = h.cidx.size();
+    hipStream_t s = I->stream;
+    HIPCHK(hipMemcpyAsync((void *)D.iv, I->up_iv.data(), h.d.ny * sizeof(int4), hipMemcpyHostToDevice, s));
+    if (G) {
+        HIPCHK(hipMemcpyAsync((void *)D.goff, I->up_goff.data(), G * 4, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync((void *)D.cptr, h.cptr.data(), (G + 1) * 4, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync((void *)D.gd, I->up_gd.data(), I->up_gd.size(), hipMemcpyHostToDevice, s));
+    }
+    if (nnz) {
+        HIPCHK(hipMemcpyAsync((void *)D.coff, I->up_coff.data(), nnz * 4, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync((void *)D.w4, I->up_w4.data(), I->up_w4.size(), hipMemcpyHostToDevice, s));
+    }
+    if (h.np) {
+        HIPCHK(hipMemcpyAsync((void *)D.pij, h.probe_ij.data(), 2 * h.np * 4, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync((void *)D.pw, h.probe_w.data(), 16 * h.np * 8, hipMemcpyHostToDevice, s));
+    }
+    I->d_inst = (DevInst *)(b + L.inst);
+    HIPCHK(hipMemcpyAsync(I->d_inst, &I->dev, sizeof(DevInst), hipMemcpyHostToDevice, s));
+    I->d_work1 = (int4 *)(b + L.work1);
+    I->work1_cap = work1_capacity(h);
+    I->d_work2 = (int2 *)(b + L.work2);
+    I->up_work2.resize(G);
+    for (size_t g = 0; g < G; ++g) I->up_work2[g] = make_int2(0, (int)g);
+    I->nwork2 = (int)G;
+    if (G) HIPCHK(hipMemcpyAsync(I->d_work2, I->up_work2.data(), G * sizeof(int2), hipMemcpyHostToDevice, s));
+    I->d_sij = (int *)(b + L.sij);
+    I->d_sw = (double *)(b + L.sw);
+    I->d_sout = (double *)(b + L.sout);
+    lee_status st = upload_work1(I);
+    if (st != LEE_OK) return st;
+    I->bound = true;
+    return lee_init_fields(I);
+}
+
+lee_status lee_init_fields(lee_instance *I)
+{
+    if (!I || !I->bound) return fail(LEE_E_STATE, "instance not bound");
+    const Host &h = I->host;
+    const Layout L = layout(h);
+    hipStream_t s = I->stream;
+    const int prec = h.d.precision;
+    for (int k = 0; k < 9; ++k) HIPCHK(launch_fill(prec, I->base + L.planes[k], plane_elems(h), s));
+    for (int k = 0; k < 3; ++k) HIPCHK(launch_fill(prec, I->base + L.psi[k], 2 * std::max<size_t>(h.gidx.size(), 1), s));
+    HIPCHK(launch_fill_bytes(I->base + L.trace, std::max<size_t>((size_t)h.trace_cap * h.np * 3, 1) * 8, s));
+    HIPCHK(launch_fill_bytes(I->base + L.dft, 2 * std::max(h.np, 1) * 8, s));
+    I->up_counters[0] = 0;
+    I->up_counters[1] = LLONG_MAX;
+    I->up_counters[2] = 1;   // active flag lives in the low word of the third slot
+    HIPCHK(hipMemcpyAsync(I->dev.step, I->up_counters, sizeof(I->up_counters), hipMemcpyHostToDevice, s));
+    HIPCHK(launch_init_ic(prec, I->d_inst, h.d.nx, h.d.ny, h.d.ic_kind, h.d.ic, s));
+    I->next_stage = 0;
+    I->steps_issued = 0;
+    return LEE_OK;
+}
+
+lee_status lee_rk_stage(lee_instance *I, int32_t stage)
+{
+    if (!I || !I->bound) return fail(LEE_E_STATE, "instance not bound");
+    if (stage < 0 || stage > 3) return fail(LEE_E_ARG, "stage must be 0..3");
+    if (stage != I->next_stage) return fail(LEE_E_STATE, "stages must be issued in order 0, 1, 2, 3");
+    HIPCHK(issue_stage(I, stage));
+    I->next_stage = (stage + 1) & 3;
+    if (stage == 3) ++I->steps_issued;
+    return LEE_OK;
+}
+
+lee_status lee_step_n(lee_instance *I, int64_t n)
+{
+    if (!I || !I->bound) return fail(LEE_E_STATE, "instance not bound");
+    if (n < 0) return fail(LEE_E_ARG, "n < 0");
+    if (I->next_stage != 0) return fail(LEE_E_STATE, "a partial step is pending");
+    if (n == 0) return LEE_OK;
+    if (I->stream == nullptr) {      // the legacy default stream cannot be captured
+        for (int64_t k = 0; k < n; ++k)
+            for (int l = 0; l < 4; ++l) HIPCHK(issue_stage(I, l));
+        I->steps_issued += n;
+        return LEE_OK;
+    }
+    if (!I->exec) {
+        HIPCHK(hipStreamBeginCapture(I->stream, hipStreamCaptureModeThreadLocal));
+        hipError_t e = hipSuccess;
+        for (int l = 0; l < 4 && e == hipSuccess; ++l) e = issue_stage(I, l);
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(I->stream, &g);
+        if (e != hipSuccess) {
+            if (g) hipGraphDestroy(g);
+            return hip_fail(e, "capturing the step");
+        }
+        if (e2 != hipSuccess) return hip_fail(e2, "hipStreamEndCapture");
+        I->graph = g;
+        HIPCHK(hipGraphInstantiate(&I->exec, I->graph, nullptr, nullptr, 0));
+    }
+    for (int64_t k = 0; k < n; ++k) HIPCHK(hipGraphLaunch(I->exec, I->stream));
+    I->steps_issued += n;
+    return LEE_OK;
+}
+
+lee_status lee_set_tiling(lee_instance *I, int32_t vec, int32_t rows, int32_t waves)
+{
+    if (!I) return fail(LEE_E_ARG, "null instance");
+    const bool f32 = I->host.d.precision == LEE_F32;
+    if (!((f32 && (vec == 2 || vec == 4)) || (!f32 && vec == 2))) return fail(LEE_E_ARG, "unsupported vec");
+    if (rows < 4 || rows > 4096) return fail(LEE_E_ARG, "rows must lie in [4, 4096]");
+    if (waves != 1 && waves != 2 && waves != 4) return fail(LEE_E_ARG, "waves must be 1, 2 or 4");
+    if (I->next_stage != 0) return fail(LEE_E_STATE, "a partial step is pending");
+    I->vec = vec;
+    I->rows = rows;
+    I->waves = waves;
+    drop_graph(I);
+    if (I->bound) return upload_work1(I);
+    return LEE_OK;
+}
+
+lee_status lee_get_step(const lee_instance *I, int64_t *step)
+{
+    if (!I || !step) return fail(LEE_E_ARG, "null argument");
+    *step = I->steps_issued;
+    return LEE_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+template <typename T>
+lee_status copy_plane_out(lee_instance *I, int reg, int f, double *out)
+{
+    const Host &h = I->host;
+    std::vector<T> tmp((size_t)h.d.nx * h.d.ny);
+    HIPCHK(hipMemcpy2DAsync(tmp.data(), h.d.nx * sizeof(T), I->dev.f[reg][f], pitch_of(h) * sizeof(T),
+                            h.d.nx * sizeof(T), h.d.ny, hipMemcpyDeviceToHost, I->stream));
+    HIPCHK(hipStreamSynchronize(I->stream));
+    for (size_t k = 0; k < tmp.size(); ++k) out[k] = (double)tmp[k];
+    return LEE_OK;
+}
+
+template <typename T>
+lee_status copy_plane_in(lee_instance *I, int f, const double *in)
+{
+    const Host &h = I->host;
+    std::vector<T> tmp((size_t)h.d.nx * h.d.ny);
+    for (size_t k = 0; k < tmp.size(); ++k) tmp[k] = h.fluid[k] ? (T)in[k] : (T)0;
+    HIPCHK(hipMemcpy2DAsync(I->dev.f[0][f], pitch_of(h) * sizeof(T), tmp.data(), h.d.nx * sizeof(T),
+                            h.d.nx * sizeof(T), h.d.ny, hipMemcpyHostToDevice, I->stream));
+    HIPCHK(hipStreamSynchronize(I->stream));
+    return LEE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lee_status lee_get_fields(lee_instance *I, double *p, double *u, double *v)
+{
+    if (!I || !I->bound) return fail(LEE_E_STATE, "instance not bound");
+    if (I->next_stage != 0) return fail(LEE_E_STATE, "a partial step is pending");
+    double *o[3] = {p, u, v};
+    for (int f = 0; f < 3; ++f) {
+        if (!o[f]) continue;
+        lee_status s = I->host.d.precision == LEE_F32 ? copy_plane_out<float>(I, 0, f, o[f])
+                                                      : copy_plane_out<double>(I, 0, f, o[f]);
+        if (s != LEE_OK) return s;
+    }
+    return LEE_OK;
+}
+
+lee_status lee_set_fields(lee_instance *I, const double *p, const double *u, const double *v)
+{
+    if (!I || !I->bound) return fail(LEE_E_STATE, "instance not bound");
+    if (I->next_stage != 0) return fail(LEE_E_STATE, "a partial step is pending");
+    const double *in[3] = {p, u, v};
+    for (int f = 0; f < 3; ++f) {
+        if (!in[f]) continue;
+        lee_status s = I->host.d.precision == LEE_F32 ? copy_plane_in<float>(I, f, in[f])
+                                                      : copy_plane_in<double>(I, f, in[f]);
+        if (s != LEE_OK) return s;
+    }
+    return LEE_OK;
+}
+
+lee_status lee_get_ade_states(lee_instance *I, double *out)
+{
+    if (!I || !I->bound || !out) return fail(LEE_E_ARG, "instance not bound or null output");
+    const size_t n = 2 * I->host.gidx.size();
+    if (!n) return LEE_OK;
+    if (I->host.d.precision == LEE_F32) {
+        std::vector<float> t(n);
+        HIPCHK(hipMemcpyAsync(t.data(), I->dev.psi[0], n * 4, hipMemcpyDeviceToHost, I->stream));
+        HIPCHK(hipStreamSynchronize(I->stream));
+        for (size_t k = 0; k < n; ++k) out[k] = t[k];
+    } else {
+        HIPCHK(hipMemcpyAsync(out, I->dev.psi[0], n * 8, hipMemcpyDeviceToHost, I->stream));
+        HIPCHK(hipStreamSynchronize(I->stream));
+    }
+    return LEE_OK;
+}
+
+lee_status lee_probe(lee_instance *I, int32_t np, const double *xy, double *out)
+{
+    if (!I || !I->bound) return fail(LEE_E_STATE, "instance not bound");
+    if (np < 0 || np > SAMPLE_MAX || (np > 0 && (!xy || !out))) return fail(LEE_E_ARG, "probe arguments");
+    if (I->next_stage != 0) return fail(LEE_E_STATE, "a partial step is pending");
+    if (np == 0) return LEE_OK;
+    std::vector<int> ij(2 * np);
+    std::vector<double> w(16 * np);
+    for (int k = 0; k < np; ++k) {
+        lee_status s = host_probe_stencil(&I->host, xy[2 * k], xy[2 * k + 1], &ij[2 * k], &ij[2 * k + 1], &w[16 * k]);
+        if (s != LEE_OK) return s;
+    }
+    HIPCHK(hipMemcpyAsync(I->d_sij, ij.data(), ij.size() * 4, hipMemcpyHostToDevice, I->stream));
+    HIPCHK(hipMemcpyAsync(I->d_sw, w.data(), w.size() * 8, hipMemcpyHostToDevice, I->stream));
+    HIPCHK(launch_sample(I->host.d.precision, I->d_inst, I->d_sij, I->d_sw, np, I->d_sout, I->stream));
+    HIPCHK(hipMemcpyAsync(out, I->d_sout, 3 * np * 8, hipMemcpyDeviceToHost, I->stream));
+    HIPCHK(hipStreamSynchronize(I->stream));
+    return LEE_OK;
+}
+
+lee_status lee_probe_traces(lee_instance *I, double *out, int64_t cap, int64_t *n)
+{
+    if (!I || !I->bound || !n) return fail(LEE_E_ARG, "instance not bound or null argument");
+    const Host &h = I->host;
+    *n = 0;
+    if (h.np == 0 || h.trace_cap == 0) return LEE_OK;
+    long long done = 0;
+    HIPCHK(hipMemcpyAsync(&done, I->dev.step, 8, hipMemcpyDeviceToHost, I->stream));
+    std::vector<double> ring((size_t)h.trace_cap * h.np * 3);
+    HIPCHK(hipMemcpyAsync(ring.data(), I->dev.trace, ring.size() * 8, hipMemcpyDeviceToHost, I->stream));
+    HIPCHK(hipStreamSynchronize(I->stream));
+    int64_t m = std::min<int64_t>({(int64_t)done, (int64_t)h.trace_cap, cap});
+    if (m > 0 && !out) return fail(LEE_E_ARG, "null output");
+    const int64_t first = done - m;
+    const size_t row = (size_t)h.np * 3;
+    for (int64_t s = 0; s < m; ++s)
+        std::memcpy(out + s * row, ring.data() + (size_t)((first + s) % h.trace_cap) * row, row * 8);
+    *n = m;
+    return LEE_OK;
+}
+
+lee_status lee_probe_dft(lee_instance *I, double *out)
+{
+    if (!I || !I->bound || !out) return fail(LEE_E_ARG, "instance not bound or null output");
+    const Host &h = I->host;
+    if (h.np == 0) return LEE_OK;
+    std::vector<double> acc(2 * (size_t)h.np);
+    HIPCHK(hipMemcpyAsync(acc.data(), I->dev.dft, acc.size() * 8, hipMemcpyDeviceToHost, I->stream));
+    HIPCHK(hipStreamSynchronize(I->stream));
+    const double N = h.dft_count > 0 ? (double)h.dft_count : 1.0;
+    for (int k = 0; k < h.np; ++k) {      // P = (2i/N) (Sr + i Si)
+        out[2 * k] = -2.0 * acc[2 * k + 1] / N;
+        out[2 * k + 1] = 2.0 * acc[2 * k] / N;
+    }
+    return LEE_OK;
+}
+
+lee_status lee_export_lists(const lee_instance *I, int32_t *ghost_idx, int32_t *cloud_ptr, int32_t *cloud_idx,
+                            int8_t *degree, double *weights, double *beta, double *geom)
+{
+    if (!I) return fail(LEE_E_ARG, "null instance");
+    const Host &h = I->host;
+    if (!h.built) return fail(LEE_E_STATE, "lee_build_ghosts first");
+    const size_t G = h.gidx.size(), nnz = h.cidx.size();
+    if (ghost_idx) std::copy(h.gidx.begin(), h.gidx.end(), ghost_idx);
+    if (cloud_ptr) std::copy(h.cptr.begin(), h.cptr.end(), cloud_ptr);
+    if (cloud_idx) std::copy(h.cidx.begin(), h.cidx.end(), cloud_idx);
+    if (degree) std::copy(h.deg.begin(), h.deg.end(), degree);
+    if (weights) std::copy(h.w4.begin(), h.w4.end(), weights);
+    if (beta) std::copy(h.beta.begin(), h.beta.end(), beta);
+    if (geom)
+        for (size_t g = 0; g < G; ++g) {
+            geom[5 * g + 0] = h.bx[g];
+            geom[5 * g + 1] = h.by[g];
+            geom[5 * g + 2] = h.gnx[g];
+            geom[5 * g + 3] = h.gny[g];
+            geom[5 * g + 4] = h.r[g];
+        }
+    (void)nnz;
+    return LEE_OK;
+}
+
+lee_status lee_time_kernels(lee_instance *I, int64_t n, double *sweep_us, double *ghost_us, double *step_us)
+{
+    if (!I || !I->bound) return fail(LEE_E_STATE, "instance not bound");
+    if (n <= 0) return fail(LEE_E_ARG, "n must be positive");
+    if (I->next_stage != 0) return fail(LEE_E_STATE, "a partial step is pending");
+    constexpr int CH = 32;                       // steps per event chunk
+    std::vector<hipEvent_t> ev(CH * 16 + 2);
+    for (auto &e : ev) HIPCHK(hipEventCreate(&e));
+    const int prec = I->host.d.precision;
+    double tsw = 0, tgh = 0, tstep = 0;
+    int64_t done = 0;
+    lee_status st = LEE_OK;
+    while (done < n && st == LEE_OK) {
+        const int m = (int)std::min<int64_t>(CH, n - done);
+        hipEventRecord(ev[CH * 16], I->stream);
+        for (int k = 0; k < m; ++k)
+            for (int l = 0; l < 4; ++l) {
+                hipEvent_t *e = &ev[(k * 4 + l) * 4];
+                hipEventRecord(e[0], I->stream);
+                launch_ghost(prec, I->d_inst, I->d_work2, I->nwork2, l, I->stream);
+                hipEventRecord(e[1], I->stream);
+                hipEventRecord(e[2], I->stream);
+                launch_sweep(prec, I->vec, I->host.d.filter_sigma > 0.0, I->waves, I->d_inst, I->d_work1, I->nwork1,
+                             l, 0, I->stream);
+                hipEventRecord(e[3], I->stream);
+                if (l == 3) launch_step_end(prec, I->d_inst, 1, I->stream);
+            }
+        hipEventRecord(ev[CH * 16 + 1], I->stream);
+        hipError_t e = hipEventSynchronize(ev[CH * 16 + 1]);
+        if (e != hipSuccess) {
+            st = hip_fail(e, "timing run");
+            break;
+        }
+        for (int k = 0; k < m * 4; ++k) {
+            float a = 0, b = 0;
+            hipEventElapsedTime(&a, ev[k * 4 + 0], ev[k * 4 + 1]);
+            hipEventElapsedTime(&b, ev[k * 4 + 2], ev[k * 4 + 3]);
+            tgh += a;
+            tsw += b;
+        }
+        float c = 0;
+        hipEventElapsedTime(&c, ev[CH * 16], ev[CH * 16 + 1]);
+        tstep += c;
+        done += m;
+    }
+    for (auto &e : ev) hipEventDestroy(e);
+    if (st != LEE_OK) return st;
+    I->steps_issued += n;
+    if (sweep_us) *sweep_us = 1000.0 * tsw / (4.0 * n);
+    if (ghost_us) *ghost_us = 1000.0 * tgh / (4.0 * n);
+    if (step_us) *step_us = 1000.0 * tstep / n;
+    return LEE_OK;
+}
+
+void lee_destroy(lee_instance *I)
+{
+    if (!I) return;
+    drop_graph(I);
+    delete I;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// batches: one launch per phase over the work of all members
+
+struct lee_batch {
+    std::vector<lee_instance *> members;
+    int prec = LEE_F32;
+    bool filt = true;
+    int vec = 4, rows = 32, waves = 1, pblocks = 0;
+    hipStream_t stream = nullptr;
+    int device = -1;
+    DevInst *d_table = nullptr;
+    int4 *d_work1 = nullptr;
+    int nwork1 = 0;
+    int2 *d_work2 = nullptr;
+    int nwork2 = 0;
+    std::vector<DevInst> up_table;
+    std::vector<int4> up_work1;
+    std::vector<int2> up_work2;
+    std::vector<long long> up_budget;      // (budget, active) pairs
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+void batch_drop_graph(lee_batch *B)
+{
+    if (B->exec) hipGraphExecDestroy(B->exec);
+    if (B->graph) hipGraphDestroy(B->graph);
+    B->exec = nullptr;
+    B->graph = nullptr;
+}
+
+hipError_t batch_issue_stage(lee_batch *B, int stage)
+{
+    hipError_t e = launch_ghost(B->prec, B->d_table, B->d_work2, B->nwork2, stage, B->stream);
+    if (e != hipSuccess) return e;
+    int blocks = 0;
+    if (B->pblocks > 0) blocks = std::min(B->pblocks, (B->nwork1 + B->waves - 1) / B->waves);
+    e = launch_sweep(B->prec, B->vec, B->filt, B->waves, B->d_table, B->d_work1, B->nwork1, stage, blocks, B->stream);
+    if (e != hipSuccess) return e;
+    if (stage == 3) e = launch_step_end(B->prec, B->d_table, (int)B->members.size(), B->stream);
+    return e;
+}
+
+void batch_free(lee_batch *B)
+{
+    batch_drop_graph(B);
+    if (B->d_table) hipFree(B->d_table);
+    if (B->d_work1) hipFree(B->d_work1);
+    if (B->d_work2) hipFree(B->d_work2);
+    B->d_table = nullptr;
+    B->d_work1 = nullptr;
+    B->d_work2 = nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+lee_status lee_batch_create(lee_instance *const *v, int32_t n, const lee_batch_opts *opts, lee_batch **out)
+{
+    if (!v || n <= 0 || !out) return fail(LEE_E_ARG, "batch arguments");
+    *out = nullptr;
+    for (int k = 0; k < n; ++k) {
+        if (!v[k] || !v[k]->bound) return fail(LEE_E_STATE, "every member must be bound");
+        if (v[k]->next_stage != 0) return fail(LEE_E_STATE, "a member has a partial step pending");
+        if (v[k]->host.d.precision != v[0]->host.d.precision) return fail(LEE_E_ARG, "mixed precision");
+        if ((v[k]->host.d.filter_sigma > 0.0) != (v[0]->host.d.filter_sigma > 0.0))
+            return fail(LEE_E_ARG, "mixed filter on/off");
+        if (v[k]->device != v[0]->device) return fail(LEE_E_ARG, "members on different devices");
+    }
+    lee_batch *B = new (std::nothrow) lee_batch();
+    if (!B) return fail(LEE_E_NOMEM, "host allocation");
+    B->members.assign(v, v + n);
+    B->prec = v[0]->host.d.precision;
+    B->filt = v[0]->host.d.filter_sigma > 0.0;
+    B->stream = v[0]->stream;
+    B->device = v[0]->device;
+    B->vec = B->prec == LEE_F32 ? 4 : 2;
+    B->rows = 32;
+    B->waves = 1;
+    if (opts) {
+        if (opts->vec) B->vec = opts->vec;
+        if (opts->rows) B->rows = opts->rows;
+        if (opts->waves) B->waves = opts->waves;
+        B->pblocks = opts->persistent_blocks;
+    }
+    const bool f32 = B->prec == LEE_F32;
+    if (!((f32 && (B->vec == 2 || B->vec == 4)) || (!f32 && B->vec == 2)) || B->rows < 4 ||
+        (B->waves != 1 && B->waves != 2 && B->waves != 4) || B->pblocks < 0) {
+        delete B;
+        return fail(LEE_E_ARG, "batch tiling options");
+    }
+    if (B->pblocks > 0) B->pblocks = (B->pblocks + 7) / 8 * 8;   // keep the XCD pattern
+    std::vector<int4> items;
+    for (int k = 0; k < n; ++k) build_work1(v[k]->host, k, B->vec, B->rows, 1, items, false);
+    // XCD-aware grouping over the whole list (see build_work1)
+    const int units = (int)((items.size() + B->waves - 1) / B->waves);
+    const int per = (units + 7) / 8;
+    for (int b = 0; b < 8 * per; ++b) {
+        const int su = (b % 8) * per + b / 8;
+        for (int w = 0; w < B->waves; ++w) {
+            const size_t q = (size_t)su * B->waves + w;
+            B->up_work1.push_back(su < units && q < items.size() ? items[q] : make_int4(-1, 0, 0, 1));
+        }
+    }
+    for (int k = 0; k < n; ++k)
+        for (int g = 0; g < (int)v[k]->host.gidx.size(); ++g) B->up_work2.push_back(make_int2(k, g));
+    for (int k = 0; k < n; ++k) B->up_table.push_back(v[k]->dev);
+    B->nwork1 = (int)B->up_work1.size();
+    B->nwork2 = (int)B->up_work2.size();
+    hipError_t e = hipSuccess;
+    e = hipMalloc(&B->d_table, n * sizeof(DevInst));
+    if (e == hipSuccess) e = hipMalloc(&B->d_work1, std::max<size_t>(B->up_work1.size(), 1) * sizeof(int4));
+    if (e == hipSuccess) e = hipMalloc(&B->d_work2, std::max<size_t>(B->up_work2.size(), 1) * sizeof(int2));
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(B->d_table, B->up_table.data(), n * sizeof(DevInst), hipMemcpyHostToDevice, B->stream);
+    if (e == hipSuccess && B->nwork1)
+        e = hipMemcpyAsync(B->d_work1, B->up_work1.data(), B->nwork1 * sizeof(int4), hipMemcpyHostToDevice,
+                           B->stream);
+    if (e == hipSuccess && B->nwork2)
+        e = hipMemcpyAsync(B->d_work2, B->up_work2.data(), B->nwork2 * sizeof(int2), hipMemcpyHostToDevice,
+                           B->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(B->stream);
+    if (e != hipSuccess) {
+        batch_free(B);
+        delete B;
+        return hip_fail(e, "batch set-up");
+    }
+    *out = B;
+    return LEE_OK;
+}
+
+lee_status lee_batch_set_budget(lee_batch *B, const int64_t *steps)
+{
+    if (!B || !steps) return fail(LEE_E_ARG, "null argument");
+    const size_t n = B->members.size();
+    B->up_budget.assign(2 * n, 0);
+    for (size_t k = 0; k < n; ++k) {
+        if (steps[k] < 0) return fail(LEE_E_ARG, "negative budget");
+        B->up_budget[2 * k] = steps[k];
+        B->up_budget[2 * k + 1] = steps[k] > 0 ? 1 : 0;
+        HIPCHK(hipMemcpyAsync(B->members[k]->dev.budget, &B->up_budget[2 * k], 16, hipMemcpyHostToDevice, B->stream));
+    }
+    HIPCHK(hipStreamSynchronize(B->stream));
+    return LEE_OK;
+}
+
+lee_status lee_batch_step_n(lee_batch *B, int64_t n)
+{
+    if (!B) return fail(LEE_E_ARG, "null batch");
+    if (n < 0) return fail(LEE_E_ARG, "n < 0");
+    if (n == 0) return LEE_OK;
+    if (B->stream == nullptr) {
+        for (int64_t k = 0; k < n; ++k)
+            for (int l = 0; l < 4; ++l) HIPCHK(batch_issue_stage(B, l));
+    } else {
+        if (!B->exec) {
+            HIPCHK(hipStreamBeginCapture(B->stream, hipStreamCaptureModeThreadLocal));
+            hipError_t e = hipSuccess;
+            for (int l = 0; l < 4 && e == hipSuccess; ++l) e = batch_issue_stage(B, l);
+            hipGraph_t g = nullptr;
+            hipError_t e2 = hipStreamEndCapture(B->stream, &g);
+            if (e != hipSuccess) {
+                if (g) hipGraphDestroy(g);
+                return hip_fail(e, "capturing the batch step");
+            }
+            if (e2 != hipSuccess) return hip_fail(e2, "hipStreamEndCapture");
+            B->graph = g;
+            HIPCHK(hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0));
+        }
+        for (int64_t k = 0; k < n; ++k) HIPCHK(hipGraphLaunch(B->exec, B->stream));
+    }
+    for (auto *I : B->members) I->steps_issued += n;   // upper bound; budgets may idle members
+    return LEE_OK;
+}
+
+lee_status lee_batch_time_kernels(lee_batch *B, int64_t n, double *sweep_us, double *ghost_us, double *step_us)
+{
+    if (!B) return fail(LEE_E_ARG, "null batch");
+    if (n <= 0) return fail(LEE_E_ARG, "n must be positive");
+    constexpr int CH = 16;
+    std::vector<hipEvent_t> ev(CH * 16 + 2);
+    for (auto &e : ev) HIPCHK(hipEventCreate(&e));
+    double tsw = 0, tgh = 0, tstep = 0;
+    int64_t done = 0;
+    lee_status st = LEE_OK;
+    int blocks = 0;
+    if (B->pblocks > 0) blocks = std::min(B->pblocks, (B->nwork1 + B->waves - 1) / B->waves);
+    while (done < n) {
+        const int m = (int)std::min<int64_t>(CH, n - done);
+        hipEventRecord(ev[CH * 16], B->stream);
+        for (int k = 0; k < m; ++k)
+            for (int l = 0; l < 4; ++l) {
+                hipEvent_t *e = &ev[(k * 4 + l) * 4];
+                hipEventRecord(e[0], B->stream);
+                launch_ghost(B->prec, B->d_table, B->d_work2, B->nwork2, l, B->stream);
+                hipEventRecord(e[1], B->stream);
+                hipEventRecord(e[2], B->stream);
+                launch_sweep(B->prec, B->vec, B->filt, B->waves, B->d_table, B->d_work1, B->nwork1, l, blocks,
+                             B->stream);
+                hipEventRecord(e[3], B->stream);
+                if (l == 3) launch_step_end(B->prec, B->d_table, (int)B->members.size(), B->stream);
+            }
+        hipEventRecord(ev[CH * 16 + 1], B->stream);
+        hipError_t e = hipEventSynchronize(ev[CH * 16 + 1]);
+        if (e != hipSuccess) {
+            st = hip_fail(e, "batch timing run");
+            break;
+        }
+        for (int k = 0; k < m * 4; ++k) {
+            float a = 0, b = 0;
+            hipEventElapsedTime(&a, ev[k * 4 + 0], ev[k * 4 + 1]);
+            hipEventElapsedTime(&b, ev[k * 4 + 2], ev[k * 4 + 3]);
+            tgh += a;
+            tsw += b;
+        }
+        float c = 0;
+        hipEventElapsedTime(&c, ev[CH * 16], ev[CH * 16 + 1]);
+        tstep += c;
+        done += m;
+    }
+    for (auto &e : ev) hipEventDestroy(e);
+    if (st != LEE_OK) return st;
+    for (auto *I : B->members) I->steps_issued += n;
+    if (sweep_us) *sweep_us = 1000.0 * tsw / (4.0 * n);
+    if (ghost_us) *ghost_us = 1000.0 * tgh / (4.0 * n);
+    if (step_us) *step_us = 1000.0 * tstep / n;
+    return LEE_OK;
+}
+
+void lee_batch_destroy(lee_batch *B)
+{
+    if (!B) return;
+    batch_free(B);
+    delete B;
+}
+
+}  // extern "C"

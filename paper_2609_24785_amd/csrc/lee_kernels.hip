@@ -1,0 +1,540 @@
+// HIP kernels for gfx950 (MI355X): one Runge-Kutta stage of the 2-D LEE with
+// a ghost-point immersed boundary and the two-state MSD ADE.
+//
+//   k_ghost  Sec. 3.2 steps 1-5: per ghost, gathers its cloud of the stage
+//            input with the four composed weights (p_BP read-out, free,
+//            Dirichlet, Neumann), advances the ADE derivative, and writes the
+//            ghost values and the stage value of the ADE states.
+//   k_sweep  Sec. 3.2 step 6: DRP first derivatives (eq. DRP_s) in x and y,
+//            11-point selective-filter damping, sponge, monopole source and
+//            the low-storage RK stage update at every fluid node.  A wave owns
+//            a strip of 64*VEC columns (8 halo columns each side, so 16 of
+//            them are read-only) and marches down (or up) a tile of rows,
+//            keeping the 11-row window of p, u, v in registers; the centre
+//            row goes through LDS for the x neighbours.  Alternate tiles march
+//            in opposite directions so that two vertically adjacent tiles read
+//            their shared halo rows at about the same time (L2 reuse).
+//   k_step_end  step counter, per-member budget, probe sampling and DFT.
+//
+// No matrix cores: the stage is a memory-bound stencil (about 3 flop per byte).
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "lee_device.h"
+
+namespace lee {
+
+template <typename T, int N>
+struct alignas(sizeof(T) * N) VecT {
+    T v[N];
+};
+
+// Orders this wave's LDS writes before its following LDS reads.  Each wave owns
+// its LDS rows, so no workgroup barrier is needed (and waves of one workgroup
+// may march tiles of different lengths).
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// stage -> buffer roles: input q^(l-1), output q^(l); q^n is buffer 0
+__device__ __forceinline__ int in_buf(int stage) { return stage == 0 ? 0 : (stage == 2 ? 2 : 1); }
+__device__ __forceinline__ int out_buf(int stage) { return stage == 0 ? 1 : (stage == 1 ? 2 : (stage == 2 ? 1 : 0)); }
+
+// ---------------------------------------------------------------------------
+// ghost fill + ADE
+
+template <typename T, int GL>
+__global__ __launch_bounds__(256) void k_ghost(const DevInst *__restrict__ insts,
+                                               const int2 *__restrict__ work, int nwork, int stage)
+{
+    const int gid = (int)((blockIdx.x * blockDim.x + threadIdx.x) / GL);
+    const int sub = (int)(threadIdx.x % GL);
+    if (gid >= nwork) return;                       // whole GL-lane groups leave together
+    const int2 wk = work[gid];
+    const DevInst &I = insts[wk.x];
+    if (!*I.active) return;
+    const int g = wk.y;
+    const int ib = in_buf(stage), ob = out_buf(stage);
+    T *P = (T *)I.f[ib][0];
+    T *U = (T *)I.f[ib][1];
+    T *V = (T *)I.f[ib][2];
+    const T *gd = (const T *)I.gd + 4 * (size_t)g;
+    const T nx = gd[0], ny = gd[1];
+    const T *w4 = (const T *)I.w4;
+    T a0 = 0, aF = 0, aD = 0, aN = 0;
+    const int e1 = I.cptr[g + 1];
+    for (int e = I.cptr[g] + sub; e < e1; e += GL) {
+        const int off = I.coff[e];
+        const VecT<T, 4> w = *(const VecT<T, 4> *)(w4 + 4 * (size_t)e);
+        const T p = P[off], u = U[off], v = V[off];
+        a0 += w.v[0] * p;
+        aN += w.v[3] * p;
+        aD += w.v[2] * (nx * u + ny * v);
+        aF += w.v[1] * (-ny * u + nx * v);
+    }
+#pragma unroll
+    for (int m = GL / 2; m >= 1; m >>= 1) {
+        a0 += __shfl_xor(a0, m, GL);
+        aF += __shfl_xor(aF, m, GL);
+        aD += __shfl_xor(aD, m, GL);
+        aN += __shfl_xor(aN, m, GL);
+    }
+    if (sub != 0) return;
+    // steps 2-3: ADE derivative, wall normal velocity and its time derivative
+    T d1 = 0, d2 = 0, Un = 0, Ud = 0;
+    const T *psi_in = (const T *)I.psi[ib];
+    const T s1 = psi_in[2 * g], s2 = psi_in[2 * g + 1];
+    if (I.ade_kind == 1) {
+        const T a = (T)I.ade[0], b = (T)I.ade[1], c1 = (T)I.ade[2], c2 = (T)I.ade[3];
+        d1 = -a * s1 - b * s2 + a0;
+        d2 = -a * s2 + b * s1;
+        Un = c1 * s1 + c2 * s2;
+        Ud = c1 * d1 + c2 * d2;
+    } else if (I.ade_kind == 2) {
+        const T l1 = (T)I.ade[0], l2 = (T)I.ade[1], c1 = (T)I.ade[2], c2 = (T)I.ade[3];
+        d1 = l1 * s1 + a0;
+        d2 = l2 * s2 + a0;
+        Un = c1 * s1 + c2 * s2;
+        Ud = c1 * d1 + c2 * d2;
+    }
+    // steps 4-5: Neumann for p (dp/dn = +du_n/dt in the wall-to-fluid frame),
+    // Dirichlet for u.n (= -u_n), free for u.t
+    const T pg = aN + gd[3] * ((T)I.h * Ud);
+    const T un = aD + gd[2] * (-Un);
+    const T ut = aF;
+    const int go = I.goff[g];
+    P[go] = pg;
+    U[go] = nx * un - ny * ut;
+    V[go] = ny * un + nx * ut;
+    if (I.ade_kind != 0) {
+        const T *psi_n = (const T *)I.psi[0];
+        T *psi_out = (T *)I.psi[ob];
+        const T adt = (T)I.alpha_dt[stage];
+        psi_out[2 * g] = psi_n[2 * g] + adt * d1;
+        psi_out[2 * g + 1] = psi_n[2 * g + 1] + adt * d2;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// stage sweep
+
+template <typename T, int VEC>
+__device__ __forceinline__ void load_row(T (&dst)[3][VEC], const T *p, const T *u, const T *v, long off)
+{
+    const VecT<T, VEC> a = *(const VecT<T, VEC> *)(p + off);
+    const VecT<T, VEC> b = *(const VecT<T, VEC> *)(u + off);
+    const VecT<T, VEC> c = *(const VecT<T, VEC> *)(v + off);
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+        dst[0][e] = a.v[e];
+        dst[1][e] = b.v[e];
+        dst[2][e] = c.v[e];
+    }
+}
+
+template <typename T, int VEC, bool FILT, int WPB>
+__global__ __launch_bounds__(64 * WPB) void k_sweep(const DevInst *__restrict__ insts,
+                                                    const int4 *__restrict__ work, int nwork, int stage)
+{
+    constexpr int NL = 64 * VEC;                 // loaded columns per strip
+    constexpr int KM = (5 + VEC - 1) / VEC;      // LDS chunks left of the lane's own
+    constexpr int KP = (VEC + 4) / VEC;          // chunks right of it
+    constexpr int XW = (KM + 1 + KP) * VEC;      // x window held per lane
+    __shared__ T lds_all[WPB][3][NL];
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    T(*lds)[NL] = lds_all[wv];
+
+    for (int w = blockIdx.x * WPB + wv; w < nwork; w += gridDim.x * WPB) {
+        const int4 wk = work[w];
+        if (wk.x < 0) continue;                   // idle slot of the XCD-aware order
+        const DevInst &I = insts[wk.x];
+        if (!*I.active) continue;                 // uniform per wave
+        const int c0 = wk.y;                      // first output column
+        const int r0 = wk.z;
+        const int dir = wk.w < 0 ? -1 : 1;
+        const int r1 = wk.w < 0 ? -wk.w : wk.w;
+        const int nrows = r1 - r0;
+        const int jbeg = dir > 0 ? r0 : r1 - 1;
+        const int ib = in_buf(stage), ob = out_buf(stage);
+        const long pitch = I.pitch;
+        const T *Pi = (const T *)I.f[ib][0];
+        const T *Ui = (const T *)I.f[ib][1];
+        const T *Vi = (const T *)I.f[ib][2];
+        const T *Pn = (const T *)I.f[0][0];
+        const T *Un = (const T *)I.f[0][1];
+        const T *Vn = (const T *)I.f[0][2];
+        T *Po = (T *)I.f[ob][0];
+        T *Uo = (T *)I.f[ob][1];
+        T *Vo = (T *)I.f[ob][2];
+        const int col0 = c0 - 8 + lane * VEC;     // first column of this lane
+        const bool out_lane = (col0 + VEC > c0) && (col0 < c0 + NL - 16);
+        // coefficients
+        T ax[5];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) ax[k] = (T)I.ax[k];
+        T fd[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) fd[k] = (T)I.fd[k];
+        const T adt = (T)I.alpha_dt[stage];
+        const T ydir = (T)dir;
+        const bool has_src = I.has_src && !(I.src_i1 < c0 || I.src_i0 >= c0 + NL - 16) &&
+                             !(I.src_j1 < r0 || I.src_j0 >= r1);
+        T amp = 0;
+        if (has_src) {
+            const double t = ((double)*I.step + I.c_stage[stage]) * I.dt;
+            amp = (T)(I.src_a * sin(I.src_om * t));
+        }
+        const int sw = I.sponge_w;
+
+        T q[11][3][VEC];
+        // prologue: rows jbeg - 5 dir .. jbeg + 4 dir
+#pragma unroll
+        for (int s = 0; s < 10; ++s) load_row<T, VEC>(q[s], Pi, Ui, Vi, (long)(jbeg + (s - 5) * dir) * pitch + col0);
+
+        for (int it = 0; it < nrows; ++it) {
+            const int j = jbeg + it * dir;
+            load_row<T, VEC>(q[10], Pi, Ui, Vi, (long)(j + 5 * dir) * pitch + col0);
+            T qn[3][VEC];
+            if (stage != 0) load_row<T, VEC>(qn, Pn, Un, Vn, (long)j * pitch + col0);
+            const int4 iv = I.iv[j];
+            wave_lds_sync();
+            {
+                VecT<T, VEC> a, b, c;
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) {
+                    a.v[e] = q[5][0][e];
+                    b.v[e] = q[5][1][e];
+                    c.v[e] = q[5][2][e];
+                }
+                *(VecT<T, VEC> *)&lds[0][lane * VEC] = a;
+                *(VecT<T, VEC> *)&lds[1][lane * VEC] = b;
+                if (FILT) *(VecT<T, VEC> *)&lds[2][lane * VEC] = c;
+            }
+            wave_lds_sync();
+            if (out_lane) {
+                // y parts and the centre term from the register window
+                T rp[VEC], ru[VEC], rv[VEC];
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) {
+                    T dpdy = 0, dvdy = 0;
+#pragma unroll
+                    for (int k = 1; k <= 5; ++k) {
+                        dpdy += ax[k - 1] * (q[5 + k][0][e] - q[5 - k][0][e]);
+                        dvdy += ax[k - 1] * (q[5 + k][2][e] - q[5 - k][2][e]);
+                    }
+                    rp[e] = -ydir * dvdy;
+                    ru[e] = 0;
+                    rv[e] = -ydir * dpdy;
+                    if (FILT) {
+                        T fp = fd[0] * q[5][0][e], fu = fd[0] * q[5][1][e], fv = fd[0] * q[5][2][e];
+#pragma unroll
+                        for (int k = 1; k <= 5; ++k) {
+                            fp += fd[k] * (q[5 + k][0][e] + q[5 - k][0][e]);
+                            fu += fd[k] * (q[5 + k][1][e] + q[5 - k][1][e]);
+                            fv += fd[k] * (q[5 + k][2][e] + q[5 - k][2][e]);
+                        }
+                        rp[e] -= fp;
+                        ru[e] -= fu;
+                        rv[e] -= fv;
+                    }
+                }
+                // x parts, one field window at a time from LDS
+#pragma unroll
+                for (int f = 0; f < (FILT ? 3 : 2); ++f) {
+                    T xw[XW];
+#pragma unroll
+                    for (int k = -KM; k <= KP; ++k) {
+                        const VecT<T, VEC> a = *(const VecT<T, VEC> *)&lds[f][lane * VEC + k * VEC];
+#pragma unroll
+                        for (int e = 0; e < VEC; ++e) xw[(k + KM) * VEC + e] = a.v[e];
+                    }
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) {
+                        const int x = KM * VEC + e;
+                        if (f < 2) {
+                            T dx = 0;
+#pragma unroll
+                            for (int k = 1; k <= 5; ++k) dx += ax[k - 1] * (xw[x + k] - xw[x - k]);
+                            if (f == 0) ru[e] -= dx;     // -dp/dx
+                            else rp[e] -= dx;            // -du/dx
+                        }
+                        if (FILT) {
+                            T fx = 0;
+#pragma unroll
+                            for (int k = 1; k <= 5; ++k) fx += fd[k] * (xw[x + k] + xw[x - k]);
+                            if (f == 0) rp[e] -= fx;
+                            else if (f == 1) ru[e] -= fx;
+                            else rv[e] -= fx;
+                        }
+                    }
+                }
+                T ro[3][VEC];
+                bool ok[VEC];
+                bool all = true;
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) {
+                    const int col = col0 + e;
+                    if (sw > 0) {
+                        int eg = min(min(col, j), min(I.nx - 1 - col, I.ny - 1 - j));
+                        if (eg < sw) {
+                            const T f = (T)(sw - eg) / (T)sw;
+                            const T sg = (T)I.sponge_s * f * f;
+                            rp[e] -= sg * q[5][0][e];
+                            ru[e] -= sg * q[5][1][e];
+                            rv[e] -= sg * q[5][2][e];
+                        }
+                    }
+                    if (has_src) {      // offsets from the source's nearest node: no cancellation
+                        const T xx = (T)(col - I.src_ic) * (T)I.h - (T)I.src_fx;
+                        const T yy = (T)(j - I.src_jc) * (T)I.h - (T)I.src_fy;
+                        rp[e] += amp * exp(-(T)I.src_b * (xx * xx + yy * yy));
+                    }
+                    const T p0 = stage != 0 ? qn[0][e] : q[5][0][e];
+                    const T u0 = stage != 0 ? qn[1][e] : q[5][1][e];
+                    const T v0 = stage != 0 ? qn[2][e] : q[5][2][e];
+                    ro[0][e] = p0 + adt * rp[e];
+                    ro[1][e] = u0 + adt * ru[e];
+                    ro[2][e] = v0 + adt * rv[e];
+                    ok[e] = (col >= iv.x && col < iv.y) || (col >= iv.z && col < iv.w);
+                    all = all && ok[e];
+                }
+                const long off = (long)j * pitch + col0;
+                if (all) {
+                    VecT<T, VEC> a, b, c;
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) {
+                        a.v[e] = ro[0][e];
+                        b.v[e] = ro[1][e];
+                        c.v[e] = ro[2][e];
+                    }
+                    *(VecT<T, VEC> *)(Po + off) = a;
+                    *(VecT<T, VEC> *)(Uo + off) = b;
+                    *(VecT<T, VEC> *)(Vo + off) = c;
+                } else {
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e)
+                        if (ok[e]) {
+                            Po[off + e] = ro[0][e];
+                            Uo[off + e] = ro[1][e];
+                            Vo[off + e] = ro[2][e];
+                        }
+                }
+            }
+#pragma unroll
+            for (int s = 0; s < 10; ++s)
+#pragma unroll
+                for (int f = 0; f < 3; ++f)
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) q[s][f][e] = q[s + 1][f][e];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// end of step: counters, probes, DFT
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_step_end(const DevInst *__restrict__ insts)
+{
+    const DevInst &I = insts[blockIdx.x];
+    if (!*I.active) return;
+    const long long step = *I.step;                 // index of the step just completed
+    const T *P = (const T *)I.f[0][0];
+    const T *U = (const T *)I.f[0][1];
+    const T *V = (const T *)I.f[0][2];
+    const long pitch = I.pitch;
+    const bool in_dft = I.dft_count > 0 && step >= I.dft_start && step < I.dft_start + I.dft_count;
+    double cs = 0, sn = 0;
+    if (in_dft) {
+        const double t = (double)(step + 1) * I.dt;
+        cs = cos(I.dft_omega * t);
+        sn = sin(I.dft_omega * t);
+    }
+    for (int k = threadIdx.x; k < I.np; k += blockDim.x) {
+        const int i0 = I.pij[2 * k], j0 = I.pij[2 * k + 1];
+        const double *w = I.pw + 16 * (size_t)k;
+        double ap = 0, au = 0, av = 0;
+        for (int b = 0; b < 4; ++b)
+            for (int a = 0; a < 4; ++a) {
+                const long off = (long)(j0 + b) * pitch + (i0 + a);
+                const double ww = w[b * 4 + a];
+                ap += ww * (double)P[off];
+                au += ww * (double)U[off];
+                av += ww * (double)V[off];
+            }
+        if (I.trace_cap > 0) {
+            double *tr = I.trace + ((size_t)(step % I.trace_cap) * I.np + k) * 3;
+            tr[0] = ap;
+            tr[1] = au;
+            tr[2] = av;
+        }
+        if (in_dft) {                               // sum p exp(-i omega t)
+            I.dft[2 * k] += ap * cs;
+            I.dft[2 * k + 1] -= ap * sn;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        *I.step = step + 1;
+        const long long b = *I.budget - 1;
+        *I.budget = b;
+        *I.active = b > 0 ? 1 : 0;
+    }
+}
+
+template <typename T>
+__global__ void k_fill(T *p, size_t n, T v)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// initial condition at fluid nodes of q^n (Sec. 2.1, 4.1, 4.2)
+template <typename T>
+__global__ void k_init_ic(const DevInst *__restrict__ insts, int ic_kind, double c0, double c1, double c2,
+                          double c3, double c4, double c5, double c6)
+{
+    const DevInst &I = insts[0];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i >= I.nx || j >= I.ny) return;
+    const int4 iv = I.iv[j];
+    if (!((i >= iv.x && i < iv.y) || (i >= iv.z && i < iv.w))) return;
+    const double x = I.x0 + (double)i * I.h, y = I.y0 + (double)j * I.h;
+    double p = 0, u = 0, v = 0;
+    if (ic_kind == 1) {
+        const double b = 0.6931471805599453 / (c3 * c3);
+        p = c2 * exp(-b * ((x - c0) * (x - c0) + (y - c1) * (y - c1)));
+    } else if (ic_kind == 2) {
+        const double s = (x - c0) * c2 + (y - c1) * c3;
+        p = 0.5 * c4 * exp(-(c5 * c5) * s * s) * cos(6.283185307179586 * c6 * s);
+        u = p * c2;
+        v = p * c3;
+    }
+    const long off = (long)j * I.pitch + i;
+    ((T *)I.f[0][0])[off] = (T)p;
+    ((T *)I.f[0][1])[off] = (T)u;
+    ((T *)I.f[0][2])[off] = (T)v;
+}
+
+template <typename T>
+__global__ void k_sample(const DevInst *__restrict__ insts, const int *__restrict__ ij, const double *__restrict__ w,
+                         int np, double *out)
+{
+    const DevInst &I = insts[0];
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= np) return;
+    double acc[3] = {0, 0, 0};
+    for (int b = 0; b < 4; ++b)
+        for (int a = 0; a < 4; ++a) {
+            const long off = (long)(ij[2 * k + 1] + b) * I.pitch + (ij[2 * k] + a);
+            for (int f = 0; f < 3; ++f) acc[f] += w[16 * k + b * 4 + a] * (double)((const T *)I.f[0][f])[off];
+        }
+    for (int f = 0; f < 3; ++f) out[3 * k + f] = acc[f];
+}
+
+// ---------------------------------------------------------------------------
+// launch wrappers
+
+template <typename T, int VEC, bool FILT, int WPB>
+static hipError_t launch_sweep_t(const DevInst *insts, const int4 *work, int nwork, int stage, int blocks,
+                                 hipStream_t s)
+{
+    const int nb = blocks > 0 ? blocks : (nwork + WPB - 1) / WPB;
+    hipLaunchKernelGGL((k_sweep<T, VEC, FILT, WPB>), dim3(nb), dim3(64 * WPB), 0, s, insts, work, nwork, stage);
+    return hipGetLastError();
+}
+
+template <typename T, int VEC, bool FILT>
+static hipError_t launch_sweep_w(const DevInst *insts, const int4 *work, int nwork, int stage, int waves,
+                                 int blocks, hipStream_t s)
+{
+    if (waves == 4) return launch_sweep_t<T, VEC, FILT, 4>(insts, work, nwork, stage, blocks, s);
+    if (waves == 2) return launch_sweep_t<T, VEC, FILT, 2>(insts, work, nwork, stage, blocks, s);
+    return launch_sweep_t<T, VEC, FILT, 1>(insts, work, nwork, stage, blocks, s);
+}
+
+hipError_t launch_sweep(int prec, int vec, bool filt, int waves, const DevInst *insts, const int4 *work,
+                        int nwork, int stage, int blocks, hipStream_t s)
+{
+    if (nwork <= 0) return hipSuccess;
+    if (prec == LEE_F32) {
+        if (vec == 4) return filt ? launch_sweep_w<float, 4, true>(insts, work, nwork, stage, waves, blocks, s)
+                                  : launch_sweep_w<float, 4, false>(insts, work, nwork, stage, waves, blocks, s);
+        return filt ? launch_sweep_w<float, 2, true>(insts, work, nwork, stage, waves, blocks, s)
+                    : launch_sweep_w<float, 2, false>(insts, work, nwork, stage, waves, blocks, s);
+    }
+    return filt ? launch_sweep_w<double, 2, true>(insts, work, nwork, stage, waves, blocks, s)
+                : launch_sweep_w<double, 2, false>(insts, work, nwork, stage, waves, blocks, s);
+}
+
+hipError_t launch_ghost(int prec, const DevInst *insts, const int2 *work, int nwork, int stage, hipStream_t s)
+{
+    if (nwork <= 0) return hipSuccess;
+    constexpr int GL = 16;
+    const int nb = (nwork * GL + 255) / 256;
+    if (prec == LEE_F32)
+        hipLaunchKernelGGL((k_ghost<float, GL>), dim3(nb), dim3(256), 0, s, insts, work, nwork, stage);
+    else
+        hipLaunchKernelGGL((k_ghost<double, GL>), dim3(nb), dim3(256), 0, s, insts, work, nwork, stage);
+    return hipGetLastError();
+}
+
+hipError_t launch_step_end(int prec, const DevInst *insts, int ninst, hipStream_t s)
+{
+    if (prec == LEE_F32)
+        hipLaunchKernelGGL((k_step_end<float>), dim3(ninst), dim3(256), 0, s, insts);
+    else
+        hipLaunchKernelGGL((k_step_end<double>), dim3(ninst), dim3(256), 0, s, insts);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(int prec, void *p, size_t n, hipStream_t s)
+{
+    const int nb = (int)((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096);
+    if (n == 0) return hipSuccess;
+    if (prec == LEE_F32)
+        hipLaunchKernelGGL((k_fill<float>), dim3(nb), dim3(256), 0, s, (float *)p, n, 0.0f);
+    else
+        hipLaunchKernelGGL((k_fill<double>), dim3(nb), dim3(256), 0, s, (double *)p, n, 0.0);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_bytes(void *p, size_t bytes, hipStream_t s)
+{
+    const size_t n = bytes / 4;
+    if (n == 0) return hipSuccess;
+    const int nb = (int)((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096);
+    hipLaunchKernelGGL((k_fill<uint32_t>), dim3(nb), dim3(256), 0, s, (uint32_t *)p, n, 0u);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_ic(int prec, const DevInst *insts, int nx, int ny, int kind, const double *c, hipStream_t s)
+{
+    dim3 grid((nx + 255) / 256, ny);
+    if (prec == LEE_F32)
+        hipLaunchKernelGGL((k_init_ic<float>), grid, dim3(256), 0, s, insts, kind, c[0], c[1], c[2], c[3], c[4],
+                           c[5], c[6]);
+    else
+        hipLaunchKernelGGL((k_init_ic<double>), grid, dim3(256), 0, s, insts, kind, c[0], c[1], c[2], c[3], c[4],
+                           c[5], c[6]);
+    return hipGetLastError();
+}
+
+hipError_t launch_sample(int prec, const DevInst *insts, const int *ij, const double *w, int np, double *out,
+                         hipStream_t s)
+{
+    if (np <= 0) return hipSuccess;
+    if (prec == LEE_F32)
+        hipLaunchKernelGGL((k_sample<float>), dim3((np + 63) / 64), dim3(64), 0, s, insts, ij, w, np, out);
+    else
+        hipLaunchKernelGGL((k_sample<double>), dim3((np + 63) / 64), dim3(64), 0, s, insts, ij, w, np, out);
+    return hipGetLastError();
+}
+
+}  // namespace lee

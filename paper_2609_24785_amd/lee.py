@@ -1,0 +1,249 @@
+"""Python binding of liblee: argument marshalling only.
+
+Every step of the method runs in the library's kernels; PyTorch provides the
+device memory (a uint8 tensor handed to lee_bind) and the stream.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+from typing import Optional, Sequence
+
+import numpy as np
+
+from . import _lib
+from ._lib import (BatchOpts, CaseDesc, GhostSummary, ImpedanceDesc, LeeError, c_double, c_int64, c_size_t,
+                   c_void_p, check, load)
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(c_void_p)
+
+
+def case_desc(case, precision: str = "f32") -> CaseDesc:
+    """Marshal a lee_cases.Case into the C description."""
+    d = CaseDesc()
+    d.nx, d.ny, d.x0, d.y0, d.h = case.nx, case.ny, case.x0, case.y0, case.h
+    d.stencil_half = case.H
+    d.cfl = case.cfl
+    d.filter_sigma = case.filter_sigma
+    d.sponge_cells = case.sponge_cells
+    d.sponge_sigma = case.sponge_sigma
+    d.precision = _lib.F32 if precision == "f32" else _lib.F64
+    w = case.wall
+    d.wall_kind = _lib.WALL[w.kind]
+    d.wall_cx, d.wall_cy, d.wall_nx, d.wall_ny, d.wall_rc = w.cx, w.cy, w.nx, w.ny, w.rc
+    ic = case.ic
+    if ic is None:
+        d.ic_kind = 0
+    elif type(ic).__name__ == "Pulse":
+        d.ic_kind = 1
+        for k, v in enumerate((ic.xs, ic.ys, ic.a, ic.w)):
+            d.ic[k] = v
+    else:
+        d.ic_kind = 2
+        for k, v in enumerate((ic.xs, ic.ys, ic.dx, ic.dy, ic.a, ic.alpha, ic.k)):
+            d.ic[k] = v
+    if case.source is not None:
+        s = case.source
+        d.src_kind = 1
+        for k, v in enumerate((s.xs, s.ys, s.a, s.w, s.omega)):
+            d.src[k] = v
+    return d
+
+
+def impedance_desc(imp) -> ImpedanceDesc:
+    z = ImpedanceDesc()
+    if imp.kind == "rigid":
+        z.kind = _lib.Z_RIGID
+    else:
+        z.kind = _lib.Z_MSD
+        z.R, z.M, z.K = imp.R, imp.M, imp.K
+    return z
+
+
+class Instance:
+    """One solve: set-up on the host, fields and lists in caller-owned HBM."""
+
+    def __init__(self, case, precision: str = "f32", device: str = "cuda:0", stream=None,
+                 trace_capacity: Optional[int] = None, dft: Optional[tuple] = None, bind: bool = True):
+        self.lib = load()
+        self.case = case
+        self.precision = precision
+        self._h = c_void_p()
+        check(self.lib.lee_setup_grid(ctypes.byref(case_desc(case, precision)), ctypes.byref(self._h)),
+              "lee_setup_grid")
+        self.summary = GhostSummary()
+        z = impedance_desc(case.impedance)
+        st = self.lib.lee_build_ghosts(self._h, ctypes.byref(z), 4, ctypes.byref(self.summary))
+        if st != 0:
+            self.close()
+            check(st, "lee_build_ghosts")
+        if case.probes:
+            xy = np.ascontiguousarray(np.array(case.probes, dtype=np.float64).ravel())
+            cap = trace_capacity if trace_capacity is not None else max(case.steps, 1)
+            om, start, count = dft if dft is not None else (0.0, 0, 0)
+            st = self.lib.lee_set_probes(self._h, len(case.probes), _ptr(xy), cap, om, start, count)
+            if st != 0:
+                self.close()
+                check(st, "lee_set_probes")
+        self.buf = None
+        self.stream = None
+        if bind:
+            self.bind(device, stream)
+
+    # ---- device memory ------------------------------------------------------
+    def required_bytes(self) -> int:
+        n = c_size_t()
+        check(self.lib.lee_required_bytes(self._h, ctypes.byref(n)), "lee_required_bytes")
+        return n.value
+
+    def bind(self, device: str = "cuda:0", stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU: the library runs only on the device")
+        dev = torch.device(device)
+        torch.cuda.set_device(dev)
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=dev)
+        nbytes = self.required_bytes()
+        self.buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+        base = self.buf.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        check(self.lib.lee_bind(self._h, c_void_p(aligned), nbytes, c_void_p(self.stream.cuda_stream)),
+              "lee_bind")
+
+    # ---- stepping -----------------------------------------------------------
+    def init_fields(self):
+        check(self.lib.lee_init_fields(self._h), "lee_init_fields")
+
+    def rk_stage(self, stage: int):
+        check(self.lib.lee_rk_stage(self._h, stage), "lee_rk_stage")
+
+    def step_n(self, n: int):
+        check(self.lib.lee_step_n(self._h, n), "lee_step_n")
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+    # ---- outputs ------------------------------------------------------------
+    def fields(self):
+        c = self.case
+        p = np.zeros((c.ny, c.nx))
+        u = np.zeros_like(p)
+        v = np.zeros_like(p)
+        check(self.lib.lee_get_fields(self._h, _ptr(p), _ptr(u), _ptr(v)), "lee_get_fields")
+        return p, u, v
+
+    def set_fields(self, p=None, u=None, v=None):
+        arrs = [None if a is None else np.ascontiguousarray(a, dtype=np.float64) for a in (p, u, v)]
+        check(self.lib.lee_set_fields(self._h, *(_ptr(a) for a in arrs)), "lee_set_fields")
+
+    def ade_states(self):
+        out = np.zeros(2 * self.summary.G)
+        check(self.lib.lee_get_ade_states(self._h, _ptr(out)), "lee_get_ade_states")
+        return out.reshape(-1, 2)
+
+    def probe(self, xy: Sequence[Sequence[float]]):
+        xy = np.ascontiguousarray(np.asarray(xy, dtype=np.float64).reshape(-1, 2))
+        out = np.zeros((len(xy), 3))
+        check(self.lib.lee_probe(self._h, len(xy), _ptr(xy), _ptr(out)), "lee_probe")
+        return out
+
+    def traces(self, cap: Optional[int] = None):
+        npb = len(self.case.probes)
+        if npb == 0:
+            return np.zeros((0, 0, 3))
+        cap = cap if cap is not None else 1 << 30
+        done = c_int64()
+        check(self.lib.lee_probe_traces(self._h, None, 0, ctypes.byref(done)), "lee_probe_traces")
+        step = self.step
+        m = min(step, cap)
+        out = np.zeros((max(m, 1), npb, 3))
+        check(self.lib.lee_probe_traces(self._h, _ptr(out), m, ctypes.byref(done)), "lee_probe_traces")
+        return out[:done.value]
+
+    def dft(self):
+        out = np.zeros(2 * len(self.case.probes))
+        check(self.lib.lee_probe_dft(self._h, _ptr(out)), "lee_probe_dft")
+        return out[0::2] + 1j * out[1::2]
+
+    @property
+    def step(self) -> int:
+        s = c_int64()
+        check(self.lib.lee_get_step(self._h, ctypes.byref(s)), "lee_get_step")
+        return s.value
+
+    def export_lists(self):
+        G, nnz = self.summary.G, self.summary.nnz
+        gi = np.zeros(G, dtype=np.int32)
+        cp = np.zeros(G + 1, dtype=np.int32)
+        ci = np.zeros(nnz, dtype=np.int32)
+        dg = np.zeros(G, dtype=np.int8)
+        w = np.zeros(4 * nnz)
+        b = np.zeros(2 * G)
+        geo = np.zeros(5 * G)
+        check(self.lib.lee_export_lists(self._h, *(_ptr(a) for a in (gi, cp, ci, dg, w, b, geo))),
+              "lee_export_lists")
+        return dict(ghost_idx=gi, cloud_ptr=cp, cloud_idx=ci, degree=dg, weights=w.reshape(-1, 4),
+                    beta=b.reshape(-1, 2), geom=geo.reshape(-1, 5))
+
+    def set_tiling(self, vec: int, rows: int, waves: int = 1):
+        check(self.lib.lee_set_tiling(self._h, vec, rows, waves), "lee_set_tiling")
+
+    def time_kernels(self, n: int):
+        a, b, c = c_double(), c_double(), c_double()
+        check(self.lib.lee_time_kernels(self._h, n, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
+              "lee_time_kernels")
+        return a.value, b.value, c.value
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self.lib.lee_destroy(self._h)
+            self._h = c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Bound instances advanced together: one launch per phase over all members."""
+
+    def __init__(self, members: Sequence[Instance], vec: int = 0, rows: int = 0, waves: int = 0,
+                 persistent_blocks: int = 0):
+        self.lib = load()
+        self.members = list(members)
+        arr = (c_void_p * len(members))(*[m._h.value for m in members])
+        opts = BatchOpts(vec, rows, waves, persistent_blocks)
+        self._h = c_void_p()
+        check(self.lib.lee_batch_create(arr, len(members), ctypes.byref(opts), ctypes.byref(self._h)),
+              "lee_batch_create")
+
+    def set_budget(self, steps: Sequence[int]):
+        a = np.ascontiguousarray(np.asarray(steps, dtype=np.int64))
+        check(self.lib.lee_batch_set_budget(self._h, _ptr(a)), "lee_batch_set_budget")
+
+    def step_n(self, n: int):
+        check(self.lib.lee_batch_step_n(self._h, n), "lee_batch_step_n")
+
+    def time_kernels(self, n: int):
+        a, b, c = c_double(), c_double(), c_double()
+        check(self.lib.lee_batch_time_kernels(self._h, n, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
+              "lee_batch_time_kernels")
+        return a.value, b.value, c.value
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self.lib.lee_batch_destroy(self._h)
+            self._h = c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+__all__ = ["Instance", "Batch", "LeeError", "case_desc", "impedance_desc"]
