@@ -214,12 +214,26 @@ lee_status lee_export_lists(const lee_instance *inst, int32_t *ghost_idx, int32_
                             double *geom);
 
 /*
- * Sweep tiling: vec = columns per lane (FP32: 2 or 4; FP64: 2), rows = rows
- * per marching tile (>= 1), waves = waves per workgroup (1, 2 or 4).
- * Invalidates the captured graph.  Defaults come from the built-in tuned
- * table.
+ * Stage-sweep kernel and tile shape.  LEE_SWEEP_TILE: a 256-thread workgroup
+ * loads a cols x rows tile plus its halo into LDS and computes it; shapes:
+ * FP32 cols 128 or 256 with rows 8, 16 or 32; FP64 cols 128 with rows 4, 8
+ * or 16, cols 256 with rows 4 or 8.  LEE_SWEEP_MARCH: each wave marches a
+ * strip of 64 vec - 16 columns down `rows` rows (>= 4) keeping an 11-row
+ * register window; vec 2 or 4 (FP32), 2 (FP64); waves per workgroup 1, 2
+ * or 4.  Other shapes -> LEE_E_ARG.  Invalidates the captured graph.
  */
-lee_status lee_set_tiling(lee_instance *inst, int32_t vec, int32_t rows, int32_t waves);
+#define LEE_SWEEP_TILE 0
+#define LEE_SWEEP_MARCH 1
+typedef struct {
+    int32_t kind;            /* LEE_SWEEP_TILE or LEE_SWEEP_MARCH */
+    int32_t vec;             /* march: columns per lane */
+    int32_t cols;            /* tile: columns per tile */
+    int32_t rows;            /* rows per tile / per march */
+    int32_t waves;           /* march: waves per workgroup */
+} lee_tiling;
+
+lee_status lee_set_tiling(lee_instance *inst, const lee_tiling *t);
+lee_status lee_get_tiling(const lee_instance *inst, lee_tiling *t);
 
 /*
  * Measurement: run n steps eagerly with HIP events around every sweep
@@ -229,6 +243,11 @@ lee_status lee_set_tiling(lee_instance *inst, int32_t vec, int32_t rows, int32_t
 lee_status lee_time_kernels(lee_instance *inst, int64_t n, double *sweep_us, double *ghost_us,
                             double *step_us);
 
+/* Measurement utility: asynchronous device copy of `bytes` (multiple of 16,
+ * 16-byte aligned buffers) on hip_stream.  Its traffic is exactly 2 x bytes,
+ * which calibrates hardware byte counters and the achievable HBM rate. */
+lee_status lee_stream_copy(void *dst, const void *src, size_t bytes, void *hip_stream);
+
 /* Free host structures and device-side objects the library created (graph,
  * events); the bound device memory stays the caller's. */
 void lee_destroy(lee_instance *inst);
@@ -236,7 +255,7 @@ void lee_destroy(lee_instance *inst);
 /* ---------------- batches: many instances in one launch per phase -------- */
 
 typedef struct {
-    int32_t vec, rows, waves;   /* sweep tiling for the whole batch (0 = tuned default) */
+    lee_tiling tiling;          /* sweep tiling for the whole batch (kind < 0: built-in default) */
     int32_t persistent_blocks;  /* 0 = one workgroup per work item */
 } lee_batch_opts;
 

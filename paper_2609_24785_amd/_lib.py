@@ -5,7 +5,8 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liblee.so")
+# LEE_LIB_PATH selects another build of the same library (e.g. for A/B timing)
+LIB_PATH = os.environ.get("LEE_LIB_PATH") or os.path.join(HERE, "liblee.so")
 
 LEE_OK = 0
 STATUS = {0: "LEE_OK", -1: "LEE_E_ARG", -2: "LEE_E_GEOMETRY", -3: "LEE_E_CRITICAL_DAMPING",
@@ -38,8 +39,18 @@ class GhostSummary(ctypes.Structure):
                 ("fluid_nodes", c_int64), ("ade_kind", c_int32), ("poles", c_double * 4)]
 
 
+SWEEP_TILE, SWEEP_MARCH = 0, 1
+
+
+class Tiling(ctypes.Structure):
+    _fields_ = [("kind", c_int32), ("vec", c_int32), ("cols", c_int32), ("rows", c_int32), ("waves", c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 class BatchOpts(ctypes.Structure):
-    _fields_ = [("vec", c_int32), ("rows", c_int32), ("waves", c_int32), ("persistent_blocks", c_int32)]
+    _fields_ = [("tiling", Tiling), ("persistent_blocks", c_int32)]
 
 
 # name -> (restype, argtypes)
@@ -61,9 +72,11 @@ SIGNATURES = {
     "lee_get_ade_states": (c_int32, [c_void_p, c_void_p]),
     "lee_get_step": (c_int32, [c_void_p, ctypes.POINTER(c_int64)]),
     "lee_export_lists": (c_int32, [c_void_p] + [c_void_p] * 7),
-    "lee_set_tiling": (c_int32, [c_void_p, c_int32, c_int32, c_int32]),
+    "lee_set_tiling": (c_int32, [c_void_p, ctypes.POINTER(Tiling)]),
+    "lee_get_tiling": (c_int32, [c_void_p, ctypes.POINTER(Tiling)]),
     "lee_time_kernels": (c_int32, [c_void_p, c_int64, ctypes.POINTER(c_double), ctypes.POINTER(c_double),
                                    ctypes.POINTER(c_double)]),
+    "lee_stream_copy": (c_int32, [c_void_p, c_void_p, c_size_t, c_void_p]),
     "lee_destroy": (None, [c_void_p]),
     "lee_batch_create": (c_int32, [ctypes.POINTER(c_void_p), c_int32, ctypes.POINTER(BatchOpts),
                                    ctypes.POINTER(c_void_p)]),
@@ -84,9 +97,15 @@ class LeeError(RuntimeError):
 
 
 def load() -> ctypes.CDLL:
-    """Load liblee.so; raises if it has not been built (no fallback path)."""
+    """Load liblee.so; raises if it has not been built (no fallback path).
+
+    torch is imported first: it ships its own HIP runtime under the same
+    soname as the system one the library links, and whichever loads first is
+    the one the process uses.  Loading torch's first keeps a single runtime
+    for the tensors that hold the library's memory and for its launches."""
     global _lib
     if _lib is None:
+        import torch  # noqa: F401  (selects the process's HIP runtime)
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with paper_2609_24785_amd/build.py")
         lib = ctypes.CDLL(LIB_PATH)

@@ -16,7 +16,7 @@ using namespace lee;
 
 struct lee_instance {
     Host host;
-    int vec = 0, rows = 0, waves = 1;
+    lee_tiling tl{};
     // device
     bool bound = false;
     int device = -1;
@@ -28,7 +28,7 @@ struct lee_instance {
     int4 *d_work1 = nullptr;
     size_t work1_cap = 0;
     int nwork1 = 0;
-    int2 *d_work2 = nullptr;
+    int4 *d_work2 = nullptr;
     int nwork2 = 0;
     int *d_sij = nullptr;
     double *d_sw = nullptr, *d_sout = nullptr;
@@ -36,8 +36,9 @@ struct lee_instance {
     std::vector<char> up_w4, up_gd;
     std::vector<int> up_goff, up_coff;
     std::vector<int4> up_work1, up_iv;
-    std::vector<int2> up_work2;
+    std::vector<int4> up_work2;
     long long up_counters[3] = {0, LLONG_MAX, 1};
+    double up_amp[4] = {0, 0, 0, 0};
     // sequencing
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -70,7 +71,7 @@ size_t work1_capacity(const Host &h)
 }
 
 struct Layout {
-    size_t inst, planes[9], psi[3], iv, goff, cptr, coff, w4, gd, counters, pij, pw, trace, dft, work1, work2,
+    size_t inst, planes[9], psi[3], iv, goff, cptr, coff, w4, gd, counters, amp, pij, pw, trace, dft, work1, work2,
         sij, sw, sout, total;
 };
 
@@ -95,12 +96,13 @@ Layout layout(const Host &h)
     L.w4 = take(4 * std::max<size_t>(nnz, 1) * es);
     L.gd = take(4 * std::max<size_t>(G, 1) * es);
     L.counters = take(3 * 8);
+    L.amp = take(4 * 8);
     L.pij = take(2 * std::max(h.np, 1) * 4);
     L.pw = take(16 * std::max(h.np, 1) * 8);
     L.trace = take(std::max<size_t>((size_t)h.trace_cap * h.np * 3, 1) * 8);
     L.dft = take(2 * std::max(h.np, 1) * 8);
     L.work1 = take(work1_capacity(h) * sizeof(int4));
-    L.work2 = take(std::max<size_t>(G, 1) * sizeof(int2));
+    L.work2 = take(std::max<size_t>(G, 1) * sizeof(int4));
     L.sij = take(2 * SAMPLE_MAX * 4);
     L.sw = take(16 * SAMPLE_MAX * 8);
     L.sout = take(3 * SAMPLE_MAX * 8);
@@ -119,35 +121,71 @@ lee_status hip_fail(hipError_t e, const char *what)
         if (e_ != hipSuccess) return hip_fail(e_, #x); \
     } while (0)
 
-void default_tiling(lee_instance *I)
+// Reorder work so that workgroup b (which the hardware places on XCD b mod 8)
+// takes unit (b mod 8) * per + b / 8: each XCD gets a contiguous run of
+// neighbouring tiles and shares their halos in its own L2.  Idle slots
+// (instance -1) keep the pattern when the count is not a multiple of 8.
+void xcd_order(const std::vector<int4> &items, int per_unit, std::vector<int4> &out)
 {
-    const Host &h = I->host;
-    if (h.d.precision == LEE_F32)
-        I->vec = 4;
-    else
-        I->vec = 2;
-    // enough rows per tile to amortise the 10 halo rows, enough tiles to fill
-    // 256 CUs: aim at >= 2048 waves
-    const int ow = 64 * I->vec - 16;
-    const long strips = (h.d.nx + ow - 1) / ow;
-    int rows = 64;
-    while (rows > 8 && strips * ((h.d.ny + rows - 1) / rows) < 2048) rows /= 2;
-    I->rows = rows;
-    I->waves = 1;
+    const int units = (int)((items.size() + per_unit - 1) / per_unit);
+    const int per = (units + 7) / 8;
+    for (int b = 0; b < 8 * per; ++b) {
+        const int su = (b % 8) * per + b / 8;
+        for (int w = 0; w < per_unit; ++w) {
+            const size_t k = (size_t)su * per_unit + w;
+            out.push_back(su < units && k < items.size() ? items[k] : make_int4(-1, 0, 0, 1));
+        }
+    }
 }
 
-// Sweep work list: one item per (strip, row tile) holding fluid nodes;
-// alternate row tiles march in opposite directions; items are grouped so that
-// consecutive workgroups of one XCD (workgroup id mod 8) cover neighbouring
-// tiles.
-void build_work1(const Host &h, int inst_id, int vec, int rows, int waves, std::vector<int4> &out, bool xcd)
+bool tiling_valid(int prec, const lee_tiling &t)
 {
-    const int ow = 64 * vec - 16;
+    if (t.kind == LEE_SWEEP_TILE) return tile_shape_supported(prec, t.cols, t.rows);
+    if (t.kind == LEE_SWEEP_MARCH) {
+        const bool f32 = prec == LEE_F32;
+        if (!((f32 && (t.vec == 2 || t.vec == 4)) || (!f32 && t.vec == 2))) return false;
+        return t.rows >= 4 && t.rows <= 4096 && (t.waves == 1 || t.waves == 2 || t.waves == 4);
+    }
+    return false;
+}
+
+// Built-in choice: the 2-D tile kernel; small grids take short tiles so that
+// the launch still holds a few thousand workgroups.
+lee_tiling default_tiling_for(int prec, int nx, int ny)
+{
+    lee_tiling t{};
+    t.kind = LEE_SWEEP_TILE;
+    t.cols = 128;
+    t.vec = prec == LEE_F32 ? 4 : 2;
+    t.waves = 1;
+    const long cells = (long)nx * ny;
+    if (prec == LEE_F32)
+        t.rows = cells >= 4096L * 4096 ? 32 : 16;
+    else
+        t.rows = cells >= 4096L * 4096 ? 16 : 8;
+    return t;
+}
+
+void default_tiling(lee_instance *I)
+{
+    I->tl = default_tiling_for(I->host.d.precision, I->host.d.nx, I->host.d.ny);
+}
+
+// Sweep work list: one item per (column block, row tile) holding fluid nodes.
+// A march item covers 64 vec - 16 output columns and alternates its direction
+// between row tiles; a tile item covers `cols` columns.  Items are grouped so
+// that the consecutive workgroups of one XCD (workgroup id mod 8) cover
+// neighbouring tiles.
+void build_work1(const Host &h, int inst_id, const lee_tiling &t, std::vector<int4> &out, bool xcd)
+{
+    const int ow = t.kind == LEE_SWEEP_MARCH ? 64 * t.vec - 16 : t.cols;
+    const int per_unit = t.kind == LEE_SWEEP_MARCH ? t.waves : 1;
+    const int rows = t.rows;
     const int strips = (h.d.nx + ow - 1) / ow;
     const int tiles = (h.d.ny + rows - 1) / rows;
     std::vector<int4> items;
-    for (int t = 0; t < tiles; ++t) {
-        const int r0 = t * rows, r1 = std::min(r0 + rows, h.d.ny);
+    for (int r = 0; r < tiles; ++r) {
+        const int r0 = r * rows, r1 = std::min(r0 + rows, h.d.ny);
         for (int s = 0; s < strips; ++s) {
             const int c0 = s * ow, c1 = std::min(c0 + ow, h.d.nx);
             bool any = false;
@@ -157,31 +195,20 @@ void build_work1(const Host &h, int inst_id, int vec, int rows, int waves, std::
                     if (iv[2 * q] < iv[2 * q + 1] && iv[2 * q] < c1 && iv[2 * q + 1] > c0) any = true;
             }
             if (!any) continue;
-            items.push_back(make_int4(inst_id, c0, r0, (t & 1) ? -r1 : r1));
+            items.push_back(make_int4(inst_id, c0, r0, (r & 1) ? -r1 : r1));
         }
     }
     if (!xcd) {
         out.insert(out.end(), items.begin(), items.end());
         return;
     }
-    const int units = (int)((items.size() + waves - 1) / waves);
-    const int per = (units + 7) / 8;
-    for (int b = 0; b < 8 * per; ++b) {
-        const int su = (b % 8) * per + b / 8;
-        for (int w = 0; w < waves; ++w) {
-            const size_t k = (size_t)su * waves + w;
-            if (su < units && k < items.size())
-                out.push_back(items[k]);
-            else
-                out.push_back(make_int4(-1, 0, 0, 1));   // idle slot keeps the XCD pattern
-        }
-    }
+    xcd_order(items, per_unit, out);
 }
 
 lee_status upload_work1(lee_instance *I)
 {
     I->up_work1.clear();
-    build_work1(I->host, 0, I->vec, I->rows, I->waves, I->up_work1, true);
+    build_work1(I->host, 0, I->tl, I->up_work1, true);
     if (I->up_work1.size() > I->work1_cap) return fail(LEE_E_ARG, "tiling produces too many work items");
     I->nwork1 = (int)I->up_work1.size();
     HIPCHK(hipMemcpyAsync(I->d_work1, I->up_work1.data(), I->up_work1.size() * sizeof(int4),
@@ -197,13 +224,19 @@ void drop_graph(lee_instance *I)
     I->graph = nullptr;
 }
 
+hipError_t sweep(int prec, bool filt, const lee_tiling &t, const DevInst *insts, const int4 *work, int nwork,
+                 int stage, int blocks, hipStream_t s)
+{
+    if (t.kind == LEE_SWEEP_TILE) return launch_tile(prec, filt, t.cols, t.rows, insts, work, nwork, stage, blocks, s);
+    return launch_sweep(prec, t.vec, filt, t.waves, insts, work, nwork, stage, blocks, s);
+}
+
 hipError_t issue_stage(lee_instance *I, int stage)
 {
     const int prec = I->host.d.precision;
     hipError_t e = launch_ghost(prec, I->d_inst, I->d_work2, I->nwork2, stage, I->stream);
     if (e != hipSuccess) return e;
-    e = launch_sweep(prec, I->vec, I->host.d.filter_sigma > 0.0, I->waves, I->d_inst, I->d_work1, I->nwork1,
-                     stage, 0, I->stream);
+    e = sweep(prec, I->host.d.filter_sigma > 0.0, I->tl, I->d_inst, I->d_work1, I->nwork1, stage, 0, I->stream);
     if (e != hipSuccess) return e;
     if (stage == 3) e = launch_step_end(prec, I->d_inst, 1, I->stream);
     return e;
@@ -226,10 +259,11 @@ void pack_lists(lee_instance *I)
         gd[4 * g + 2] = (T)h.beta[2 * g];
         gd[4 * g + 3] = (T)h.beta[2 * g + 1];
     }
+    const int org = FRAME * pitch + LPAD;
     I->up_goff.resize(G);
-    for (size_t g = 0; g < G; ++g) I->up_goff[g] = (h.gidx[g] / h.d.nx) * pitch + h.gidx[g] % h.d.nx;
+    for (size_t g = 0; g < G; ++g) I->up_goff[g] = org + (h.gidx[g] / h.d.nx) * pitch + h.gidx[g] % h.d.nx;
     I->up_coff.resize(nnz);
-    for (size_t e = 0; e < nnz; ++e) I->up_coff[e] = (h.cidx[e] / h.d.nx) * pitch + h.cidx[e] % h.d.nx;
+    for (size_t e = 0; e < nnz; ++e) I->up_coff[e] = org + (h.cidx[e] / h.d.nx) * pitch + h.cidx[e] % h.d.nx;
 }
 
 }  // namespace
@@ -306,11 +340,11 @@ lee_status lee_bind(lee_instance *I, void *dev_ptr, size_t bytes, void *hip_stre
     char *b = I->base;
     const int pitch = pitch_of(h);
     const size_t es = esize(h);
-    const size_t origin = ((size_t)FRAME * pitch + LPAD) * es;
     DevInst &D = I->dev;
     std::memset(&D, 0, sizeof(D));
     for (int r = 0; r < 3; ++r)
-        for (int f = 0; f < 3; ++f) D.f[r][f] = b + L.planes[3 * r + f] + origin;
+        for (int f = 0; f < 3; ++f) D.f[r][f] = b + L.planes[3 * r + f];
+    D.org = FRAME * pitch + LPAD;
     for (int r = 0; r < 3; ++r) D.psi[r] = b + L.psi[r];
     D.iv = (const int4 *)(b + L.iv);
     D.goff = (const int *)(b + L.goff);
@@ -321,6 +355,7 @@ lee_status lee_bind(lee_instance *I, void *dev_ptr, size_t bytes, void *hip_stre
     D.step = (long long *)(b + L.counters);
     D.budget = D.step + 1;
     D.active = (int *)(D.step + 2);
+    D.amp = (double *)(b + L.amp);
     D.pij = (const int *)(b + L.pij);
     D.pw = (const double *)(b + L.pw);
     D.trace = (double *)(b + L.trace);
@@ -349,6 +384,8 @@ lee_status lee_bind(lee_instance *I, void *dev_ptr, size_t bytes, void *hip_stre
     const double sd = h.d.filter_sigma / h.dt;
     D.fd[0] = sd * 2.0 * FD[0];
     for (int k = 1; k < 6; ++k) D.fd[k] = sd * FD[k];
+    for (int k = 0; k < 5; ++k) D.axf[k] = (float)D.ax[k];
+    for (int k = 0; k < 6; ++k) D.fdf[k] = (float)D.fd[k];
     static const double ALPHA[4] = {0.25, 1.0 / 3.0, 0.5, 1.0};
     static const double CST[4] = {0.0, 0.25, 1.0 / 3.0, 0.5};
     for (int l = 0; l < 4; ++l) {
@@ -405,11 +442,11 @@ lee_status lee_bind(lee_instance *I, void *dev_ptr, size_t bytes, void *hip_stre
     HIPCHK(hipMemcpyAsync(I->d_inst, &I->dev, sizeof(DevInst), hipMemcpyHostToDevice, s));
     I->d_work1 = (int4 *)(b + L.work1);
     I->work1_cap = work1_capacity(h);
-    I->d_work2 = (int2 *)(b + L.work2);
+    I->d_work2 = (int4 *)(b + L.work2);
     I->up_work2.resize(G);
-    for (size_t g = 0; g < G; ++g) I->up_work2[g] = make_int2(0, (int)g);
+    for (size_t g = 0; g < G; ++g) I->up_work2[g] = make_int4(0, (int)g, h.cptr[g], h.cptr[g + 1]);
     I->nwork2 = (int)G;
-    if (G) HIPCHK(hipMemcpyAsync(I->d_work2, I->up_work2.data(), G * sizeof(int2), hipMemcpyHostToDevice, s));
+    if (G) HIPCHK(hipMemcpyAsync(I->d_work2, I->up_work2.data(), G * sizeof(int4), hipMemcpyHostToDevice, s));
     I->d_sij = (int *)(b + L.sij);
     I->d_sw = (double *)(b + L.sw);
     I->d_sout = (double *)(b + L.sout);
@@ -434,6 +471,9 @@ lee_status lee_init_fields(lee_instance *I)
     I->up_counters[1] = LLONG_MAX;
     I->up_counters[2] = 1;   // active flag lives in the low word of the third slot
     HIPCHK(hipMemcpyAsync(I->dev.step, I->up_counters, sizeof(I->up_counters), hipMemcpyHostToDevice, s));
+    for (int l = 0; l < 4; ++l)        // stage amplitudes of step 0
+        I->up_amp[l] = I->dev.has_src ? I->dev.src_a * std::sin(I->dev.src_om * (I->dev.c_stage[l] * I->dev.dt)) : 0.0;
+    HIPCHK(hipMemcpyAsync(I->dev.amp, I->up_amp, sizeof(I->up_amp), hipMemcpyHostToDevice, s));
     HIPCHK(launch_init_ic(prec, I->d_inst, h.d.nx, h.d.ny, h.d.ic_kind, h.d.ic, s));
     I->next_stage = 0;
     I->steps_issued = 0;
@@ -482,19 +522,21 @@ lee_status lee_step_n(lee_instance *I, int64_t n)
     return LEE_OK;
 }
 
-lee_status lee_set_tiling(lee_instance *I, int32_t vec, int32_t rows, int32_t waves)
+lee_status lee_set_tiling(lee_instance *I, const lee_tiling *t)
 {
-    if (!I) return fail(LEE_E_ARG, "null instance");
-    const bool f32 = I->host.d.precision == LEE_F32;
-    if (!((f32 && (vec == 2 || vec == 4)) || (!f32 && vec == 2))) return fail(LEE_E_ARG, "unsupported vec");
-    if (rows < 4 || rows > 4096) return fail(LEE_E_ARG, "rows must lie in [4, 4096]");
-    if (waves != 1 && waves != 2 && waves != 4) return fail(LEE_E_ARG, "waves must be 1, 2 or 4");
+    if (!I || !t) return fail(LEE_E_ARG, "null argument");
+    if (!tiling_valid(I->host.d.precision, *t)) return fail(LEE_E_ARG, "unsupported tiling");
     if (I->next_stage != 0) return fail(LEE_E_STATE, "a partial step is pending");
-    I->vec = vec;
-    I->rows = rows;
-    I->waves = waves;
+    I->tl = *t;
     drop_graph(I);
     if (I->bound) return upload_work1(I);
+    return LEE_OK;
+}
+
+lee_status lee_get_tiling(const lee_instance *I, lee_tiling *t)
+{
+    if (!I || !t) return fail(LEE_E_ARG, "null argument");
+    *t = I->tl;
     return LEE_OK;
 }
 
@@ -514,7 +556,7 @@ lee_status copy_plane_out(lee_instance *I, int reg, int f, double *out)
 {
     const Host &h = I->host;
     std::vector<T> tmp((size_t)h.d.nx * h.d.ny);
-    HIPCHK(hipMemcpy2DAsync(tmp.data(), h.d.nx * sizeof(T), I->dev.f[reg][f], pitch_of(h) * sizeof(T),
+    HIPCHK(hipMemcpy2DAsync(tmp.data(), h.d.nx * sizeof(T), (T *)I->dev.f[reg][f] + I->dev.org, pitch_of(h) * sizeof(T),
                             h.d.nx * sizeof(T), h.d.ny, hipMemcpyDeviceToHost, I->stream));
     HIPCHK(hipStreamSynchronize(I->stream));
     for (size_t k = 0; k < tmp.size(); ++k) out[k] = (double)tmp[k];
@@ -527,7 +569,7 @@ lee_status copy_plane_in(lee_instance *I, int f, const double *in)
     const Host &h = I->host;
     std::vector<T> tmp((size_t)h.d.nx * h.d.ny);
     for (size_t k = 0; k < tmp.size(); ++k) tmp[k] = h.fluid[k] ? (T)in[k] : (T)0;
-    HIPCHK(hipMemcpy2DAsync(I->dev.f[0][f], pitch_of(h) * sizeof(T), tmp.data(), h.d.nx * sizeof(T),
+    HIPCHK(hipMemcpy2DAsync((T *)I->dev.f[0][f] + I->dev.org, pitch_of(h) * sizeof(T), tmp.data(), h.d.nx * sizeof(T),
                             h.d.nx * sizeof(T), h.d.ny, hipMemcpyHostToDevice, I->stream));
     HIPCHK(hipStreamSynchronize(I->stream));
     return LEE_OK;
@@ -686,8 +728,7 @@ lee_status lee_time_kernels(lee_instance *I, int64_t n, double *sweep_us, double
                 launch_ghost(prec, I->d_inst, I->d_work2, I->nwork2, l, I->stream);
                 hipEventRecord(e[1], I->stream);
                 hipEventRecord(e[2], I->stream);
-                launch_sweep(prec, I->vec, I->host.d.filter_sigma > 0.0, I->waves, I->d_inst, I->d_work1, I->nwork1,
-                             l, 0, I->stream);
+                sweep(prec, I->host.d.filter_sigma > 0.0, I->tl, I->d_inst, I->d_work1, I->nwork1, l, 0, I->stream);
                 hipEventRecord(e[3], I->stream);
                 if (l == 3) launch_step_end(prec, I->d_inst, 1, I->stream);
             }
@@ -718,6 +759,14 @@ lee_status lee_time_kernels(lee_instance *I, int64_t n, double *sweep_us, double
     return LEE_OK;
 }
 
+lee_status lee_stream_copy(void *dst, const void *src, size_t bytes, void *hip_stream)
+{
+    if (!dst || !src || (bytes & 15) || (((uintptr_t)dst | (uintptr_t)src) & 15))
+        return fail(LEE_E_ARG, "copy needs 16-byte aligned buffers and a multiple of 16 bytes");
+    HIPCHK(launch_copy(src, dst, bytes, (hipStream_t)hip_stream));
+    return LEE_OK;
+}
+
 void lee_destroy(lee_instance *I)
 {
     if (!I) return;
@@ -734,17 +783,18 @@ struct lee_batch {
     std::vector<lee_instance *> members;
     int prec = LEE_F32;
     bool filt = true;
-    int vec = 4, rows = 32, waves = 1, pblocks = 0;
+    lee_tiling tl{};
+    int pblocks = 0;
     hipStream_t stream = nullptr;
     int device = -1;
     DevInst *d_table = nullptr;
     int4 *d_work1 = nullptr;
     int nwork1 = 0;
-    int2 *d_work2 = nullptr;
+    int4 *d_work2 = nullptr;
     int nwork2 = 0;
     std::vector<DevInst> up_table;
     std::vector<int4> up_work1;
-    std::vector<int2> up_work2;
+    std::vector<int4> up_work2;
     std::vector<long long> up_budget;      // (budget, active) pairs
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -765,8 +815,9 @@ hipError_t batch_issue_stage(lee_batch *B, int stage)
     hipError_t e = launch_ghost(B->prec, B->d_table, B->d_work2, B->nwork2, stage, B->stream);
     if (e != hipSuccess) return e;
     int blocks = 0;
-    if (B->pblocks > 0) blocks = std::min(B->pblocks, (B->nwork1 + B->waves - 1) / B->waves);
-    e = launch_sweep(B->prec, B->vec, B->filt, B->waves, B->d_table, B->d_work1, B->nwork1, stage, blocks, B->stream);
+    const int per = B->tl.kind == LEE_SWEEP_MARCH ? B->tl.waves : 1;
+    if (B->pblocks > 0) blocks = std::min(B->pblocks, (B->nwork1 + per - 1) / per);
+    e = sweep(B->prec, B->filt, B->tl, B->d_table, B->d_work1, B->nwork1, stage, blocks, B->stream);
     if (e != hipSuccess) return e;
     if (stage == 3) e = launch_step_end(B->prec, B->d_table, (int)B->members.size(), B->stream);
     return e;
@@ -806,50 +857,36 @@ lee_status lee_batch_create(lee_instance *const *v, int32_t n, const lee_batch_o
     B->filt = v[0]->host.d.filter_sigma > 0.0;
     B->stream = v[0]->stream;
     B->device = v[0]->device;
-    B->vec = B->prec == LEE_F32 ? 4 : 2;
-    B->rows = 32;
-    B->waves = 1;
+    B->tl = default_tiling_for(B->prec, 4096, 4096);
     if (opts) {
-        if (opts->vec) B->vec = opts->vec;
-        if (opts->rows) B->rows = opts->rows;
-        if (opts->waves) B->waves = opts->waves;
+        if (opts->tiling.kind >= 0) B->tl = opts->tiling;
         B->pblocks = opts->persistent_blocks;
     }
-    const bool f32 = B->prec == LEE_F32;
-    if (!((f32 && (B->vec == 2 || B->vec == 4)) || (!f32 && B->vec == 2)) || B->rows < 4 ||
-        (B->waves != 1 && B->waves != 2 && B->waves != 4) || B->pblocks < 0) {
+    if (!tiling_valid(B->prec, B->tl) || B->pblocks < 0) {
         delete B;
         return fail(LEE_E_ARG, "batch tiling options");
     }
     if (B->pblocks > 0) B->pblocks = (B->pblocks + 7) / 8 * 8;   // keep the XCD pattern
     std::vector<int4> items;
-    for (int k = 0; k < n; ++k) build_work1(v[k]->host, k, B->vec, B->rows, 1, items, false);
-    // XCD-aware grouping over the whole list (see build_work1)
-    const int units = (int)((items.size() + B->waves - 1) / B->waves);
-    const int per = (units + 7) / 8;
-    for (int b = 0; b < 8 * per; ++b) {
-        const int su = (b % 8) * per + b / 8;
-        for (int w = 0; w < B->waves; ++w) {
-            const size_t q = (size_t)su * B->waves + w;
-            B->up_work1.push_back(su < units && q < items.size() ? items[q] : make_int4(-1, 0, 0, 1));
-        }
-    }
+    for (int k = 0; k < n; ++k) build_work1(v[k]->host, k, B->tl, items, false);
+    xcd_order(items, B->tl.kind == LEE_SWEEP_MARCH ? B->tl.waves : 1, B->up_work1);
     for (int k = 0; k < n; ++k)
-        for (int g = 0; g < (int)v[k]->host.gidx.size(); ++g) B->up_work2.push_back(make_int2(k, g));
+        for (int g = 0; g < (int)v[k]->host.gidx.size(); ++g)
+            B->up_work2.push_back(make_int4(k, g, v[k]->host.cptr[g], v[k]->host.cptr[g + 1]));
     for (int k = 0; k < n; ++k) B->up_table.push_back(v[k]->dev);
     B->nwork1 = (int)B->up_work1.size();
     B->nwork2 = (int)B->up_work2.size();
     hipError_t e = hipSuccess;
     e = hipMalloc(&B->d_table, n * sizeof(DevInst));
     if (e == hipSuccess) e = hipMalloc(&B->d_work1, std::max<size_t>(B->up_work1.size(), 1) * sizeof(int4));
-    if (e == hipSuccess) e = hipMalloc(&B->d_work2, std::max<size_t>(B->up_work2.size(), 1) * sizeof(int2));
+    if (e == hipSuccess) e = hipMalloc(&B->d_work2, std::max<size_t>(B->up_work2.size(), 1) * sizeof(int4));
     if (e == hipSuccess)
         e = hipMemcpyAsync(B->d_table, B->up_table.data(), n * sizeof(DevInst), hipMemcpyHostToDevice, B->stream);
     if (e == hipSuccess && B->nwork1)
         e = hipMemcpyAsync(B->d_work1, B->up_work1.data(), B->nwork1 * sizeof(int4), hipMemcpyHostToDevice,
                            B->stream);
     if (e == hipSuccess && B->nwork2)
-        e = hipMemcpyAsync(B->d_work2, B->up_work2.data(), B->nwork2 * sizeof(int2), hipMemcpyHostToDevice,
+        e = hipMemcpyAsync(B->d_work2, B->up_work2.data(), B->nwork2 * sizeof(int4), hipMemcpyHostToDevice,
                            B->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(B->stream);
     if (e != hipSuccess) {
@@ -916,7 +953,8 @@ lee_status lee_batch_time_kernels(lee_batch *B, int64_t n, double *sweep_us, dou
     int64_t done = 0;
     lee_status st = LEE_OK;
     int blocks = 0;
-    if (B->pblocks > 0) blocks = std::min(B->pblocks, (B->nwork1 + B->waves - 1) / B->waves);
+    const int per = B->tl.kind == LEE_SWEEP_MARCH ? B->tl.waves : 1;
+    if (B->pblocks > 0) blocks = std::min(B->pblocks, (B->nwork1 + per - 1) / per);
     while (done < n) {
         const int m = (int)std::min<int64_t>(CH, n - done);
         hipEventRecord(ev[CH * 16], B->stream);
@@ -927,8 +965,7 @@ lee_status lee_batch_time_kernels(lee_batch *B, int64_t n, double *sweep_us, dou
                 launch_ghost(B->prec, B->d_table, B->d_work2, B->nwork2, l, B->stream);
                 hipEventRecord(e[1], B->stream);
                 hipEventRecord(e[2], B->stream);
-                launch_sweep(B->prec, B->vec, B->filt, B->waves, B->d_table, B->d_work1, B->nwork1, l, blocks,
-                             B->stream);
+                sweep(B->prec, B->filt, B->tl, B->d_table, B->d_work1, B->nwork1, l, blocks, B->stream);
                 hipEventRecord(e[3], B->stream);
                 if (l == 3) launch_step_end(B->prec, B->d_table, (int)B->members.size(), B->stream);
             }

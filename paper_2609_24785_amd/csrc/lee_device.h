@@ -10,18 +10,21 @@
 namespace lee {
 
 // One instance as the kernels see it; lives in device memory (an array of
-// them forms a batch table).  Field planes point at node (0, 0); row j starts
-// j * pitch elements later; the frame and padding around the domain hold 0.
+// them forms a batch table).  Field planes point at the start of their
+// allocation; node (i, j) sits at element org + j * pitch + i (always a
+// non-negative 32-bit offset, frame rows included); the frame and padding
+// around the domain hold 0.
 struct DevInst {
     void *f[3][3];          // [register set A, B, C][p, u, v]; A holds q^n
     void *psi[3];           // ADE states per register set, 2 per ghost
     const int4 *iv;         // per row: fluid columns [x, y) and [z, w)
-    const int *goff;        // ghost plane offsets
+    const int *goff;        // ghost plane offsets (from the plane start)
     const int *cptr;        // cloud CSR pointers (G + 1)
-    const int *coff;        // cloud plane offsets
+    const int *coff;        // cloud plane offsets (from the plane start)
     const void *w4;         // 4 weights per cloud entry (T)
     const void *gd;         // per ghost: n_x, n_y, beta_D, beta_N (T)
     long long *step;        // completed steps
+    double *amp;            // source amplitude a sin(omega t_l) of the 4 stages of the next step
     long long *budget;      // remaining steps; the member idles at 0
     int *active;            // 1 while budget > 0
     const int *pij;         // probe stencil origins
@@ -33,11 +36,14 @@ struct DevInst {
     double dft_omega;
     int np;
     int nx, ny, pitch, G;
+    int org;                // element offset of node (0, 0) in a plane
     int sponge_w, has_src, ade_kind;
     int src_ic, src_jc;     // source's nearest node
     int src_i0, src_i1, src_j0, src_j1;  // node box outside which the source underflows
     double x0, y0, h, dt;
     double ax[5];           // a_k / h (zero beyond the stencil half-width)
+    float axf[5];           // the same in FP32
+    float fdf[6];           // fd in FP32
     double fd[6];           // (sigma_d / dt) * (2 d_0, d_1 .. d_5): damping of D_x + D_y
     double alpha_dt[4];     // alpha_l dt
     double c_stage[4];      // stage time offsets c_l (in steps)
@@ -48,12 +54,16 @@ struct DevInst {
 
 hipError_t launch_sweep(int prec, int vec, bool filt, int waves, const DevInst *insts, const int4 *work,
                         int nwork, int stage, int blocks, hipStream_t s);
-hipError_t launch_ghost(int prec, const DevInst *insts, const int2 *work, int nwork, int stage, hipStream_t s);
+bool tile_shape_supported(int prec, int tx, int ty);
+hipError_t launch_tile(int prec, bool filt, int tx, int ty, const DevInst *insts, const int4 *work, int nwork,
+                       int stage, int blocks, hipStream_t s);
+hipError_t launch_ghost(int prec, const DevInst *insts, const int4 *work, int nwork, int stage, hipStream_t s);
 hipError_t launch_step_end(int prec, const DevInst *insts, int ninst, hipStream_t s);
 hipError_t launch_fill(int prec, void *p, size_t n, hipStream_t s);
 hipError_t launch_fill_bytes(void *p, size_t bytes, hipStream_t s);
 hipError_t launch_init_ic(int prec, const DevInst *insts, int nx, int ny, int kind, const double *c,
                           hipStream_t s);
+hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t s);
 hipError_t launch_sample(int prec, const DevInst *insts, const int *ij, const double *w, int np, double *out,
                          hipStream_t s);
 

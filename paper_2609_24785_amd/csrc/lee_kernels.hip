@@ -19,6 +19,7 @@
 // No matrix cores: the stage is a memory-bound stencil (about 3 flop per byte).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "lee_device.h"
@@ -29,6 +30,35 @@ template <typename T, int N>
 struct alignas(sizeof(T) * N) VecT {
     T v[N];
 };
+
+// Pointers read from the instance record are generic; casting them to the
+// global address space lets the compiler emit global (not flat) memory
+// instructions and know that they never alias LDS.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define GLOBAL __attribute__((address_space(1)))
+#else
+#define GLOBAL
+#endif
+template <typename T>
+__device__ __forceinline__ GLOBAL T *gp(void *p)
+{
+    return (GLOBAL T *)p;
+}
+template <typename T>
+__device__ __forceinline__ const GLOBAL T *gp(const void *p)
+{
+    return (const GLOBAL T *)p;
+}
+template <typename T, int N>
+__device__ __forceinline__ VecT<T, N> vld(const GLOBAL T *p)
+{
+    return *(const GLOBAL VecT<T, N> *)p;
+}
+template <typename T, int N>
+__device__ __forceinline__ void vst(GLOBAL T *p, const VecT<T, N> &v)
+{
+    *(GLOBAL VecT<T, N> *)p = v;
+}
 
 // Orders this wave's LDS writes before its following LDS reads.  Each wave owns
 // its LDS rows, so no workgroup barrier is needed (and waves of one workgroup
@@ -49,32 +79,49 @@ __device__ __forceinline__ int out_buf(int stage) { return stage == 0 ? 1 : (sta
 
 template <typename T, int GL>
 __global__ __launch_bounds__(256) void k_ghost(const DevInst *__restrict__ insts,
-                                               const int2 *__restrict__ work, int nwork, int stage)
+                                               const int4 *__restrict__ work, int nwork, int stage)
 {
     const int gid = (int)((blockIdx.x * blockDim.x + threadIdx.x) / GL);
     const int sub = (int)(threadIdx.x % GL);
     if (gid >= nwork) return;                       // whole GL-lane groups leave together
-    const int2 wk = work[gid];
+    const int4 wk = work[gid];                      // instance, ghost, cloud entries [z, w)
     const DevInst &I = insts[wk.x];
-    if (!*I.active) return;
+    if (!*gp<int>(I.active)) return;
     const int g = wk.y;
     const int ib = in_buf(stage), ob = out_buf(stage);
-    T *P = (T *)I.f[ib][0];
-    T *U = (T *)I.f[ib][1];
-    T *V = (T *)I.f[ib][2];
-    const T *gd = (const T *)I.gd + 4 * (size_t)g;
+    GLOBAL T *P = gp<T>(I.f[ib][0]);
+    GLOBAL T *U = gp<T>(I.f[ib][1]);
+    GLOBAL T *V = gp<T>(I.f[ib][2]);
+    const VecT<T, 4> gdv = vld<T, 4>(gp<T>(I.gd) + 4 * (size_t)g);
+    const T *gd = gdv.v;
     const T nx = gd[0], ny = gd[1];
-    const T *w4 = (const T *)I.w4;
+    const GLOBAL T *w4 = gp<T>(I.w4);
+    const GLOBAL int *coff = gp<int>(I.coff);
     T a0 = 0, aF = 0, aD = 0, aN = 0;
-    const int e1 = I.cptr[g + 1];
-    for (int e = I.cptr[g] + sub; e < e1; e += GL) {
-        const int off = I.coff[e];
-        const VecT<T, 4> w = *(const VecT<T, 4> *)(w4 + 4 * (size_t)e);
-        const T p = P[off], u = U[off], v = V[off];
-        a0 += w.v[0] * p;
-        aN += w.v[3] * p;
-        aD += w.v[2] * (nx * u + ny * v);
-        aF += w.v[1] * (-ny * u + nx * v);
+    const int e0 = wk.z, e1 = wk.w;
+    constexpr int MAXE = 4;                         // entries per lane per pass
+    for (int base = e0; base < e1; base += GL * MAXE) {
+        // all offsets and weights first, then all field values: two dependent
+        // round trips per pass instead of two per entry
+        int off[MAXE];
+        VecT<T, 4> w[MAXE];
+#pragma unroll
+        for (int k = 0; k < MAXE; ++k) {
+            const int e = base + sub + k * GL;
+            const bool ok = e < e1;
+            off[k] = ok ? coff[e] : -1;
+            if (ok) w[k] = vld<T, 4>(w4 + 4 * (size_t)e);
+            else w[k] = VecT<T, 4>{{0, 0, 0, 0}};
+        }
+#pragma unroll
+        for (int k = 0; k < MAXE; ++k) {
+            if (off[k] < 0) continue;
+            const T p = P[off[k]], u = U[off[k]], v = V[off[k]];
+            a0 += w[k].v[0] * p;
+            aN += w[k].v[3] * p;
+            aD += w[k].v[2] * (nx * u + ny * v);
+            aF += w[k].v[1] * (-ny * u + nx * v);
+        }
     }
 #pragma unroll
     for (int m = GL / 2; m >= 1; m >>= 1) {
@@ -86,7 +133,7 @@ __global__ __launch_bounds__(256) void k_ghost(const DevInst *__restrict__ insts
     if (sub != 0) return;
     // steps 2-3: ADE derivative, wall normal velocity and its time derivative
     T d1 = 0, d2 = 0, Un = 0, Ud = 0;
-    const T *psi_in = (const T *)I.psi[ib];
+    const GLOBAL T *psi_in = gp<T>(I.psi[ib]);
     const T s1 = psi_in[2 * g], s2 = psi_in[2 * g + 1];
     if (I.ade_kind == 1) {
         const T a = (T)I.ade[0], b = (T)I.ade[1], c1 = (T)I.ade[2], c2 = (T)I.ade[3];
@@ -106,13 +153,13 @@ __global__ __launch_bounds__(256) void k_ghost(const DevInst *__restrict__ insts
     const T pg = aN + gd[3] * ((T)I.h * Ud);
     const T un = aD + gd[2] * (-Un);
     const T ut = aF;
-    const int go = I.goff[g];
+    const int go = gp<int>(I.goff)[g];
     P[go] = pg;
     U[go] = nx * un - ny * ut;
     V[go] = ny * un + nx * ut;
     if (I.ade_kind != 0) {
-        const T *psi_n = (const T *)I.psi[0];
-        T *psi_out = (T *)I.psi[ob];
+        const GLOBAL T *psi_n = gp<T>(I.psi[0]);
+        GLOBAL T *psi_out = gp<T>(I.psi[ob]);
         const T adt = (T)I.alpha_dt[stage];
         psi_out[2 * g] = psi_n[2 * g] + adt * d1;
         psi_out[2 * g + 1] = psi_n[2 * g + 1] + adt * d2;
@@ -123,11 +170,12 @@ __global__ __launch_bounds__(256) void k_ghost(const DevInst *__restrict__ insts
 // stage sweep
 
 template <typename T, int VEC>
-__device__ __forceinline__ void load_row(T (&dst)[3][VEC], const T *p, const T *u, const T *v, long off)
+__device__ __forceinline__ void load_row(T (&dst)[3][VEC], const GLOBAL T *p, const GLOBAL T *u,
+                                         const GLOBAL T *v, unsigned off)
 {
-    const VecT<T, VEC> a = *(const VecT<T, VEC> *)(p + off);
-    const VecT<T, VEC> b = *(const VecT<T, VEC> *)(u + off);
-    const VecT<T, VEC> c = *(const VecT<T, VEC> *)(v + off);
+    const VecT<T, VEC> a = vld<T, VEC>(p + off);
+    const VecT<T, VEC> b = vld<T, VEC>(u + off);
+    const VecT<T, VEC> c = vld<T, VEC>(v + off);
 #pragma unroll
     for (int e = 0; e < VEC; ++e) {
         dst[0][e] = a.v[e];
@@ -153,7 +201,7 @@ __global__ __launch_bounds__(64 * WPB) void k_sweep(const DevInst *__restrict__ 
         const int4 wk = work[w];
         if (wk.x < 0) continue;                   // idle slot of the XCD-aware order
         const DevInst &I = insts[wk.x];
-        if (!*I.active) continue;                 // uniform per wave
+        if (!*gp<int>(I.active)) continue;        // uniform per wave
         const int c0 = wk.y;                      // first output column
         const int r0 = wk.z;
         const int dir = wk.w < 0 ? -1 : 1;
@@ -161,16 +209,17 @@ __global__ __launch_bounds__(64 * WPB) void k_sweep(const DevInst *__restrict__ 
         const int nrows = r1 - r0;
         const int jbeg = dir > 0 ? r0 : r1 - 1;
         const int ib = in_buf(stage), ob = out_buf(stage);
-        const long pitch = I.pitch;
-        const T *Pi = (const T *)I.f[ib][0];
-        const T *Ui = (const T *)I.f[ib][1];
-        const T *Vi = (const T *)I.f[ib][2];
-        const T *Pn = (const T *)I.f[0][0];
-        const T *Un = (const T *)I.f[0][1];
-        const T *Vn = (const T *)I.f[0][2];
-        T *Po = (T *)I.f[ob][0];
-        T *Uo = (T *)I.f[ob][1];
-        T *Vo = (T *)I.f[ob][2];
+        const int pitch = I.pitch;
+        const int org = I.org;
+        const GLOBAL T *Pi = gp<T>(I.f[ib][0]);
+        const GLOBAL T *Ui = gp<T>(I.f[ib][1]);
+        const GLOBAL T *Vi = gp<T>(I.f[ib][2]);
+        const GLOBAL T *Pn = gp<T>(I.f[0][0]);
+        const GLOBAL T *Un = gp<T>(I.f[0][1]);
+        const GLOBAL T *Vn = gp<T>(I.f[0][2]);
+        GLOBAL T *Po = gp<T>(I.f[ob][0]);
+        GLOBAL T *Uo = gp<T>(I.f[ob][1]);
+        GLOBAL T *Vo = gp<T>(I.f[ob][2]);
         const int col0 = c0 - 8 + lane * VEC;     // first column of this lane
         const bool out_lane = (col0 + VEC > c0) && (col0 < c0 + NL - 16);
         // coefficients
@@ -184,24 +233,21 @@ __global__ __launch_bounds__(64 * WPB) void k_sweep(const DevInst *__restrict__ 
         const T ydir = (T)dir;
         const bool has_src = I.has_src && !(I.src_i1 < c0 || I.src_i0 >= c0 + NL - 16) &&
                              !(I.src_j1 < r0 || I.src_j0 >= r1);
-        T amp = 0;
-        if (has_src) {
-            const double t = ((double)*I.step + I.c_stage[stage]) * I.dt;
-            amp = (T)(I.src_a * sin(I.src_om * t));
-        }
+        const T amp = has_src ? (T)gp<double>(I.amp)[stage] : (T)0;
         const int sw = I.sponge_w;
 
         T q[11][3][VEC];
         // prologue: rows jbeg - 5 dir .. jbeg + 4 dir
 #pragma unroll
-        for (int s = 0; s < 10; ++s) load_row<T, VEC>(q[s], Pi, Ui, Vi, (long)(jbeg + (s - 5) * dir) * pitch + col0);
+        for (int s = 0; s < 10; ++s)
+            load_row<T, VEC>(q[s], Pi, Ui, Vi, (unsigned)(org + (jbeg + (s - 5) * dir) * pitch + col0));
 
         for (int it = 0; it < nrows; ++it) {
             const int j = jbeg + it * dir;
-            load_row<T, VEC>(q[10], Pi, Ui, Vi, (long)(j + 5 * dir) * pitch + col0);
+            load_row<T, VEC>(q[10], Pi, Ui, Vi, (unsigned)(org + (j + 5 * dir) * pitch + col0));
             T qn[3][VEC];
-            if (stage != 0) load_row<T, VEC>(qn, Pn, Un, Vn, (long)j * pitch + col0);
-            const int4 iv = I.iv[j];
+            if (stage != 0) load_row<T, VEC>(qn, Pn, Un, Vn, (unsigned)(org + j * pitch + col0));
+            const int4 iv = gp<int4>(I.iv)[j];
             wave_lds_sync();
             {
                 VecT<T, VEC> a, b, c;
@@ -303,7 +349,7 @@ __global__ __launch_bounds__(64 * WPB) void k_sweep(const DevInst *__restrict__ 
                     ok[e] = (col >= iv.x && col < iv.y) || (col >= iv.z && col < iv.w);
                     all = all && ok[e];
                 }
-                const long off = (long)j * pitch + col0;
+                const unsigned off = (unsigned)(org + j * pitch + col0);
                 if (all) {
                     VecT<T, VEC> a, b, c;
 #pragma unroll
@@ -312,9 +358,9 @@ __global__ __launch_bounds__(64 * WPB) void k_sweep(const DevInst *__restrict__ 
                         b.v[e] = ro[1][e];
                         c.v[e] = ro[2][e];
                     }
-                    *(VecT<T, VEC> *)(Po + off) = a;
-                    *(VecT<T, VEC> *)(Uo + off) = b;
-                    *(VecT<T, VEC> *)(Vo + off) = c;
+                    vst<T, VEC>(Po + off, a);
+                    vst<T, VEC>(Uo + off, b);
+                    vst<T, VEC>(Vo + off, c);
                 } else {
 #pragma unroll
                     for (int e = 0; e < VEC; ++e)
@@ -331,6 +377,261 @@ __global__ __launch_bounds__(64 * WPB) void k_sweep(const DevInst *__restrict__ 
                 for (int f = 0; f < 3; ++f)
 #pragma unroll
                     for (int e = 0; e < VEC; ++e) q[s][f][e] = q[s + 1][f][e];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// stage sweep, 2-D tile variant.  A 256-thread workgroup owns a TX x TY
+// tile.  Its read region of q^(l-1) (the tile plus 5 halo rows above and
+// below and 8 halo columns left and right, corners skipped) and its block of
+// q^n are copied straight from global memory into LDS with 16-byte
+// global_load_lds instructions (no register staging, so all of the tile's
+// traffic is in flight at once).  Each thread then computes VEC consecutive
+// nodes of one row at a time, reading the 11-point windows of each field from
+// LDS.
+
+#if defined(__HIP_DEVICE_COMPILE__)
+#define LOCAL __attribute__((address_space(3)))
+#else
+#define LOCAL
+#endif
+
+// stencil coefficients in the arithmetic precision (FP32 copies are kept in
+// the record so they load straight into scalar registers)
+template <typename T>
+__device__ __forceinline__ void coefs(const DevInst &I, T (&ax)[5], T (&fd)[6]);
+template <>
+__device__ __forceinline__ void coefs<float>(const DevInst &I, float (&ax)[5], float (&fd)[6])
+{
+#pragma unroll
+    for (int k = 0; k < 5; ++k) ax[k] = I.axf[k];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) fd[k] = I.fdf[k];
+}
+template <>
+__device__ __forceinline__ void coefs<double>(const DevInst &I, double (&ax)[5], double (&fd)[6])
+{
+#pragma unroll
+    for (int k = 0; k < 5; ++k) ax[k] = I.ax[k];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) fd[k] = I.fd[k];
+}
+
+// 16 bytes from src (per lane) to LDS at lds_wave_base + 16 * lane.
+__device__ __forceinline__ void dma16(const void *src, void *lds_wave_base)
+{
+    __builtin_amdgcn_global_load_lds((const GLOBAL void *)src, (LOCAL void *)lds_wave_base, 16, 0, 0);
+}
+
+// One field's contribution to the right-hand sides of VEC nodes of one row
+// (LDS row y, first LDS column lc): F = 0 (p): -dp/dx -> u, -dp/dy -> v;
+// F = 1 (u): -du/dx -> p; F = 2 (v): -dv/dy -> p; and the filter damping of
+// the field itself, written as sum_k d_k (f_{+k} + f_{-k} - 2 f_0) over both
+// directions (equal to d_0 f_0 + sum_k d_k (f_{+k} + f_{-k}) per direction
+// since d_0 + 2 sum_k d_k = 0, and free of the cancellation of large terms).
+template <typename T, int VEC, bool FILT, int F, int LW>
+__device__ __forceinline__ void row_field(const T (*lds)[LW], int y, int lc, const T (&ax)[5], const T (&fd)[6],
+                                          T (&rp)[VEC], T (&ru)[VEC], T (&rv)[VEC])
+{
+    constexpr int KM = (5 + VEC - 1) / VEC;
+    constexpr int KP = (VEC + 4) / VEC;
+    constexpr int XW = (KM + 1 + KP) * VEC;
+    T yw[11][VEC];
+#pragma unroll
+    for (int k = 0; k < 11; ++k) {
+        const VecT<T, VEC> a = *(const VecT<T, VEC> *)&lds[y - 5 + k][lc];
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) yw[k][e] = a.v[e];
+    }
+    T xw[XW];
+    if (F != 2 || FILT) {
+#pragma unroll
+        for (int k = -KM; k <= KP; ++k) {
+            const VecT<T, VEC> a = *(const VecT<T, VEC> *)&lds[y][lc + k * VEC];
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) xw[(k + KM) * VEC + e] = a.v[e];
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+        const int x = KM * VEC + e;
+        if (F != 1) {
+            T dy = 0;
+#pragma unroll
+            for (int k = 1; k <= 5; ++k) dy += ax[k - 1] * (yw[5 + k][e] - yw[5 - k][e]);
+            if (F == 0) rv[e] -= dy;
+            else rp[e] -= dy;
+        }
+        if (F != 2) {
+            T dx = 0;
+#pragma unroll
+            for (int k = 1; k <= 5; ++k) dx += ax[k - 1] * (xw[x + k] - xw[x - k]);
+            if (F == 0) ru[e] -= dx;
+            else rp[e] -= dx;
+        }
+        if (FILT) {
+            const T c2 = yw[5][e] + yw[5][e];
+            T fl = 0;
+#pragma unroll
+            for (int k = 1; k <= 5; ++k)
+                fl += fd[k] * (((xw[x + k] + xw[x - k]) - c2) + ((yw[5 + k][e] + yw[5 - k][e]) - c2));
+            if (F == 0) rp[e] -= fl;
+            else if (F == 1) ru[e] -= fl;
+            else rv[e] -= fl;
+        }
+    }
+}
+
+// Forces the partial sums to be materialised here and orders the following
+// LDS reads after them (an empty asm statement: no instruction is emitted).
+template <typename T, int VEC>
+__device__ __forceinline__ void pin_sums(T (&rp)[VEC], T (&ru)[VEC], T (&rv)[VEC])
+{
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) asm volatile("" : "+v"(rp[e]), "+v"(ru[e]), "+v"(rv[e])::"memory");
+}
+
+template <typename T, int VEC, bool FILT, int TX, int TY>
+__global__ __launch_bounds__(256) void k_tile(const DevInst *__restrict__ insts, const int4 *__restrict__ work,
+                                              int nwork, int stage)
+{
+    constexpr int NT = 256;
+    constexpr int NCX = TX / VEC;                // column groups
+    constexpr int RG = NT / NCX;                 // rows in flight per pass
+    constexpr int R = TY + 10;                   // LDS rows of the read region
+    constexpr int LW = TX + 16;                  // LDS columns of the read region
+    constexpr int CW = LW / VEC;                 // 16-byte chunks per LDS row
+    constexpr int HC = 8 / VEC;                  // halo chunks per side
+    constexpr int NCH = R * CW;                  // chunks per field (region)
+    constexpr int QCW = TX / VEC;                // chunks per q^n row
+    constexpr int NQ = TY * QCW;                 // chunks per field (q^n block)
+    static_assert(sizeof(T) * VEC == 16, "16-byte chunks");
+    __shared__ T lds[3][R][LW];
+    __shared__ T ldn[3][TY][TX];
+    const int w = blockIdx.x;
+    if (w >= nwork) return;
+    const int4 wk = work[w];
+    if (wk.x < 0) return;                        // idle slot of the XCD-aware order
+    const DevInst &I = insts[wk.x];
+    if (!*gp<int>(I.active)) return;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int c0 = wk.y, r0 = wk.z;
+    const int r1 = wk.w < 0 ? -wk.w : wk.w;
+    const int ib = in_buf(stage), ob = out_buf(stage);
+    const int pitch = I.pitch;
+    const int org = I.org;
+    const int rowmax = I.ny + 4;                 // last allocated frame row
+
+    // ---- load phase: DMA into LDS, 64 chunks per wave instruction ----
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+        const T *src = (const T *)I.f[ib][f];
+        for (int base = wave * 64; base < NCH; base += NT) {
+            const int q = base + lane;
+            const int row = q / CW, cc = q - (q / CW) * CW;
+            const int gr = r0 - 5 + row;
+            const bool halo_row = row < 5 || row >= TY + 5;
+            const bool ok = q < NCH && !(halo_row && (cc < HC || cc >= CW - HC)) && gr <= rowmax;
+            if (ok) dma16(src + (unsigned)(org + gr * pitch + (c0 - 8 + cc * VEC)), &lds[f][0][0] + base * VEC);
+        }
+    }
+    if (stage != 0) {
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+            const T *src = (const T *)I.f[0][f];
+            for (int base = wave * 64; base < NQ; base += NT) {
+                const int q = base + lane;
+                const int row = q / QCW, cc = q - (q / QCW) * QCW;
+                const int gr = r0 + row;
+                if (q < NQ && gr <= rowmax)
+                    dma16(src + (unsigned)(org + gr * pitch + c0 + cc * VEC), &ldn[f][0][0] + base * VEC);
+            }
+        }
+    }
+    T ax[5], fd[6];
+    coefs<T>(I, ax, fd);
+    const T adt = (T)I.alpha_dt[stage];
+    const int sw = I.sponge_w;
+    const bool has_src = I.has_src && !(I.src_i1 < c0 || I.src_i0 >= c0 + TX) && !(I.src_j1 < r0 || I.src_j0 >= r1);
+    const T amp = has_src ? (T)gp<double>(I.amp)[stage] : (T)0;
+    GLOBAL T *Po = gp<T>(I.f[ob][0]);
+    GLOBAL T *Uo = gp<T>(I.f[ob][1]);
+    GLOBAL T *Vo = gp<T>(I.f[ob][2]);
+    __builtin_amdgcn_s_waitcnt(0);               // this wave's DMA has landed in LDS
+    __syncthreads();                             // ... and every other wave's
+
+    // ---- compute phase: one row of VEC nodes at a time ----
+    const int cg = tid % NCX;
+    const int tc = cg * VEC;
+    const int lc = tc + 8;
+    const int gc = c0 + tc;
+#pragma unroll 1
+    for (int i = tid / NCX; i < TY; i += RG) {
+        const int j = r0 + i;
+        if (j >= r1) break;
+        const int y = i + 5;
+        T rp[VEC], ru[VEC], rv[VEC];
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) rp[e] = ru[e] = rv[e] = 0;
+        // one field's windows live at a time: each field's sums are pinned
+        // (empty asm, no instructions) before the next field's LDS reads
+        row_field<T, VEC, FILT, 0>(lds[0], y, lc, ax, fd, rp, ru, rv);
+        pin_sums<T, VEC>(rp, ru, rv);
+        row_field<T, VEC, FILT, 1>(lds[1], y, lc, ax, fd, rp, ru, rv);
+        pin_sums<T, VEC>(rp, ru, rv);
+        row_field<T, VEC, FILT, 2>(lds[2], y, lc, ax, fd, rp, ru, rv);
+        const int4 iv = gp<int4>(I.iv)[j];
+        const VecT<T, VEC> pc = *(const VecT<T, VEC> *)&lds[0][y][lc];
+        const VecT<T, VEC> uc = *(const VecT<T, VEC> *)&lds[1][y][lc];
+        const VecT<T, VEC> vc = *(const VecT<T, VEC> *)&lds[2][y][lc];
+        VecT<T, VEC> pn = pc, un = uc, vn = vc;
+        if (stage != 0) {
+            pn = *(const VecT<T, VEC> *)&ldn[0][i][tc];
+            un = *(const VecT<T, VEC> *)&ldn[1][i][tc];
+            vn = *(const VecT<T, VEC> *)&ldn[2][i][tc];
+        }
+        VecT<T, VEC> po, uo, vo;
+        bool ok[VEC];
+        bool all = true;
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+            const int col = gc + e;
+            if (sw > 0) {
+                const int eg = min(min(col, j), min(I.nx - 1 - col, I.ny - 1 - j));
+                if (eg < sw) {
+                    const T fr = (T)(sw - eg) / (T)sw;
+                    const T sg = (T)I.sponge_s * fr * fr;
+                    rp[e] -= sg * pc.v[e];
+                    ru[e] -= sg * uc.v[e];
+                    rv[e] -= sg * vc.v[e];
+                }
+            }
+            if (has_src) {
+                const T xx = (T)(col - I.src_ic) * (T)I.h - (T)I.src_fx;
+                const T yy = (T)(j - I.src_jc) * (T)I.h - (T)I.src_fy;
+                rp[e] += amp * exp(-(T)I.src_b * (xx * xx + yy * yy));
+            }
+            po.v[e] = pn.v[e] + adt * rp[e];
+            uo.v[e] = un.v[e] + adt * ru[e];
+            vo.v[e] = vn.v[e] + adt * rv[e];
+            ok[e] = (col >= iv.x && col < iv.y) || (col >= iv.z && col < iv.w);
+            all = all && ok[e];
+        }
+        const unsigned off = (unsigned)(org + j * pitch + gc);
+        if (all) {
+            vst<T, VEC>(Po + off, po);
+            vst<T, VEC>(Uo + off, uo);
+            vst<T, VEC>(Vo + off, vo);
+        } else {
+#pragma unroll
+            for (int e = 0; e < VEC; ++e)
+                if (ok[e]) {
+                    Po[off + e] = po.v[e];
+                    Uo[off + e] = uo.v[e];
+                    Vo[off + e] = vo.v[e];
+                }
         }
     }
 }
@@ -361,7 +662,7 @@ __global__ __launch_bounds__(256) void k_step_end(const DevInst *__restrict__ in
         double ap = 0, au = 0, av = 0;
         for (int b = 0; b < 4; ++b)
             for (int a = 0; a < 4; ++a) {
-                const long off = (long)(j0 + b) * pitch + (i0 + a);
+                const long off = (long)I.org + (long)(j0 + b) * pitch + (i0 + a);
                 const double ww = w[b * 4 + a];
                 ap += ww * (double)P[off];
                 au += ww * (double)U[off];
@@ -377,6 +678,10 @@ __global__ __launch_bounds__(256) void k_step_end(const DevInst *__restrict__ in
             I.dft[2 * k] += ap * cs;
             I.dft[2 * k + 1] -= ap * sn;
         }
+    }
+    if (I.has_src && threadIdx.x < 4) {           // stage amplitudes of the next step, FP64
+        const double t = ((double)(step + 1) + I.c_stage[threadIdx.x]) * I.dt;
+        I.amp[threadIdx.x] = I.src_a * sin(I.src_om * t);
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -416,7 +721,7 @@ __global__ void k_init_ic(const DevInst *__restrict__ insts, int ic_kind, double
         u = p * c2;
         v = p * c3;
     }
-    const long off = (long)j * I.pitch + i;
+    const long off = (long)I.org + (long)j * I.pitch + i;
     ((T *)I.f[0][0])[off] = (T)p;
     ((T *)I.f[0][1])[off] = (T)u;
     ((T *)I.f[0][2])[off] = (T)v;
@@ -432,7 +737,7 @@ __global__ void k_sample(const DevInst *__restrict__ insts, const int *__restric
     double acc[3] = {0, 0, 0};
     for (int b = 0; b < 4; ++b)
         for (int a = 0; a < 4; ++a) {
-            const long off = (long)(ij[2 * k + 1] + b) * I.pitch + (ij[2 * k] + a);
+            const long off = (long)I.org + (long)(ij[2 * k + 1] + b) * I.pitch + (ij[2 * k] + a);
             for (int f = 0; f < 3; ++f) acc[f] += w[16 * k + b * 4 + a] * (double)((const T *)I.f[0][f])[off];
         }
     for (int f = 0; f < 3; ++f) out[3 * k + f] = acc[f];
@@ -473,7 +778,59 @@ hipError_t launch_sweep(int prec, int vec, bool filt, int waves, const DevInst *
                 : launch_sweep_w<double, 2, false>(insts, work, nwork, stage, waves, blocks, s);
 }
 
-hipError_t launch_ghost(int prec, const DevInst *insts, const int2 *work, int nwork, int stage, hipStream_t s)
+
+template <typename T, int VEC, bool FILT, int TX, int TY>
+static hipError_t launch_tile_t(const DevInst *insts, const int4 *work, int nwork, int stage, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_tile<T, VEC, FILT, TX, TY>), dim3(nwork), dim3(256), 0, s, insts, work, nwork, stage);
+    return hipGetLastError();
+}
+
+// supported tile shapes (columns x rows)
+template <typename T, int VEC, bool FILT>
+static hipError_t launch_tile_v(int tx, int ty, const DevInst *insts, const int4 *work, int nwork, int stage,
+                                hipStream_t s)
+{
+    constexpr bool F4 = sizeof(T) == 4;
+    if (tx == 128) {
+        if (ty == 4) return launch_tile_t<T, VEC, FILT, 128, 4>(insts, work, nwork, stage, s);
+        if (ty == 8) return launch_tile_t<T, VEC, FILT, 128, 8>(insts, work, nwork, stage, s);
+        if (ty == 16) return launch_tile_t<T, VEC, FILT, 128, 16>(insts, work, nwork, stage, s);
+        if (F4 && ty == 32) return launch_tile_t<T, VEC, FILT, 128, (F4 ? 32 : 16)>(insts, work, nwork, stage, s);
+    } else if (tx == 256) {
+        if (ty == 4) return launch_tile_t<T, VEC, FILT, 256, 4>(insts, work, nwork, stage, s);
+        if (F4 && ty == 8) return launch_tile_t<T, VEC, FILT, 256, (F4 ? 8 : 4)>(insts, work, nwork, stage, s);
+        if (F4 && ty == 16) return launch_tile_t<T, VEC, FILT, 256, (F4 ? 16 : 4)>(insts, work, nwork, stage, s);
+    } else if (tx == 64) {
+        if (ty == 8) return launch_tile_t<T, VEC, FILT, 64, 8>(insts, work, nwork, stage, s);
+        if (ty == 16) return launch_tile_t<T, VEC, FILT, 64, 16>(insts, work, nwork, stage, s);
+        if (ty == 32) return launch_tile_t<T, VEC, FILT, 64, 32>(insts, work, nwork, stage, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+bool tile_shape_supported(int prec, int tx, int ty)
+{
+    const bool f4 = prec == LEE_F32;
+    if (tx == 128) return ty == 4 || ty == 8 || ty == 16 || (f4 && ty == 32);
+    if (tx == 256) return ty == 4 || (f4 && (ty == 8 || ty == 16));
+    if (tx == 64) return ty == 8 || ty == 16 || ty == 32;
+    return false;
+}
+
+hipError_t launch_tile(int prec, bool filt, int tx, int ty, const DevInst *insts, const int4 *work, int nwork,
+                       int stage, int blocks, hipStream_t s)
+{
+    (void)blocks;                                // one workgroup per tile
+    if (nwork <= 0) return hipSuccess;
+    if (prec == LEE_F32)
+        return filt ? launch_tile_v<float, 4, true>(tx, ty, insts, work, nwork, stage, s)
+                    : launch_tile_v<float, 4, false>(tx, ty, insts, work, nwork, stage, s);
+    return filt ? launch_tile_v<double, 2, true>(tx, ty, insts, work, nwork, stage, s)
+                : launch_tile_v<double, 2, false>(tx, ty, insts, work, nwork, stage, s);
+}
+
+hipError_t launch_ghost(int prec, const DevInst *insts, const int4 *work, int nwork, int stage, hipStream_t s)
 {
     if (nwork <= 0) return hipSuccess;
     constexpr int GL = 16;
@@ -534,6 +891,28 @@ hipError_t launch_sample(int prec, const DevInst *insts, const int *ij, const do
         hipLaunchKernelGGL((k_sample<float>), dim3((np + 63) / 64), dim3(64), 0, s, insts, ij, w, np, out);
     else
         hipLaunchKernelGGL((k_sample<double>), dim3((np + 63) / 64), dim3(64), 0, s, insts, ij, w, np, out);
+    return hipGetLastError();
+}
+
+}  // namespace lee
+
+namespace lee {
+
+// plain device copy, 16 bytes per lane per iteration: the reference kernel of
+// known traffic (2 x bytes) for calibrating hardware byte counters and the
+// achievable HBM rate
+__global__ __launch_bounds__(256) void k_copy(const uint4 *__restrict__ src, uint4 *__restrict__ dst, size_t n)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t s)
+{
+    const size_t n = bytes / 16;
+    if (n == 0) return hipSuccess;
+    const int nb = (int)std::min<size_t>((n + 255) / 256, 256 * 64);
+    hipLaunchKernelGGL(k_copy, dim3(nb), dim3(256), 0, s, (const uint4 *)src, (uint4 *)dst, n);
     return hipGetLastError();
 }
 

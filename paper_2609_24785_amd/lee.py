@@ -12,8 +12,16 @@ from typing import Optional, Sequence
 import numpy as np
 
 from . import _lib
-from ._lib import (BatchOpts, CaseDesc, GhostSummary, ImpedanceDesc, LeeError, c_double, c_int64, c_size_t,
-                   c_void_p, check, load)
+from ._lib import (BatchOpts, CaseDesc, GhostSummary, ImpedanceDesc, LeeError, Tiling, c_double, c_int64,
+                   c_size_t, c_void_p, check, load)
+
+
+def make_tiling(kind="tile", vec=0, cols=128, rows=16, waves=1) -> Tiling:
+    """kind "tile" (cols x rows LDS tiles) or "march" (vec, rows, waves)."""
+    t = Tiling()
+    t.kind = _lib.SWEEP_TILE if kind == "tile" else _lib.SWEEP_MARCH
+    t.vec, t.cols, t.rows, t.waves = vec, cols, rows, waves
+    return t
 
 
 def _ptr(a: Optional[np.ndarray]):
@@ -187,8 +195,16 @@ class Instance:
         return dict(ghost_idx=gi, cloud_ptr=cp, cloud_idx=ci, degree=dg, weights=w.reshape(-1, 4),
                     beta=b.reshape(-1, 2), geom=geo.reshape(-1, 5))
 
-    def set_tiling(self, vec: int, rows: int, waves: int = 1):
-        check(self.lib.lee_set_tiling(self._h, vec, rows, waves), "lee_set_tiling")
+    def set_tiling(self, kind="tile", vec=0, cols=128, rows=16, waves=1):
+        t = make_tiling(kind, vec, cols, rows, waves)
+        check(self.lib.lee_set_tiling(self._h, ctypes.byref(t)), "lee_set_tiling")
+
+    def get_tiling(self) -> dict:
+        t = Tiling()
+        check(self.lib.lee_get_tiling(self._h, ctypes.byref(t)), "lee_get_tiling")
+        d = t.as_dict()
+        d["kind"] = "tile" if d["kind"] == _lib.SWEEP_TILE else "march"
+        return d
 
     def time_kernels(self, n: int):
         a, b, c = c_double(), c_double(), c_double()
@@ -211,12 +227,16 @@ class Instance:
 class Batch:
     """Bound instances advanced together: one launch per phase over all members."""
 
-    def __init__(self, members: Sequence[Instance], vec: int = 0, rows: int = 0, waves: int = 0,
-                 persistent_blocks: int = 0):
+    def __init__(self, members: Sequence[Instance], tiling: Optional[dict] = None, persistent_blocks: int = 0):
         self.lib = load()
         self.members = list(members)
         arr = (c_void_p * len(members))(*[m._h.value for m in members])
-        opts = BatchOpts(vec, rows, waves, persistent_blocks)
+        opts = BatchOpts()
+        if tiling is None:
+            opts.tiling.kind = -1
+        else:
+            opts.tiling = make_tiling(**tiling)
+        opts.persistent_blocks = persistent_blocks
         self._h = c_void_p()
         check(self.lib.lee_batch_create(arr, len(members), ctypes.byref(opts), ctypes.byref(self._h)),
               "lee_batch_create")

@@ -1,0 +1,75 @@
+"""GPU batches: members advanced by one launch per phase over all of them.
+
+Every member of a batch runs the same per-node arithmetic as when it runs
+alone, so its fields must be bit-identical to a solo run of the same number
+of steps; per-member budgets let finished members idle.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import lee_cases as lc
+
+pytestmark = pytest.mark.gpu
+
+
+def _lee():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2609_24785_amd.lee import Batch, Instance
+    return Instance, Batch
+
+
+def _members():
+    return [
+        lc.small_cylinder(96, 20),
+        lc.small_cylinder(160, 20).replace(wall=lc.Wall("circle", 0.21, -0.13, rc=0.9),
+                                           impedance=lc.Impedance("msd", R=2.0, M=0.2, K=0.5)),
+        lc.small_cylinder(128, 20, impedance=lc.Impedance("rigid")),
+        lc.flat_wall_201(20),
+        lc.small_cylinder(224, 20).replace(ny=97, y0=-3.5, probes=((2.5, 0.0),)),
+    ]
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_batch_equals_solo_bitwise(prec):
+    Instance, Batch = _lee()
+    cases = _members()
+    print(f"[batch] {len(cases)} members {prec}", flush=True)
+    solo = []
+    for c in cases:
+        i = Instance(c, prec)
+        i.step_n(12)
+        i.synchronize()
+        solo.append(i.fields())
+    mem = [Instance(c, prec) for c in cases]
+    b = Batch(mem)
+    b.step_n(12)
+    for m, ref in zip(mem, solo):
+        m.synchronize()
+        got = m.fields()
+        for x, y in zip(got, ref):
+            assert np.array_equal(x, y)
+
+
+def test_batch_budgets_idle_finished_members():
+    Instance, Batch = _lee()
+    cases = _members()[:3]
+    budgets = [5, 12, 0]
+    solo = []
+    for c, n in zip(cases, budgets):
+        i = Instance(c, "f32")
+        if n:
+            i.step_n(n)
+        i.synchronize()
+        solo.append(i.fields())
+    mem = [Instance(c, "f32") for c in cases]
+    b = Batch(mem, tiling=dict(kind="tile", cols=64, rows=16))
+    b.set_budget(budgets)
+    b.step_n(12)
+    for m, ref in zip(mem, solo):
+        m.synchronize()
+        for x, y in zip(m.fields(), ref):
+            assert np.array_equal(x, y)

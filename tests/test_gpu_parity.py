@@ -35,7 +35,7 @@ def _compare(case, steps, prec, tol, tiling=None):
     _say(f"[parity] {case.name} {case.nx}x{case.ny} steps={steps} prec={prec} tiling={tiling}")
     inst = Instance(case, prec)
     if tiling:
-        inst.set_tiling(*tiling)
+        inst.set_tiling(**tiling)
     inst.step_n(steps)
     inst.synchronize()
     p, u, v = inst.fields()
@@ -64,11 +64,24 @@ def test_small_cylinder_matches_oracle(prec, tol):
     _compare(lc.small_cylinder(96, 60), 60, prec, tol)
 
 
-@pytest.mark.parametrize("tiling", [(2, 4, 1), (2, 16, 2), (4, 8, 4), (4, 64, 1)])
+TILINGS_F32 = [dict(kind="march", vec=2, rows=4, waves=1), dict(kind="march", vec=2, rows=16, waves=2),
+               dict(kind="march", vec=4, rows=8, waves=4), dict(kind="march", vec=4, rows=64, waves=1)] + \
+              [dict(kind="tile", cols=c, rows=r) for c in (64, 128, 256) for r in (4, 8, 16, 32)
+               if not (c == 256 and r == 32) and not (c == 64 and r == 4)]
+TILINGS_F64 = [dict(kind="march", vec=2, rows=8, waves=2), dict(kind="tile", cols=64, rows=8)] + \
+              [dict(kind="tile", cols=128, rows=r) for r in (4, 8, 16)] + [dict(kind="tile", cols=256, rows=4)]
+
+
+@pytest.mark.parametrize("tiling", TILINGS_F32, ids=lambda t: "-".join(str(v) for v in t.values()))
 def test_tilings_agree_fp32(tiling):
     case = lc.small_cylinder(250, 30).replace(ny=203)
-    if tiling[0] == 4 or True:
-        _compare(case, 30, "f32", 1e-4, tiling=tiling)
+    _compare(case, 30, "f32", 1e-4, tiling=tiling)
+
+
+@pytest.mark.parametrize("tiling", TILINGS_F64, ids=lambda t: "-".join(str(v) for v in t.values()))
+def test_tilings_agree_fp64(tiling):
+    case = lc.small_cylinder(250, 30).replace(ny=203)
+    _compare(case, 30, "f64", 1e-9, tiling=tiling)
 
 
 def test_stages_equal_graph_step_bitwise():
