@@ -215,12 +215,15 @@ lee_status lee_export_lists(const lee_instance *inst, int32_t *ghost_idx, int32_
 
 /*
  * Stage-sweep kernel and tile shape.  LEE_SWEEP_TILE: a 256-thread workgroup
- * loads a cols x rows tile plus its halo into LDS and computes it; shapes:
- * FP32 cols 128 or 256 with rows 8, 16 or 32; FP64 cols 128 with rows 4, 8
- * or 16, cols 256 with rows 4 or 8.  LEE_SWEEP_MARCH: each wave marches a
- * strip of 64 vec - 16 columns down `rows` rows (>= 4) keeping an 11-row
- * register window; vec 2 or 4 (FP32), 2 (FP64); waves per workgroup 1, 2
- * or 4.  Other shapes -> LEE_E_ARG.  Invalidates the captured graph.
+ * copies a cols x rows tile plus its 5-point halo into LDS and computes it;
+ * shapes: FP32 cols 64 with rows 8, 16 or 32, cols 128 with rows 4, 8, 16 or
+ * 32, cols 256 with rows 4, 8 or 16; FP64 cols 64 with rows 8, 16 or 32,
+ * cols 128 with rows 4, 8 or 16, cols 256 with rows 4.  Default: cols 64, rows
+ * 16 (FP32) or 8 (FP64).
+ * LEE_SWEEP_MARCH: each wave marches a strip of 64 vec - 16 columns down
+ * `rows` rows (>= 4) keeping an 11-row register window; vec 2 or 4 (FP32),
+ * 2 (FP64); waves per workgroup 1, 2 or 4.  Other shapes -> LEE_E_ARG.
+ * Invalidates the captured graph.
  */
 #define LEE_SWEEP_TILE 0
 #define LEE_SWEEP_MARCH 1

@@ -48,6 +48,7 @@ struct DevInst {
     double alpha_dt[4];     // alpha_l dt
     double c_stage[4];      // stage time offsets c_l (in steps)
     double sponge_s;
+    double sponge_inv;      // 1 / sponge_w
     double src_a, src_b, src_om, src_fx, src_fy;
     double ade[4];
 };

@@ -86,23 +86,25 @@ __global__ __launch_bounds__(256) void k_ghost(const DevInst *__restrict__ insts
     if (gid >= nwork) return;                       // whole GL-lane groups leave together
     const int4 wk = work[gid];                      // instance, ghost, cloud entries [z, w)
     const DevInst &I = insts[wk.x];
-    if (!*gp<int>(I.active)) return;
     const int g = wk.y;
     const int ib = in_buf(stage), ob = out_buf(stage);
     GLOBAL T *P = gp<T>(I.f[ib][0]);
     GLOBAL T *U = gp<T>(I.f[ib][1]);
     GLOBAL T *V = gp<T>(I.f[ib][2]);
+    // independent loads first (member flag, ghost data, ADE states, cloud
+    // offsets and weights); the field values are the only dependent round trip
+    const int active = *gp<int>(I.active);
     const VecT<T, 4> gdv = vld<T, 4>(gp<T>(I.gd) + 4 * (size_t)g);
-    const T *gd = gdv.v;
-    const T nx = gd[0], ny = gd[1];
+    const VecT<T, 2> psv = vld<T, 2>(gp<T>(I.psi[ib]) + 2 * (size_t)g);
+    const VecT<T, 2> psn = vld<T, 2>(gp<T>(I.psi[0]) + 2 * (size_t)g);
     const GLOBAL T *w4 = gp<T>(I.w4);
     const GLOBAL int *coff = gp<int>(I.coff);
+    const int go = gp<int>(I.goff)[g];
+    const T nx = gdv.v[0], ny = gdv.v[1];
     T a0 = 0, aF = 0, aD = 0, aN = 0;
     const int e0 = wk.z, e1 = wk.w;
     constexpr int MAXE = 4;                         // entries per lane per pass
     for (int base = e0; base < e1; base += GL * MAXE) {
-        // all offsets and weights first, then all field values: two dependent
-        // round trips per pass instead of two per entry
         int off[MAXE];
         VecT<T, 4> w[MAXE];
 #pragma unroll
@@ -130,11 +132,10 @@ __global__ __launch_bounds__(256) void k_ghost(const DevInst *__restrict__ insts
         aD += __shfl_xor(aD, m, GL);
         aN += __shfl_xor(aN, m, GL);
     }
-    if (sub != 0) return;
+    if (sub != 0 || !active) return;
     // steps 2-3: ADE derivative, wall normal velocity and its time derivative
     T d1 = 0, d2 = 0, Un = 0, Ud = 0;
-    const GLOBAL T *psi_in = gp<T>(I.psi[ib]);
-    const T s1 = psi_in[2 * g], s2 = psi_in[2 * g + 1];
+    const T s1 = psv.v[0], s2 = psv.v[1];
     if (I.ade_kind == 1) {
         const T a = (T)I.ade[0], b = (T)I.ade[1], c1 = (T)I.ade[2], c2 = (T)I.ade[3];
         d1 = -a * s1 - b * s2 + a0;
@@ -150,19 +151,17 @@ __global__ __launch_bounds__(256) void k_ghost(const DevInst *__restrict__ insts
     }
     // steps 4-5: Neumann for p (dp/dn = +du_n/dt in the wall-to-fluid frame),
     // Dirichlet for u.n (= -u_n), free for u.t
-    const T pg = aN + gd[3] * ((T)I.h * Ud);
-    const T un = aD + gd[2] * (-Un);
+    const T pg = aN + gdv.v[3] * ((T)I.h * Ud);
+    const T un = aD + gdv.v[2] * (-Un);
     const T ut = aF;
-    const int go = gp<int>(I.goff)[g];
     P[go] = pg;
     U[go] = nx * un - ny * ut;
     V[go] = ny * un + nx * ut;
     if (I.ade_kind != 0) {
-        const GLOBAL T *psi_n = gp<T>(I.psi[0]);
         GLOBAL T *psi_out = gp<T>(I.psi[ob]);
         const T adt = (T)I.alpha_dt[stage];
-        psi_out[2 * g] = psi_n[2 * g] + adt * d1;
-        psi_out[2 * g + 1] = psi_n[2 * g + 1] + adt * d2;
+        psi_out[2 * g] = psn.v[0] + adt * d1;
+        psi_out[2 * g + 1] = psn.v[1] + adt * d2;
     }
 }
 
@@ -397,6 +396,18 @@ __global__ __launch_bounds__(64 * WPB) void k_sweep(const DevInst *__restrict__ 
 #define LOCAL
 #endif
 
+typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
+
+// One aligned 16-byte LDS read.  The empty asm keeps all four words live so
+// the compiler cannot split the read into narrower, bank-conflicting pieces.
+template <typename T, int VEC>
+__device__ __forceinline__ VecT<T, VEC> lds16(const T *p)
+{
+    u32x4_t w = *(const u32x4_t *)p;
+    asm volatile("" : "+v"(w));
+    return __builtin_bit_cast(VecT<T, VEC>, w);
+}
+
 // stencil coefficients in the arithmetic precision (FP32 copies are kept in
 // the record so they load straight into scalar registers)
 template <typename T>
@@ -426,10 +437,10 @@ __device__ __forceinline__ void dma16(const void *src, void *lds_wave_base)
 
 // One field's contribution to the right-hand sides of VEC nodes of one row
 // (LDS row y, first LDS column lc): F = 0 (p): -dp/dx -> u, -dp/dy -> v;
-// F = 1 (u): -du/dx -> p; F = 2 (v): -dv/dy -> p; and the filter damping of
-// the field itself, written as sum_k d_k (f_{+k} + f_{-k} - 2 f_0) over both
-// directions (equal to d_0 f_0 + sum_k d_k (f_{+k} + f_{-k}) per direction
-// since d_0 + 2 sum_k d_k = 0, and free of the cancellation of large terms).
+// F = 1 (u): -du/dx -> p; F = 2 (v): -dv/dy -> p; and the selective-filter
+// damping of the field itself, (2 d_0) f_0 + sum_k d_k (f_{+k} + f_{-k})
+// summed over both directions (fd holds these coefficients times sigma/dt).
+// The pair sums and differences of each offset are formed once and shared.
 template <typename T, int VEC, bool FILT, int F, int LW>
 __device__ __forceinline__ void row_field(const T (*lds)[LW], int y, int lc, const T (&ax)[5], const T (&fd)[6],
                                           T (&rp)[VEC], T (&ru)[VEC], T (&rv)[VEC])
@@ -440,7 +451,7 @@ __device__ __forceinline__ void row_field(const T (*lds)[LW], int y, int lc, con
     T yw[11][VEC];
 #pragma unroll
     for (int k = 0; k < 11; ++k) {
-        const VecT<T, VEC> a = *(const VecT<T, VEC> *)&lds[y - 5 + k][lc];
+        const VecT<T, VEC> a = lds16<T, VEC>(&lds[y - 5 + k][lc]);
 #pragma unroll
         for (int e = 0; e < VEC; ++e) yw[k][e] = a.v[e];
     }
@@ -448,7 +459,12 @@ __device__ __forceinline__ void row_field(const T (*lds)[LW], int y, int lc, con
     if (F != 2 || FILT) {
 #pragma unroll
         for (int k = -KM; k <= KP; ++k) {
-            const VecT<T, VEC> a = *(const VecT<T, VEC> *)&lds[y][lc + k * VEC];
+            if (k == 0) {                        // the centre chunk is the y window's
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) xw[KM * VEC + e] = yw[5][e];
+                continue;
+            }
+            const VecT<T, VEC> a = lds16<T, VEC>(&lds[y][lc + k * VEC]);
 #pragma unroll
             for (int e = 0; e < VEC; ++e) xw[(k + KM) * VEC + e] = a.v[e];
         }
@@ -456,29 +472,25 @@ __device__ __forceinline__ void row_field(const T (*lds)[LW], int y, int lc, con
 #pragma unroll
     for (int e = 0; e < VEC; ++e) {
         const int x = KM * VEC + e;
-        if (F != 1) {
-            T dy = 0;
+        T dy = 0, dx = 0, fl = FILT ? fd[0] * yw[5][e] : (T)0;
 #pragma unroll
-            for (int k = 1; k <= 5; ++k) dy += ax[k - 1] * (yw[5 + k][e] - yw[5 - k][e]);
-            if (F == 0) rv[e] -= dy;
-            else rp[e] -= dy;
+        for (int k = 1; k <= 5; ++k) {
+            const T yp = yw[5 + k][e], ym = yw[5 - k][e];
+            const T xp = xw[x + k], xm = xw[x - k];
+            if (F != 1) dy += ax[k - 1] * (yp - ym);
+            if (F != 2) dx += ax[k - 1] * (xp - xm);
+            if (FILT) fl += fd[k] * ((xp + xm) + (yp + ym));
         }
-        if (F != 2) {
-            T dx = 0;
-#pragma unroll
-            for (int k = 1; k <= 5; ++k) dx += ax[k - 1] * (xw[x + k] - xw[x - k]);
-            if (F == 0) ru[e] -= dx;
-            else rp[e] -= dx;
-        }
-        if (FILT) {
-            const T c2 = yw[5][e] + yw[5][e];
-            T fl = 0;
-#pragma unroll
-            for (int k = 1; k <= 5; ++k)
-                fl += fd[k] * (((xw[x + k] + xw[x - k]) - c2) + ((yw[5 + k][e] + yw[5 - k][e]) - c2));
-            if (F == 0) rp[e] -= fl;
-            else if (F == 1) ru[e] -= fl;
-            else rv[e] -= fl;
+        if (F == 0) {
+            rv[e] -= dy;
+            ru[e] -= dx;
+            if (FILT) rp[e] -= fl;
+        } else if (F == 1) {
+            rp[e] -= dx;
+            if (FILT) ru[e] -= fl;
+        } else {
+            rp[e] -= dy;
+            if (FILT) rv[e] -= fl;
         }
     }
 }
@@ -507,8 +519,8 @@ __global__ __launch_bounds__(256) void k_tile(const DevInst *__restrict__ insts,
     constexpr int QCW = TX / VEC;                // chunks per q^n row
     constexpr int NQ = TY * QCW;                 // chunks per field (q^n block)
     static_assert(sizeof(T) * VEC == 16, "16-byte chunks");
-    __shared__ T lds[3][R][LW];
-    __shared__ T ldn[3][TY][TX];
+    __shared__ alignas(16) T lds[3][R][LW];
+    __shared__ alignas(16) T ldn[3][TY][TX];
     const int w = blockIdx.x;
     if (w >= nwork) return;
     const int4 wk = work[w];
@@ -554,6 +566,9 @@ __global__ __launch_bounds__(256) void k_tile(const DevInst *__restrict__ insts,
     coefs<T>(I, ax, fd);
     const T adt = (T)I.alpha_dt[stage];
     const int sw = I.sponge_w;
+    // the sponge band and the source box are tested once per tile
+    const bool in_sponge = sw > 0 && (c0 < sw || r0 < sw || c0 + TX > I.nx - sw || r1 > I.ny - sw);
+    const T sp_inv = (T)I.sponge_inv, sp_s = (T)I.sponge_s;
     const bool has_src = I.has_src && !(I.src_i1 < c0 || I.src_i0 >= c0 + TX) && !(I.src_j1 < r0 || I.src_j0 >= r1);
     const T amp = has_src ? (T)gp<double>(I.amp)[stage] : (T)0;
     GLOBAL T *Po = gp<T>(I.f[ob][0]);
@@ -598,11 +613,11 @@ __global__ __launch_bounds__(256) void k_tile(const DevInst *__restrict__ insts,
 #pragma unroll
         for (int e = 0; e < VEC; ++e) {
             const int col = gc + e;
-            if (sw > 0) {
+            if (in_sponge) {
                 const int eg = min(min(col, j), min(I.nx - 1 - col, I.ny - 1 - j));
                 if (eg < sw) {
-                    const T fr = (T)(sw - eg) / (T)sw;
-                    const T sg = (T)I.sponge_s * fr * fr;
+                    const T fr = (T)(sw - eg) * sp_inv;
+                    const T sg = sp_s * fr * fr;
                     rp[e] -= sg * pc.v[e];
                     ru[e] -= sg * uc.v[e];
                     rv[e] -= sg * vc.v[e];
@@ -817,6 +832,7 @@ bool tile_shape_supported(int prec, int tx, int ty)
     if (tx == 64) return ty == 8 || ty == 16 || ty == 32;
     return false;
 }
+
 
 hipError_t launch_tile(int prec, bool filt, int tx, int ty, const DevInst *insts, const int4 *work, int nwork,
                        int stage, int blocks, hipStream_t s)

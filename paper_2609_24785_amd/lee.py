@@ -16,10 +16,13 @@ from ._lib import (BatchOpts, CaseDesc, GhostSummary, ImpedanceDesc, LeeError, T
                    c_size_t, c_void_p, check, load)
 
 
+KINDS = {"tile": _lib.SWEEP_TILE, "march": _lib.SWEEP_MARCH}
+
+
 def make_tiling(kind="tile", vec=0, cols=128, rows=16, waves=1) -> Tiling:
     """kind "tile" (cols x rows LDS tiles) or "march" (vec, rows, waves)."""
     t = Tiling()
-    t.kind = _lib.SWEEP_TILE if kind == "tile" else _lib.SWEEP_MARCH
+    t.kind = KINDS[kind]
     t.vec, t.cols, t.rows, t.waves = vec, cols, rows, waves
     return t
 
@@ -203,7 +206,7 @@ class Instance:
         t = Tiling()
         check(self.lib.lee_get_tiling(self._h, ctypes.byref(t)), "lee_get_tiling")
         d = t.as_dict()
-        d["kind"] = "tile" if d["kind"] == _lib.SWEEP_TILE else "march"
+        d["kind"] = {v: k for k, v in KINDS.items()}[d["kind"]]
         return d
 
     def time_kernels(self, n: int):

@@ -136,3 +136,5 @@ def test_unbound_calls_are_state_errors():
     for t in (make_tiling("march", vec=2, rows=16), make_tiling("tile", cols=256, rows=4)):
         assert lib.lee_set_tiling(inst._h, ctypes.byref(t)) == 0
     assert inst.get_tiling()["cols"] == 256
+    inst.set_tiling("march", vec=2, rows=8, waves=2)
+    assert inst.get_tiling()["kind"] == "march"
