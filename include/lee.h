@@ -219,11 +219,14 @@ lee_status lee_export_lists(const lee_instance *inst, int32_t *ghost_idx, int32_
  * shapes: FP32 cols 64 with rows 8, 16 or 32, cols 128 with rows 4, 8, 16 or
  * 32, cols 256 with rows 4, 8 or 16; FP64 cols 64 with rows 8, 16 or 32,
  * cols 128 with rows 4, 8 or 16, cols 256 with rows 4.  Default: cols 64, rows
- * 16 (FP32) or 8 (FP64).
+ * 16 (FP32) or 8 (FP64), not fused.
  * LEE_SWEEP_MARCH: each wave marches a strip of 64 vec - 16 columns down
  * `rows` rows (>= 4) keeping an 11-row register window; vec 2 or 4 (FP32),
  * 2 (FP64); waves per workgroup 1, 2 or 4.  Other shapes -> LEE_E_ARG.
- * Invalidates the captured graph.
+ * Invalidates the captured graph.  With `fused`, the ghost fill of a stage runs
+ * in the first workgroups of the sweep launch, and only the tiles whose
+ * stencils read ghost nodes wait for it; the results are bit-for-bit those
+ * of the two-launch form.
  */
 #define LEE_SWEEP_TILE 0
 #define LEE_SWEEP_MARCH 1
@@ -233,6 +236,8 @@ typedef struct {
     int32_t cols;            /* tile: columns per tile */
     int32_t rows;            /* rows per tile / per march */
     int32_t waves;           /* march: waves per workgroup */
+    int32_t fused;           /* tile: 1 = a stage's ghost fill and sweep in one launch,
+                                0 = two launches (the default); march: ignored */
 } lee_tiling;
 
 lee_status lee_set_tiling(lee_instance *inst, const lee_tiling *t);
@@ -250,6 +255,12 @@ lee_status lee_time_kernels(lee_instance *inst, int64_t n, double *sweep_us, dou
  * 16-byte aligned buffers) on hip_stream.  Its traffic is exactly 2 x bytes,
  * which calibrates hardware byte counters and the achievable HBM rate. */
 lee_status lee_stream_copy(void *dst, const void *src, size_t bytes, void *hip_stream);
+
+/* Wait for the instance's stream.  LEE_E_DEVICE if a fused stage's wait for
+ * its ghost fill ran out of polls (the results of that stage are then not
+ * valid; this does not happen while the device dispatches workgroups in
+ * order).  lee_get_fields and lee_get_step report the same condition. */
+lee_status lee_synchronize(lee_instance *inst);
 
 /* Free host structures and device-side objects the library created (graph,
  * events); the bound device memory stays the caller's. */
@@ -280,6 +291,9 @@ lee_status lee_batch_set_budget(lee_batch *b, const int64_t *steps);
 
 /* n steps of every member with a positive budget; asynchronous. */
 lee_status lee_batch_step_n(lee_batch *b, int64_t n);
+
+/* Wait for the batch's stream; LEE_E_DEVICE as for lee_synchronize. */
+lee_status lee_batch_synchronize(lee_batch *b);
 
 /* Synchronising: mean per-launch sweep and ghost durations over n eager steps. */
 lee_status lee_batch_time_kernels(lee_batch *b, int64_t n, double *sweep_us, double *ghost_us,

@@ -3,13 +3,12 @@ equations with a normal-stencil ghost-point immersed boundary and a
 mass-spring-damper ADE impedance wall.
 
 The compute path is liblee.so (HIP kernels for gfx950 behind the C ABI of
-include/lee.h); this package only marshals arguments.  Importing it loads the
-library and fails loudly if it has not been built.
+include/lee.h); this package only marshals arguments.  The library is loaded
+on first use (creating an Instance or Batch, or calling _lib.load()), which
+fails loudly if it has not been built.  Importing the package does not load
+it, so that the build module can run while an outdated library is present.
 """
-from ._lib import LeeError, load as _load
-
-_load()
-
-from .lee import Batch, Instance  # noqa: E402
+from ._lib import LeeError
+from .lee import Batch, Instance
 
 __all__ = ["Instance", "Batch", "LeeError"]

@@ -43,7 +43,8 @@ SWEEP_TILE, SWEEP_MARCH = 0, 1
 
 
 class Tiling(ctypes.Structure):
-    _fields_ = [("kind", c_int32), ("vec", c_int32), ("cols", c_int32), ("rows", c_int32), ("waves", c_int32)]
+    _fields_ = [("kind", c_int32), ("vec", c_int32), ("cols", c_int32), ("rows", c_int32), ("waves", c_int32),
+                ("fused", c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -77,6 +78,8 @@ SIGNATURES = {
     "lee_time_kernels": (c_int32, [c_void_p, c_int64, ctypes.POINTER(c_double), ctypes.POINTER(c_double),
                                    ctypes.POINTER(c_double)]),
     "lee_stream_copy": (c_int32, [c_void_p, c_void_p, c_size_t, c_void_p]),
+    "lee_synchronize": (c_int32, [c_void_p]),
+    "lee_batch_synchronize": (c_int32, [c_void_p]),
     "lee_destroy": (None, [c_void_p]),
     "lee_batch_create": (c_int32, [ctypes.POINTER(c_void_p), c_int32, ctypes.POINTER(BatchOpts),
                                    ctypes.POINTER(c_void_p)]),

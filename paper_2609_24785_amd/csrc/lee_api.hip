@@ -30,6 +30,7 @@ struct lee_instance {
     int nwork1 = 0;
     int4 *d_work2 = nullptr;
     int nwork2 = 0;
+    int *d_sync = nullptr;          // fused-stage counters and error flag
     int *d_sij = nullptr;
     double *d_sw = nullptr, *d_sout = nullptr;
     // host staging kept alive for asynchronous uploads
@@ -72,7 +73,7 @@ size_t work1_capacity(const Host &h)
 
 struct Layout {
     size_t inst, planes[9], psi[3], iv, goff, cptr, coff, w4, gd, counters, amp, pij, pw, trace, dft, work1, work2,
-        sij, sw, sout, total;
+        sync, sij, sw, sout, total;
 };
 
 Layout layout(const Host &h)
@@ -103,6 +104,7 @@ Layout layout(const Host &h)
     L.dft = take(2 * std::max(h.np, 1) * 8);
     L.work1 = take(work1_capacity(h) * sizeof(int4));
     L.work2 = take(std::max<size_t>(G, 1) * sizeof(int4));
+    L.sync = take(SYNC_INTS * sizeof(int));
     L.sij = take(2 * SAMPLE_MAX * 4);
     L.sw = take(16 * SAMPLE_MAX * 8);
     L.sout = take(3 * SAMPLE_MAX * 8);
@@ -140,7 +142,7 @@ void xcd_order(const std::vector<int4> &items, int per_unit, std::vector<int4> &
 
 bool tiling_valid(int prec, const lee_tiling &t)
 {
-    if (t.kind == LEE_SWEEP_TILE) return tile_shape_supported(prec, t.cols, t.rows);
+    if (t.kind == LEE_SWEEP_TILE) return (t.fused == 0 || t.fused == 1) && tile_shape_supported(prec, t.cols, t.rows);
     if (t.kind == LEE_SWEEP_MARCH) {
         const bool f32 = prec == LEE_F32;
         if (!((f32 && (t.vec == 2 || t.vec == 4)) || (!f32 && t.vec == 2))) return false;
@@ -150,7 +152,8 @@ bool tiling_valid(int prec, const lee_tiling &t)
 }
 
 // Built-in choice: the 2-D tile kernel with the shape measured fastest on
-// MI355X at both 1024^2 and 4096^2 (64 columns; 16 rows FP32, 8 rows FP64).
+// MI355X at both 1024^2 and 4096^2 (64 columns; 16 rows FP32, 8 rows FP64),
+// ghost fill and sweep in two launches.
 lee_tiling default_tiling_for(int prec, int nx, int ny)
 {
     (void)nx;
@@ -161,6 +164,7 @@ lee_tiling default_tiling_for(int prec, int nx, int ny)
     t.vec = prec == LEE_F32 ? 4 : 2;
     t.waves = 1;
     t.rows = prec == LEE_F32 ? 16 : 8;
+    t.fused = 0;                                 // measured: fused wins only for FP64 on small grids
     return t;
 }
 
@@ -181,6 +185,19 @@ void build_work1(const Host &h, int inst_id, const lee_tiling &t, std::vector<in
     const int rows = t.rows;
     const int strips = (h.d.nx + ow - 1) / ow;
     const int tiles = (h.d.ny + rows - 1) / rows;
+    // fused tile sweep: flag the tiles whose read region (the tile and H = 5
+    // nodes around it) holds a ghost node
+    std::vector<char> dep;
+    if (t.kind == LEE_SWEEP_TILE && t.fused) {
+        dep.assign((size_t)strips * tiles, 0);
+        for (int g : h.gidx) {
+            const int gi = g % h.d.nx, gj = g / h.d.nx;
+            for (int r = std::max(0, (gj - 5) / rows - 1); r < tiles && r * rows - 5 <= gj; ++r)
+                if (gj < r * rows + rows + 5)
+                    for (int s = std::max(0, (gi - 5) / ow - 1); s < strips && s * ow - 5 <= gi; ++s)
+                        if (gi < s * ow + ow + 5) dep[(size_t)r * strips + s] = 1;
+        }
+    }
     std::vector<int4> items;
     for (int r = 0; r < tiles; ++r) {
         const int r0 = r * rows, r1 = std::min(r0 + rows, h.d.ny);
@@ -193,7 +210,8 @@ void build_work1(const Host &h, int inst_id, const lee_tiling &t, std::vector<in
                     if (iv[2 * q] < iv[2 * q + 1] && iv[2 * q] < c1 && iv[2 * q + 1] > c0) any = true;
             }
             if (!any) continue;
-            items.push_back(make_int4(inst_id, c0, r0, (r & 1) ? -r1 : r1));
+            const int flag = !dep.empty() && dep[(size_t)r * strips + s] ? TILE_DEP_BIT : 0;
+            items.push_back(make_int4(inst_id | flag, c0, r0, (r & 1) ? -r1 : r1));
         }
     }
     if (!xcd) {
@@ -229,15 +247,49 @@ hipError_t sweep(int prec, bool filt, const lee_tiling &t, const DevInst *insts,
     return launch_sweep(prec, t.vec, filt, t.waves, insts, work, nwork, stage, blocks, s);
 }
 
-hipError_t issue_stage(lee_instance *I, int stage)
+bool fused(const lee_tiling &t) { return t.kind == LEE_SWEEP_TILE && t.fused; }
+
+// The ghost fill and sweep of one stage: one fused launch, or two launches.
+// Events, when given, bracket the ghost launch (g0, g1) and the sweep or
+// fused launch (s0, s1).
+hipError_t stage_launches(int prec, bool filt, const lee_tiling &t, const DevInst *insts, const int4 *work1,
+                          int nwork1, const int4 *work2, int nwork2, int *sync, int stage, int blocks, hipStream_t s,
+                          hipEvent_t *ev = nullptr)
+{
+    hipError_t e = hipSuccess;
+    if (ev) hipEventRecord(ev[0], s);
+    if (!fused(t)) e = launch_ghost(prec, insts, work2, nwork2, stage, s);
+    if (ev) {
+        hipEventRecord(ev[1], s);
+        hipEventRecord(ev[2], s);
+    }
+    if (e != hipSuccess) return e;
+    if (fused(t))
+        e = launch_stage(prec, filt, t.cols, t.rows, insts, work1, nwork1, work2, nwork2, stage, sync, SPIN_LIMIT, s);
+    else
+        e = sweep(prec, filt, t, insts, work1, nwork1, stage, blocks, s);
+    if (ev) hipEventRecord(ev[3], s);
+    return e;
+}
+
+hipError_t issue_stage(lee_instance *I, int stage, hipEvent_t *ev = nullptr)
 {
     const int prec = I->host.d.precision;
-    hipError_t e = launch_ghost(prec, I->d_inst, I->d_work2, I->nwork2, stage, I->stream);
-    if (e != hipSuccess) return e;
-    e = sweep(prec, I->host.d.filter_sigma > 0.0, I->tl, I->d_inst, I->d_work1, I->nwork1, stage, 0, I->stream);
+    hipError_t e = stage_launches(prec, I->host.d.filter_sigma > 0.0, I->tl, I->d_inst, I->d_work1, I->nwork1,
+                                  I->d_work2, I->nwork2, I->d_sync, stage, 0, I->stream, ev);
     if (e != hipSuccess) return e;
     if (stage == 3) e = launch_step_end(prec, I->d_inst, 1, I->stream);
     return e;
+}
+
+// Waits for the stream and reports a fused stage whose ghost wait ran out.
+lee_status check_sync(const int *d_sync, hipStream_t s)
+{
+    int flag = 0;
+    HIPCHK(hipMemcpyAsync(&flag, d_sync + 4, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (flag) return fail(LEE_E_DEVICE, "a fused stage stopped waiting for its ghost fill (spin limit)");
+    return LEE_OK;
 }
 
 template <typename T>
@@ -446,6 +498,7 @@ lee_status lee_bind(lee_instance *I, void *dev_ptr, size_t bytes, void *hip_stre
     for (size_t g = 0; g < G; ++g) I->up_work2[g] = make_int4(0, (int)g, h.cptr[g], h.cptr[g + 1]);
     I->nwork2 = (int)G;
     if (G) HIPCHK(hipMemcpyAsync(I->d_work2, I->up_work2.data(), G * sizeof(int4), hipMemcpyHostToDevice, s));
+    I->d_sync = (int *)(b + L.sync);
     I->d_sij = (int *)(b + L.sij);
     I->d_sw = (double *)(b + L.sw);
     I->d_sout = (double *)(b + L.sout);
@@ -466,6 +519,7 @@ lee_status lee_init_fields(lee_instance *I)
     for (int k = 0; k < 3; ++k) HIPCHK(launch_fill(prec, I->base + L.psi[k], 2 * std::max<size_t>(h.gidx.size(), 1), s));
     HIPCHK(launch_fill_bytes(I->base + L.trace, std::max<size_t>((size_t)h.trace_cap * h.np * 3, 1) * 8, s));
     HIPCHK(launch_fill_bytes(I->base + L.dft, 2 * std::max(h.np, 1) * 8, s));
+    HIPCHK(launch_fill_bytes(I->base + L.sync, SYNC_INTS * sizeof(int), s));
     I->up_counters[0] = 0;
     I->up_counters[1] = LLONG_MAX;
     I->up_counters[2] = 1;   // active flag lives in the low word of the third slot
@@ -543,7 +597,14 @@ lee_status lee_get_step(const lee_instance *I, int64_t *step)
 {
     if (!I || !step) return fail(LEE_E_ARG, "null argument");
     *step = I->steps_issued;
+    if (I->bound) return check_sync(I->d_sync, I->stream);
     return LEE_OK;
+}
+
+lee_status lee_synchronize(lee_instance *I)
+{
+    if (!I || !I->bound) return fail(LEE_E_STATE, "instance not bound");
+    return check_sync(I->d_sync, I->stream);
 }
 
 }  // extern "C"
@@ -589,7 +650,7 @@ lee_status lee_get_fields(lee_instance *I, double *p, double *u, double *v)
                                                       : copy_plane_out<double>(I, 0, f, o[f]);
         if (s != LEE_OK) return s;
     }
-    return LEE_OK;
+    return check_sync(I->d_sync, I->stream);
 }
 
 lee_status lee_set_fields(lee_instance *I, const double *p, const double *u, const double *v)
@@ -722,14 +783,7 @@ lee_status lee_time_kernels(lee_instance *I, int64_t n, double *sweep_us, double
         hipEventRecord(ev[CH * 16], I->stream);
         for (int k = 0; k < m; ++k)
             for (int l = 0; l < 4; ++l) {
-                hipEvent_t *e = &ev[(k * 4 + l) * 4];
-                hipEventRecord(e[0], I->stream);
-                launch_ghost(prec, I->d_inst, I->d_work2, I->nwork2, l, I->stream);
-                hipEventRecord(e[1], I->stream);
-                hipEventRecord(e[2], I->stream);
-                sweep(prec, I->host.d.filter_sigma > 0.0, I->tl, I->d_inst, I->d_work1, I->nwork1, l, 0, I->stream);
-                hipEventRecord(e[3], I->stream);
-                if (l == 3) launch_step_end(prec, I->d_inst, 1, I->stream);
+                issue_stage(I, l, &ev[(k * 4 + l) * 4]);
             }
         hipEventRecord(ev[CH * 16 + 1], I->stream);
         hipError_t e = hipEventSynchronize(ev[CH * 16 + 1]);
@@ -791,6 +845,7 @@ struct lee_batch {
     int nwork1 = 0;
     int4 *d_work2 = nullptr;
     int nwork2 = 0;
+    int *d_sync = nullptr;
     std::vector<DevInst> up_table;
     std::vector<int4> up_work1;
     std::vector<int4> up_work2;
@@ -809,14 +864,13 @@ void batch_drop_graph(lee_batch *B)
     B->graph = nullptr;
 }
 
-hipError_t batch_issue_stage(lee_batch *B, int stage)
+hipError_t batch_issue_stage(lee_batch *B, int stage, hipEvent_t *ev = nullptr)
 {
-    hipError_t e = launch_ghost(B->prec, B->d_table, B->d_work2, B->nwork2, stage, B->stream);
-    if (e != hipSuccess) return e;
     int blocks = 0;
     const int per = B->tl.kind == LEE_SWEEP_MARCH ? B->tl.waves : 1;
     if (B->pblocks > 0) blocks = std::min(B->pblocks, (B->nwork1 + per - 1) / per);
-    e = sweep(B->prec, B->filt, B->tl, B->d_table, B->d_work1, B->nwork1, stage, blocks, B->stream);
+    hipError_t e = stage_launches(B->prec, B->filt, B->tl, B->d_table, B->d_work1, B->nwork1, B->d_work2, B->nwork2,
+                                  B->d_sync, stage, blocks, B->stream, ev);
     if (e != hipSuccess) return e;
     if (stage == 3) e = launch_step_end(B->prec, B->d_table, (int)B->members.size(), B->stream);
     return e;
@@ -828,6 +882,8 @@ void batch_free(lee_batch *B)
     if (B->d_table) hipFree(B->d_table);
     if (B->d_work1) hipFree(B->d_work1);
     if (B->d_work2) hipFree(B->d_work2);
+    if (B->d_sync) hipFree(B->d_sync);
+    B->d_sync = nullptr;
     B->d_table = nullptr;
     B->d_work1 = nullptr;
     B->d_work2 = nullptr;
@@ -879,6 +935,8 @@ lee_status lee_batch_create(lee_instance *const *v, int32_t n, const lee_batch_o
     e = hipMalloc(&B->d_table, n * sizeof(DevInst));
     if (e == hipSuccess) e = hipMalloc(&B->d_work1, std::max<size_t>(B->up_work1.size(), 1) * sizeof(int4));
     if (e == hipSuccess) e = hipMalloc(&B->d_work2, std::max<size_t>(B->up_work2.size(), 1) * sizeof(int4));
+    if (e == hipSuccess) e = hipMalloc(&B->d_sync, SYNC_INTS * sizeof(int));
+    if (e == hipSuccess) e = launch_fill_bytes(B->d_sync, SYNC_INTS * sizeof(int), B->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(B->d_table, B->up_table.data(), n * sizeof(DevInst), hipMemcpyHostToDevice, B->stream);
     if (e == hipSuccess && B->nwork1)
@@ -951,22 +1009,12 @@ lee_status lee_batch_time_kernels(lee_batch *B, int64_t n, double *sweep_us, dou
     double tsw = 0, tgh = 0, tstep = 0;
     int64_t done = 0;
     lee_status st = LEE_OK;
-    int blocks = 0;
-    const int per = B->tl.kind == LEE_SWEEP_MARCH ? B->tl.waves : 1;
-    if (B->pblocks > 0) blocks = std::min(B->pblocks, (B->nwork1 + per - 1) / per);
     while (done < n) {
         const int m = (int)std::min<int64_t>(CH, n - done);
         hipEventRecord(ev[CH * 16], B->stream);
         for (int k = 0; k < m; ++k)
             for (int l = 0; l < 4; ++l) {
-                hipEvent_t *e = &ev[(k * 4 + l) * 4];
-                hipEventRecord(e[0], B->stream);
-                launch_ghost(B->prec, B->d_table, B->d_work2, B->nwork2, l, B->stream);
-                hipEventRecord(e[1], B->stream);
-                hipEventRecord(e[2], B->stream);
-                sweep(B->prec, B->filt, B->tl, B->d_table, B->d_work1, B->nwork1, l, blocks, B->stream);
-                hipEventRecord(e[3], B->stream);
-                if (l == 3) launch_step_end(B->prec, B->d_table, (int)B->members.size(), B->stream);
+                batch_issue_stage(B, l, &ev[(k * 4 + l) * 4]);
             }
         hipEventRecord(ev[CH * 16 + 1], B->stream);
         hipError_t e = hipEventSynchronize(ev[CH * 16 + 1]);
@@ -993,6 +1041,12 @@ lee_status lee_batch_time_kernels(lee_batch *B, int64_t n, double *sweep_us, dou
     if (ghost_us) *ghost_us = 1000.0 * tgh / (4.0 * n);
     if (step_us) *step_us = 1000.0 * tstep / n;
     return LEE_OK;
+}
+
+lee_status lee_batch_synchronize(lee_batch *B)
+{
+    if (!B) return fail(LEE_E_ARG, "null batch");
+    return check_sync(B->d_sync, B->stream);
 }
 
 void lee_batch_destroy(lee_batch *B)

@@ -58,6 +58,14 @@ hipError_t launch_sweep(int prec, int vec, bool filt, int waves, const DevInst *
 bool tile_shape_supported(int prec, int tx, int ty);
 hipError_t launch_tile(int prec, bool filt, int tx, int ty, const DevInst *insts, const int4 *work, int nwork,
                        int stage, int blocks, hipStream_t s);
+// One launch for a stage with the tile sweep: ghost workgroups first, then
+// the tiles (items flagged with DEP_BIT wait for the ghosts).  sync holds 4
+// stage counters and an error flag (5 ints, zero before first use).
+hipError_t launch_stage(int prec, bool filt, int tx, int ty, const DevInst *insts, const int4 *work1, int nwork1,
+                        const int4 *work2, int nwork2, int stage, int *sync, int spin_limit, hipStream_t s);
+constexpr int TILE_DEP_BIT = 1 << 30;
+constexpr int SYNC_INTS = 8;
+constexpr int SPIN_LIMIT = 1 << 20;             // polls before a ghost wait gives up (about a second)
 hipError_t launch_ghost(int prec, const DevInst *insts, const int4 *work, int nwork, int stage, hipStream_t s);
 hipError_t launch_step_end(int prec, const DevInst *insts, int ninst, hipStream_t s);
 hipError_t launch_fill(int prec, void *p, size_t n, hipStream_t s);

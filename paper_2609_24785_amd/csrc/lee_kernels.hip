@@ -77,12 +77,11 @@ __device__ __forceinline__ int out_buf(int stage) { return stage == 0 ? 1 : (sta
 // ---------------------------------------------------------------------------
 // ghost fill + ADE
 
+// One ghost per GL-lane group (gid); sub is the lane within the group.
 template <typename T, int GL>
-__global__ __launch_bounds__(256) void k_ghost(const DevInst *__restrict__ insts,
-                                               const int4 *__restrict__ work, int nwork, int stage)
+__device__ __forceinline__ void ghost_item(const DevInst *__restrict__ insts, const int4 *__restrict__ work,
+                                           int nwork, int gid, int sub, int stage)
 {
-    const int gid = (int)((blockIdx.x * blockDim.x + threadIdx.x) / GL);
-    const int sub = (int)(threadIdx.x % GL);
     if (gid >= nwork) return;                       // whole GL-lane groups leave together
     const int4 wk = work[gid];                      // instance, ghost, cloud entries [z, w)
     const DevInst &I = insts[wk.x];
@@ -163,6 +162,14 @@ __global__ __launch_bounds__(256) void k_ghost(const DevInst *__restrict__ insts
         psi_out[2 * g] = psn.v[0] + adt * d1;
         psi_out[2 * g + 1] = psn.v[1] + adt * d2;
     }
+}
+
+template <typename T, int GL>
+__global__ __launch_bounds__(256) void k_ghost(const DevInst *__restrict__ insts,
+                                               const int4 *__restrict__ work, int nwork, int stage)
+{
+    ghost_item<T, GL>(insts, work, nwork, (int)((blockIdx.x * blockDim.x + threadIdx.x) / GL),
+                      (int)(threadIdx.x % GL), stage);
 }
 
 // ---------------------------------------------------------------------------
@@ -504,9 +511,9 @@ __device__ __forceinline__ void pin_sums(T (&rp)[VEC], T (&ru)[VEC], T (&rv)[VEC
     for (int e = 0; e < VEC; ++e) asm volatile("" : "+v"(rp[e]), "+v"(ru[e]), "+v"(rv[e])::"memory");
 }
 
+// One tile: wk = {instance, first column, first row, +-(end row)}.
 template <typename T, int VEC, bool FILT, int TX, int TY>
-__global__ __launch_bounds__(256) void k_tile(const DevInst *__restrict__ insts, const int4 *__restrict__ work,
-                                              int nwork, int stage)
+__device__ __forceinline__ void tile_body(const DevInst *__restrict__ insts, const int4 wk, int stage)
 {
     constexpr int NT = 256;
     constexpr int NCX = TX / VEC;                // column groups
@@ -521,10 +528,6 @@ __global__ __launch_bounds__(256) void k_tile(const DevInst *__restrict__ insts,
     static_assert(sizeof(T) * VEC == 16, "16-byte chunks");
     __shared__ alignas(16) T lds[3][R][LW];
     __shared__ alignas(16) T ldn[3][TY][TX];
-    const int w = blockIdx.x;
-    if (w >= nwork) return;
-    const int4 wk = work[w];
-    if (wk.x < 0) return;                        // idle slot of the XCD-aware order
     const DevInst &I = insts[wk.x];
     if (!*gp<int>(I.active)) return;
     const int tid = threadIdx.x;
@@ -649,6 +652,70 @@ __global__ __launch_bounds__(256) void k_tile(const DevInst *__restrict__ insts,
                 }
         }
     }
+}
+
+// Work items of the tile sweep: x = instance | DEP_BIT when the tile's read
+// region holds ghost nodes, -1 for an idle slot of the XCD-aware order.
+constexpr int DEP_BIT = TILE_DEP_BIT;
+
+template <typename T, int VEC, bool FILT, int TX, int TY>
+__global__ __launch_bounds__(256) void k_tile(const DevInst *__restrict__ insts, const int4 *__restrict__ work,
+                                              int nwork, int stage)
+{
+    const int w = blockIdx.x;
+    if (w >= nwork) return;
+    int4 wk = work[w];
+    if (wk.x < 0) return;
+    wk.x &= DEP_BIT - 1;
+    tile_body<T, VEC, FILT, TX, TY>(insts, wk, stage);
+}
+
+// One stage in one launch: ghost fill and ADE update (the first ngb
+// workgroups, 256 / GL ghosts each), then the tile sweep (the rest).  Tiles
+// whose read region holds no ghost node start at once; the others wait until
+// every ghost workgroup has published its writes (release/acquire on an
+// agent-scope counter).  Ghost workgroups have the lowest ids, so they are
+// dispatched no later than any tile that waits for them; the wait is bounded
+// by spin_limit polls all the same, and a wait that runs out raises the
+// error flag sync[4] instead of hanging.  sync[stage] counts finished ghost
+// workgroups; block 0 clears the previous stage's counter, whose launch has
+// completed.
+template <typename T, int VEC, bool FILT, int TX, int TY, int GL>
+__global__ __launch_bounds__(256) void k_stage(const DevInst *__restrict__ insts, const int4 *__restrict__ work1,
+                                               int nwork1, const int4 *__restrict__ work2, int nwork2, int ngb,
+                                               int stage, int *sync, int spin_limit)
+{
+    const int tid = threadIdx.x;
+    if (blockIdx.x == 0 && tid == 0)
+        __hip_atomic_store(&sync[(stage + 3) & 3], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if ((int)blockIdx.x < ngb) {
+        ghost_item<T, GL>(insts, work2, nwork2, (int)blockIdx.x * (256 / GL) + tid / GL, tid % GL, stage);
+        __syncthreads();
+        if (tid == 0) __hip_atomic_fetch_add(&sync[stage], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        return;
+    }
+    const int w = (int)blockIdx.x - ngb;
+    if (w >= nwork1) return;
+    int4 wk = work1[w];
+    if (wk.x < 0) return;
+    if (wk.x & DEP_BIT) {
+        if (tid == 0) {
+            // relaxed polls (an acquire load would invalidate this XCD's L2
+            // on every poll), then one acquire fence for the ghost writes
+            int polls = 0;
+            while (__hip_atomic_load(&sync[stage], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < ngb) {
+                if (++polls > spin_limit) {
+                    __hip_atomic_fetch_or(&sync[4], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+        __syncthreads();
+        wk.x &= DEP_BIT - 1;
+    }
+    tile_body<T, VEC, FILT, TX, TY>(insts, wk, stage);
 }
 
 // ---------------------------------------------------------------------------
@@ -794,32 +861,50 @@ hipError_t launch_sweep(int prec, int vec, bool filt, int waves, const DevInst *
 }
 
 
+constexpr int GHOST_LANES = 16;                  // lanes per ghost
+
+// Fused launch arguments (the ghost part); ngb == 0 launches the plain sweep.
+struct FuseArgs {
+    const int4 *work2;
+    int nwork2;
+    int *sync;
+    int spin_limit;
+};
+
 template <typename T, int VEC, bool FILT, int TX, int TY>
-static hipError_t launch_tile_t(const DevInst *insts, const int4 *work, int nwork, int stage, hipStream_t s)
+static hipError_t launch_tile_t(const DevInst *insts, const int4 *work, int nwork, int stage, const FuseArgs *fa,
+                                hipStream_t s)
 {
-    hipLaunchKernelGGL((k_tile<T, VEC, FILT, TX, TY>), dim3(nwork), dim3(256), 0, s, insts, work, nwork, stage);
+    if (!fa) {
+        hipLaunchKernelGGL((k_tile<T, VEC, FILT, TX, TY>), dim3(nwork), dim3(256), 0, s, insts, work, nwork, stage);
+    } else {
+        // ghost workgroups first, rounded to 8 so the tiles keep their XCD order
+        const int ngb = ((fa->nwork2 * GHOST_LANES + 255) / 256 + 7) / 8 * 8;
+        hipLaunchKernelGGL((k_stage<T, VEC, FILT, TX, TY, GHOST_LANES>), dim3(ngb + nwork), dim3(256), 0, s, insts,
+                           work, nwork, fa->work2, fa->nwork2, ngb, stage, fa->sync, fa->spin_limit);
+    }
     return hipGetLastError();
 }
 
 // supported tile shapes (columns x rows)
 template <typename T, int VEC, bool FILT>
 static hipError_t launch_tile_v(int tx, int ty, const DevInst *insts, const int4 *work, int nwork, int stage,
-                                hipStream_t s)
+                                const FuseArgs *fa, hipStream_t s)
 {
     constexpr bool F4 = sizeof(T) == 4;
     if (tx == 128) {
-        if (ty == 4) return launch_tile_t<T, VEC, FILT, 128, 4>(insts, work, nwork, stage, s);
-        if (ty == 8) return launch_tile_t<T, VEC, FILT, 128, 8>(insts, work, nwork, stage, s);
-        if (ty == 16) return launch_tile_t<T, VEC, FILT, 128, 16>(insts, work, nwork, stage, s);
-        if (F4 && ty == 32) return launch_tile_t<T, VEC, FILT, 128, (F4 ? 32 : 16)>(insts, work, nwork, stage, s);
+        if (ty == 4) return launch_tile_t<T, VEC, FILT, 128, 4>(insts, work, nwork, stage, fa, s);
+        if (ty == 8) return launch_tile_t<T, VEC, FILT, 128, 8>(insts, work, nwork, stage, fa, s);
+        if (ty == 16) return launch_tile_t<T, VEC, FILT, 128, 16>(insts, work, nwork, stage, fa, s);
+        if (F4 && ty == 32) return launch_tile_t<T, VEC, FILT, 128, (F4 ? 32 : 16)>(insts, work, nwork, stage, fa, s);
     } else if (tx == 256) {
-        if (ty == 4) return launch_tile_t<T, VEC, FILT, 256, 4>(insts, work, nwork, stage, s);
-        if (F4 && ty == 8) return launch_tile_t<T, VEC, FILT, 256, (F4 ? 8 : 4)>(insts, work, nwork, stage, s);
-        if (F4 && ty == 16) return launch_tile_t<T, VEC, FILT, 256, (F4 ? 16 : 4)>(insts, work, nwork, stage, s);
+        if (ty == 4) return launch_tile_t<T, VEC, FILT, 256, 4>(insts, work, nwork, stage, fa, s);
+        if (F4 && ty == 8) return launch_tile_t<T, VEC, FILT, 256, (F4 ? 8 : 4)>(insts, work, nwork, stage, fa, s);
+        if (F4 && ty == 16) return launch_tile_t<T, VEC, FILT, 256, (F4 ? 16 : 4)>(insts, work, nwork, stage, fa, s);
     } else if (tx == 64) {
-        if (ty == 8) return launch_tile_t<T, VEC, FILT, 64, 8>(insts, work, nwork, stage, s);
-        if (ty == 16) return launch_tile_t<T, VEC, FILT, 64, 16>(insts, work, nwork, stage, s);
-        if (ty == 32) return launch_tile_t<T, VEC, FILT, 64, 32>(insts, work, nwork, stage, s);
+        if (ty == 8) return launch_tile_t<T, VEC, FILT, 64, 8>(insts, work, nwork, stage, fa, s);
+        if (ty == 16) return launch_tile_t<T, VEC, FILT, 64, 16>(insts, work, nwork, stage, fa, s);
+        if (ty == 32) return launch_tile_t<T, VEC, FILT, 64, 32>(insts, work, nwork, stage, fa, s);
     }
     return hipErrorInvalidValue;
 }
@@ -840,16 +925,28 @@ hipError_t launch_tile(int prec, bool filt, int tx, int ty, const DevInst *insts
     (void)blocks;                                // one workgroup per tile
     if (nwork <= 0) return hipSuccess;
     if (prec == LEE_F32)
-        return filt ? launch_tile_v<float, 4, true>(tx, ty, insts, work, nwork, stage, s)
-                    : launch_tile_v<float, 4, false>(tx, ty, insts, work, nwork, stage, s);
-    return filt ? launch_tile_v<double, 2, true>(tx, ty, insts, work, nwork, stage, s)
-                : launch_tile_v<double, 2, false>(tx, ty, insts, work, nwork, stage, s);
+        return filt ? launch_tile_v<float, 4, true>(tx, ty, insts, work, nwork, stage, nullptr, s)
+                    : launch_tile_v<float, 4, false>(tx, ty, insts, work, nwork, stage, nullptr, s);
+    return filt ? launch_tile_v<double, 2, true>(tx, ty, insts, work, nwork, stage, nullptr, s)
+                : launch_tile_v<double, 2, false>(tx, ty, insts, work, nwork, stage, nullptr, s);
+}
+
+hipError_t launch_stage(int prec, bool filt, int tx, int ty, const DevInst *insts, const int4 *work1, int nwork1,
+                        const int4 *work2, int nwork2, int stage, int *sync, int spin_limit, hipStream_t s)
+{
+    if (nwork2 <= 0) return launch_tile(prec, filt, tx, ty, insts, work1, nwork1, stage, 0, s);
+    const FuseArgs fa{work2, nwork2, sync, spin_limit};
+    if (prec == LEE_F32)
+        return filt ? launch_tile_v<float, 4, true>(tx, ty, insts, work1, nwork1, stage, &fa, s)
+                    : launch_tile_v<float, 4, false>(tx, ty, insts, work1, nwork1, stage, &fa, s);
+    return filt ? launch_tile_v<double, 2, true>(tx, ty, insts, work1, nwork1, stage, &fa, s)
+                : launch_tile_v<double, 2, false>(tx, ty, insts, work1, nwork1, stage, &fa, s);
 }
 
 hipError_t launch_ghost(int prec, const DevInst *insts, const int4 *work, int nwork, int stage, hipStream_t s)
 {
     if (nwork <= 0) return hipSuccess;
-    constexpr int GL = 16;
+    constexpr int GL = GHOST_LANES;
     const int nb = (nwork * GL + 255) / 256;
     if (prec == LEE_F32)
         hipLaunchKernelGGL((k_ghost<float, GL>), dim3(nb), dim3(256), 0, s, insts, work, nwork, stage);

@@ -19,11 +19,12 @@ from ._lib import (BatchOpts, CaseDesc, GhostSummary, ImpedanceDesc, LeeError, T
 KINDS = {"tile": _lib.SWEEP_TILE, "march": _lib.SWEEP_MARCH}
 
 
-def make_tiling(kind="tile", vec=0, cols=128, rows=16, waves=1) -> Tiling:
-    """kind "tile" (cols x rows LDS tiles) or "march" (vec, rows, waves)."""
+def make_tiling(kind="tile", vec=0, cols=64, rows=16, waves=1, fused=0) -> Tiling:
+    """kind "tile" (cols x rows LDS tiles; fused: ghost fill in the same
+    launch) or "march" (vec, rows, waves)."""
     t = Tiling()
     t.kind = KINDS[kind]
-    t.vec, t.cols, t.rows, t.waves = vec, cols, rows, waves
+    t.vec, t.cols, t.rows, t.waves, t.fused = vec, cols, rows, waves, fused
     return t
 
 
@@ -134,7 +135,8 @@ class Instance:
         check(self.lib.lee_step_n(self._h, n), "lee_step_n")
 
     def synchronize(self):
-        self.stream.synchronize()
+        """Wait for the stream; raises if a fused stage's ghost wait ran out."""
+        check(self.lib.lee_synchronize(self._h), "lee_synchronize")
 
     # ---- outputs ------------------------------------------------------------
     def fields(self):
@@ -198,8 +200,8 @@ class Instance:
         return dict(ghost_idx=gi, cloud_ptr=cp, cloud_idx=ci, degree=dg, weights=w.reshape(-1, 4),
                     beta=b.reshape(-1, 2), geom=geo.reshape(-1, 5))
 
-    def set_tiling(self, kind="tile", vec=0, cols=128, rows=16, waves=1):
-        t = make_tiling(kind, vec, cols, rows, waves)
+    def set_tiling(self, kind="tile", vec=0, cols=64, rows=16, waves=1, fused=0):
+        t = make_tiling(kind, vec, cols, rows, waves, fused)
         check(self.lib.lee_set_tiling(self._h, ctypes.byref(t)), "lee_set_tiling")
 
     def get_tiling(self) -> dict:
@@ -250,6 +252,9 @@ class Batch:
 
     def step_n(self, n: int):
         check(self.lib.lee_batch_step_n(self._h, n), "lee_batch_step_n")
+
+    def synchronize(self):
+        check(self.lib.lee_batch_synchronize(self._h), "lee_batch_synchronize")
 
     def time_kernels(self, n: int):
         a, b, c = c_double(), c_double(), c_double()

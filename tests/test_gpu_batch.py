@@ -33,20 +33,24 @@ def _members():
     ]
 
 
-@pytest.mark.parametrize("prec", ["f32", "f64"])
-def test_batch_equals_solo_bitwise(prec):
+@pytest.mark.parametrize("prec,fused", [("f32", 1), ("f64", 1), ("f32", 0)])
+def test_batch_equals_solo_bitwise(prec, fused):
+    """Solo members run the two-launch stage; the batch runs fused or not."""
     Instance, Batch = _lee()
     cases = _members()
-    print(f"[batch] {len(cases)} members {prec}", flush=True)
+    print(f"[batch] {len(cases)} members {prec} fused={fused}", flush=True)
+    rows = 16 if prec == "f32" else 8
     solo = []
     for c in cases:
         i = Instance(c, prec)
+        i.set_tiling("tile", cols=64, rows=rows, fused=0)
         i.step_n(12)
         i.synchronize()
         solo.append(i.fields())
     mem = [Instance(c, prec) for c in cases]
-    b = Batch(mem)
+    b = Batch(mem, tiling=dict(kind="tile", cols=64, rows=rows, fused=fused))
     b.step_n(12)
+    b.synchronize()
     for m, ref in zip(mem, solo):
         m.synchronize()
         got = m.fields()

@@ -64,7 +64,7 @@ def test_small_cylinder_matches_oracle(prec, tol):
     _compare(lc.small_cylinder(96, 60), 60, prec, tol)
 
 
-TILINGS_F32 = [dict(kind="march", vec=2, rows=4, waves=1), dict(kind="march", vec=2, rows=16, waves=2),
+TILINGS_F32 = [dict(kind="tile", cols=64, rows=16, fused=0), dict(kind="march", vec=2, rows=4, waves=1), dict(kind="march", vec=2, rows=16, waves=2),
                dict(kind="march", vec=4, rows=8, waves=4), dict(kind="march", vec=4, rows=64, waves=1)] + \
               [dict(kind="tile", cols=c, rows=r) for c in (64, 128, 256) for r in (4, 8, 16, 32)
                if not (c == 256 and r == 32) and not (c == 64 and r == 4)]
@@ -82,6 +82,29 @@ def test_tilings_agree_fp32(tiling):
 def test_tilings_agree_fp64(tiling):
     case = lc.small_cylinder(250, 30).replace(ny=203)
     _compare(case, 30, "f64", 1e-9, tiling=tiling)
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_fused_stage_equals_two_launches_bitwise(prec):
+    """The fused launch (ghost workgroups first, dependent tiles waiting) gives
+    the same bits as a ghost launch followed by a sweep launch."""
+    Instance, _ = _lee()
+    rows = 16 if prec == "f32" else 8
+    for case in (lc.small_cylinder(160, 20), lc.flat_wall_201(20), lc.cylinder_pulse_1024(20)):
+        _say(f"[fused] {case.name} {case.nx}x{case.ny} {prec}")
+        a = Instance(case, prec)
+        b = Instance(case, prec)
+        a.set_tiling("tile", cols=64, rows=rows, fused=1)
+        b.set_tiling("tile", cols=64, rows=rows, fused=0)
+        a.step_n(20)
+        b.step_n(20)
+        a.synchronize()
+        b.synchronize()
+        for x, y in zip(a.fields(), b.fields()):
+            assert np.array_equal(x, y)
+        assert np.array_equal(a.ade_states(), b.ade_states())
+        if case.probes:
+            assert np.array_equal(a.traces(), b.traces())
 
 
 def test_stages_equal_graph_step_bitwise():
