@@ -1,30 +1,37 @@
 #!/usr/bin/env python3
 """Throughput of the LEE + ghost-point IBM + ADE stage on one MI355X.
 
-Metric: fluid grid-point Runge-Kutta stage updates per second, FP32 (the
-reported value) and FP64, with the FP32 result's relative L2 error against
-the FP64 oracle on the same workload.  Workload: the cylinder reflecting a
-pulse on a 1024^2 grid (16/1024 spacing, r_c = 0.5, impedance (0.5, 0.02,
-10), 11-point DRP + 11-point filter).  A "step" is one full RK4 time step:
-four stages, each a ghost fill + ADE launch and a stage-sweep launch, plus
-the step-end probe kernel, replayed from a captured hipGraph.
+Metric: fluid grid-point Runge-Kutta stage updates per second.  The reported
+value is FP32; FP64 is reported beside it, with the FP32 result's relative L2
+error against the FP64 oracle and against the FP64 GPU run.
 
-Roofline: the stage sweep dominates (>99% of bytes).  Its algorithmic traffic
-per launch is the average over the four stages of (stage 1: read q^n,
-write q^(1): 24 B; stages 2-4: read q^n and q^(l-1), write q^(l): 36 B) per
-fluid node = 33 B (FP32), divided by the launch duration measured with HIP
-events on the library's stream.
+Workload: the cylinder reflecting a pulse on a 1024^2 grid (h = 1/64 on
+[-8, 8)^2, r_c = 0.5, impedance (R, m, k) = (0.5, 0.02, 10), 11-point DRP and
+11-point filter, LSRK4 at CFL 0.5, 8 probes on r = 5).  A step is one full
+RK4 time step (four stages of ghost fill + ADE update and stage sweep, then
+the step-end probe kernel), replayed from a captured hipGraph.  Inputs are
+resident in HBM when the timed region starts.
 
-Also reported: FP64 throughput, the batched workload (uneven instances in
-one launch per phase) when --batch is given, and the oracle on the host
-cores over a bounded sample of the same workload.
+Roofline: the stage sweep moves more than 98% of the bytes.  Its algorithmic
+traffic per launch is the mean over the four stages of 24 B (stage 1: read
+q^n, write q^(1)) and 36 B (stages 2-4: read q^n and q^(l-1), write q^(l))
+per fluid node, 33 B in FP32, divided by the mean launch time measured with
+HIP events on the library's stream over back-to-back launches.
+
+Also reported: the flat-wall case (201^2, FP64) against the oracle, the
+monopole case (4096^2) throughput in both precisions, and the oracle on the
+host cores over a bounded sample of the benchmark workload.
+
+Other modes: --profile-run (a short fixed sequence for rocprofv3), and
+--counters FETCH_CSV WRITE_CSV (turns two rocprofv3 --pmc counter files of
+the profile run into the sweep's HBM traffic per launch, calibrated by the
+copy kernel of known size the profile run ends with).
 """
 from __future__ import annotations
 
 import argparse
 import hashlib
 import json
-import math
 import os
 import sys
 import time
@@ -35,6 +42,9 @@ sys.path.insert(0, HERE)
 METRIC = "grid-pt RK-stage updates/s FP32 vs FP64 at 1e-4 rel L2; p50/p99 solve latency"
 UNIT = "grid-pt RK-stage updates/s"
 HBM_PEAK_GBS = 8000.0
+BYTES_PER_NODE_STAGE = {"f32": (24.0 + 3 * 36.0) / 4.0, "f64": (48.0 + 3 * 72.0) / 4.0}
+COUNTERS_JSON = os.path.join(HERE, "profiles", "sweep_counters.json")
+COPY_BYTES = 1 << 28                     # the profile run's calibration copy (256 MiB)
 
 
 def _kernel_hash() -> str:
@@ -42,17 +52,71 @@ def _kernel_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def _traffic(bytes_alg_per_launch: float):
-    """HBM bytes per sweep launch from the committed counter summary, if it was
-    taken on the current kernel source."""
-    path = os.path.join(HERE, "profiles", "sweep_counters.json")
-    if not os.path.exists(path):
+def _traffic(kernel: str):
+    """HBM bytes per sweep launch from the committed counter summary, when it
+    was taken on the current kernel source and the same kernel instance."""
+    if not os.path.exists(COUNTERS_JSON):
         return None
-    with open(path) as f:
+    with open(COUNTERS_JSON) as f:
         d = json.load(f)
-    if d.get("kernel_sha") != _kernel_hash():
+    if d.get("kernel_sha") != _kernel_hash() or d.get("kernel") != kernel:
         return None
     return d.get("hbm_bytes_per_launch")
+
+
+def _kernel_name(tiling: dict, prec: str) -> str:
+    t = "float, 4" if prec == "f32" else "double, 2"
+    if tiling["kind"] == "tile":
+        k = "k_stage" if tiling.get("fused") else "k_tile"
+        extra = ", 16" if tiling.get("fused") else ""
+        return f"lee::{k}<{t}, true, {tiling['cols']}, {tiling['rows']}{extra}>"
+    return f"lee::k_sweep<{t.split(',')[0]}, {tiling['vec']}, true, {tiling['waves']}>"
+
+
+def _timed(case, prec: str, steps: int, warmup: int):
+    """Graph-replayed steps of one instance; returns the rate and the instance."""
+    import torch
+    from paper_2609_24785_amd.lee import Instance
+
+    inst = Instance(case, prec, trace_capacity=max(steps + warmup, 1))
+    inst.step_n(warmup)
+    inst.synchronize()
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(inst.stream):
+        ev0.record()
+    t0 = time.perf_counter()
+    inst.step_n(steps)
+    with torch.cuda.stream(inst.stream):
+        ev1.record()
+    inst.synchronize()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    fluid = inst.summary.fluid_nodes
+    return dict(inst=inst, wall=wall, gpu_ms=ev0.elapsed_time(ev1), steps=steps, fluid=fluid,
+                value=fluid * 4.0 * steps / wall)
+
+
+def _kernel_times(case, prec: str, n: int):
+    """Mean per-launch times of the sweep and ghost kernels (back-to-back
+    launches on the library's stream, one event pair per kernel kind)."""
+    from paper_2609_24785_amd.lee import Instance
+
+    inst = Instance(case, prec, trace_capacity=1)
+    inst.time_kernels(2)                                  # warm the code objects
+    sweep_us, ghost_us, step_us = inst.time_kernels(n)
+    tiling = inst.get_tiling()
+    fluid = inst.summary.fluid_nodes
+    ghosts = inst.summary.G
+    inst.close()
+    return dict(sweep_us=sweep_us, ghost_us=ghost_us, eager_step_us=step_us, tiling=tiling, fluid=fluid,
+                ghosts=ghosts, kernel=_kernel_name(tiling, prec))
+
+
+def _max_rel_l2(a, b, mask):
+    from oracle.solver import relative_l2
+    return max(relative_l2(x, y, mask) for x, y in zip(a, b))
 
 
 def run(args):
@@ -60,126 +124,136 @@ def run(args):
     import torch
 
     import lee_cases as lc
-    from paper_2609_24785_amd.lee import Instance
 
     if not torch.cuda.is_available():
         print(json.dumps({"metric": METRIC, "error": "no GPU visible"}))
         return 1
     torch.cuda.set_device(0)
     case = lc.cylinder_pulse_1024(steps=args.steps)
-    total = args.warmup + args.steps + args.kernel_steps
-    res = {}
-    insts = {}
-    for prec in ("f32", "f64"):
-        inst = Instance(case, prec, trace_capacity=max(total, 1))
-        insts[prec] = inst
-        fluid = inst.summary.fluid_nodes
-        inst.step_n(args.warmup)
-        inst.synchronize()
-        steps = args.steps if prec == "f32" else args.steps
-        torch.cuda.synchronize()
-        ev0 = torch.cuda.Event(enable_timing=True)
-        ev1 = torch.cuda.Event(enable_timing=True)
-        with torch.cuda.stream(inst.stream):
-            ev0.record()
-        t0 = time.perf_counter()
-        inst.step_n(steps)
-        with torch.cuda.stream(inst.stream):
-            ev1.record()
-        inst.synchronize()
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        wall = t1 - t0
-        gpu_ms = ev0.elapsed_time(ev1)
-        # per-launch durations of the sweep and ghost kernels (HIP events on the
-        # library's stream around every launch)
-        sweep_us, ghost_us, eager_step_us = inst.time_kernels(args.kernel_steps)
-        res[prec] = dict(wall=wall, gpu_ms=gpu_ms, steps=steps, fluid=fluid, sweep_us=sweep_us,
-                         ghost_us=ghost_us, eager_step_us=eager_step_us,
-                         value=fluid * 4.0 * steps / wall)
-    p32 = insts["f32"].fields()
-    p64 = insts["f64"].fields()
-    import oracle.solver as osv   # CPU baseline and error reference (test infrastructure)
+    print(f"[bench] {case.name}: {args.steps} steps after {args.warmup} warm-up, FP32 then FP64",
+          file=sys.stderr, flush=True)
+    r32 = _timed(case, "f32", args.steps, args.warmup)
+    r64 = _timed(case, "f64", args.steps, args.warmup)
+    print("[bench] kernel timing", file=sys.stderr, flush=True)
+    k32 = _kernel_times(case, "f32", args.kernel_steps)
+    k64 = _kernel_times(case, "f64", args.kernel_steps)
+
+    import oracle.solver as osv          # error reference and CPU baseline (test infrastructure)
     from oracle.geometry import fluid_mask
     mask = fluid_mask(case)
-    rel_32_64 = max(osv.relative_l2(a, b, mask) for a, b in zip(p32, p64))
+    f32 = r32["inst"].fields()
+    f64 = r64["inst"].fields()
+    rel_32_64 = _max_rel_l2(f32, f64, mask)
+    # error relative to the size of the initial pulse (the field decays as the
+    # pulse leaves the 1024^2 window; see the design notes)
+    p64 = f64[0]
+    init_norm = float(np.sqrt(np.sum((case.ic.a * np.exp(-np.log(2.0) * (
+        (case.x0 + case.h * np.arange(case.nx))[None, :] - case.ic.xs) ** 2 / case.ic.w ** 2
+        - np.log(2.0) * ((case.y0 + case.h * np.arange(case.ny))[:, None] - case.ic.ys) ** 2
+        / case.ic.w ** 2))[mask] ** 2)))
+    abs_32_64 = float(np.sqrt(np.sum((f32[0] - p64)[mask] ** 2))) / init_norm
 
-    r = res["f32"]
-    esz = 4
-    bytes_per_node = (24.0 + 3 * 36.0) / 4.0          # average over the four stages (FP32)
-    alg_bytes = bytes_per_node * r["fluid"]
-    achieved = alg_bytes / (r["sweep_us"] * 1e-6) / 1e9
+    bpn = BYTES_PER_NODE_STAGE["f32"]
+    alg_bytes = bpn * k32["fluid"]
+    achieved = alg_bytes / (k32["sweep_us"] * 1e-6) / 1e9
+    ach64 = BYTES_PER_NODE_STAGE["f64"] * k64["fluid"] / (k64["sweep_us"] * 1e-6) / 1e9
+    traffic = _traffic(k32["kernel"])
     out = {
         "metric": METRIC,
-        "value": r["value"],
+        "value": r32["value"],
         "unit": UNIT,
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1000.0 * r["wall"] / r["steps"],
+        "ms_per_step": 1000.0 * r32["wall"] / r32["steps"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": "cylinder-pulse 1024x1024, dx=1/64 on [-8,8)^2, r_c=0.5 shifted (0.3h,0.3h), "
-                        "Gaussian pulse (4,0) a=1e-3 w=0.2, MSD R=0.5 m=0.02 k=10, 11-pt DRP + 11-pt filter "
-                        "sigma=0.2, LSRK4 CFL 0.5, 8 probes on r=5",
+            "workload": "cylinder-pulse 1024x1024, h=1/64 on [-8,8)^2, r_c=0.5 centred (0.3h,0.3h), Gaussian "
+                        "pulse (4,0) a=1e-3 w=0.2, MSD R=0.5 m=0.02 k=10, 11-pt DRP + 11-pt filter sigma=0.2, "
+                        "LSRK4 CFL 0.5, 8 probes on r=5",
             "grid": [case.nx, case.ny],
-            "fluid_nodes": r["fluid"],
-            "ghosts": int(insts["f32"].summary.G),
-            "stages_per_step": 4,
-            "launch": "hipGraph per step: 4 x (ghost fill+ADE, stage sweep) + step end",
+            "fluid_nodes": r32["fluid"],
+            "ghosts": int(r32["inst"].summary.G),
+            "tiling_f32": k32["tiling"],
+            "tiling_f64": k64["tiling"],
+            "launch": "hipGraph per step: 4 x (ghost fill + ADE, stage sweep) + step end",
         },
-        "fp64_value": res["f64"]["value"],
+        "fp64_value": r64["value"],
+        "fp64_ms_per_step": 1000.0 * r64["wall"] / r64["steps"],
         "fp32_vs_fp64_rel_l2": rel_32_64,
-        "gpu_event_ms_per_step": r["gpu_ms"] / r["steps"],
-        "kernels_us": {"sweep_f32": r["sweep_us"], "ghost_f32": r["ghost_us"],
-                       "sweep_f64": res["f64"]["sweep_us"], "ghost_f64": res["f64"]["ghost_us"],
-                       "eager_step_f32": r["eager_step_us"]},
+        "fp32_vs_fp64_err_over_initial_norm": abs_32_64,
+        "gpu_event_ms_per_step": r32["gpu_ms"] / r32["steps"],
+        "kernels_us": {"sweep_f32": k32["sweep_us"], "ghost_f32": k32["ghost_us"],
+                       "sweep_f64": k64["sweep_us"], "ghost_f64": k64["ghost_us"],
+                       "eager_step_f32": k32["eager_step_us"], "eager_step_f64": k64["eager_step_us"]},
         "roofline": {
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": _traffic(alg_bytes),
-            "kernel": "k_sweep<float,4,filter,1>",
+            "traffic": traffic,
+            "kernel": k32["kernel"],
             "alg_bytes_per_launch": alg_bytes,
+            "launch_us": k32["sweep_us"],
         },
+        "roofline_f64": {"kernel": k64["kernel"], "achieved": ach64, "frac": ach64 / HBM_PEAK_GBS,
+                         "launch_us": k64["sweep_us"]},
     }
-    # FP64 roofline of the same kernel (66 B per node-stage)
-    out["roofline_f64_frac"] = (2 * alg_bytes / (res["f64"]["sweep_us"] * 1e-6) / 1e9) / HBM_PEAK_GBS
+    r32["inst"].close()
+    r64["inst"].close()
+
+    if not args.quick:
+        print("[bench] flat wall 201^2 FP64 against the oracle", file=sys.stderr, flush=True)
+        flat = lc.flat_wall_201(500)
+        rf = _timed(flat, "f64", 500, 0)
+        s = osv.OracleSolver(flat)
+        s.run(500)
+        out["flat_wall_201_f64"] = {"value": rf["value"], "steps": 500,
+                                    "rel_l2_vs_oracle": _max_rel_l2(rf["inst"].fields(), s.fields(), s.fluid)}
+        rf["inst"].close()
+        print("[bench] monopole 4096^2", file=sys.stderr, flush=True)
+        mono = lc.monopole_4096(args.mono_steps)
+        mres = {}
+        for prec in ("f32", "f64"):
+            rm = _timed(mono, prec, args.mono_steps, 10)
+            mres[prec] = {"value": rm["value"], "ms_per_step": 1000.0 * rm["wall"] / rm["steps"],
+                          "fluid_nodes": rm["fluid"]}
+            rm["inst"].close()
+            torch.cuda.empty_cache()
+        out["monopole_4096"] = dict(steps=args.mono_steps, **mres)
 
     if not args.no_cpu_baseline:
+        print(f"[bench] oracle on the host: {args.cpu_steps} steps", file=sys.stderr, flush=True)
         nthreads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
         s = osv.OracleSolver(case)
         t0 = time.perf_counter()
         s.run(args.cpu_steps)
         t1 = time.perf_counter()
-        cpu_rate = r["fluid"] * 4.0 * args.cpu_steps / (t1 - t0)
-        # the FP32 GPU path on the same sample, against the oracle
-        g = Instance(case, "f32")
+        cpu_rate = r32["fluid"] * 4.0 * args.cpu_steps / (t1 - t0)
+        from paper_2609_24785_amd.lee import Instance
+        g = Instance(case, "f32", trace_capacity=1)
         g.step_n(args.cpu_steps)
         g.synchronize()
-        gf = g.fields()
-        of = s.fields()
-        rel = max(osv.relative_l2(a, b, mask) for a, b in zip(gf, of))
         out["cpu_baseline"] = {
             "value": cpu_rate, "unit": UNIT, "cores": nthreads, "kind": "oracle",
-            "sample": f"same workload, first {args.cpu_steps} steps, FP64 C core with OpenMP over rows, "
-                      f"stepping loop only ({t1 - t0:.1f} s)",
+            "sample": f"the benchmark workload's first {args.cpu_steps} steps (FP64 C core, OpenMP over rows, "
+                      f"stepping loop only, {t1 - t0:.1f} s)",
         }
-        out["fp32_vs_oracle_rel_l2"] = rel
+        out["fp32_vs_oracle_rel_l2"] = _max_rel_l2(g.fields(), s.fields(), mask)
         out["fp32_vs_oracle_steps"] = args.cpu_steps
+        g.close()
     print(json.dumps(out), flush=True)
     return 0
 
 
 def profile_run(args):
-    """A short fixed sequence for hardware profilers: the benchmark workload for
-    a few steps (graph replay, FP32), then a copy of known size."""
+    """A short fixed sequence for hardware profilers: the benchmark workload
+    (FP32, graph replay), then three copies of COPY_BYTES bytes."""
     import torch
 
     import lee_cases as lc
@@ -191,15 +265,61 @@ def profile_run(args):
     inst = Instance(case, "f32", trace_capacity=args.steps + args.warmup)
     inst.step_n(args.warmup + args.steps)
     inst.synchronize()
-    nbytes = 1 << 30
-    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
-    b = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    a = torch.empty(COPY_BYTES, dtype=torch.uint8, device="cuda")
+    b = torch.empty(COPY_BYTES, dtype=torch.uint8, device="cuda")
     s = torch.cuda.current_stream()
     for _ in range(3):
-        _lib.check(_lib.load().lee_stream_copy(a.data_ptr(), b.data_ptr(), nbytes, s.cuda_stream), "copy")
+        _lib.check(_lib.load().lee_stream_copy(a.data_ptr(), b.data_ptr(), COPY_BYTES, s.cuda_stream), "copy")
     torch.cuda.synchronize()
-    print(json.dumps({"profile_run": True, "steps": args.steps + args.warmup, "copy_bytes": nbytes,
-                      "fluid_nodes": inst.summary.fluid_nodes}), flush=True)
+    print(json.dumps({"profile_run": True, "steps": args.steps + args.warmup, "copy_bytes": COPY_BYTES,
+                      "fluid_nodes": inst.summary.fluid_nodes, "tiling": inst.get_tiling(),
+                      "kernel": _kernel_name(inst.get_tiling(), "f32")}), flush=True)
+    return 0
+
+
+def counters(args):
+    """Sweep traffic per launch from two rocprofv3 --pmc runs of --profile-run
+    (FETCH_SIZE, WRITE_SIZE in KiB per dispatch), each scaled so that the copy
+    kernel of known size reads as COPY_BYTES fetched and COPY_BYTES written."""
+    import csv
+
+    import lee_cases as lc
+
+    def per_kernel(path, counter):
+        sums, counts = {}, {}
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                if r["Counter_Name"] != counter:
+                    continue
+                k = r["Kernel_Name"]
+                sums[k] = sums.get(k, 0.0) + float(r["Counter_Value"])
+                counts[k] = counts.get(k, 0) + 1
+        return {k: (sums[k] / counts[k], counts[k]) for k in sums}
+
+    fetch = per_kernel(args.counters[0], "FETCH_SIZE")
+    write = per_kernel(args.counters[1], "WRITE_SIZE")
+    copy_name = next(k for k in fetch if "k_copy" in k)
+    sweep_name = next(k for k in fetch if "k_tile<float, 4, true" in k or "k_stage<float, 4, true" in k)
+    kib = 1024.0
+    fetch_scale = COPY_BYTES / (fetch[copy_name][0] * kib)
+    write_scale = COPY_BYTES / (write[copy_name][0] * kib)
+    fb = fetch[sweep_name][0] * kib * fetch_scale
+    wb = write[sweep_name][0] * kib * write_scale
+    case = lc.cylinder_pulse_1024(10)
+    from paper_2609_24785_amd.lee import Instance
+    inst = Instance(case, "f32", bind=False)
+    fluid = inst.summary.fluid_nodes
+    alg = BYTES_PER_NODE_STAGE["f32"] * fluid
+    short = sweep_name.split("(")[0].replace("void ", "")
+    d = {"kernel": short, "kernel_sha": _kernel_hash(), "dispatches": fetch[sweep_name][1],
+         "fetch_kib_per_dispatch": fetch[sweep_name][0], "write_kib_per_dispatch": write[sweep_name][0],
+         "copy_fetch_kib": fetch[copy_name][0], "copy_write_kib": write[copy_name][0],
+         "fetch_scale": fetch_scale, "write_scale": write_scale,
+         "hbm_bytes_per_launch": fb + wb, "alg_bytes_per_launch": alg, "traffic_over_alg": (fb + wb) / alg}
+    os.makedirs(os.path.dirname(COUNTERS_JSON), exist_ok=True)
+    with open(COUNTERS_JSON, "w") as f:
+        json.dump(d, f, indent=1)
+    print(json.dumps(d))
     return 0
 
 
@@ -209,15 +329,20 @@ def main():
     ap.add_argument("--steps", type=int, default=4000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--kernel-steps", type=int, default=200)
-    ap.add_argument("--cpu-steps", type=int, default=200)
+    ap.add_argument("--cpu-steps", type=int, default=2000)
+    ap.add_argument("--mono-steps", type=int, default=200)
+    ap.add_argument("--quick", action="store_true", help="skip the flat-wall and monopole extras")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-run", action="store_true")
+    ap.add_argument("--counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: the path is a single-GPU kernel and this build has no "
-              "multi-GPU mode (instances shard by bytes with no communication; see the design notes).",
-              file=sys.stderr)
+        print(f"bench.py measures one GPU (asked for {args.gpus}): the stage is a single-GPU kernel and this "
+              "library has no multi-GPU mode.  Independent instances would shard across GPUs by bytes with no "
+              "communication; see the design notes.", file=sys.stderr)
         return 2
+    if args.counters:
+        return counters(args)
     if args.profile_run:
         return profile_run(args)
     return run(args)

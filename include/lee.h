@@ -241,12 +241,26 @@ typedef struct {
 } lee_tiling;
 
 lee_status lee_set_tiling(lee_instance *inst, const lee_tiling *t);
+
+/*
+ * Steps per captured hipGraph for lee_step_n (and batches): steps > 0
+ * captures that many consecutive steps in one graph (at most 256; a single-
+ * step graph covers the remainder of n), 0 selects the built-in default (16
+ * steps), a negative value launches every kernel eagerly without graphs.  Invalidates
+ * the captured graphs.
+ */
+lee_status lee_set_graph_steps(lee_instance *inst, int32_t steps);
 lee_status lee_get_tiling(const lee_instance *inst, lee_tiling *t);
 
 /*
- * Measurement: run n steps eagerly with HIP events around every sweep
- * launch on the bound stream and return the mean sweep and ghost-kernel
- * durations in microseconds (synchronising).
+ * Measurement (synchronising, on the bound stream).  Runs, each bracketed by
+ * one pair of HIP events: 4n ghost launches (stages 0..3 in turn), 4n sweep
+ * launches (the fused launch when the tiling is fused), then n eager steps.
+ * Returns the mean per-launch ghost and sweep times and the mean step time
+ * in microseconds; a mean over back-to-back launches includes the gap
+ * between launches.  The repeated launches are not valid steps, so the
+ * fields, ADE states, step counter and traces are reset to the initial
+ * condition afterwards (as by lee_init_fields).
  */
 lee_status lee_time_kernels(lee_instance *inst, int64_t n, double *sweep_us, double *ghost_us,
                             double *step_us);
@@ -271,13 +285,14 @@ void lee_destroy(lee_instance *inst);
 typedef struct {
     lee_tiling tiling;          /* sweep tiling for the whole batch (kind < 0: built-in default) */
     int32_t persistent_blocks;  /* 0 = one workgroup per work item */
+    int32_t graph_steps;        /* as lee_set_graph_steps */
 } lee_batch_opts;
 
 /*
  * Group n bound instances of the same precision and stencil into a batch
  * advanced by one launch per phase (ghost fill, sweep, step end) over a
- * flat work list spanning all members, captured as one hipGraph per step on
- * the stream of the first member.  The instance table lives in device memory
+ * flat work list spanning all members, captured in hipGraphs on the stream
+ * of the first member.  The instance table lives in device memory
  * owned by the batch (allocated by the library).  Members keep their own
  * step counters; lee_batch_set_budget lets finished members idle without
  * re-capturing.
@@ -295,7 +310,8 @@ lee_status lee_batch_step_n(lee_batch *b, int64_t n);
 /* Wait for the batch's stream; LEE_E_DEVICE as for lee_synchronize. */
 lee_status lee_batch_synchronize(lee_batch *b);
 
-/* Synchronising: mean per-launch sweep and ghost durations over n eager steps. */
+/* As lee_time_kernels, over the whole batch; every member is reset to its
+ * initial condition afterwards. */
 lee_status lee_batch_time_kernels(lee_batch *b, int64_t n, double *sweep_us, double *ghost_us,
                                   double *step_us);
 

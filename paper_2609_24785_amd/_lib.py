@@ -51,7 +51,7 @@ class Tiling(ctypes.Structure):
 
 
 class BatchOpts(ctypes.Structure):
-    _fields_ = [("tiling", Tiling), ("persistent_blocks", c_int32)]
+    _fields_ = [("tiling", Tiling), ("persistent_blocks", c_int32), ("graph_steps", c_int32)]
 
 
 # name -> (restype, argtypes)
@@ -79,6 +79,7 @@ SIGNATURES = {
                                    ctypes.POINTER(c_double)]),
     "lee_stream_copy": (c_int32, [c_void_p, c_void_p, c_size_t, c_void_p]),
     "lee_synchronize": (c_int32, [c_void_p]),
+    "lee_set_graph_steps": (c_int32, [c_void_p, c_int32]),
     "lee_batch_synchronize": (c_int32, [c_void_p]),
     "lee_destroy": (None, [c_void_p]),
     "lee_batch_create": (c_int32, [ctypes.POINTER(c_void_p), c_int32, ctypes.POINTER(BatchOpts),

@@ -7,12 +7,33 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
+#include <initializer_list>
 #include <string>
 #include <vector>
 
 #include "lee_device.h"
 
 using namespace lee;
+
+// Captured steps: `many` holds `per` consecutive steps, `one` a single step
+// for the remainder.  per == 0 launches every kernel eagerly.
+struct StepGraphs {
+    int per = 1;
+    hipGraph_t gm = nullptr, g1 = nullptr;
+    hipGraphExec_t em = nullptr, e1 = nullptr;
+    void drop()
+    {
+        if (em) hipGraphExecDestroy(em);
+        if (e1) hipGraphExecDestroy(e1);
+        if (gm) hipGraphDestroy(gm);
+        if (g1) hipGraphDestroy(g1);
+        em = e1 = nullptr;
+        gm = g1 = nullptr;
+    }
+};
+constexpr int GRAPH_STEPS_DEFAULT = 16;            // measured: amortises the gap between graph launches
+constexpr int GRAPH_STEPS_MAX = 256;
 
 struct lee_instance {
     Host host;
@@ -41,8 +62,7 @@ struct lee_instance {
     long long up_counters[3] = {0, LLONG_MAX, 1};
     double up_amp[4] = {0, 0, 0, 0};
     // sequencing
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    StepGraphs graphs;
     int next_stage = 0;
     int64_t steps_issued = 0;
 };
@@ -232,13 +252,47 @@ lee_status upload_work1(lee_instance *I)
     return LEE_OK;
 }
 
-void drop_graph(lee_instance *I)
+void drop_graph(lee_instance *I) { I->graphs.drop(); }
+
+// n steps on stream s through the captured graphs (or eagerly); issue_step
+// enqueues the launches of one step.
+lee_status run_steps(StepGraphs &G, hipStream_t s, int64_t n, const std::function<hipError_t()> &issue_step)
 {
-    if (I->exec) hipGraphExecDestroy(I->exec);
-    if (I->graph) hipGraphDestroy(I->graph);
-    I->exec = nullptr;
-    I->graph = nullptr;
+    if (s == nullptr || G.per == 0) {            // the legacy default stream cannot be captured
+        for (int64_t k = 0; k < n; ++k) HIPCHK(issue_step());
+        return LEE_OK;
+    }
+    auto capture = [&](int steps, hipGraph_t &g, hipGraphExec_t &ex) -> lee_status {
+        HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        hipError_t e = hipSuccess;
+        for (int k = 0; k < steps && e == hipSuccess; ++k) e = issue_step();
+        hipGraph_t cg = nullptr;
+        hipError_t e2 = hipStreamEndCapture(s, &cg);
+        if (e != hipSuccess) {
+            if (cg) hipGraphDestroy(cg);
+            return hip_fail(e, "capturing steps");
+        }
+        if (e2 != hipSuccess) return hip_fail(e2, "hipStreamEndCapture");
+        g = cg;
+        HIPCHK(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
+        return LEE_OK;
+    };
+    const int64_t full = G.per > 1 ? n / G.per : 0;
+    const int64_t rest = n - full * G.per;
+    if (full > 0 && !G.em) {
+        lee_status st = capture(G.per, G.gm, G.em);
+        if (st != LEE_OK) return st;
+    }
+    if (rest > 0 && !G.e1) {
+        lee_status st = capture(1, G.g1, G.e1);
+        if (st != LEE_OK) return st;
+    }
+    for (int64_t k = 0; k < full; ++k) HIPCHK(hipGraphLaunch(G.em, s));
+    for (int64_t k = 0; k < rest; ++k) HIPCHK(hipGraphLaunch(G.e1, s));
+    return LEE_OK;
 }
+
+int graph_steps_from(int32_t v) { return v == 0 ? GRAPH_STEPS_DEFAULT : (v < 0 ? 0 : v); }
 
 hipError_t sweep(int prec, bool filt, const lee_tiling &t, const DevInst *insts, const int4 *work, int nwork,
                  int stage, int blocks, hipStream_t s)
@@ -280,6 +334,29 @@ hipError_t issue_stage(lee_instance *I, int stage, hipEvent_t *ev = nullptr)
     if (e != hipSuccess) return e;
     if (stage == 3) e = launch_step_end(prec, I->d_inst, 1, I->stream);
     return e;
+}
+
+// Times each run (a sequence of asynchronous launches) with one pair of
+// events on stream s; out[k] receives run k's duration in microseconds.
+lee_status time_runs(hipStream_t s, std::initializer_list<std::function<hipError_t()>> runs, double *out)
+{
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(hipEventCreate(&e0));
+    hipError_t e = hipEventCreate(&e1);
+    int k = 0;
+    for (auto it = runs.begin(); it != runs.end() && e == hipSuccess; ++it, ++k) {
+        e = hipEventRecord(e0, s);
+        if (e == hipSuccess) e = (*it)();
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        out[k] = 1000.0 * ms;
+    }
+    hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    if (e != hipSuccess) return hip_fail(e, "timing run");
+    return LEE_OK;
 }
 
 // Waits for the stream and reports a fused stage whose ghost wait ran out.
@@ -550,28 +627,22 @@ lee_status lee_step_n(lee_instance *I, int64_t n)
     if (n < 0) return fail(LEE_E_ARG, "n < 0");
     if (I->next_stage != 0) return fail(LEE_E_STATE, "a partial step is pending");
     if (n == 0) return LEE_OK;
-    if (I->stream == nullptr) {      // the legacy default stream cannot be captured
-        for (int64_t k = 0; k < n; ++k)
-            for (int l = 0; l < 4; ++l) HIPCHK(issue_stage(I, l));
-        I->steps_issued += n;
-        return LEE_OK;
-    }
-    if (!I->exec) {
-        HIPCHK(hipStreamBeginCapture(I->stream, hipStreamCaptureModeThreadLocal));
+    lee_status st = run_steps(I->graphs, I->stream, n, [I]() {
         hipError_t e = hipSuccess;
         for (int l = 0; l < 4 && e == hipSuccess; ++l) e = issue_stage(I, l);
-        hipGraph_t g = nullptr;
-        hipError_t e2 = hipStreamEndCapture(I->stream, &g);
-        if (e != hipSuccess) {
-            if (g) hipGraphDestroy(g);
-            return hip_fail(e, "capturing the step");
-        }
-        if (e2 != hipSuccess) return hip_fail(e2, "hipStreamEndCapture");
-        I->graph = g;
-        HIPCHK(hipGraphInstantiate(&I->exec, I->graph, nullptr, nullptr, 0));
-    }
-    for (int64_t k = 0; k < n; ++k) HIPCHK(hipGraphLaunch(I->exec, I->stream));
+        return e;
+    });
+    if (st != LEE_OK) return st;
     I->steps_issued += n;
+    return LEE_OK;
+}
+
+lee_status lee_set_graph_steps(lee_instance *I, int32_t steps)
+{
+    if (!I) return fail(LEE_E_ARG, "null instance");
+    if (steps > GRAPH_STEPS_MAX) return fail(LEE_E_ARG, "too many steps per graph");
+    drop_graph(I);
+    I->graphs.per = graph_steps_from(steps);
     return LEE_OK;
 }
 
@@ -771,44 +842,38 @@ lee_status lee_time_kernels(lee_instance *I, int64_t n, double *sweep_us, double
     if (!I || !I->bound) return fail(LEE_E_STATE, "instance not bound");
     if (n <= 0) return fail(LEE_E_ARG, "n must be positive");
     if (I->next_stage != 0) return fail(LEE_E_STATE, "a partial step is pending");
-    constexpr int CH = 32;                       // steps per event chunk
-    std::vector<hipEvent_t> ev(CH * 16 + 2);
-    for (auto &e : ev) HIPCHK(hipEventCreate(&e));
     const int prec = I->host.d.precision;
-    double tsw = 0, tgh = 0, tstep = 0;
-    int64_t done = 0;
-    lee_status st = LEE_OK;
-    while (done < n && st == LEE_OK) {
-        const int m = (int)std::min<int64_t>(CH, n - done);
-        hipEventRecord(ev[CH * 16], I->stream);
-        for (int k = 0; k < m; ++k)
-            for (int l = 0; l < 4; ++l) {
-                issue_stage(I, l, &ev[(k * 4 + l) * 4]);
-            }
-        hipEventRecord(ev[CH * 16 + 1], I->stream);
-        hipError_t e = hipEventSynchronize(ev[CH * 16 + 1]);
-        if (e != hipSuccess) {
-            st = hip_fail(e, "timing run");
-            break;
+    const bool filt = I->host.d.filter_sigma > 0.0;
+    auto ghosts = [&]() -> hipError_t {
+        hipError_t e = hipSuccess;
+        for (int64_t k = 0; k < 4 * n && e == hipSuccess; ++k)
+            e = launch_ghost(prec, I->d_inst, I->d_work2, I->nwork2, (int)(k & 3), I->stream);
+        return e;
+    };
+    auto sweeps = [&]() -> hipError_t {
+        hipError_t e = hipSuccess;
+        for (int64_t k = 0; k < 4 * n && e == hipSuccess; ++k) {
+            const int l = (int)(k & 3);
+            e = fused(I->tl) ? launch_stage(prec, filt, I->tl.cols, I->tl.rows, I->d_inst, I->d_work1, I->nwork1,
+                                            I->d_work2, I->nwork2, l, I->d_sync, SPIN_LIMIT, I->stream)
+                             : sweep(prec, filt, I->tl, I->d_inst, I->d_work1, I->nwork1, l, 0, I->stream);
         }
-        for (int k = 0; k < m * 4; ++k) {
-            float a = 0, b = 0;
-            hipEventElapsedTime(&a, ev[k * 4 + 0], ev[k * 4 + 1]);
-            hipEventElapsedTime(&b, ev[k * 4 + 2], ev[k * 4 + 3]);
-            tgh += a;
-            tsw += b;
-        }
-        float c = 0;
-        hipEventElapsedTime(&c, ev[CH * 16], ev[CH * 16 + 1]);
-        tstep += c;
-        done += m;
-    }
-    for (auto &e : ev) hipEventDestroy(e);
+        return e;
+    };
+    auto steps = [&]() -> hipError_t {
+        hipError_t e = hipSuccess;
+        for (int64_t k = 0; k < n && e == hipSuccess; ++k)
+            for (int l = 0; l < 4 && e == hipSuccess; ++l) e = issue_stage(I, l);
+        return e;
+    };
+    double out[3] = {0, 0, 0};
+    lee_status st = time_runs(I->stream, {ghosts, sweeps, steps}, out);
+    lee_status st2 = lee_init_fields(I);
     if (st != LEE_OK) return st;
-    I->steps_issued += n;
-    if (sweep_us) *sweep_us = 1000.0 * tsw / (4.0 * n);
-    if (ghost_us) *ghost_us = 1000.0 * tgh / (4.0 * n);
-    if (step_us) *step_us = 1000.0 * tstep / n;
+    if (st2 != LEE_OK) return st2;
+    if (ghost_us) *ghost_us = out[0] / (4.0 * n);
+    if (sweep_us) *sweep_us = out[1] / (4.0 * n);
+    if (step_us) *step_us = out[2] / n;
     return LEE_OK;
 }
 
@@ -850,19 +915,12 @@ struct lee_batch {
     std::vector<int4> up_work1;
     std::vector<int4> up_work2;
     std::vector<long long> up_budget;      // (budget, active) pairs
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    StepGraphs graphs;
 };
 
 namespace {
 
-void batch_drop_graph(lee_batch *B)
-{
-    if (B->exec) hipGraphExecDestroy(B->exec);
-    if (B->graph) hipGraphDestroy(B->graph);
-    B->exec = nullptr;
-    B->graph = nullptr;
-}
+void batch_drop_graph(lee_batch *B) { B->graphs.drop(); }
 
 hipError_t batch_issue_stage(lee_batch *B, int stage, hipEvent_t *ev = nullptr)
 {
@@ -916,6 +974,11 @@ lee_status lee_batch_create(lee_instance *const *v, int32_t n, const lee_batch_o
     if (opts) {
         if (opts->tiling.kind >= 0) B->tl = opts->tiling;
         B->pblocks = opts->persistent_blocks;
+        if (opts->graph_steps > GRAPH_STEPS_MAX) {
+            delete B;
+            return fail(LEE_E_ARG, "too many steps per graph");
+        }
+        B->graphs.per = graph_steps_from(opts->graph_steps);
     }
     if (!tiling_valid(B->prec, B->tl) || B->pblocks < 0) {
         delete B;
@@ -975,26 +1038,12 @@ lee_status lee_batch_step_n(lee_batch *B, int64_t n)
     if (!B) return fail(LEE_E_ARG, "null batch");
     if (n < 0) return fail(LEE_E_ARG, "n < 0");
     if (n == 0) return LEE_OK;
-    if (B->stream == nullptr) {
-        for (int64_t k = 0; k < n; ++k)
-            for (int l = 0; l < 4; ++l) HIPCHK(batch_issue_stage(B, l));
-    } else {
-        if (!B->exec) {
-            HIPCHK(hipStreamBeginCapture(B->stream, hipStreamCaptureModeThreadLocal));
-            hipError_t e = hipSuccess;
-            for (int l = 0; l < 4 && e == hipSuccess; ++l) e = batch_issue_stage(B, l);
-            hipGraph_t g = nullptr;
-            hipError_t e2 = hipStreamEndCapture(B->stream, &g);
-            if (e != hipSuccess) {
-                if (g) hipGraphDestroy(g);
-                return hip_fail(e, "capturing the batch step");
-            }
-            if (e2 != hipSuccess) return hip_fail(e2, "hipStreamEndCapture");
-            B->graph = g;
-            HIPCHK(hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0));
-        }
-        for (int64_t k = 0; k < n; ++k) HIPCHK(hipGraphLaunch(B->exec, B->stream));
-    }
+    lee_status st = run_steps(B->graphs, B->stream, n, [B]() {
+        hipError_t e = hipSuccess;
+        for (int l = 0; l < 4 && e == hipSuccess; ++l) e = batch_issue_stage(B, l);
+        return e;
+    });
+    if (st != LEE_OK) return st;
     for (auto *I : B->members) I->steps_issued += n;   // upper bound; budgets may idle members
     return LEE_OK;
 }
@@ -1003,43 +1052,41 @@ lee_status lee_batch_time_kernels(lee_batch *B, int64_t n, double *sweep_us, dou
 {
     if (!B) return fail(LEE_E_ARG, "null batch");
     if (n <= 0) return fail(LEE_E_ARG, "n must be positive");
-    constexpr int CH = 16;
-    std::vector<hipEvent_t> ev(CH * 16 + 2);
-    for (auto &e : ev) HIPCHK(hipEventCreate(&e));
-    double tsw = 0, tgh = 0, tstep = 0;
-    int64_t done = 0;
-    lee_status st = LEE_OK;
-    while (done < n) {
-        const int m = (int)std::min<int64_t>(CH, n - done);
-        hipEventRecord(ev[CH * 16], B->stream);
-        for (int k = 0; k < m; ++k)
-            for (int l = 0; l < 4; ++l) {
-                batch_issue_stage(B, l, &ev[(k * 4 + l) * 4]);
-            }
-        hipEventRecord(ev[CH * 16 + 1], B->stream);
-        hipError_t e = hipEventSynchronize(ev[CH * 16 + 1]);
-        if (e != hipSuccess) {
-            st = hip_fail(e, "batch timing run");
-            break;
+    int blocks = 0;
+    const int per = B->tl.kind == LEE_SWEEP_MARCH ? B->tl.waves : 1;
+    if (B->pblocks > 0) blocks = std::min(B->pblocks, (B->nwork1 + per - 1) / per);
+    auto ghosts = [&]() -> hipError_t {
+        hipError_t e = hipSuccess;
+        for (int64_t k = 0; k < 4 * n && e == hipSuccess; ++k)
+            e = launch_ghost(B->prec, B->d_table, B->d_work2, B->nwork2, (int)(k & 3), B->stream);
+        return e;
+    };
+    auto sweeps = [&]() -> hipError_t {
+        hipError_t e = hipSuccess;
+        for (int64_t k = 0; k < 4 * n && e == hipSuccess; ++k) {
+            const int l = (int)(k & 3);
+            e = fused(B->tl) ? launch_stage(B->prec, B->filt, B->tl.cols, B->tl.rows, B->d_table, B->d_work1,
+                                            B->nwork1, B->d_work2, B->nwork2, l, B->d_sync, SPIN_LIMIT, B->stream)
+                             : sweep(B->prec, B->filt, B->tl, B->d_table, B->d_work1, B->nwork1, l, blocks, B->stream);
         }
-        for (int k = 0; k < m * 4; ++k) {
-            float a = 0, b = 0;
-            hipEventElapsedTime(&a, ev[k * 4 + 0], ev[k * 4 + 1]);
-            hipEventElapsedTime(&b, ev[k * 4 + 2], ev[k * 4 + 3]);
-            tgh += a;
-            tsw += b;
-        }
-        float c = 0;
-        hipEventElapsedTime(&c, ev[CH * 16], ev[CH * 16 + 1]);
-        tstep += c;
-        done += m;
+        return e;
+    };
+    auto steps = [&]() -> hipError_t {
+        hipError_t e = hipSuccess;
+        for (int64_t k = 0; k < n && e == hipSuccess; ++k)
+            for (int l = 0; l < 4 && e == hipSuccess; ++l) e = batch_issue_stage(B, l);
+        return e;
+    };
+    double out[3] = {0, 0, 0};
+    lee_status st = time_runs(B->stream, {ghosts, sweeps, steps}, out);
+    for (auto *I : B->members) {
+        lee_status s2 = lee_init_fields(I);
+        if (st == LEE_OK) st = s2;
     }
-    for (auto &e : ev) hipEventDestroy(e);
     if (st != LEE_OK) return st;
-    for (auto *I : B->members) I->steps_issued += n;
-    if (sweep_us) *sweep_us = 1000.0 * tsw / (4.0 * n);
-    if (ghost_us) *ghost_us = 1000.0 * tgh / (4.0 * n);
-    if (step_us) *step_us = 1000.0 * tstep / n;
+    if (ghost_us) *ghost_us = out[0] / (4.0 * n);
+    if (sweep_us) *sweep_us = out[1] / (4.0 * n);
+    if (step_us) *step_us = out[2] / n;
     return LEE_OK;
 }
 

@@ -204,6 +204,10 @@ class Instance:
         t = make_tiling(kind, vec, cols, rows, waves, fused)
         check(self.lib.lee_set_tiling(self._h, ctypes.byref(t)), "lee_set_tiling")
 
+    def set_graph_steps(self, steps: int):
+        """Steps per captured hipGraph (0: built-in default, < 0: eager launches)."""
+        check(self.lib.lee_set_graph_steps(self._h, steps), "lee_set_graph_steps")
+
     def get_tiling(self) -> dict:
         t = Tiling()
         check(self.lib.lee_get_tiling(self._h, ctypes.byref(t)), "lee_get_tiling")
@@ -232,7 +236,8 @@ class Instance:
 class Batch:
     """Bound instances advanced together: one launch per phase over all members."""
 
-    def __init__(self, members: Sequence[Instance], tiling: Optional[dict] = None, persistent_blocks: int = 0):
+    def __init__(self, members: Sequence[Instance], tiling: Optional[dict] = None, persistent_blocks: int = 0,
+                 graph_steps: int = 0):
         self.lib = load()
         self.members = list(members)
         arr = (c_void_p * len(members))(*[m._h.value for m in members])
@@ -242,6 +247,7 @@ class Batch:
         else:
             opts.tiling = make_tiling(**tiling)
         opts.persistent_blocks = persistent_blocks
+        opts.graph_steps = graph_steps
         self._h = c_void_p()
         check(self.lib.lee_batch_create(arr, len(members), ctypes.byref(opts), ctypes.byref(self._h)),
               "lee_batch_create")

@@ -107,6 +107,29 @@ def test_fused_stage_equals_two_launches_bitwise(prec):
             assert np.array_equal(a.traces(), b.traces())
 
 
+def test_graph_steps_equal_eager_bitwise():
+    """Eager launches, one-step graphs and multi-step graphs (with a
+    remainder) give the same bits."""
+    Instance, _ = _lee()
+    case = lc.small_cylinder(128, 13)
+    ref = None
+    for g in (-1, 1, 4, 8):
+        _say(f"[graph-steps] {g}")
+        a = Instance(case, "f32")
+        a.set_graph_steps(g)
+        a.step_n(6)
+        a.step_n(7)
+        a.synchronize()
+        got = (a.fields(), a.ade_states(), a.traces())
+        if ref is None:
+            ref = got
+            continue
+        for x, y in zip(got[0], ref[0]):
+            assert np.array_equal(x, y)
+        assert np.array_equal(got[1], ref[1])
+        assert np.array_equal(got[2], ref[2])
+
+
 def test_stages_equal_graph_step_bitwise():
     Instance, _ = _lee()
     case = lc.small_cylinder(128, 10)
