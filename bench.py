@@ -18,14 +18,17 @@ q^n, write q^(1)) and 36 B (stages 2-4: read q^n and q^(l-1), write q^(l))
 per fluid node, 33 B in FP32, divided by the mean launch time measured with
 HIP events on the library's stream over back-to-back launches.
 
-Also reported: the flat-wall case (201^2, FP64) against the oracle, the
-monopole case (4096^2) throughput in both precisions, and the oracle on the
-host cores over a bounded sample of the benchmark workload.
+The launch configuration (tile shape, fused or two-launch stage, steps per
+graph) is chosen by the library's autotuner on a scratch instance first.
+Also reported: the oracle on the host cores over a bounded sample of the
+benchmark workload.
 
-Other modes: --profile-run (a short fixed sequence for rocprofv3), and
---counters FETCH_CSV WRITE_CSV (turns two rocprofv3 --pmc counter files of
-the profile run into the sweep's HBM traffic per launch, calibrated by the
-copy kernel of known size the profile run ends with).
+Other modes: --extras (a second JSON line: the flat-wall case against the
+oracle, the 4096^2 monopole case, and the batch of 256 uneven instances),
+--profile-run (a short fixed sequence for rocprofv3), and
+--counters FETCH_CSV WRITE_CSV KERNEL (turns two rocprofv3 --pmc counter
+files of the profile run into KERNEL's HBM traffic per launch, calibrated by
+the copy kernel of known size the profile run ends with).
 """
 from __future__ import annotations
 
@@ -43,6 +46,15 @@ METRIC = "grid-pt RK-stage updates/s FP32 vs FP64 at 1e-4 rel L2; p50/p99 solve 
 UNIT = "grid-pt RK-stage updates/s"
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_NODE_STAGE = {"f32": (24.0 + 3 * 36.0) / 4.0, "f64": (48.0 + 3 * 72.0) / 4.0}
+
+
+def ghost_bytes(prec: str, G: int, nnz: int) -> float:
+    """Algorithmic bytes of one stage's ghost fill: per cloud entry 4 weights
+    and an offset; per ghost its geometry, two ADE state reads and one write,
+    its offset and the three ghost values written (the gathered fluid values
+    are the sweep's)."""
+    e = 4 if prec == "f32" else 8
+    return nnz * (4 * e + 4) + G * (4 * e + 3 * 2 * e + 4 + 3 * e)
 COUNTERS_JSON = os.path.join(HERE, "profiles", "sweep_counters.json")
 COPY_BYTES = 1 << 28                     # the profile run's calibration copy (256 MiB)
 
@@ -73,12 +85,19 @@ def _kernel_name(tiling: dict, prec: str) -> str:
     return f"lee::k_sweep<{t.split(',')[0]}, {tiling['vec']}, true, {tiling['waves']}>"
 
 
-def _timed(case, prec: str, steps: int, warmup: int):
+def _apply(inst, choice):
+    if choice:
+        inst.set_tiling(**choice["tiling"])
+        inst.set_graph_steps(choice["graph_steps"])
+
+
+def _timed(case, prec: str, steps: int, warmup: int, choice=None):
     """Graph-replayed steps of one instance; returns the rate and the instance."""
     import torch
     from paper_2609_24785_amd.lee import Instance
 
     inst = Instance(case, prec, trace_capacity=max(steps + warmup, 1))
+    _apply(inst, choice)
     inst.step_n(warmup)
     inst.synchronize()
     torch.cuda.synchronize()
@@ -98,20 +117,23 @@ def _timed(case, prec: str, steps: int, warmup: int):
                 value=fluid * 4.0 * steps / wall)
 
 
-def _kernel_times(case, prec: str, n: int):
+def _kernel_times(case, prec: str, n: int, choice=None):
     """Mean per-launch times of the sweep and ghost kernels (back-to-back
     launches on the library's stream, one event pair per kernel kind)."""
     from paper_2609_24785_amd.lee import Instance
 
     inst = Instance(case, prec, trace_capacity=1)
+    _apply(inst, choice)
     inst.time_kernels(2)                                  # warm the code objects
     sweep_us, ghost_us, step_us = inst.time_kernels(n)
     tiling = inst.get_tiling()
     fluid = inst.summary.fluid_nodes
     ghosts = inst.summary.G
+    nnz = inst.summary.nnz
     inst.close()
+    alg = BYTES_PER_NODE_STAGE[prec] * fluid + (ghost_bytes(prec, ghosts, nnz) if tiling.get("fused") else 0.0)
     return dict(sweep_us=sweep_us, ghost_us=ghost_us, eager_step_us=step_us, tiling=tiling, fluid=fluid,
-                ghosts=ghosts, kernel=_kernel_name(tiling, prec))
+                ghosts=ghosts, nnz=nnz, kernel=_kernel_name(tiling, prec), alg_bytes=alg)
 
 
 def _max_rel_l2(a, b, mask):
@@ -129,14 +151,19 @@ def run(args):
         print(json.dumps({"metric": METRIC, "error": "no GPU visible"}))
         return 1
     torch.cuda.set_device(0)
+    from paper_2609_24785_amd import tune
     case = lc.cylinder_pulse_1024(steps=args.steps)
+    print("[bench] autotuning the launch configuration", file=sys.stderr, flush=True)
+    cache = tune.TuneCache(args.tune_cache)             # the shipped table, then live trials
+    ch32 = tune.tune_case(case, "f32", cache)
+    ch64 = tune.tune_case(case, "f64", cache)
     print(f"[bench] {case.name}: {args.steps} steps after {args.warmup} warm-up, FP32 then FP64",
           file=sys.stderr, flush=True)
-    r32 = _timed(case, "f32", args.steps, args.warmup)
-    r64 = _timed(case, "f64", args.steps, args.warmup)
+    r32 = _timed(case, "f32", args.steps, args.warmup, ch32)
+    r64 = _timed(case, "f64", args.steps, args.warmup, ch64)
     print("[bench] kernel timing", file=sys.stderr, flush=True)
-    k32 = _kernel_times(case, "f32", args.kernel_steps)
-    k64 = _kernel_times(case, "f64", args.kernel_steps)
+    k32 = _kernel_times(case, "f32", args.kernel_steps, ch32)
+    k64 = _kernel_times(case, "f64", args.kernel_steps, ch64)
 
     import oracle.solver as osv          # error reference and CPU baseline (test infrastructure)
     from oracle.geometry import fluid_mask
@@ -153,10 +180,9 @@ def run(args):
         / case.ic.w ** 2))[mask] ** 2)))
     abs_32_64 = float(np.sqrt(np.sum((f32[0] - p64)[mask] ** 2))) / init_norm
 
-    bpn = BYTES_PER_NODE_STAGE["f32"]
-    alg_bytes = bpn * k32["fluid"]
+    alg_bytes = k32["alg_bytes"]
     achieved = alg_bytes / (k32["sweep_us"] * 1e-6) / 1e9
-    ach64 = BYTES_PER_NODE_STAGE["f64"] * k64["fluid"] / (k64["sweep_us"] * 1e-6) / 1e9
+    ach64 = k64["alg_bytes"] / (k64["sweep_us"] * 1e-6) / 1e9
     traffic = _traffic(k32["kernel"])
     out = {
         "metric": METRIC,
@@ -180,7 +206,11 @@ def run(args):
             "ghosts": int(r32["inst"].summary.G),
             "tiling_f32": k32["tiling"],
             "tiling_f64": k64["tiling"],
-            "launch": "hipGraph per step: 4 x (ghost fill + ADE, stage sweep) + step end",
+            "graph_steps": ch32["graph_steps"],
+            "tuning_from": "table" if ch32.get("cached") else "trials",
+            "tuned_step_us": {"f32": ch32["step_us"], "f64": ch64["step_us"]},
+            "launch": "hipGraphs of captured steps; a step is 4 x (ghost fill + ADE, stage sweep; one launch "
+                      "when fused) + step end; configuration from the autotuner",
         },
         "fp64_value": r64["value"],
         "fp64_ms_per_step": 1000.0 * r64["wall"] / r64["steps"],
@@ -207,26 +237,6 @@ def run(args):
     r32["inst"].close()
     r64["inst"].close()
 
-    if not args.quick:
-        print("[bench] flat wall 201^2 FP64 against the oracle", file=sys.stderr, flush=True)
-        flat = lc.flat_wall_201(500)
-        rf = _timed(flat, "f64", 500, 0)
-        s = osv.OracleSolver(flat)
-        s.run(500)
-        out["flat_wall_201_f64"] = {"value": rf["value"], "steps": 500,
-                                    "rel_l2_vs_oracle": _max_rel_l2(rf["inst"].fields(), s.fields(), s.fluid)}
-        rf["inst"].close()
-        print("[bench] monopole 4096^2", file=sys.stderr, flush=True)
-        mono = lc.monopole_4096(args.mono_steps)
-        mres = {}
-        for prec in ("f32", "f64"):
-            rm = _timed(mono, prec, args.mono_steps, 10)
-            mres[prec] = {"value": rm["value"], "ms_per_step": 1000.0 * rm["wall"] / rm["steps"],
-                          "fluid_nodes": rm["fluid"]}
-            rm["inst"].close()
-            torch.cuda.empty_cache()
-        out["monopole_4096"] = dict(steps=args.mono_steps, **mres)
-
     if not args.no_cpu_baseline:
         print(f"[bench] oracle on the host: {args.cpu_steps} steps", file=sys.stderr, flush=True)
         nthreads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
@@ -251,6 +261,78 @@ def run(args):
     return 0
 
 
+def extras(args):
+    """Second JSON line: the other configurations (not the benchmark line)."""
+    import torch
+
+    import lee_cases as lc
+    import oracle.solver as osv
+    from paper_2609_24785_amd import tune
+    from paper_2609_24785_amd._lib import LeeError
+    from paper_2609_24785_amd.lee import Batch, Instance
+
+    torch.cuda.set_device(0)
+    out = {"extras": True}
+    cache = tune.TuneCache(args.tune_cache)
+    print("[extras] flat wall 201^2 FP64 against the oracle", file=sys.stderr, flush=True)
+    flat = lc.flat_wall_201(500)
+    rf = _timed(flat, "f64", 500, 0)
+    s = osv.OracleSolver(flat)
+    s.run(500)
+    out["flat_wall_201_f64"] = {"value": rf["value"], "unit": UNIT, "steps": 500,
+                                "rel_l2_vs_oracle": _max_rel_l2(rf["inst"].fields(), s.fields(), s.fluid)}
+    rf["inst"].close()
+    print("[extras] monopole 4096^2", file=sys.stderr, flush=True)
+    mono = lc.monopole_4096(args.mono_steps)
+    mres = {}
+    for prec in ("f32", "f64"):
+        ch = tune.tune_case(mono, prec, cache)
+        rm = _timed(mono, prec, args.mono_steps, 16, ch)
+        mres[prec] = {"value": rm["value"], "ms_per_step": 1000.0 * rm["wall"] / rm["steps"],
+                      "fluid_nodes": rm["fluid"], "tiling": ch["tiling"]}
+        rm["inst"].close()
+        torch.cuda.empty_cache()
+    out["monopole_4096"] = dict(steps=args.mono_steps, unit=UNIT, **mres)
+
+    print(f"[extras] batch of {args.batch_size} uneven instances", file=sys.stderr, flush=True)
+    gen = lc.batch_candidates(steps=args.batch_steps)
+    members, rejected = [], 0
+    t0 = time.perf_counter()
+    while len(members) < args.batch_size:
+        c = next(gen)
+        try:
+            members.append(Instance(c, "f32", trace_capacity=1))
+        except LeeError:
+            rejected += 1
+    setup_s = time.perf_counter() - t0
+    fluid = sum(m.summary.fluid_nodes for m in members)
+    b = Batch(members)
+    ch = tune.tune_batch(b, cache)
+    b.step_n(4)
+    b.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(members[0].stream):
+        ev0.record()
+    t0 = time.perf_counter()
+    b.step_n(args.batch_steps)
+    with torch.cuda.stream(members[0].stream):
+        ev1.record()
+    b.synchronize()
+    wall = time.perf_counter() - t0
+    sides = [m.case.nx for m in members]
+    out["batch_256"] = {"value": fluid * 4.0 * args.batch_steps / wall, "unit": UNIT, "members": len(members),
+                        "rejected_candidates": rejected, "fluid_nodes": fluid, "steps": args.batch_steps,
+                        "ms_per_step": 1000.0 * wall / args.batch_steps,
+                        "gpu_ms_per_step": ev0.elapsed_time(ev1) / args.batch_steps,
+                        "sides": {str(k): sides.count(k) for k in sorted(set(sides))},
+                        "host_setup_s": setup_s, "tiling": ch["tiling"], "graph_steps": ch["graph_steps"],
+                        "roofline_frac": fluid * 4.0 * args.batch_steps * BYTES_PER_NODE_STAGE["f32"]
+                        / wall / 1e9 / HBM_PEAK_GBS}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def profile_run(args):
     """A short fixed sequence for hardware profilers: the benchmark workload
     (FP32, graph replay), then three copies of COPY_BYTES bytes."""
@@ -260,9 +342,13 @@ def profile_run(args):
     from paper_2609_24785_amd import _lib
     from paper_2609_24785_amd.lee import Instance
 
+    from paper_2609_24785_amd import tune
+
     torch.cuda.set_device(0)
     case = lc.cylinder_pulse_1024(steps=args.steps)
+    ch = tune.tune_case(case, "f32", tune.TuneCache(args.tune_cache))
     inst = Instance(case, "f32", trace_capacity=args.steps + args.warmup)
+    _apply(inst, ch)
     inst.step_n(args.warmup + args.steps)
     inst.synchronize()
     a = torch.empty(COPY_BYTES, dtype=torch.uint8, device="cuda")
@@ -299,7 +385,7 @@ def counters(args):
     fetch = per_kernel(args.counters[0], "FETCH_SIZE")
     write = per_kernel(args.counters[1], "WRITE_SIZE")
     copy_name = next(k for k in fetch if "k_copy" in k)
-    sweep_name = next(k for k in fetch if "k_tile<float, 4, true" in k or "k_stage<float, 4, true" in k)
+    sweep_name = next(k for k in fetch if k.replace("void ", "").startswith(args.counters[2] + "("))
     kib = 1024.0
     fetch_scale = COPY_BYTES / (fetch[copy_name][0] * kib)
     write_scale = COPY_BYTES / (write[copy_name][0] * kib)
@@ -310,6 +396,8 @@ def counters(args):
     inst = Instance(case, "f32", bind=False)
     fluid = inst.summary.fluid_nodes
     alg = BYTES_PER_NODE_STAGE["f32"] * fluid
+    if "k_stage" in sweep_name:                       # the fused launch also fills the ghosts
+        alg += ghost_bytes("f32", inst.summary.G, inst.summary.nnz)
     short = sweep_name.split("(")[0].replace("void ", "")
     d = {"kernel": short, "kernel_sha": _kernel_hash(), "dispatches": fetch[sweep_name][1],
          "fetch_kib_per_dispatch": fetch[sweep_name][0], "write_kib_per_dispatch": write[sweep_name][0],
@@ -331,10 +419,13 @@ def main():
     ap.add_argument("--kernel-steps", type=int, default=200)
     ap.add_argument("--cpu-steps", type=int, default=2000)
     ap.add_argument("--mono-steps", type=int, default=200)
-    ap.add_argument("--quick", action="store_true", help="skip the flat-wall and monopole extras")
+    ap.add_argument("--extras", action="store_true", help="the other configurations, as a second JSON line")
+    ap.add_argument("--batch-size", type=int, default=256)
+    ap.add_argument("--batch-steps", type=int, default=2000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-run", action="store_true")
-    ap.add_argument("--counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
+    ap.add_argument("--counters", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "KERNEL"))
+    ap.add_argument("--tune-cache", default=None, help="JSON file for autotuner choices (over the shipped table)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU (asked for {args.gpus}): the stage is a single-GPU kernel and this "
@@ -345,6 +436,8 @@ def main():
         return counters(args)
     if args.profile_run:
         return profile_run(args)
+    if args.extras:
+        return extras(args)
     return run(args)
 
 

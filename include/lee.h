@@ -307,6 +307,12 @@ lee_status lee_batch_set_budget(lee_batch *b, const int64_t *steps);
 /* n steps of every member with a positive budget; asynchronous. */
 lee_status lee_batch_step_n(lee_batch *b, int64_t n);
 
+/* The batch's sweep tiling (rebuilds its work list; synchronising) and steps
+ * per captured graph, as lee_set_tiling and lee_set_graph_steps. */
+lee_status lee_batch_set_tiling(lee_batch *b, const lee_tiling *t);
+lee_status lee_batch_get_tiling(const lee_batch *b, lee_tiling *t);
+lee_status lee_batch_set_graph_steps(lee_batch *b, int32_t steps);
+
 /* Wait for the batch's stream; LEE_E_DEVICE as for lee_synchronize. */
 lee_status lee_batch_synchronize(lee_batch *b);
 

@@ -81,6 +81,9 @@ SIGNATURES = {
     "lee_synchronize": (c_int32, [c_void_p]),
     "lee_set_graph_steps": (c_int32, [c_void_p, c_int32]),
     "lee_batch_synchronize": (c_int32, [c_void_p]),
+    "lee_batch_set_tiling": (c_int32, [c_void_p, ctypes.POINTER(Tiling)]),
+    "lee_batch_get_tiling": (c_int32, [c_void_p, ctypes.POINTER(Tiling)]),
+    "lee_batch_set_graph_steps": (c_int32, [c_void_p, c_int32]),
     "lee_destroy": (None, [c_void_p]),
     "lee_batch_create": (c_int32, [ctypes.POINTER(c_void_p), c_int32, ctypes.POINTER(BatchOpts),
                                    ctypes.POINTER(c_void_p)]),

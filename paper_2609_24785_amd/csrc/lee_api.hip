@@ -907,6 +907,7 @@ struct lee_batch {
     int device = -1;
     DevInst *d_table = nullptr;
     int4 *d_work1 = nullptr;
+    size_t work1_cap = 0;
     int nwork1 = 0;
     int4 *d_work2 = nullptr;
     int nwork2 = 0;
@@ -921,6 +922,16 @@ struct lee_batch {
 namespace {
 
 void batch_drop_graph(lee_batch *B) { B->graphs.drop(); }
+
+// The sweep work list over all members, in XCD-aware order.
+void batch_build_work1(lee_batch *B)
+{
+    std::vector<int4> items;
+    for (size_t k = 0; k < B->members.size(); ++k) build_work1(B->members[k]->host, (int)k, B->tl, items, false);
+    B->up_work1.clear();
+    xcd_order(items, B->tl.kind == LEE_SWEEP_MARCH ? B->tl.waves : 1, B->up_work1);
+    B->nwork1 = (int)B->up_work1.size();
+}
 
 hipError_t batch_issue_stage(lee_batch *B, int stage, hipEvent_t *ev = nullptr)
 {
@@ -985,9 +996,7 @@ lee_status lee_batch_create(lee_instance *const *v, int32_t n, const lee_batch_o
         return fail(LEE_E_ARG, "batch tiling options");
     }
     if (B->pblocks > 0) B->pblocks = (B->pblocks + 7) / 8 * 8;   // keep the XCD pattern
-    std::vector<int4> items;
-    for (int k = 0; k < n; ++k) build_work1(v[k]->host, k, B->tl, items, false);
-    xcd_order(items, B->tl.kind == LEE_SWEEP_MARCH ? B->tl.waves : 1, B->up_work1);
+    batch_build_work1(B);
     for (int k = 0; k < n; ++k)
         for (int g = 0; g < (int)v[k]->host.gidx.size(); ++g)
             B->up_work2.push_back(make_int4(k, g, v[k]->host.cptr[g], v[k]->host.cptr[g + 1]));
@@ -997,6 +1006,7 @@ lee_status lee_batch_create(lee_instance *const *v, int32_t n, const lee_batch_o
     hipError_t e = hipSuccess;
     e = hipMalloc(&B->d_table, n * sizeof(DevInst));
     if (e == hipSuccess) e = hipMalloc(&B->d_work1, std::max<size_t>(B->up_work1.size(), 1) * sizeof(int4));
+    B->work1_cap = std::max<size_t>(B->up_work1.size(), 1);
     if (e == hipSuccess) e = hipMalloc(&B->d_work2, std::max<size_t>(B->up_work2.size(), 1) * sizeof(int4));
     if (e == hipSuccess) e = hipMalloc(&B->d_sync, SYNC_INTS * sizeof(int));
     if (e == hipSuccess) e = launch_fill_bytes(B->d_sync, SYNC_INTS * sizeof(int), B->stream);
@@ -1094,6 +1104,43 @@ lee_status lee_batch_synchronize(lee_batch *B)
 {
     if (!B) return fail(LEE_E_ARG, "null batch");
     return check_sync(B->d_sync, B->stream);
+}
+
+lee_status lee_batch_set_tiling(lee_batch *B, const lee_tiling *t)
+{
+    if (!B || !t) return fail(LEE_E_ARG, "null argument");
+    if (!tiling_valid(B->prec, *t)) return fail(LEE_E_ARG, "unsupported tiling");
+    HIPCHK(hipStreamSynchronize(B->stream));     // the old list may still be read
+    batch_drop_graph(B);
+    B->tl = *t;
+    batch_build_work1(B);
+    if (B->up_work1.size() > B->work1_cap) {
+        if (B->d_work1) HIPCHK(hipFree(B->d_work1));
+        B->d_work1 = nullptr;
+        HIPCHK(hipMalloc(&B->d_work1, B->up_work1.size() * sizeof(int4)));
+        B->work1_cap = B->up_work1.size();
+    }
+    if (B->nwork1)
+        HIPCHK(hipMemcpyAsync(B->d_work1, B->up_work1.data(), B->nwork1 * sizeof(int4), hipMemcpyHostToDevice,
+                              B->stream));
+    HIPCHK(hipStreamSynchronize(B->stream));
+    return LEE_OK;
+}
+
+lee_status lee_batch_get_tiling(const lee_batch *B, lee_tiling *t)
+{
+    if (!B || !t) return fail(LEE_E_ARG, "null argument");
+    *t = B->tl;
+    return LEE_OK;
+}
+
+lee_status lee_batch_set_graph_steps(lee_batch *B, int32_t steps)
+{
+    if (!B) return fail(LEE_E_ARG, "null batch");
+    if (steps > GRAPH_STEPS_MAX) return fail(LEE_E_ARG, "too many steps per graph");
+    batch_drop_graph(B);
+    B->graphs.per = graph_steps_from(steps);
+    return LEE_OK;
 }
 
 void lee_batch_destroy(lee_batch *B)

@@ -262,6 +262,25 @@ class Batch:
     def synchronize(self):
         check(self.lib.lee_batch_synchronize(self._h), "lee_batch_synchronize")
 
+    def set_tiling(self, kind="tile", vec=0, cols=64, rows=16, waves=1, fused=0):
+        t = make_tiling(kind, vec, cols, rows, waves, fused)
+        check(self.lib.lee_batch_set_tiling(self._h, ctypes.byref(t)), "lee_batch_set_tiling")
+
+    def get_tiling(self) -> dict:
+        t = Tiling()
+        check(self.lib.lee_batch_get_tiling(self._h, ctypes.byref(t)), "lee_batch_get_tiling")
+        d = t.as_dict()
+        d["kind"] = {v: k for k, v in KINDS.items()}[d["kind"]]
+        return d
+
+    def set_graph_steps(self, steps: int):
+        check(self.lib.lee_batch_set_graph_steps(self._h, steps), "lee_batch_set_graph_steps")
+
+    def init_fields(self):
+        """Reset every member to its initial condition (and an unlimited budget)."""
+        for m in self.members:
+            m.init_fields()
+
     def time_kernels(self, n: int):
         a, b, c = c_double(), c_double(), c_double()
         check(self.lib.lee_batch_time_kernels(self._h, n, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),

@@ -1,0 +1,72 @@
+"""Autotuner host logic: candidates, selection, cache keys (no GPU)."""
+import ctypes
+import json
+
+import pytest
+
+import lee_cases as lc
+from paper_2609_24785_amd import tune
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_every_candidate_is_a_supported_tiling(prec):
+    from paper_2609_24785_amd import _lib
+    from paper_2609_24785_amd.lee import Instance, make_tiling
+    inst = Instance(lc.small_cylinder(96), prec, bind=False)
+    lib = _lib.load()
+    cands = tune.candidates(prec)
+    assert len(cands) >= 6
+    assert {c["tiling"]["fused"] for c in cands} == {0, 1}
+    for c in cands:
+        t = make_tiling(**c["tiling"])
+        assert lib.lee_set_tiling(inst._h, ctypes.byref(t)) == 0, c
+        assert c["graph_steps"] > 0
+
+
+def test_select_takes_the_fastest_and_skips_failures():
+    cands = [{"tiling": {"cols": c}, "graph_steps": 16} for c in (1, 2, 3, 4)]
+    times = {1: 5.0, 2: 3.0, 3: None, 4: float("nan")}
+
+    def measure(c):
+        t = times[c["tiling"]["cols"]]
+        if t is None:
+            raise RuntimeError("rejected")
+        return t
+
+    best, table = tune.select(measure, cands)
+    assert best["tiling"]["cols"] == 2 and best["step_us"] == 3.0
+    assert len(table) == 4
+    assert table[2]["step_us"] is None and "rejected" in table[2]["error"]
+    assert table[3]["step_us"] is None
+    with pytest.raises(RuntimeError):
+        tune.select(lambda c: float("inf"), cands)
+
+
+def test_size_class_groups_nearby_problems():
+    a = tune.size_class(1_045_359, 855)
+    assert a == tune.size_class(1_000_000, 830)
+    assert a != tune.size_class(2_200_000, 855)
+    assert a != tune.size_class(1_045_359, 855, members=2)
+    assert tune.cache_key("gfx950:sramecc+:xnack-", "f32", a).startswith("gfx950|f32|")
+
+
+def test_cache_round_trip(tmp_path):
+    p = str(tmp_path / "tune.json")
+    c = tune.TuneCache(p, shipped=False)
+    assert c.get("k") is None
+    choice = {"tiling": {"kind": "tile", "cols": 64, "rows": 16, "fused": 1}, "graph_steps": 16, "step_us": 57.9}
+    c.put("k", choice)
+    assert json.load(open(p))["k"] == choice
+    assert tune.TuneCache(p, shipped=False).get("k") == choice
+    assert tune.TuneCache(p).get("k") == choice          # the file's entries take precedence
+
+
+def test_shipped_table_entries_are_candidates():
+    import os
+    if not os.path.exists(tune.SHIPPED_TABLE):
+        pytest.skip("no shipped table")
+    base = tune.TuneCache(None).base
+    assert base
+    for key, v in base.items():
+        prec = key.split("|")[1]
+        assert {"tiling": v["tiling"], "graph_steps": v["graph_steps"]} in tune.candidates(prec), key
