@@ -136,6 +136,30 @@ def _kernel_times(case, prec: str, n: int, choice=None):
                 ghosts=ghosts, nnz=nnz, kernel=_kernel_name(tiling, prec), alg_bytes=alg)
 
 
+def _copy_rate(nbytes: int = 1 << 30, reps: int = 10) -> float:
+    """Achievable HBM rate: the library's plain copy kernel, GB/s (read + write)."""
+    import torch
+    from paper_2609_24785_amd import _lib
+
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    s = torch.cuda.current_stream()
+    lib = _lib.load()
+    for _ in range(2):
+        _lib.check(lib.lee_stream_copy(b.data_ptr(), a.data_ptr(), nbytes, s.cuda_stream), "copy")
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        _lib.check(lib.lee_stream_copy(b.data_ptr(), a.data_ptr(), nbytes, s.cuda_stream), "copy")
+    e1.record()
+    torch.cuda.synchronize()
+    rate = 2.0 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return rate
+
+
 def _max_rel_l2(a, b, mask):
     from oracle.solver import relative_l2
     return max(relative_l2(x, y, mask) for x, y in zip(a, b))
@@ -164,6 +188,8 @@ def run(args):
     print("[bench] kernel timing", file=sys.stderr, flush=True)
     k32 = _kernel_times(case, "f32", args.kernel_steps, ch32)
     k64 = _kernel_times(case, "f64", args.kernel_steps, ch64)
+
+    copy_gbs = _copy_rate()
 
     import oracle.solver as osv          # error reference and CPU baseline (test infrastructure)
     from oracle.geometry import fluid_mask
@@ -230,6 +256,7 @@ def run(args):
             "kernel": k32["kernel"],
             "alg_bytes_per_launch": alg_bytes,
             "launch_us": k32["sweep_us"],
+            "copy_kernel_GBs": copy_gbs,
         },
         "roofline_f64": {"kernel": k64["kernel"], "achieved": ach64, "frac": ach64 / HBM_PEAK_GBS,
                          "launch_us": k64["sweep_us"]},

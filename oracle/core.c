@@ -23,6 +23,13 @@
  *
  * Fields are (ny + 2F) x (nx + 2F) row-major arrays: the domain plus a frame of
  * F = 5 nodes held at zero on every side.
+ *
+ * Parity: the interior scheme is pinned by the free-field pulse and monopole
+ * closed forms, the walls by the image solution, the plane-wave reflection of
+ * the impedance and the convergence orders (tests).  The outer sponge is a
+ * reading (the paper truncates its domains with radiation conditions instead):
+ * its profile sigma(d) = sigma_max ((W - d) / W)^2 is parity unpinned; a test
+ * checks only that it removes energy.
  */
 #include <math.h>
 #include <stdlib.h>
