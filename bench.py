@@ -25,6 +25,8 @@ benchmark workload.
 
 Other modes: --extras (a second JSON line: the flat-wall case against the
 oracle, the 4096^2 monopole case, and the batch of 256 uneven instances),
+--serve (the served request stream: Poisson arrivals, continuous batching,
+admission by HBM budget; throughput and p50/p99 latency),
 --profile-run (a short fixed sequence for rocprofv3), and
 --counters FETCH_CSV WRITE_CSV KERNEL (turns two rocprofv3 --pmc counter
 files of the profile run into KERNEL's HBM traffic per launch, calibrated by
@@ -35,6 +37,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -360,6 +363,44 @@ def extras(args):
     return 0
 
 
+def serve(args):
+    """Served request stream: a JSON line with throughput and p50/p99 latency."""
+    import numpy as np
+    import torch
+
+    import lee_cases as lc
+    from paper_2609_24785_amd.serve import GpuBackend, Request, Server
+
+    torch.cuda.set_device(0)
+    reqs = [Request(k, c, t) for k, (t, c) in
+            enumerate(lc.request_stream(seed=26091, rate=args.serve_rate, duration=args.serve_duration))]
+    print(f"[serve] {len(reqs)} requests over {args.serve_duration} s at {args.serve_rate}/s", file=sys.stderr,
+          flush=True)
+    be = GpuBackend("f32")
+    try:
+        srv = Server(be, budget_bytes=args.serve_budget_gb * 1e9, chunk=args.serve_chunk)
+        res = srv.run(reqs)
+    finally:
+        be.close()
+    ok = [r for r in res if r.error is None]
+    # the reflection estimate at resonance against the exact value
+    dev = []
+    for r in ok:
+        if r.reflection and r.reflection.get("R_est") and r.reflection["R_est"][1] is not None:
+            a, b = r.reflection["R_est"][1], r.reflection["R_exact"][1]
+            dev.append(math.hypot(a[0] - b[0], a[1] - b[1]))
+    out = {"serve": True, "metric": "served solves: throughput and p50/p99 latency", "unit": UNIT,
+           "arrival_rate": args.serve_rate, "window_s": args.serve_duration, "chunk_steps": args.serve_chunk,
+           "budget_gb": args.serve_budget_gb, "dtype": "f32",
+           "value": srv.stats["throughput"], **srv.stats,
+           "mean_steps": float(np.mean([r.steps for r in ok])) if ok else 0.0,
+           "mean_fluid_nodes": float(np.mean([r.nodes for r in ok])) if ok else 0.0,
+           "rejected_reasons": sorted({(r.error or "")[:60] for r in res if r.error}),
+           "reflection_at_resonance_abs_dev_median": float(np.median(dev)) if dev else None}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def profile_run(args):
     """A short fixed sequence for hardware profilers: the benchmark workload
     (FP32, graph replay), then three copies of COPY_BYTES bytes."""
@@ -451,6 +492,11 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=2000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-run", action="store_true")
+    ap.add_argument("--serve", action="store_true", help="the served request stream, as its own JSON line")
+    ap.add_argument("--serve-rate", type=float, default=50.0)
+    ap.add_argument("--serve-duration", type=float, default=2.0)
+    ap.add_argument("--serve-chunk", type=int, default=100)
+    ap.add_argument("--serve-budget-gb", type=float, default=200.0)
     ap.add_argument("--counters", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "KERNEL"))
     ap.add_argument("--tune-cache", default=None, help="JSON file for autotuner choices (over the shipped table)")
     args = ap.parse_args()
@@ -465,6 +511,8 @@ def main():
         return profile_run(args)
     if args.extras:
         return extras(args)
+    if args.serve:
+        return serve(args)
     return run(args)
 
 

@@ -188,6 +188,20 @@ lee_status lee_probe_traces(lee_instance *inst, double *out, int64_t cap, int64_
 /* Synchronising: running DFT amplitudes, out[2k] = Re P_k, out[2k+1] = Im P_k. */
 lee_status lee_probe_dft(lee_instance *inst, double *out);
 
+/*
+ * Watched ghost (Coupling section, steps 1-3): before lee_bind, choose the
+ * ghost whose boundary point is nearest (x, y) (ties: the lowest index;
+ * *ghost receives its index, NULL allowed) and keep a ring of `capacity`
+ * steps of its boundary pressure p_BP and wall normal velocity u_n,BP
+ * (positive into the wall) at the first stage of each step, in FP64.  With
+ * capacity 0 nothing is recorded.  LEE_E_ARG without ghosts.
+ */
+lee_status lee_set_watch(lee_instance *inst, double x, double y, int64_t capacity, int32_t *ghost);
+
+/* The last min(steps, capacity, cap) recorded (p_BP, u_n,BP) pairs, oldest
+ * first, into out[2 * cap]; *n receives the count.  Synchronising. */
+lee_status lee_watch_traces(lee_instance *inst, double *out, int64_t cap, int64_t *n);
+
 /* Synchronising: copy q^n at the domain nodes into caller arrays of
  * ny * nx doubles (row-major, x fastest); any pointer may be NULL. */
 lee_status lee_get_fields(lee_instance *inst, double *p, double *u, double *v);
@@ -198,7 +212,9 @@ lee_status lee_set_fields(lee_instance *inst, const double *p, const double *u, 
 /* Synchronising: ADE states after the last full step, out[2g + {0,1}]. */
 lee_status lee_get_ade_states(lee_instance *inst, double *out);
 
-/* Completed steps (host-side count of issued steps). */
+/* Completed steps: the device's step counter once the stream is idle
+ * (synchronising; budgets of a batch may have idled the instance); before
+ * lee_bind, 0.  Reports a spent fused-stage wait as lee_synchronize does. */
 lee_status lee_get_step(const lee_instance *inst, int64_t *step);
 
 /*
@@ -299,6 +315,16 @@ typedef struct {
  */
 lee_status lee_batch_create(lee_instance *const *v, int32_t n, const lee_batch_opts *opts,
                             lee_batch **out);
+
+/* Membership: add a bound instance (same precision, filter setting and
+ * device; its own stream is synchronised first) or remove one (the batch's
+ * stream is synchronised first).  The device table and work lists are
+ * rebuilt and the captured graphs dropped; the next lee_batch_step_n
+ * captures again.  A batch may become empty (stepping it is then a no-op).
+ * Budgets are per position: set them again after a membership change. */
+lee_status lee_batch_add(lee_batch *b, lee_instance *inst);
+lee_status lee_batch_remove(lee_batch *b, lee_instance *inst);
+lee_status lee_batch_size(const lee_batch *b, int32_t *n);
 
 /* Per-member remaining step budget: a member advances only while its budget
  * is positive (budget decremented on device every step).  n entries. */

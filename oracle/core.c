@@ -56,6 +56,7 @@ typedef struct {
     const double *bir;          /* G*5  Birkhoff mu_i(-r) */
     int ade_kind;               /* 0 rigid, 1 complex pair, 2 real poles */
     double ade[4];              /* complex: a, b, B1, C1; real: l1, l2, A1, A2 */
+    int watch_g;                /* ghost whose p_BP and u_n,BP are recorded (-1: none) */
 } oc_case;
 
 static const double RK_ALPHA[4] = {0.25, 1.0 / 3.0, 0.5, 1.0};
@@ -68,10 +69,11 @@ static long long pad_index(const oc_case *c, long long lin)
 }
 
 /* steps 1-5 for every ghost; writes ghost values into (p, u, v) and the
- * stage value of the auxiliary states into psi_out */
+ * stage value of the auxiliary states into psi_out; when watch is given, the
+ * watched ghost's p_BP and u_n,BP go to watch[0], watch[1] (recording only) */
 static void fill_ghosts(const oc_case *c, double *p, double *u, double *v,
                         const double *psi_in, const double *psi_n, double *psi_out,
-                        double alpha)
+                        double alpha, double *watch)
 {
     int g;
 #pragma omp parallel for schedule(static)
@@ -120,6 +122,10 @@ static void fill_ghosts(const oc_case *c, double *p, double *u, double *v,
             pg += B[i] * fp[i];
             ung += L[i] * un[i];
             utg += L[i] * ut[i];
+        }
+        if (watch && g == c->watch_g) {
+            watch[0] = pBP;
+            watch[1] = U;
         }
         long long q = pad_index(c, c->gidx[g]);
         p[q] = pg;
@@ -202,11 +208,12 @@ static void sweep(const oc_case *c, const double *p, const double *u, const doub
  * Advance nsteps full steps from step counter step0.  After every step the
  * probes are sampled from q^{n+1}: trace[(s*np + k)*3 + {0,1,2}] = p, u, v at
  * probe k, with 4x4 interpolation weights probe_w[k*16 + b*4 + a] applied to
- * node (probe_ij[2k] + a, probe_ij[2k+1] + b).
+ * node (probe_ij[2k] + a, probe_ij[2k+1] + b).  watch (2 per step, may be
+ * NULL) receives the watched ghost's p_BP and u_n,BP of the step's first stage.
  */
 int oc_run(const oc_case *c, double *p, double *u, double *v, double *psi,
            long long step0, int nsteps, int np, const long long *probe_ij,
-           const double *probe_w, double *trace)
+           const double *probe_w, double *trace, double *watch)
 {
     const long long sy = c->nx + 2 * c->F;
     const long long n = sy * (long long)(c->ny + 2 * c->F);
@@ -222,7 +229,7 @@ int oc_run(const oc_case *c, double *p, double *u, double *v, double *psi,
             double *ps = l == 0 ? p : S[0], *us = l == 0 ? u : S[1], *vs = l == 0 ? v : S[2];
             const double *psi_in = l == 0 ? psi : psS;
             double t = ((double)(step0 + s) + RK_C[l]) * c->dt;
-            fill_ghosts(c, ps, us, vs, psi_in, psi, psT, RK_ALPHA[l]);
+            fill_ghosts(c, ps, us, vs, psi_in, psi, psT, RK_ALPHA[l], (watch && l == 0) ? watch + 2 * s : NULL);
             sweep(c, p, u, v, ps, us, vs, T[0], T[1], T[2], RK_ALPHA[l], t);
             for (k = 0; k < 3; ++k) { double *x = S[k]; S[k] = T[k]; T[k] = x; }
             { double *x = psS; psS = psT; psT = x; }

@@ -43,6 +43,7 @@ class _OcCase(ctypes.Structure):
         ("cptr", ctypes.c_void_p), ("cidx", ctypes.c_void_p), ("W", ctypes.c_void_p),
         ("lag", ctypes.c_void_p), ("bir", ctypes.c_void_p),
         ("ade_kind", ctypes.c_int), ("ade", ctypes.c_double * 4),
+        ("watch_g", ctypes.c_int),
     ]
 
 
@@ -54,7 +55,7 @@ def _load():
         _lib.oc_run.restype = ctypes.c_int
         _lib.oc_run.argtypes = [ctypes.POINTER(_OcCase)] + [ctypes.c_void_p] * 4 + [
             ctypes.c_longlong, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
-            ctypes.c_void_p]
+            ctypes.c_void_p, ctypes.c_void_p]
     return _lib
 
 
@@ -115,6 +116,8 @@ class OracleSolver:
         self.v = np.zeros(self.shape)
         self.psi = np.zeros(max(2 * G, 2))
         self.step = 0
+        self.watch_g = -1
+        self.watch_trace = np.zeros((0, 2))
         self._init_fields()
         self.probe_ij, self.probe_w = self._probes()
         self._keep = []
@@ -195,20 +198,37 @@ class OracleSolver:
             vals = (0.0, 0.0, 0.0, 0.0)
         for k in range(4):
             s.ade[k] = vals[k]
+        s.watch_g = -1
         return s
 
     # ---- stepping ---------------------------------------------------------
+    def set_watch(self, x: float, y: float) -> int:
+        """Record, every step, p_BP and u_n,BP (first stage) of the ghost whose
+        boundary point is nearest (x, y) (ties: the lowest ghost index)."""
+        if len(self.gidx) == 0:
+            raise ValueError("no ghost points")
+        d2 = (self.bx - x) * (self.bx - x) + (self.by - y) * (self.by - y)
+        g = int(np.argmin(d2))
+        self._cs.watch_g = g
+        self.watch_g = g
+        return g
+
     def run(self, nsteps: int) -> np.ndarray:
-        """Advance nsteps; returns probe traces [nsteps, nprobes, 3]."""
+        """Advance nsteps; returns probe traces [nsteps, nprobes, 3].  With a
+        watched ghost, its (p_BP, u_n,BP) per step are appended to
+        self.watch_trace."""
         lib = _load()
         npb = len(self.case.probes)
         trace = np.zeros((max(nsteps, 1), max(npb, 1), 3))
+        watch = np.zeros((max(nsteps, 1), 2))
         rc = lib.oc_run(ctypes.byref(self._cs), _ptr(self.p), _ptr(self.u), _ptr(self.v),
                         _ptr(self.psi), self.step, nsteps, npb, _ptr(self.probe_ij),
-                        _ptr(self.probe_w), _ptr(trace))
+                        _ptr(self.probe_w), _ptr(trace), _ptr(watch) if self.watch_g >= 0 else None)
         if rc != 0:
             raise MemoryError("oracle core allocation failed")
         self.step += nsteps
+        if self.watch_g >= 0:
+            self.watch_trace = np.concatenate([self.watch_trace, watch[:nsteps]])
         return trace[:nsteps, :npb]
 
     # ---- views ------------------------------------------------------------

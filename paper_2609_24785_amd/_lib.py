@@ -79,8 +79,13 @@ SIGNATURES = {
                                    ctypes.POINTER(c_double)]),
     "lee_stream_copy": (c_int32, [c_void_p, c_void_p, c_size_t, c_void_p]),
     "lee_synchronize": (c_int32, [c_void_p]),
+    "lee_set_watch": (c_int32, [c_void_p, c_double, c_double, c_int64, ctypes.POINTER(c_int32)]),
+    "lee_watch_traces": (c_int32, [c_void_p, c_void_p, c_int64, ctypes.POINTER(c_int64)]),
     "lee_set_graph_steps": (c_int32, [c_void_p, c_int32]),
     "lee_batch_synchronize": (c_int32, [c_void_p]),
+    "lee_batch_add": (c_int32, [c_void_p, c_void_p]),
+    "lee_batch_remove": (c_int32, [c_void_p, c_void_p]),
+    "lee_batch_size": (c_int32, [c_void_p, ctypes.POINTER(c_int32)]),
     "lee_batch_set_tiling": (c_int32, [c_void_p, ctypes.POINTER(Tiling)]),
     "lee_batch_get_tiling": (c_int32, [c_void_p, ctypes.POINTER(Tiling)]),
     "lee_batch_set_graph_steps": (c_int32, [c_void_p, c_int32]),

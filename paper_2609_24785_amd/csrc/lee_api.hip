@@ -92,8 +92,8 @@ size_t work1_capacity(const Host &h)
 }
 
 struct Layout {
-    size_t inst, planes[9], psi[3], iv, goff, cptr, coff, w4, gd, counters, amp, pij, pw, trace, dft, work1, work2,
-        sync, sij, sw, sout, total;
+    size_t inst, planes[9], psi[3], iv, goff, cptr, coff, w4, gd, counters, amp, pij, pw, trace, dft, watch, work1,
+        work2, sync, sij, sw, sout, total;
 };
 
 Layout layout(const Host &h)
@@ -122,6 +122,7 @@ Layout layout(const Host &h)
     L.pw = take(16 * std::max(h.np, 1) * 8);
     L.trace = take(std::max<size_t>((size_t)h.trace_cap * h.np * 3, 1) * 8);
     L.dft = take(2 * std::max(h.np, 1) * 8);
+    L.watch = take(2 * std::max<size_t>((size_t)h.watch_cap, 1) * 8);
     L.work1 = take(work1_capacity(h) * sizeof(int4));
     L.work2 = take(std::max<size_t>(G, 1) * sizeof(int4));
     L.sync = take(SYNC_INTS * sizeof(int));
@@ -443,6 +444,53 @@ lee_status lee_set_probes(lee_instance *I, int32_t np, const double *xy, int64_t
     return LEE_OK;
 }
 
+lee_status lee_set_watch(lee_instance *I, double x, double y, int64_t capacity, int32_t *ghost)
+{
+    if (!I) return fail(LEE_E_ARG, "null instance");
+    if (I->bound) return fail(LEE_E_STATE, "lee_set_watch after lee_bind");
+    Host &h = I->host;
+    if (!h.built) return fail(LEE_E_STATE, "lee_build_ghosts first");
+    if (h.gidx.empty()) return fail(LEE_E_ARG, "no ghost points to watch");
+    if (capacity < 0) return fail(LEE_E_ARG, "negative capacity");
+    int best = 0;
+    double bd = 0.0;
+    for (int g = 0; g < (int)h.gidx.size(); ++g) {
+        const double dx = h.bx[g] - x, dy = h.by[g] - y;
+        const double d2 = dx * dx + dy * dy;
+        if (g == 0 || d2 < bd) {
+            best = g;
+            bd = d2;
+        }
+    }
+    h.watch_g = capacity > 0 ? best : -1;
+    h.watch_cap = capacity;
+    if (ghost) *ghost = best;
+    return LEE_OK;
+}
+
+lee_status lee_watch_traces(lee_instance *I, double *out, int64_t cap, int64_t *n)
+{
+    if (!I || !I->bound || !n) return fail(LEE_E_ARG, "instance not bound or null argument");
+    const Host &h = I->host;
+    *n = 0;
+    if (h.watch_g < 0 || h.watch_cap == 0) return LEE_OK;
+    long long done = 0;
+    HIPCHK(hipMemcpyAsync(&done, I->dev.step, 8, hipMemcpyDeviceToHost, I->stream));
+    std::vector<double> ring(2 * (size_t)h.watch_cap);
+    HIPCHK(hipMemcpyAsync(ring.data(), I->dev.watch, ring.size() * 8, hipMemcpyDeviceToHost, I->stream));
+    HIPCHK(hipStreamSynchronize(I->stream));
+    int64_t m = std::min<int64_t>({(int64_t)done, (int64_t)h.watch_cap, cap});
+    if (m > 0 && !out) return fail(LEE_E_ARG, "null output");
+    const int64_t first = done - m;
+    for (int64_t s = 0; s < m; ++s) {
+        const size_t r = (size_t)((first + s) % h.watch_cap);
+        out[2 * s] = ring[2 * r];
+        out[2 * s + 1] = ring[2 * r + 1];
+    }
+    *n = m;
+    return LEE_OK;
+}
+
 lee_status lee_required_bytes(const lee_instance *I, size_t *dev_bytes)
 {
     if (!I || !dev_bytes) return fail(LEE_E_ARG, "null argument");
@@ -486,6 +534,9 @@ lee_status lee_bind(lee_instance *I, void *dev_ptr, size_t bytes, void *hip_stre
     D.pij = (const int *)(b + L.pij);
     D.pw = (const double *)(b + L.pw);
     D.trace = (double *)(b + L.trace);
+    D.watch = (double *)(b + L.watch);
+    D.watch_cap = h.watch_cap;
+    D.watch_g = h.watch_g;
     D.dft = (double *)(b + L.dft);
     D.trace_cap = h.trace_cap;
     D.dft_start = h.dft_start;
@@ -596,6 +647,7 @@ lee_status lee_init_fields(lee_instance *I)
     for (int k = 0; k < 3; ++k) HIPCHK(launch_fill(prec, I->base + L.psi[k], 2 * std::max<size_t>(h.gidx.size(), 1), s));
     HIPCHK(launch_fill_bytes(I->base + L.trace, std::max<size_t>((size_t)h.trace_cap * h.np * 3, 1) * 8, s));
     HIPCHK(launch_fill_bytes(I->base + L.dft, 2 * std::max(h.np, 1) * 8, s));
+    HIPCHK(launch_fill_bytes(I->base + L.watch, 2 * std::max<size_t>((size_t)h.watch_cap, 1) * 8, s));
     HIPCHK(launch_fill_bytes(I->base + L.sync, SYNC_INTS * sizeof(int), s));
     I->up_counters[0] = 0;
     I->up_counters[1] = LLONG_MAX;
@@ -668,7 +720,12 @@ lee_status lee_get_step(const lee_instance *I, int64_t *step)
 {
     if (!I || !step) return fail(LEE_E_ARG, "null argument");
     *step = I->steps_issued;
-    if (I->bound) return check_sync(I->d_sync, I->stream);
+    if (!I->bound) return LEE_OK;
+    lee_status st = check_sync(I->d_sync, I->stream);  // also waits for the stream
+    if (st != LEE_OK) return st;
+    long long done = 0;                                // budgets may have idled a batch member
+    HIPCHK(hipMemcpy(&done, I->dev.step, 8, hipMemcpyDeviceToHost));
+    *step = done;
     return LEE_OK;
 }
 
@@ -906,10 +963,12 @@ struct lee_batch {
     hipStream_t stream = nullptr;
     int device = -1;
     DevInst *d_table = nullptr;
+    size_t table_cap = 0;
     int4 *d_work1 = nullptr;
     size_t work1_cap = 0;
     int nwork1 = 0;
     int4 *d_work2 = nullptr;
+    size_t work2_cap = 0;
     int nwork2 = 0;
     int *d_sync = nullptr;
     std::vector<DevInst> up_table;
@@ -945,6 +1004,66 @@ hipError_t batch_issue_stage(lee_batch *B, int stage, hipEvent_t *ev = nullptr)
     return e;
 }
 
+// Grows a device array to hold n elements (synchronising before it frees the
+// old one, which queued kernels may still read).
+template <typename T>
+hipError_t grow(T *&p, size_t &cap, size_t n, hipStream_t s)
+{
+    n = std::max<size_t>(n, 1);
+    if (n <= cap) return hipSuccess;
+    const size_t want = std::max(n, 2 * cap);
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    if (p) hipFree(p);
+    p = nullptr;
+    cap = 0;
+    e = hipMalloc(&p, want * sizeof(T));
+    if (e == hipSuccess) cap = want;
+    return e;
+}
+
+// Instance table and both work lists from the member list, uploaded on the
+// batch's stream; the captured graphs are dropped.
+lee_status batch_rebuild(lee_batch *B)
+{
+    batch_drop_graph(B);
+    const size_t n = B->members.size();
+    B->up_table.clear();
+    B->up_work2.clear();
+    for (size_t k = 0; k < n; ++k) {
+        const lee_instance *I = B->members[k];
+        B->up_table.push_back(I->dev);
+        for (int g = 0; g < (int)I->host.gidx.size(); ++g)
+            B->up_work2.push_back(make_int4((int)k, g, I->host.cptr[g], I->host.cptr[g + 1]));
+    }
+    batch_build_work1(B);
+    B->nwork2 = (int)B->up_work2.size();
+    HIPCHK(grow(B->d_table, B->table_cap, n, B->stream));
+    HIPCHK(grow(B->d_work1, B->work1_cap, B->up_work1.size(), B->stream));
+    HIPCHK(grow(B->d_work2, B->work2_cap, B->up_work2.size(), B->stream));
+    if (n)
+        HIPCHK(hipMemcpyAsync(B->d_table, B->up_table.data(), n * sizeof(DevInst), hipMemcpyHostToDevice,
+                              B->stream));
+    if (B->nwork1)
+        HIPCHK(hipMemcpyAsync(B->d_work1, B->up_work1.data(), B->nwork1 * sizeof(int4), hipMemcpyHostToDevice,
+                              B->stream));
+    if (B->nwork2)
+        HIPCHK(hipMemcpyAsync(B->d_work2, B->up_work2.data(), B->nwork2 * sizeof(int4), hipMemcpyHostToDevice,
+                              B->stream));
+    HIPCHK(hipStreamSynchronize(B->stream));      // the host staging vectors change with the next rebuild
+    return LEE_OK;
+}
+
+lee_status member_ok(const lee_batch *B, const lee_instance *I)
+{
+    if (!I || !I->bound) return fail(LEE_E_STATE, "every member must be bound");
+    if (I->next_stage != 0) return fail(LEE_E_STATE, "a member has a partial step pending");
+    if (I->host.d.precision != B->prec) return fail(LEE_E_ARG, "mixed precision");
+    if ((I->host.d.filter_sigma > 0.0) != B->filt) return fail(LEE_E_ARG, "mixed filter on/off");
+    if (I->device != B->device) return fail(LEE_E_ARG, "members on different devices");
+    return LEE_OK;
+}
+
 void batch_free(lee_batch *B)
 {
     batch_drop_graph(B);
@@ -953,6 +1072,7 @@ void batch_free(lee_batch *B)
     if (B->d_work2) hipFree(B->d_work2);
     if (B->d_sync) hipFree(B->d_sync);
     B->d_sync = nullptr;
+    B->table_cap = B->work1_cap = B->work2_cap = 0;
     B->d_table = nullptr;
     B->d_work1 = nullptr;
     B->d_work2 = nullptr;
@@ -996,35 +1116,51 @@ lee_status lee_batch_create(lee_instance *const *v, int32_t n, const lee_batch_o
         return fail(LEE_E_ARG, "batch tiling options");
     }
     if (B->pblocks > 0) B->pblocks = (B->pblocks + 7) / 8 * 8;   // keep the XCD pattern
-    batch_build_work1(B);
-    for (int k = 0; k < n; ++k)
-        for (int g = 0; g < (int)v[k]->host.gidx.size(); ++g)
-            B->up_work2.push_back(make_int4(k, g, v[k]->host.cptr[g], v[k]->host.cptr[g + 1]));
-    for (int k = 0; k < n; ++k) B->up_table.push_back(v[k]->dev);
-    B->nwork1 = (int)B->up_work1.size();
-    B->nwork2 = (int)B->up_work2.size();
-    hipError_t e = hipSuccess;
-    e = hipMalloc(&B->d_table, n * sizeof(DevInst));
-    if (e == hipSuccess) e = hipMalloc(&B->d_work1, std::max<size_t>(B->up_work1.size(), 1) * sizeof(int4));
-    B->work1_cap = std::max<size_t>(B->up_work1.size(), 1);
-    if (e == hipSuccess) e = hipMalloc(&B->d_work2, std::max<size_t>(B->up_work2.size(), 1) * sizeof(int4));
-    if (e == hipSuccess) e = hipMalloc(&B->d_sync, SYNC_INTS * sizeof(int));
+    hipError_t e = hipMalloc(&B->d_sync, SYNC_INTS * sizeof(int));
     if (e == hipSuccess) e = launch_fill_bytes(B->d_sync, SYNC_INTS * sizeof(int), B->stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(B->d_table, B->up_table.data(), n * sizeof(DevInst), hipMemcpyHostToDevice, B->stream);
-    if (e == hipSuccess && B->nwork1)
-        e = hipMemcpyAsync(B->d_work1, B->up_work1.data(), B->nwork1 * sizeof(int4), hipMemcpyHostToDevice,
-                           B->stream);
-    if (e == hipSuccess && B->nwork2)
-        e = hipMemcpyAsync(B->d_work2, B->up_work2.data(), B->nwork2 * sizeof(int4), hipMemcpyHostToDevice,
-                           B->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(B->stream);
     if (e != hipSuccess) {
         batch_free(B);
         delete B;
         return hip_fail(e, "batch set-up");
     }
+    lee_status st = batch_rebuild(B);
+    if (st != LEE_OK) {
+        batch_free(B);
+        delete B;
+        return st;
+    }
     *out = B;
+    return LEE_OK;
+}
+
+lee_status lee_batch_add(lee_batch *B, lee_instance *I)
+{
+    if (!B) return fail(LEE_E_ARG, "null batch");
+    lee_status st = member_ok(B, I);
+    if (st != LEE_OK) return st;
+    if (std::find(B->members.begin(), B->members.end(), I) != B->members.end())
+        return fail(LEE_E_ARG, "already a member");
+    HIPCHK(hipStreamSynchronize(I->stream));      // its set-up ran on its own stream
+    B->members.push_back(I);
+    st = batch_rebuild(B);
+    if (st != LEE_OK) B->members.pop_back();
+    return st;
+}
+
+lee_status lee_batch_remove(lee_batch *B, lee_instance *I)
+{
+    if (!B || !I) return fail(LEE_E_ARG, "null argument");
+    auto it = std::find(B->members.begin(), B->members.end(), I);
+    if (it == B->members.end()) return fail(LEE_E_ARG, "not a member");
+    HIPCHK(hipStreamSynchronize(B->stream));      // no queued step may still use it
+    B->members.erase(it);
+    return batch_rebuild(B);
+}
+
+lee_status lee_batch_size(const lee_batch *B, int32_t *n)
+{
+    if (!B || !n) return fail(LEE_E_ARG, "null argument");
+    *n = (int32_t)B->members.size();
     return LEE_OK;
 }
 
@@ -1047,7 +1183,7 @@ lee_status lee_batch_step_n(lee_batch *B, int64_t n)
 {
     if (!B) return fail(LEE_E_ARG, "null batch");
     if (n < 0) return fail(LEE_E_ARG, "n < 0");
-    if (n == 0) return LEE_OK;
+    if (n == 0 || B->members.empty()) return LEE_OK;
     lee_status st = run_steps(B->graphs, B->stream, n, [B]() {
         hipError_t e = hipSuccess;
         for (int l = 0; l < 4 && e == hipSuccess; ++l) e = batch_issue_stage(B, l);
@@ -1061,6 +1197,7 @@ lee_status lee_batch_step_n(lee_batch *B, int64_t n)
 lee_status lee_batch_time_kernels(lee_batch *B, int64_t n, double *sweep_us, double *ghost_us, double *step_us)
 {
     if (!B) return fail(LEE_E_ARG, "null batch");
+    if (B->members.empty()) return fail(LEE_E_STATE, "empty batch");
     if (n <= 0) return fail(LEE_E_ARG, "n must be positive");
     int blocks = 0;
     const int per = B->tl.kind == LEE_SWEEP_MARCH ? B->tl.waves : 1;
@@ -1110,21 +1247,9 @@ lee_status lee_batch_set_tiling(lee_batch *B, const lee_tiling *t)
 {
     if (!B || !t) return fail(LEE_E_ARG, "null argument");
     if (!tiling_valid(B->prec, *t)) return fail(LEE_E_ARG, "unsupported tiling");
-    HIPCHK(hipStreamSynchronize(B->stream));     // the old list may still be read
-    batch_drop_graph(B);
+    HIPCHK(hipStreamSynchronize(B->stream));     // the old lists may still be read
     B->tl = *t;
-    batch_build_work1(B);
-    if (B->up_work1.size() > B->work1_cap) {
-        if (B->d_work1) HIPCHK(hipFree(B->d_work1));
-        B->d_work1 = nullptr;
-        HIPCHK(hipMalloc(&B->d_work1, B->up_work1.size() * sizeof(int4)));
-        B->work1_cap = B->up_work1.size();
-    }
-    if (B->nwork1)
-        HIPCHK(hipMemcpyAsync(B->d_work1, B->up_work1.data(), B->nwork1 * sizeof(int4), hipMemcpyHostToDevice,
-                              B->stream));
-    HIPCHK(hipStreamSynchronize(B->stream));
-    return LEE_OK;
+    return batch_rebuild(B);
 }
 
 lee_status lee_batch_get_tiling(const lee_batch *B, lee_tiling *t)

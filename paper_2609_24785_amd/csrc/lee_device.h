@@ -31,6 +31,9 @@ struct DevInst {
     const double *pw;       // probe weights, 16 per probe
     double *trace;          // ring of trace_cap steps x np x 3
     double *dft;            // 2 per probe: sum p exp(-i omega t)
+    double *watch;          // ring of watch_cap steps x (p_BP, u_n,BP) of ghost watch_g
+    long long watch_cap;
+    int watch_g;            // -1: none
     long long trace_cap;
     long long dft_start, dft_count;
     double dft_omega;

@@ -150,6 +150,11 @@ __device__ __forceinline__ void ghost_item(const DevInst *__restrict__ insts, co
     }
     // steps 4-5: Neumann for p (dp/dn = +du_n/dt in the wall-to-fluid frame),
     // Dirichlet for u.n (= -u_n), free for u.t
+    if (stage == 0 && g == I.watch_g && I.watch_cap > 0) {   // recording only
+        double *wr = I.watch + 2 * (*I.step % I.watch_cap);
+        wr[0] = (double)a0;
+        wr[1] = (double)Un;
+    }
     const T pg = aN + gdv.v[3] * ((T)I.h * Ud);
     const T un = aD + gdv.v[2] * (-Un);
     const T ut = aF;

@@ -78,7 +78,10 @@ class Instance:
     """One solve: set-up on the host, fields and lists in caller-owned HBM."""
 
     def __init__(self, case, precision: str = "f32", device: str = "cuda:0", stream=None,
-                 trace_capacity: Optional[int] = None, dft: Optional[tuple] = None, bind: bool = True):
+                 trace_capacity: Optional[int] = None, dft: Optional[tuple] = None, bind: bool = True,
+                 watch: Optional[tuple] = None):
+        """watch = (x, y, capacity): record p_BP and u_n,BP of the ghost whose
+        boundary point is nearest (x, y) for up to `capacity` steps."""
         self.lib = load()
         self.case = case
         self.precision = precision
@@ -99,6 +102,14 @@ class Instance:
             if st != 0:
                 self.close()
                 check(st, "lee_set_probes")
+        self.watch_g = -1
+        if watch is not None:
+            g = ctypes.c_int32()
+            st = self.lib.lee_set_watch(self._h, float(watch[0]), float(watch[1]), int(watch[2]), ctypes.byref(g))
+            if st != 0:
+                self.close()
+                check(st, "lee_set_watch")
+            self.watch_g = g.value
         self.buf = None
         self.stream = None
         if bind:
@@ -174,6 +185,14 @@ class Instance:
         out = np.zeros((max(m, 1), npb, 3))
         check(self.lib.lee_probe_traces(self._h, _ptr(out), m, ctypes.byref(done)), "lee_probe_traces")
         return out[:done.value]
+
+    def watch_traces(self, cap: Optional[int] = None) -> np.ndarray:
+        """Recorded (p_BP, u_n,BP) per step of the watched ghost, oldest first."""
+        cap = cap if cap is not None else max(self.step, 1)
+        out = np.zeros((max(cap, 1), 2))
+        n = c_int64()
+        check(self.lib.lee_watch_traces(self._h, _ptr(out), cap, ctypes.byref(n)), "lee_watch_traces")
+        return out[:n.value]
 
     def dft(self):
         out = np.zeros(2 * len(self.case.probes))
@@ -251,6 +270,19 @@ class Batch:
         self._h = c_void_p()
         check(self.lib.lee_batch_create(arr, len(members), ctypes.byref(opts), ctypes.byref(self._h)),
               "lee_batch_create")
+
+    def add(self, inst: "Instance"):
+        check(self.lib.lee_batch_add(self._h, inst._h), "lee_batch_add")
+        self.members.append(inst)
+
+    def remove(self, inst: "Instance"):
+        check(self.lib.lee_batch_remove(self._h, inst._h), "lee_batch_remove")
+        self.members.remove(inst)
+
+    def __len__(self) -> int:
+        n = ctypes.c_int32()
+        check(self.lib.lee_batch_size(self._h, ctypes.byref(n)), "lee_batch_size")
+        return n.value
 
     def set_budget(self, steps: Sequence[int]):
         a = np.ascontiguousarray(np.asarray(steps, dtype=np.int64))

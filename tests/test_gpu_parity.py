@@ -55,6 +55,28 @@ def _compare(case, steps, prec, tol, tiling=None):
     return inst, ora
 
 
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-9), ("f32", 1e-4)])
+def test_watched_ghost_traces_match_oracle(prec, tol):
+    """p_BP and u_n,BP of the ghost nearest the pulse, every step, against the
+    oracle's (the boundary read-out and the ADE wall velocity themselves)."""
+    Instance, _ = _lee()
+    case = lc.small_cylinder(160, 60)
+    _say(f"[watch] {case.name} {prec}")
+    inst = Instance(case, prec, watch=(case.ic.xs, case.ic.ys, 100))
+    inst.step_n(60)
+    inst.synchronize()
+    got = inst.watch_traces()
+    ora = OracleSolver(case)
+    g = ora.set_watch(case.ic.xs, case.ic.ys)
+    assert g == inst.watch_g
+    ora.run(60)
+    ref = ora.watch_trace
+    assert got.shape == ref.shape == (60, 2)
+    for k in range(2):
+        assert np.abs(ref[:, k]).max() > 0
+        assert np.abs(got[:, k] - ref[:, k]).max() <= tol * np.abs(ref[:, k]).max()
+
+
 def test_flat_wall_fp64_matches_oracle():
     _compare(lc.flat_wall_201(500), 500, "f64", 1e-9)
 

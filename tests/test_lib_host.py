@@ -138,3 +138,13 @@ def test_unbound_calls_are_state_errors():
     assert inst.get_tiling()["cols"] == 256
     inst.set_tiling("march", vec=2, rows=8, waves=2)
     assert inst.get_tiling()["kind"] == "march"
+
+
+def test_watched_ghost_choice_matches_oracle():
+    """The ghost nearest a point (by boundary point, lowest index on ties) is
+    the same on both sides."""
+    for case, xy in ((lc.small_cylinder(96), (1.9, 0.4)), (lc.cylinder_pulse_1024(10), (4.0, 0.0)),
+                     (lc.flat_wall_201(), (20.0 * 0.5, -20.0 * 0.866)), (lc.small_cylinder(200), (0.0, 0.0))):
+        from paper_2609_24785_amd.lee import Instance
+        inst = Instance(case, "f32", bind=False, watch=(xy[0], xy[1], 10))
+        assert inst.watch_g == OracleSolver(case).set_watch(*xy)
