@@ -181,7 +181,7 @@ def run(args):
     from paper_2609_24785_amd import tune
     case = lc.cylinder_pulse_1024(steps=args.steps)
     print("[bench] autotuning the launch configuration", file=sys.stderr, flush=True)
-    cache = tune.TuneCache(args.tune_cache)             # the shipped table, then live trials
+    cache = tune.TuneCache(args.tune_cache, shipped=not args.retune)   # the shipped table, then live trials
     ch32 = tune.tune_case(case, "f32", cache)
     ch64 = tune.tune_case(case, "f64", cache)
     print(f"[bench] {case.name}: {args.steps} steps after {args.warmup} warm-up, FP32 then FP64",
@@ -303,7 +303,7 @@ def extras(args):
 
     torch.cuda.set_device(0)
     out = {"extras": True}
-    cache = tune.TuneCache(args.tune_cache)
+    cache = tune.TuneCache(args.tune_cache, shipped=not args.retune)
     print("[extras] flat wall 201^2 FP64 against the oracle", file=sys.stderr, flush=True)
     flat = lc.flat_wall_201(500)
     rf = _timed(flat, "f64", 500, 0)
@@ -499,6 +499,7 @@ def main():
     ap.add_argument("--serve-budget-gb", type=float, default=200.0)
     ap.add_argument("--counters", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "KERNEL"))
     ap.add_argument("--tune-cache", default=None, help="JSON file for autotuner choices (over the shipped table)")
+    ap.add_argument("--retune", action="store_true", help="ignore the shipped tuning table (trials only)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU (asked for {args.gpus}): the stage is a single-GPU kernel and this "

@@ -49,6 +49,10 @@ struct lee_instance {
     int4 *d_work1 = nullptr;
     size_t work1_cap = 0;
     int nwork1 = 0;
+    int2 *d_aux = nullptr;          // per work slot: range of its ghost patches
+    int tile0 = 0;                  // fused launch: id of the first tile workgroup
+    int2 *d_patch = nullptr;        // (LDS index, plane offset) of ghost nodes read by fused tiles
+    size_t patch_cap = 0;
     int4 *d_work2 = nullptr;
     int nwork2 = 0;
     int *d_sync = nullptr;          // fused-stage counters and error flag
@@ -58,6 +62,7 @@ struct lee_instance {
     std::vector<char> up_w4, up_gd;
     std::vector<int> up_goff, up_coff;
     std::vector<int4> up_work1, up_iv;
+    std::vector<int2> up_aux, up_patch;
     std::vector<int4> up_work2;
     long long up_counters[3] = {0, LLONG_MAX, 1};
     double up_amp[4] = {0, 0, 0, 0};
@@ -83,6 +88,10 @@ int pitch_of(const Host &h)
 
 size_t plane_elems(const Host &h) { return (size_t)(h.d.ny + 2 * FRAME) * pitch_of(h); }
 
+// A ghost node lies in the stencil region of at most 4 row tiles (rows >= 4)
+// and 2 column blocks (cols >= 64).
+size_t patch_capacity(const Host &h) { return 8 * h.gidx.size() + 64; }
+
 size_t work1_capacity(const Host &h)
 {
     const int ow_min = 64;                       // narrowest strip: 64-column tiles
@@ -93,7 +102,7 @@ size_t work1_capacity(const Host &h)
 
 struct Layout {
     size_t inst, planes[9], psi[3], iv, goff, cptr, coff, w4, gd, counters, amp, pij, pw, trace, dft, watch, work1,
-        work2, sync, sij, sw, sout, total;
+        aux, patch, work2, sync, sij, sw, sout, total;
 };
 
 Layout layout(const Host &h)
@@ -124,6 +133,8 @@ Layout layout(const Host &h)
     L.dft = take(2 * std::max(h.np, 1) * 8);
     L.watch = take(2 * std::max<size_t>((size_t)h.watch_cap, 1) * 8);
     L.work1 = take(work1_capacity(h) * sizeof(int4));
+    L.aux = take(work1_capacity(h) * sizeof(int2));
+    L.patch = take(patch_capacity(h) * sizeof(int2));
     L.work2 = take(std::max<size_t>(G, 1) * sizeof(int4));
     L.sync = take(SYNC_INTS * sizeof(int));
     L.sij = take(2 * SAMPLE_MAX * 4);
@@ -144,21 +155,77 @@ lee_status hip_fail(hipError_t e, const char *what)
         if (e_ != hipSuccess) return hip_fail(e_, #x); \
     } while (0)
 
-// Reorder work so that workgroup b (which the hardware places on XCD b mod 8)
-// takes unit (b mod 8) * per + b / 8: each XCD gets a contiguous run of
-// neighbouring tiles and shares their halos in its own L2.  Idle slots
-// (instance -1) keep the pattern when the count is not a multiple of 8.
-void xcd_order(const std::vector<int4> &items, int per_unit, std::vector<int4> &out)
+// Slot order of the work list: workgroup b (which the hardware places on XCD
+// b mod 8) takes unit (b mod 8) * per + b / 8, so each XCD gets a contiguous
+// run of neighbouring tiles and shares their halos in its own L2.  Returns,
+// per slot, the item index or -1 for an idle slot (they keep the pattern
+// when the count is not a multiple of 8).
+std::vector<int> xcd_slots(size_t n_items, int per_unit)
 {
-    const int units = (int)((items.size() + per_unit - 1) / per_unit);
+    std::vector<int> out;
+    const int units = (int)((n_items + per_unit - 1) / per_unit);
     const int per = (units + 7) / 8;
     for (int b = 0; b < 8 * per; ++b) {
         const int su = (b % 8) * per + b / 8;
         for (int w = 0; w < per_unit; ++w) {
             const size_t k = (size_t)su * per_unit + w;
-            out.push_back(su < units && k < items.size() ? items[k] : make_int4(-1, 0, 0, 1));
+            out.push_back(su < units && k < n_items ? (int)k : -1);
         }
     }
+    return out;
+}
+
+// Sweep items in slot order, with each dependent tile's range of patch
+// entries in aux (slot-aligned) and the entries themselves in patch.  In the
+// fused form the first ncar workgroups carry the ghost fill, and dependent
+// tiles wait for them, so no dependent tile may sit in a carrier slot: such
+// tiles are swapped with the first later plain tile (or idle slot) of the
+// same residue mod 8, which keeps them on their XCD.  If too few plain tiles
+// exist, the tiles start after ncar dedicated carrier workgroups instead.
+// Returns the id of the first tile workgroup (0 or ncar rounded up to 8).
+int order_work(const std::vector<int4> &items, const std::vector<std::vector<int2>> &patches, int per_unit,
+               int ncar, std::vector<int4> &out, std::vector<int2> &aux, std::vector<int2> &patch)
+{
+    out.clear();
+    aux.clear();
+    patch.clear();
+    std::vector<int> slots = xcd_slots(items.size(), per_unit);
+    auto dep = [&](int k) { return k >= 0 && (items[k].x & TILE_DEP_BIT); };
+    int tile0 = 0;
+    if (ncar > 0) {
+        int next[8];
+        for (int r = 0; r < 8; ++r) next[r] = ncar + ((r - ncar % 8) + 8) % 8;   // first slot >= ncar of residue r
+        for (int b = 0; b < std::min<int>(ncar, (int)slots.size()) && tile0 == 0; ++b) {
+            if (!dep(slots[b])) continue;
+            int &c = next[b % 8];
+            while (c < (int)slots.size() && dep(slots[c])) c += 8;
+            if (c >= (int)slots.size()) {
+                tile0 = (ncar + 7) / 8 * 8;      // not enough plain tiles: dedicated carriers
+                break;
+            }
+            std::swap(slots[b], slots[c]);
+            c += 8;
+        }
+        if (tile0) slots = xcd_slots(items.size(), per_unit);
+    }
+    for (int k : slots) {
+        if (k < 0) {
+            out.push_back(make_int4(-1, 0, 0, 1));
+            aux.push_back(make_int2(0, 0));
+            continue;
+        }
+        out.push_back(items[k]);
+        const int p0 = (int)patch.size();
+        if (k < (int)patches.size()) patch.insert(patch.end(), patches[k].begin(), patches[k].end());
+        aux.push_back(make_int2(p0, (int)patch.size()));
+    }
+    return tile0;
+}
+
+// Workgroups that carry the ghost fill of a fused launch (16 ghosts each).
+int carriers_for(const lee_tiling &t, size_t nwork2)
+{
+    return (t.kind == LEE_SWEEP_TILE && t.fused) ? (int)((nwork2 + 15) / 16) : 0;
 }
 
 bool tiling_valid(int prec, const lee_tiling &t)
@@ -194,32 +261,29 @@ void default_tiling(lee_instance *I)
     I->tl = default_tiling_for(I->host.d.precision, I->host.d.nx, I->host.d.ny);
 }
 
-// Sweep work list: one item per (column block, row tile) holding fluid nodes.
-// A march item covers 64 vec - 16 output columns and alternates its direction
-// between row tiles; a tile item covers `cols` columns.  Items are grouped so
-// that the consecutive workgroups of one XCD (workgroup id mod 8) cover
-// neighbouring tiles.
-void build_work1(const Host &h, int inst_id, const lee_tiling &t, std::vector<int4> &out, bool xcd)
+// Sweep work list of one instance: one item per (column block, row tile)
+// holding fluid nodes, in natural order.  A march item covers 64 vec - 16
+// output columns and alternates its direction between row tiles; a tile item
+// covers `cols` columns.  For the fused tile sweep, patches (when given)
+// receives per item the ghost nodes its stencils read, as (LDS element index
+// in the tile's copy, plane offset), and items with any are flagged
+// TILE_DEP_BIT.  The stencils of a tile read its own rows over the columns
+// [c0 - 5, c0 + cols + 5) and the 5 rows above and below over [c0, c0 + cols).
+void build_items(const Host &h, int inst_id, const lee_tiling &t, std::vector<int4> &items,
+                 std::vector<std::vector<int2>> *patches)
 {
     const int ow = t.kind == LEE_SWEEP_MARCH ? 64 * t.vec - 16 : t.cols;
-    const int per_unit = t.kind == LEE_SWEEP_MARCH ? t.waves : 1;
     const int rows = t.rows;
     const int strips = (h.d.nx + ow - 1) / ow;
     const int tiles = (h.d.ny + rows - 1) / rows;
-    // fused tile sweep: flag the tiles whose read region (the tile and H = 5
-    // nodes around it) holds a ghost node
-    std::vector<char> dep;
-    if (t.kind == LEE_SWEEP_TILE && t.fused) {
-        dep.assign((size_t)strips * tiles, 0);
-        for (int g : h.gidx) {
-            const int gi = g % h.d.nx, gj = g / h.d.nx;
-            for (int r = std::max(0, (gj - 5) / rows - 1); r < tiles && r * rows - 5 <= gj; ++r)
-                if (gj < r * rows + rows + 5)
-                    for (int s = std::max(0, (gi - 5) / ow - 1); s < strips && s * ow - 5 <= gi; ++s)
-                        if (gi < s * ow + ow + 5) dep[(size_t)r * strips + s] = 1;
-        }
+    const bool fused = t.kind == LEE_SWEEP_TILE && t.fused && patches;
+    // ghost columns by row (ascending: the ghost list is sorted by linear index)
+    std::vector<std::vector<int>> grow_cols;
+    if (fused) {
+        grow_cols.resize(h.d.ny);
+        for (int g : h.gidx) grow_cols[g / h.d.nx].push_back(g % h.d.nx);
     }
-    std::vector<int4> items;
+    const int pitch = pitch_of(h), org = FRAME * pitch + LPAD, LW = ow + 16;
     for (int r = 0; r < tiles; ++r) {
         const int r0 = r * rows, r1 = std::min(r0 + rows, h.d.ny);
         for (int s = 0; s < strips; ++s) {
@@ -231,25 +295,42 @@ void build_work1(const Host &h, int inst_id, const lee_tiling &t, std::vector<in
                     if (iv[2 * q] < iv[2 * q + 1] && iv[2 * q] < c1 && iv[2 * q + 1] > c0) any = true;
             }
             if (!any) continue;
-            const int flag = !dep.empty() && dep[(size_t)r * strips + s] ? TILE_DEP_BIT : 0;
+            std::vector<int2> pl;
+            if (fused) {
+                for (int j = std::max(0, r0 - 5); j < std::min(h.d.ny, r0 + rows + 5); ++j) {
+                    const bool own = j >= r0 && j < r0 + rows;
+                    const int lo = own ? c0 - 5 : c0, hi = own ? c0 + ow + 5 : c0 + ow;
+                    const std::vector<int> &gc = grow_cols[j];
+                    for (auto it = std::lower_bound(gc.begin(), gc.end(), lo); it != gc.end() && *it < hi; ++it)
+                        pl.push_back(make_int2((j - (r0 - 5)) * LW + (*it - (c0 - 8)), org + j * pitch + *it));
+                }
+            }
+            const int flag = pl.empty() ? 0 : TILE_DEP_BIT;
             items.push_back(make_int4(inst_id | flag, c0, r0, (r & 1) ? -r1 : r1));
+            if (patches) patches->push_back(std::move(pl));
         }
     }
-    if (!xcd) {
-        out.insert(out.end(), items.begin(), items.end());
-        return;
-    }
-    xcd_order(items, per_unit, out);
 }
+
+int per_unit_of(const lee_tiling &t) { return t.kind == LEE_SWEEP_MARCH ? t.waves : 1; }
 
 lee_status upload_work1(lee_instance *I)
 {
-    I->up_work1.clear();
-    build_work1(I->host, 0, I->tl, I->up_work1, true);
+    std::vector<int4> items;
+    std::vector<std::vector<int2>> patches;
+    build_items(I->host, 0, I->tl, items, &patches);
+    I->tile0 = order_work(items, patches, per_unit_of(I->tl), carriers_for(I->tl, I->host.gidx.size()),
+                          I->up_work1, I->up_aux, I->up_patch);
     if (I->up_work1.size() > I->work1_cap) return fail(LEE_E_ARG, "tiling produces too many work items");
+    if (I->up_patch.size() > I->patch_cap) return fail(LEE_E_ARG, "tiling produces too many ghost patches");
     I->nwork1 = (int)I->up_work1.size();
     HIPCHK(hipMemcpyAsync(I->d_work1, I->up_work1.data(), I->up_work1.size() * sizeof(int4),
                           hipMemcpyHostToDevice, I->stream));
+    HIPCHK(hipMemcpyAsync(I->d_aux, I->up_aux.data(), I->up_aux.size() * sizeof(int2), hipMemcpyHostToDevice,
+                          I->stream));
+    if (!I->up_patch.empty())
+        HIPCHK(hipMemcpyAsync(I->d_patch, I->up_patch.data(), I->up_patch.size() * sizeof(int2),
+                              hipMemcpyHostToDevice, I->stream));
     return LEE_OK;
 }
 
@@ -308,8 +389,8 @@ bool fused(const lee_tiling &t) { return t.kind == LEE_SWEEP_TILE && t.fused; }
 // Events, when given, bracket the ghost launch (g0, g1) and the sweep or
 // fused launch (s0, s1).
 hipError_t stage_launches(int prec, bool filt, const lee_tiling &t, const DevInst *insts, const int4 *work1,
-                          int nwork1, const int4 *work2, int nwork2, int *sync, int stage, int blocks, hipStream_t s,
-                          hipEvent_t *ev = nullptr)
+                          int nwork1, const int2 *aux, const int2 *patch, int tile0, const int4 *work2, int nwork2,
+                          int *sync, int stage, int blocks, hipStream_t s, hipEvent_t *ev = nullptr)
 {
     hipError_t e = hipSuccess;
     if (ev) hipEventRecord(ev[0], s);
@@ -320,7 +401,8 @@ hipError_t stage_launches(int prec, bool filt, const lee_tiling &t, const DevIns
     }
     if (e != hipSuccess) return e;
     if (fused(t))
-        e = launch_stage(prec, filt, t.cols, t.rows, insts, work1, nwork1, work2, nwork2, stage, sync, SPIN_LIMIT, s);
+        e = launch_stage(prec, filt, t.cols, t.rows, insts, work1, nwork1, aux, patch, tile0, work2, nwork2, stage,
+                         sync, SPIN_LIMIT, s);
     else
         e = sweep(prec, filt, t, insts, work1, nwork1, stage, blocks, s);
     if (ev) hipEventRecord(ev[3], s);
@@ -331,7 +413,8 @@ hipError_t issue_stage(lee_instance *I, int stage, hipEvent_t *ev = nullptr)
 {
     const int prec = I->host.d.precision;
     hipError_t e = stage_launches(prec, I->host.d.filter_sigma > 0.0, I->tl, I->d_inst, I->d_work1, I->nwork1,
-                                  I->d_work2, I->nwork2, I->d_sync, stage, 0, I->stream, ev);
+                                  I->d_aux, I->d_patch, I->tile0, I->d_work2, I->nwork2, I->d_sync, stage, 0,
+                                  I->stream, ev);
     if (e != hipSuccess) return e;
     if (stage == 3) e = launch_step_end(prec, I->d_inst, 1, I->stream);
     return e;
@@ -621,6 +704,9 @@ lee_status lee_bind(lee_instance *I, void *dev_ptr, size_t bytes, void *hip_stre
     HIPCHK(hipMemcpyAsync(I->d_inst, &I->dev, sizeof(DevInst), hipMemcpyHostToDevice, s));
     I->d_work1 = (int4 *)(b + L.work1);
     I->work1_cap = work1_capacity(h);
+    I->d_aux = (int2 *)(b + L.aux);
+    I->d_patch = (int2 *)(b + L.patch);
+    I->patch_cap = patch_capacity(h);
     I->d_work2 = (int4 *)(b + L.work2);
     I->up_work2.resize(G);
     for (size_t g = 0; g < G; ++g) I->up_work2[g] = make_int4(0, (int)g, h.cptr[g], h.cptr[g + 1]);
@@ -912,7 +998,8 @@ lee_status lee_time_kernels(lee_instance *I, int64_t n, double *sweep_us, double
         for (int64_t k = 0; k < 4 * n && e == hipSuccess; ++k) {
             const int l = (int)(k & 3);
             e = fused(I->tl) ? launch_stage(prec, filt, I->tl.cols, I->tl.rows, I->d_inst, I->d_work1, I->nwork1,
-                                            I->d_work2, I->nwork2, l, I->d_sync, SPIN_LIMIT, I->stream)
+                                            I->d_aux, I->d_patch, I->tile0, I->d_work2, I->nwork2, l, I->d_sync,
+                                            SPIN_LIMIT, I->stream)
                              : sweep(prec, filt, I->tl, I->d_inst, I->d_work1, I->nwork1, l, 0, I->stream);
         }
         return e;
@@ -973,6 +1060,10 @@ struct lee_batch {
     int *d_sync = nullptr;
     std::vector<DevInst> up_table;
     std::vector<int4> up_work1;
+    std::vector<int2> up_aux, up_patch;
+    int2 *d_aux = nullptr, *d_patch = nullptr;
+    size_t aux_cap = 0, patch_cap = 0;
+    int tile0 = 0;
     std::vector<int4> up_work2;
     std::vector<long long> up_budget;      // (budget, active) pairs
     StepGraphs graphs;
@@ -982,13 +1073,17 @@ namespace {
 
 void batch_drop_graph(lee_batch *B) { B->graphs.drop(); }
 
-// The sweep work list over all members, in XCD-aware order.
+// The sweep work list over all members, in XCD-aware order, with the ghost
+// patches of the fused form.
 void batch_build_work1(lee_batch *B)
 {
     std::vector<int4> items;
-    for (size_t k = 0; k < B->members.size(); ++k) build_work1(B->members[k]->host, (int)k, B->tl, items, false);
-    B->up_work1.clear();
-    xcd_order(items, B->tl.kind == LEE_SWEEP_MARCH ? B->tl.waves : 1, B->up_work1);
+    std::vector<std::vector<int2>> patches;
+    for (size_t k = 0; k < B->members.size(); ++k) build_items(B->members[k]->host, (int)k, B->tl, items, &patches);
+    size_t G = 0;
+    for (auto *I : B->members) G += I->host.gidx.size();
+    B->tile0 = order_work(items, patches, per_unit_of(B->tl), carriers_for(B->tl, G), B->up_work1, B->up_aux,
+                          B->up_patch);
     B->nwork1 = (int)B->up_work1.size();
 }
 
@@ -997,8 +1092,8 @@ hipError_t batch_issue_stage(lee_batch *B, int stage, hipEvent_t *ev = nullptr)
     int blocks = 0;
     const int per = B->tl.kind == LEE_SWEEP_MARCH ? B->tl.waves : 1;
     if (B->pblocks > 0) blocks = std::min(B->pblocks, (B->nwork1 + per - 1) / per);
-    hipError_t e = stage_launches(B->prec, B->filt, B->tl, B->d_table, B->d_work1, B->nwork1, B->d_work2, B->nwork2,
-                                  B->d_sync, stage, blocks, B->stream, ev);
+    hipError_t e = stage_launches(B->prec, B->filt, B->tl, B->d_table, B->d_work1, B->nwork1, B->d_aux, B->d_patch,
+                                  B->tile0, B->d_work2, B->nwork2, B->d_sync, stage, blocks, B->stream, ev);
     if (e != hipSuccess) return e;
     if (stage == 3) e = launch_step_end(B->prec, B->d_table, (int)B->members.size(), B->stream);
     return e;
@@ -1041,6 +1136,8 @@ lee_status batch_rebuild(lee_batch *B)
     HIPCHK(grow(B->d_table, B->table_cap, n, B->stream));
     HIPCHK(grow(B->d_work1, B->work1_cap, B->up_work1.size(), B->stream));
     HIPCHK(grow(B->d_work2, B->work2_cap, B->up_work2.size(), B->stream));
+    HIPCHK(grow(B->d_aux, B->aux_cap, B->up_aux.size(), B->stream));
+    HIPCHK(grow(B->d_patch, B->patch_cap, B->up_patch.size(), B->stream));
     if (n)
         HIPCHK(hipMemcpyAsync(B->d_table, B->up_table.data(), n * sizeof(DevInst), hipMemcpyHostToDevice,
                               B->stream));
@@ -1050,6 +1147,12 @@ lee_status batch_rebuild(lee_batch *B)
     if (B->nwork2)
         HIPCHK(hipMemcpyAsync(B->d_work2, B->up_work2.data(), B->nwork2 * sizeof(int4), hipMemcpyHostToDevice,
                               B->stream));
+    if (!B->up_aux.empty())
+        HIPCHK(hipMemcpyAsync(B->d_aux, B->up_aux.data(), B->up_aux.size() * sizeof(int2), hipMemcpyHostToDevice,
+                              B->stream));
+    if (!B->up_patch.empty())
+        HIPCHK(hipMemcpyAsync(B->d_patch, B->up_patch.data(), B->up_patch.size() * sizeof(int2),
+                              hipMemcpyHostToDevice, B->stream));
     HIPCHK(hipStreamSynchronize(B->stream));      // the host staging vectors change with the next rebuild
     return LEE_OK;
 }
@@ -1071,8 +1174,11 @@ void batch_free(lee_batch *B)
     if (B->d_work1) hipFree(B->d_work1);
     if (B->d_work2) hipFree(B->d_work2);
     if (B->d_sync) hipFree(B->d_sync);
+    if (B->d_aux) hipFree(B->d_aux);
+    if (B->d_patch) hipFree(B->d_patch);
     B->d_sync = nullptr;
-    B->table_cap = B->work1_cap = B->work2_cap = 0;
+    B->d_aux = B->d_patch = nullptr;
+    B->table_cap = B->work1_cap = B->work2_cap = B->aux_cap = B->patch_cap = 0;
     B->d_table = nullptr;
     B->d_work1 = nullptr;
     B->d_work2 = nullptr;
@@ -1213,7 +1319,8 @@ lee_status lee_batch_time_kernels(lee_batch *B, int64_t n, double *sweep_us, dou
         for (int64_t k = 0; k < 4 * n && e == hipSuccess; ++k) {
             const int l = (int)(k & 3);
             e = fused(B->tl) ? launch_stage(B->prec, B->filt, B->tl.cols, B->tl.rows, B->d_table, B->d_work1,
-                                            B->nwork1, B->d_work2, B->nwork2, l, B->d_sync, SPIN_LIMIT, B->stream)
+                                            B->nwork1, B->d_aux, B->d_patch, B->tile0, B->d_work2, B->nwork2, l,
+                                            B->d_sync, SPIN_LIMIT, B->stream)
                              : sweep(B->prec, B->filt, B->tl, B->d_table, B->d_work1, B->nwork1, l, blocks, B->stream);
         }
         return e;

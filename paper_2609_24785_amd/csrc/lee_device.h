@@ -61,11 +61,16 @@ hipError_t launch_sweep(int prec, int vec, bool filt, int waves, const DevInst *
 bool tile_shape_supported(int prec, int tx, int ty);
 hipError_t launch_tile(int prec, bool filt, int tx, int ty, const DevInst *insts, const int4 *work, int nwork,
                        int stage, int blocks, hipStream_t s);
-// One launch for a stage with the tile sweep: ghost workgroups first, then
-// the tiles (items flagged with DEP_BIT wait for the ghosts).  sync holds 4
-// stage counters and an error flag (5 ints, zero before first use).
+// One launch for a stage with the tile sweep: the first ceil(nwork2 / 16)
+// workgroups fill 16 ghosts each, tile k runs in workgroup tile0 + k (the
+// caller keeps dependent tiles out of the carrier workgroups).  Items flagged
+// with TILE_DEP_BIT wait for the ghosts and patch the ghost nodes they read:
+// aux[k] = [begin, end) in patch, whose entries are (LDS element index in the
+// tile's copy, plane offset).  sync holds 4 stage counters and an error flag
+// (5 ints, zero before first use).
 hipError_t launch_stage(int prec, bool filt, int tx, int ty, const DevInst *insts, const int4 *work1, int nwork1,
-                        const int4 *work2, int nwork2, int stage, int *sync, int spin_limit, hipStream_t s);
+                        const int2 *aux, const int2 *patch, int tile0, const int4 *work2, int nwork2, int stage,
+                        int *sync, int spin_limit, hipStream_t s);
 constexpr int TILE_DEP_BIT = 1 << 30;
 constexpr int SYNC_INTS = 8;
 constexpr int SPIN_LIMIT = 1 << 20;             // polls before a ghost wait gives up (about a second)

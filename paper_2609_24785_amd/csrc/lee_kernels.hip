@@ -516,9 +516,24 @@ __device__ __forceinline__ void pin_sums(T (&rp)[VEC], T (&ru)[VEC], T (&rv)[VEC
     for (int e = 0; e < VEC; ++e) asm volatile("" : "+v"(rp[e]), "+v"(ru[e]), "+v"(rv[e])::"memory");
 }
 
+// A tile of a fused stage whose stencils read ghost nodes: it waits until the
+// counter reaches `need` published ghost shares (bounded by spin_limit polls,
+// then the error flag) and then overwrites the ghost nodes in its LDS copy;
+// patch[p0, p1) holds (LDS element index, plane offset) for each ghost node
+// it reads.
+struct GhostDep {
+    int *count;
+    int *error;
+    int need;
+    int spin_limit;
+    const int2 *patch;
+    int p0, p1;
+};
+
 // One tile: wk = {instance, first column, first row, +-(end row)}.
 template <typename T, int VEC, bool FILT, int TX, int TY>
-__device__ __forceinline__ void tile_body(const DevInst *__restrict__ insts, const int4 wk, int stage)
+__device__ __forceinline__ void tile_body(const DevInst *__restrict__ insts, const int4 wk, int stage,
+                                          const GhostDep *dep)
 {
     constexpr int NT = 256;
     constexpr int NCX = TX / VEC;                // column groups
@@ -582,8 +597,33 @@ __device__ __forceinline__ void tile_body(const DevInst *__restrict__ insts, con
     GLOBAL T *Po = gp<T>(I.f[ob][0]);
     GLOBAL T *Uo = gp<T>(I.f[ob][1]);
     GLOBAL T *Vo = gp<T>(I.f[ob][2]);
+    if (dep && tid == 0) {
+        // while the copy is in flight: relaxed polls (an acquire load would
+        // invalidate this XCD's L2 on every poll), then one acquire fence
+        int polls = 0;
+        while (__hip_atomic_load(dep->count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < dep->need) {
+            if (++polls > dep->spin_limit) {
+                __hip_atomic_fetch_or(dep->error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
     __builtin_amdgcn_s_waitcnt(0);               // this wave's DMA has landed in LDS
     __syncthreads();                             // ... and every other wave's
+    if (dep) {                                   // the ghost nodes as the ghost workgroups wrote them
+        const GLOBAL T *Pi = gp<T>(I.f[ib][0]);
+        const GLOBAL T *Ui = gp<T>(I.f[ib][1]);
+        const GLOBAL T *Vi = gp<T>(I.f[ib][2]);
+        for (int e = dep->p0 + tid; e < dep->p1; e += NT) {
+            const int2 pe = dep->patch[e];
+            (&lds[0][0][0])[pe.x] = Pi[pe.y];
+            (&lds[1][0][0])[pe.x] = Ui[pe.y];
+            (&lds[2][0][0])[pe.x] = Vi[pe.y];
+        }
+        __syncthreads();
+    }
 
     // ---- compute phase: one row of VEC nodes at a time ----
     const int cg = tid % NCX;
@@ -672,55 +712,50 @@ __global__ __launch_bounds__(256) void k_tile(const DevInst *__restrict__ insts,
     int4 wk = work[w];
     if (wk.x < 0) return;
     wk.x &= DEP_BIT - 1;
-    tile_body<T, VEC, FILT, TX, TY>(insts, wk, stage);
+    tile_body<T, VEC, FILT, TX, TY>(insts, wk, stage, nullptr);
 }
 
-// One stage in one launch: ghost fill and ADE update (the first ngb
-// workgroups, 256 / GL ghosts each), then the tile sweep (the rest).  Tiles
-// whose read region holds no ghost node start at once; the others wait until
-// every ghost workgroup has published its writes (release/acquire on an
-// agent-scope counter).  Ghost workgroups have the lowest ids, so they are
-// dispatched no later than any tile that waits for them; the wait is bounded
-// by spin_limit polls all the same, and a wait that runs out raises the
-// error flag sync[4] instead of hanging.  sync[stage] counts finished ghost
-// workgroups; block 0 clears the previous stage's counter, whose launch has
+// One stage in one launch.  The first ncar workgroups each fill 256 / GL
+// ghosts (ghost fill and ADE update) before their own tile, then publish
+// with a release add on sync[stage]; no workgroups are added for the ghosts,
+// so a launch that fills the device in one wave still does.  Tiles whose
+// stencils read no ghost node run at once.  The others start their LDS copy,
+// wait until every ghost share has been published (relaxed polls, one
+// acquire fence) and then patch the ghost nodes they read (aux[w] = their
+// range in patch).  The ghost shares belong to the lowest workgroup ids and
+// no waiting tile has such an id (the host orders the work so), so they are
+// dispatched no later than any tile that waits for them and they wait for
+// nothing themselves; the wait is bounded by spin_limit polls all
+// the same, and a wait that runs out raises the error flag sync[4] instead
+// of hanging.  Block 0 clears the previous stage's counter, whose launch has
 // completed.
 template <typename T, int VEC, bool FILT, int TX, int TY, int GL>
 __global__ __launch_bounds__(256) void k_stage(const DevInst *__restrict__ insts, const int4 *__restrict__ work1,
-                                               int nwork1, const int4 *__restrict__ work2, int nwork2, int ngb,
-                                               int stage, int *sync, int spin_limit)
+                                               int nwork1, const int4 *__restrict__ work2, int nwork2, int ncar,
+                                               int tile0, int stage, int *sync, int spin_limit,
+                                               const int2 *__restrict__ aux, const int2 *__restrict__ patch)
 {
     const int tid = threadIdx.x;
-    if (blockIdx.x == 0 && tid == 0)
+    const int w = (int)blockIdx.x;
+    if (w == 0 && tid == 0)
         __hip_atomic_store(&sync[(stage + 3) & 3], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if ((int)blockIdx.x < ngb) {
-        ghost_item<T, GL>(insts, work2, nwork2, (int)blockIdx.x * (256 / GL) + tid / GL, tid % GL, stage);
+    if (w < ncar) {
+        ghost_item<T, GL>(insts, work2, nwork2, w * (256 / GL) + tid / GL, tid % GL, stage);
         __syncthreads();
         if (tid == 0) __hip_atomic_fetch_add(&sync[stage], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        return;
     }
-    const int w = (int)blockIdx.x - ngb;
-    if (w >= nwork1) return;
-    int4 wk = work1[w];
+    const int k = w - tile0;
+    if (k < 0 || k >= nwork1) return;
+    int4 wk = work1[k];
     if (wk.x < 0) return;
     if (wk.x & DEP_BIT) {
-        if (tid == 0) {
-            // relaxed polls (an acquire load would invalidate this XCD's L2
-            // on every poll), then one acquire fence for the ghost writes
-            int polls = 0;
-            while (__hip_atomic_load(&sync[stage], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < ngb) {
-                if (++polls > spin_limit) {
-                    __hip_atomic_fetch_or(&sync[4], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(2);
-            }
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        }
-        __syncthreads();
         wk.x &= DEP_BIT - 1;
+        const int2 rg = aux[k];
+        const GhostDep dep{&sync[stage], &sync[4], ncar, spin_limit, patch, rg.x, rg.y};
+        tile_body<T, VEC, FILT, TX, TY>(insts, wk, stage, &dep);
+    } else {
+        tile_body<T, VEC, FILT, TX, TY>(insts, wk, stage, nullptr);
     }
-    tile_body<T, VEC, FILT, TX, TY>(insts, wk, stage);
 }
 
 // ---------------------------------------------------------------------------
@@ -868,12 +903,15 @@ hipError_t launch_sweep(int prec, int vec, bool filt, int waves, const DevInst *
 
 constexpr int GHOST_LANES = 16;                  // lanes per ghost
 
-// Fused launch arguments (the ghost part); ngb == 0 launches the plain sweep.
+// Fused launch arguments (the ghost part and the tile offset).
 struct FuseArgs {
     const int4 *work2;
     int nwork2;
     int *sync;
     int spin_limit;
+    const int2 *aux;
+    const int2 *patch;
+    int tile0;
 };
 
 template <typename T, int VEC, bool FILT, int TX, int TY>
@@ -883,10 +921,11 @@ static hipError_t launch_tile_t(const DevInst *insts, const int4 *work, int nwor
     if (!fa) {
         hipLaunchKernelGGL((k_tile<T, VEC, FILT, TX, TY>), dim3(nwork), dim3(256), 0, s, insts, work, nwork, stage);
     } else {
-        // ghost workgroups first, rounded to 8 so the tiles keep their XCD order
-        const int ngb = ((fa->nwork2 * GHOST_LANES + 255) / 256 + 7) / 8 * 8;
-        hipLaunchKernelGGL((k_stage<T, VEC, FILT, TX, TY, GHOST_LANES>), dim3(ngb + nwork), dim3(256), 0, s, insts,
-                           work, nwork, fa->work2, fa->nwork2, ngb, stage, fa->sync, fa->spin_limit);
+        // the first ncar workgroups carry 256 / GHOST_LANES ghosts each
+        const int ncar = (fa->nwork2 * GHOST_LANES + 255) / 256;
+        hipLaunchKernelGGL((k_stage<T, VEC, FILT, TX, TY, GHOST_LANES>), dim3(std::max(ncar, fa->tile0 + nwork)),
+                           dim3(256), 0, s, insts, work, nwork, fa->work2, fa->nwork2, ncar, fa->tile0, stage,
+                           fa->sync, fa->spin_limit, fa->aux, fa->patch);
     }
     return hipGetLastError();
 }
@@ -937,10 +976,11 @@ hipError_t launch_tile(int prec, bool filt, int tx, int ty, const DevInst *insts
 }
 
 hipError_t launch_stage(int prec, bool filt, int tx, int ty, const DevInst *insts, const int4 *work1, int nwork1,
-                        const int4 *work2, int nwork2, int stage, int *sync, int spin_limit, hipStream_t s)
+                        const int2 *aux, const int2 *patch, int tile0, const int4 *work2, int nwork2, int stage,
+                        int *sync, int spin_limit, hipStream_t s)
 {
     if (nwork2 <= 0) return launch_tile(prec, filt, tx, ty, insts, work1, nwork1, stage, 0, s);
-    const FuseArgs fa{work2, nwork2, sync, spin_limit};
+    const FuseArgs fa{work2, nwork2, sync, spin_limit, aux, patch, tile0};
     if (prec == LEE_F32)
         return filt ? launch_tile_v<float, 4, true>(tx, ty, insts, work1, nwork1, stage, &fa, s)
                     : launch_tile_v<float, 4, false>(tx, ty, insts, work1, nwork1, stage, &fa, s);
