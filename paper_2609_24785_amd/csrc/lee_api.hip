@@ -89,8 +89,8 @@ int pitch_of(const Host &h)
 size_t plane_elems(const Host &h) { return (size_t)(h.d.ny + 2 * FRAME) * pitch_of(h); }
 
 // A ghost node lies in the stencil region of at most 4 row tiles (rows >= 4)
-// and 2 column blocks (cols >= 64).
-size_t patch_capacity(const Host &h) { return 8 * h.gidx.size() + 64; }
+// and 2 column blocks (cols >= 64), with one entry per field.
+size_t patch_capacity(const Host &h) { return 24 * h.gidx.size() + 64; }
 
 size_t work1_capacity(const Host &h)
 {
@@ -101,9 +101,13 @@ size_t work1_capacity(const Host &h)
 }
 
 struct Layout {
-    size_t inst, planes[9], psi[3], iv, goff, cptr, coff, w4, gd, counters, amp, pij, pw, trace, dft, watch, work1,
-        aux, patch, work2, sync, sij, sw, sout, total;
+    size_t inst, planes[9], psi[3], iv, goff, cptr, coff, w4, gd, counters, amp, pij, pw, trace, dft, watch, xg,
+        work1, aux, patch, work2, sync, sij, sw, sout, total;
 };
+
+// Exchange words of the fused stage: per ghost and field, sizeof(T) / 4
+// words of 8 bytes.
+size_t xg_bytes(const Host &h) { return 3 * (size_t)(esize(h) / 4) * std::max<size_t>(h.gidx.size(), 1) * 8; }
 
 Layout layout(const Host &h)
 {
@@ -132,6 +136,7 @@ Layout layout(const Host &h)
     L.trace = take(std::max<size_t>((size_t)h.trace_cap * h.np * 3, 1) * 8);
     L.dft = take(2 * std::max(h.np, 1) * 8);
     L.watch = take(2 * std::max<size_t>((size_t)h.watch_cap, 1) * 8);
+    L.xg = take(xg_bytes(h));
     L.work1 = take(work1_capacity(h) * sizeof(int4));
     L.aux = take(work1_capacity(h) * sizeof(int2));
     L.patch = take(patch_capacity(h) * sizeof(int2));
@@ -265,9 +270,9 @@ void default_tiling(lee_instance *I)
 // holding fluid nodes, in natural order.  A march item covers 64 vec - 16
 // output columns and alternates its direction between row tiles; a tile item
 // covers `cols` columns.  For the fused tile sweep, patches (when given)
-// receives per item the ghost nodes its stencils read, as (LDS element index
-// in the tile's copy, plane offset), and items with any are flagged
-// TILE_DEP_BIT.  The stencils of a tile read its own rows over the columns
+// receives per item the ghost nodes its stencils read, three entries per node
+// (LDS element index in the tile's copy, ghost index * 3 + field), and items
+// with any are flagged TILE_DEP_BIT.  The stencils of a tile read its own rows over the columns
 // [c0 - 5, c0 + cols + 5) and the 5 rows above and below over [c0, c0 + cols).
 void build_items(const Host &h, int inst_id, const lee_tiling &t, std::vector<int4> &items,
                  std::vector<std::vector<int2>> *patches)
@@ -277,13 +282,18 @@ void build_items(const Host &h, int inst_id, const lee_tiling &t, std::vector<in
     const int strips = (h.d.nx + ow - 1) / ow;
     const int tiles = (h.d.ny + rows - 1) / rows;
     const bool fused = t.kind == LEE_SWEEP_TILE && t.fused && patches;
-    // ghost columns by row (ascending: the ghost list is sorted by linear index)
-    std::vector<std::vector<int>> grow_cols;
+    // ghost columns by row (ascending: the ghost list is sorted by linear
+    // index) and the ghost index of each
+    std::vector<std::vector<int>> grow_cols, grow_g;
     if (fused) {
         grow_cols.resize(h.d.ny);
-        for (int g : h.gidx) grow_cols[g / h.d.nx].push_back(g % h.d.nx);
+        grow_g.resize(h.d.ny);
+        for (size_t g = 0; g < h.gidx.size(); ++g) {
+            grow_cols[h.gidx[g] / h.d.nx].push_back(h.gidx[g] % h.d.nx);
+            grow_g[h.gidx[g] / h.d.nx].push_back((int)g);
+        }
     }
-    const int pitch = pitch_of(h), org = FRAME * pitch + LPAD, LW = ow + 16;
+    const int LW = ow + 16;
     for (int r = 0; r < tiles; ++r) {
         const int r0 = r * rows, r1 = std::min(r0 + rows, h.d.ny);
         for (int s = 0; s < strips; ++s) {
@@ -301,8 +311,11 @@ void build_items(const Host &h, int inst_id, const lee_tiling &t, std::vector<in
                     const bool own = j >= r0 && j < r0 + rows;
                     const int lo = own ? c0 - 5 : c0, hi = own ? c0 + ow + 5 : c0 + ow;
                     const std::vector<int> &gc = grow_cols[j];
-                    for (auto it = std::lower_bound(gc.begin(), gc.end(), lo); it != gc.end() && *it < hi; ++it)
-                        pl.push_back(make_int2((j - (r0 - 5)) * LW + (*it - (c0 - 8)), org + j * pitch + *it));
+                    for (auto it = std::lower_bound(gc.begin(), gc.end(), lo); it != gc.end() && *it < hi; ++it) {
+                        const int g = grow_g[j][it - gc.begin()];
+                        for (int f = 0; f < 3; ++f)
+                            pl.push_back(make_int2((j - (r0 - 5)) * LW + (*it - (c0 - 8)), 3 * g + f));
+                    }
                 }
             }
             const int flag = pl.empty() ? 0 : TILE_DEP_BIT;
@@ -618,6 +631,7 @@ lee_status lee_bind(lee_instance *I, void *dev_ptr, size_t bytes, void *hip_stre
     D.pw = (const double *)(b + L.pw);
     D.trace = (double *)(b + L.trace);
     D.watch = (double *)(b + L.watch);
+    D.xg = (unsigned long long *)(b + L.xg);
     D.watch_cap = h.watch_cap;
     D.watch_g = h.watch_g;
     D.dft = (double *)(b + L.dft);
@@ -734,6 +748,7 @@ lee_status lee_init_fields(lee_instance *I)
     HIPCHK(launch_fill_bytes(I->base + L.trace, std::max<size_t>((size_t)h.trace_cap * h.np * 3, 1) * 8, s));
     HIPCHK(launch_fill_bytes(I->base + L.dft, 2 * std::max(h.np, 1) * 8, s));
     HIPCHK(launch_fill_bytes(I->base + L.watch, 2 * std::max<size_t>((size_t)h.watch_cap, 1) * 8, s));
+    HIPCHK(launch_fill_bytes(I->base + L.xg, xg_bytes(h), s));
     HIPCHK(launch_fill_bytes(I->base + L.sync, SYNC_INTS * sizeof(int), s));
     I->up_counters[0] = 0;
     I->up_counters[1] = LLONG_MAX;

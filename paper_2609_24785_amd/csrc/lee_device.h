@@ -32,6 +32,8 @@ struct DevInst {
     double *trace;          // ring of trace_cap steps x np x 3
     double *dft;            // 2 per probe: sum p exp(-i omega t)
     double *watch;          // ring of watch_cap steps x (p_BP, u_n,BP) of ghost watch_g
+    unsigned long long *xg; // ghost values of the current stage for fused launches: per ghost
+                            // and field, sizeof(T)/4 words of (32 value bits | stage epoch << 32)
     long long watch_cap;
     int watch_g;            // -1: none
     long long trace_cap;
@@ -64,10 +66,10 @@ hipError_t launch_tile(int prec, bool filt, int tx, int ty, const DevInst *insts
 // One launch for a stage with the tile sweep: the first ceil(nwork2 / 16)
 // workgroups fill 16 ghosts each, tile k runs in workgroup tile0 + k (the
 // caller keeps dependent tiles out of the carrier workgroups).  Items flagged
-// with TILE_DEP_BIT wait for the ghosts and patch the ghost nodes they read:
+// with TILE_DEP_BIT wait for the ghost values they read and patch them in:
 // aux[k] = [begin, end) in patch, whose entries are (LDS element index in the
-// tile's copy, plane offset).  sync holds 4 stage counters and an error flag
-// (5 ints, zero before first use).
+// tile's copy, ghost index * 3 + field).  sync[4] is the error flag raised by
+// a wait that runs out of polls (zero before first use).
 hipError_t launch_stage(int prec, bool filt, int tx, int ty, const DevInst *insts, const int4 *work1, int nwork1,
                         const int2 *aux, const int2 *patch, int tile0, const int4 *work2, int nwork2, int stage,
                         int *sync, int spin_limit, hipStream_t s);

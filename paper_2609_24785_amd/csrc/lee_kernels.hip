@@ -1,22 +1,30 @@
 // HIP kernels for gfx950 (MI355X): one Runge-Kutta stage of the 2-D LEE with
 // a ghost-point immersed boundary and the two-state MSD ADE.
 //
-//   k_ghost  Sec. 3.2 steps 1-5: per ghost, gathers its cloud of the stage
-//            input with the four composed weights (p_BP read-out, free,
-//            Dirichlet, Neumann), advances the ADE derivative, and writes the
-//            ghost values and the stage value of the ADE states.
-//   k_sweep  Sec. 3.2 step 6: DRP first derivatives (eq. DRP_s) in x and y,
-//            11-point selective-filter damping, sponge, monopole source and
-//            the low-storage RK stage update at every fluid node.  A wave owns
-//            a strip of 64*VEC columns (8 halo columns each side, so 16 of
-//            them are read-only) and marches down (or up) a tile of rows,
-//            keeping the 11-row window of p, u, v in registers; the centre
-//            row goes through LDS for the x neighbours.  Alternate tiles march
-//            in opposite directions so that two vertically adjacent tiles read
-//            their shared halo rows at about the same time (L2 reuse).
+//   k_ghost     Sec. 3.2 steps 1-5: per ghost, gathers its cloud of the stage
+//               input with the four composed weights (p_BP read-out, free,
+//               Dirichlet, Neumann), advances the ADE derivative, and writes
+//               the ghost values and the stage value of the ADE states.
+//   k_tile      Sec. 3.2 step 6: DRP first derivatives (eq. DRP_s) in x and y,
+//               11-point selective-filter damping, sponge, monopole source and
+//               the low-storage RK stage update at every fluid node of a tile;
+//               the workgroup copies the tile and its 5-node halo into LDS
+//               (direct global-to-LDS loads) and computes one row of VEC nodes
+//               per lane.
+//   k_stage     k_ghost and k_tile in one launch: the first workgroups fill
+//               the ghosts before their tiles; tiles that read ghost nodes
+//               wait for them and patch their LDS copy.
+//   k_sweep     the same sweep with a wave marching a strip of 64 VEC - 16
+//               columns down a run of rows and keeping the 11-row window of p,
+//               u, v in registers (the centre row goes through LDS for the x
+//               neighbours); alternate runs march in opposite directions so
+//               that vertically adjacent runs read their shared halo rows at
+//               about the same time (L2 reuse).
 //   k_step_end  step counter, per-member budget, probe sampling and DFT.
 //
-// No matrix cores: the stage is a memory-bound stencil (about 3 flop per byte).
+// No matrix cores: the stage is a stencil over three fields, bound by memory
+// traffic and, within a one-wave launch, by the vector ALU (about 110 FP32
+// operations per node).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -77,8 +85,34 @@ __device__ __forceinline__ int out_buf(int stage) { return stage == 0 ? 1 : (sta
 // ---------------------------------------------------------------------------
 // ghost fill + ADE
 
-// One ghost per GL-lane group (gid); sub is the lane within the group.
-template <typename T, int GL>
+// Stage epoch of an instance: the tag that marks ghost values published for
+// stage `stage` of step `step` (never 0, the tag of cleared words).
+__device__ __forceinline__ unsigned stage_epoch(long long step, int stage)
+{
+    return (unsigned)(step * 4 + stage + 1);
+}
+
+// Publishes one ghost value for the current stage: its 32-bit words, each
+// with the epoch in the upper half, by relaxed agent-scope atomic stores.  A
+// reader that sees the epoch sees the value stored with it (one atomic word),
+// so no release fence (an L2 write-back) is needed, and the value comes from
+// the previous launch's fields only, so nothing else must be ordered.
+template <typename T>
+__device__ __forceinline__ void xg_put(GLOBAL unsigned long long *w, T v, unsigned epoch)
+{
+    const unsigned long long tag = (unsigned long long)epoch << 32;
+    if constexpr (sizeof(T) == 4) {
+        __hip_atomic_store(w, tag | __float_as_uint(v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+        const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+        __hip_atomic_store(w, tag | (b & 0xffffffffull), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(w + 1, tag | (b >> 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// One ghost per GL-lane group (gid); sub is the lane within the group.  With
+// PUB (fused launches) the ghost values also go to the exchange words I.xg.
+template <typename T, int GL, bool PUB = false>
 __device__ __forceinline__ void ghost_item(const DevInst *__restrict__ insts, const int4 *__restrict__ work,
                                            int nwork, int gid, int sub, int stage)
 {
@@ -158,9 +192,19 @@ __device__ __forceinline__ void ghost_item(const DevInst *__restrict__ insts, co
     const T pg = aN + gdv.v[3] * ((T)I.h * Ud);
     const T un = aD + gdv.v[2] * (-Un);
     const T ut = aF;
+    const T ug = nx * un - ny * ut;
+    const T vg = ny * un + nx * ut;
     P[go] = pg;
-    U[go] = nx * un - ny * ut;
-    V[go] = ny * un + nx * ut;
+    U[go] = ug;
+    V[go] = vg;
+    if (PUB) {
+        constexpr int NW = sizeof(T) / 4;
+        const unsigned ep = stage_epoch(*gp<long long>(I.step), stage);
+        GLOBAL unsigned long long *x = gp<unsigned long long>(I.xg) + (size_t)g * 3 * NW;
+        xg_put<T>(x, pg, ep);
+        xg_put<T>(x + NW, ug, ep);
+        xg_put<T>(x + 2 * NW, vg, ep);
+    }
     if (I.ade_kind != 0) {
         GLOBAL T *psi_out = gp<T>(I.psi[ob]);
         const T adt = (T)I.alpha_dt[stage];
@@ -412,11 +456,14 @@ typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
 
 // One aligned 16-byte LDS read.  The empty asm keeps all four words live so
 // the compiler cannot split the read into narrower, bank-conflicting pieces.
+// It is not volatile: a volatile asm is a scheduling barrier, which would
+// wait for each read before issuing the next instead of keeping a window's
+// reads in flight together.
 template <typename T, int VEC>
 __device__ __forceinline__ VecT<T, VEC> lds16(const T *p)
 {
     u32x4_t w = *(const u32x4_t *)p;
-    asm volatile("" : "+v"(w));
+    asm("" : "+v"(w));
     return __builtin_bit_cast(VecT<T, VEC>, w);
 }
 
@@ -516,140 +563,301 @@ __device__ __forceinline__ void pin_sums(T (&rp)[VEC], T (&ru)[VEC], T (&rv)[VEC
     for (int e = 0; e < VEC; ++e) asm volatile("" : "+v"(rp[e]), "+v"(ru[e]), "+v"(rv[e])::"memory");
 }
 
-// A tile of a fused stage whose stencils read ghost nodes: it waits until the
-// counter reaches `need` published ghost shares (bounded by spin_limit polls,
-// then the error flag) and then overwrites the ghost nodes in its LDS copy;
-// patch[p0, p1) holds (LDS element index, plane offset) for each ghost node
-// it reads.
+// A tile of a fused stage whose stencils read ghost nodes: it takes each
+// ghost value it reads from the exchange words once they carry this stage's
+// epoch (bounded by spin_limit polls per word, then the error flag) and
+// overwrites the ghost nodes in its LDS copy; patch[p0, p1) holds (LDS
+// element index, ghost index * 3 + field) for each ghost node and field.
 struct GhostDep {
-    int *count;
     int *error;
-    int need;
     int spin_limit;
     const int2 *patch;
     int p0, p1;
 };
+
+// Shape of a cols x rows tile (TX x TY): NCX column groups of VEC nodes, RG
+// rows in flight per pass of 256 lanes, an LDS read region of R rows x LW
+// columns (CW 16-byte chunks per row, HC halo chunks per side; NCH chunks per
+// field) and a q^n block of NQ chunks per field.
+template <typename T, int VEC, int TX, int TY>
+struct TileGeo {
+    static constexpr int NT = 256;
+    static constexpr int NCX = TX / VEC;
+    static constexpr int RG = NT / NCX;
+    static constexpr int R = TY + 10;
+    static constexpr int LW = TX + 16;
+    static constexpr int CW = LW / VEC;
+    static constexpr int HC = 8 / VEC;
+    static constexpr int NCH = R * CW;
+    static constexpr int QCW = TX / VEC;
+    static constexpr int NQ = TY * QCW;
+    static_assert(sizeof(T) * VEC == 16, "16-byte chunks");
+};
+
+// Values that do not change during a launch, read with scalar loads (they
+// then never wait for vector memory traffic in flight).
+#if defined(__HIP_DEVICE_COMPILE__)
+#define CONSTAS __attribute__((address_space(4)))
+#else
+#define CONSTAS
+#endif
+template <typename T>
+__device__ __forceinline__ T sload(const void *p)
+{
+    return *(const CONSTAS T *)p;
+}
+
+// Per-tile values shared by all lanes.
+template <typename T>
+struct TileCtx {
+    int c0, r0, r1, ib, ob;
+    bool in_sponge, has_src;
+    T adt, sp_inv, sp_s, amp;
+    T ax[5], fd[6];
+};
+
+template <typename T, int TX>
+__device__ __forceinline__ TileCtx<T> tile_ctx(const DevInst &I, const int4 wk, int stage)
+{
+    TileCtx<T> c;
+    c.c0 = wk.y;
+    c.r0 = wk.z;
+    c.r1 = wk.w < 0 ? -wk.w : wk.w;
+    c.ib = in_buf(stage);
+    c.ob = out_buf(stage);
+    coefs<T>(I, c.ax, c.fd);
+    c.adt = (T)I.alpha_dt[stage];
+    const int sw = I.sponge_w;
+    // the sponge band and the source box are tested once per tile
+    c.in_sponge = sw > 0 && (c.c0 < sw || c.r0 < sw || c.c0 + TX > I.nx - sw || c.r1 > I.ny - sw);
+    c.sp_inv = (T)I.sponge_inv;
+    c.sp_s = (T)I.sponge_s;
+    c.has_src = I.has_src && !(I.src_i1 < c.c0 || I.src_i0 >= c.c0 + TX) && !(I.src_j1 < c.r0 || I.src_j0 >= c.r1);
+    c.amp = c.has_src ? (T)sload<double>(I.amp + stage) : (T)0;
+    return c;
+}
+
+// Starts the LDS copy of a tile: the read region of the stage input (rows
+// r0 - 5 .. r0 + TY + 4, columns c0 - 8 .. c0 + TX + 7, the halo rows without
+// their corner chunks, no row past the allocated frame) into reg, 64 chunks
+// per wave instruction, and, when qn is given and the stage is not the first,
+// the q^n block into qn.
+template <typename T, int VEC, int TX, int TY>
+__device__ __forceinline__ void tile_copy(const DevInst &I, const TileCtx<T> &c, int stage,
+                                          T (*reg)[TY + 10][TX + 16], T (*qn)[TY][TX])
+{
+    using G = TileGeo<T, VEC, TX, TY>;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int pitch = I.pitch, org = I.org;
+    const int rowmax = I.ny + 4;                 // last allocated frame row
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+        const T *src = (const T *)I.f[c.ib][f];
+        for (int base = wave * 64; base < G::NCH; base += G::NT) {
+            const int q = base + lane;
+            const int row = q / G::CW, cc = q - (q / G::CW) * G::CW;
+            const int gr = c.r0 - 5 + row;
+            const bool halo_row = row < 5 || row >= TY + 5;
+            const bool ok = q < G::NCH && !(halo_row && (cc < G::HC || cc >= G::CW - G::HC)) && gr <= rowmax;
+            if (ok) dma16(src + (unsigned)(org + gr * pitch + (c.c0 - 8 + cc * VEC)), &reg[f][0][0] + base * VEC);
+        }
+    }
+    if (qn && stage != 0) {
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+            const T *src = (const T *)I.f[0][f];
+            for (int base = wave * 64; base < G::NQ; base += G::NT) {
+                const int q = base + lane;
+                const int row = q / G::QCW, cc = q - (q / G::QCW) * G::QCW;
+                const int gr = c.r0 + row;
+                if (q < G::NQ && gr <= rowmax)
+                    dma16(src + (unsigned)(org + gr * pitch + c.c0 + cc * VEC), &qn[f][0][0] + base * VEC);
+            }
+        }
+    }
+}
+
+// The first two patch entries of this lane, p0 + lane and p0 + lane + 256
+// (x = -1 when absent), loaded before the ghost wait.
+__device__ __forceinline__ void patch_prefetch(const int2 *__restrict__ patch, int p0, int p1, int2 (&pre)[2])
+{
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const int e = p0 + (int)threadIdx.x + 256 * k;
+        pre[k] = e < p1 ? patch[e] : make_int2(-1, 0);
+    }
+}
+
+// One ghost value of the current stage from its exchange words: relaxed
+// agent-scope atomic loads, repeated while a word carries another epoch (at
+// most spin_limit polls, then the error flag is raised and the value is not
+// valid).
+template <typename T>
+__device__ __forceinline__ T xg_get(const GLOBAL unsigned long long *w, unsigned epoch, int spin_limit, int *error)
+{
+    constexpr int NW = sizeof(T) / 4;
+    unsigned long long b = 0;
+#pragma unroll
+    for (int k = 0; k < NW; ++k) {
+        unsigned long long v = __hip_atomic_load(w + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        int polls = 0;
+        while ((unsigned)(v >> 32) != epoch) {
+            if (++polls > spin_limit) {
+                __hip_atomic_fetch_or(error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+            v = __hip_atomic_load(w + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        b |= (v & 0xffffffffull) << (32 * k);
+    }
+    if constexpr (NW == 1)
+        return __uint_as_float((unsigned)b);
+    else
+        return __longlong_as_double((long long)b);
+}
+
+// Overwrites the ghost nodes of a tile's LDS copy with this stage's ghost
+// values: patch entries [p0, p1) are (LDS element index, ghost * 3 + field);
+// pre holds this lane's first two entries.
+template <typename T, int TX, int TY>
+__device__ __forceinline__ void tile_patch(const DevInst &I, unsigned epoch, T (*reg)[TY + 10][TX + 16],
+                                           const GhostDep &d, const int2 (&pre)[2])
+{
+    constexpr int NW = sizeof(T) / 4;
+    T *base = &reg[0][0][0];
+    constexpr int FS = (TY + 10) * (TX + 16);    // elements per field of the copy
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+        if (pre[k].x >= 0)
+            base[(pre[k].y % 3) * FS + pre[k].x] =
+                xg_get<T>(gp<unsigned long long>(I.xg) + (size_t)pre[k].y * NW, epoch, d.spin_limit, d.error);
+    for (int e = d.p0 + (int)threadIdx.x + 512; e < d.p1; e += 256) {
+        const int2 pe = d.patch[e];
+        base[(pe.y % 3) * FS + pe.x] =
+            xg_get<T>(gp<unsigned long long>(I.xg) + (size_t)pe.y * NW, epoch, d.spin_limit, d.error);
+    }
+}
+
+// Right-hand side (Sec. 3.2 step 6) and RK stage update of row i of a tile
+// for the VEC nodes of columns tc .. tc + VEC - 1 of the tile: reg is the LDS
+// copy of the stage input, (pn, un, vn) the q^n values (unused in the first
+// stage, whose input is q^n), iv the row's fluid column ranges.  Returns the
+// new values and which of the nodes are fluid.
+template <typename T, int VEC, bool FILT, int TX, int TY>
+__device__ __forceinline__ void tile_row(const DevInst &I, const TileCtx<T> &c, const T (*reg)[TY + 10][TX + 16],
+                                         int stage, int i, int tc, const int4 iv, const VecT<T, VEC> &pn_,
+                                         const VecT<T, VEC> &un_, const VecT<T, VEC> &vn_, VecT<T, VEC> &po,
+                                         VecT<T, VEC> &uo, VecT<T, VEC> &vo, bool (&ok)[VEC], bool &all)
+{
+    const int j = c.r0 + i;
+    const int y = i + 5;
+    const int lc = tc + 8;
+    const int gc = c.c0 + tc;
+    T rp[VEC], ru[VEC], rv[VEC];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) rp[e] = ru[e] = rv[e] = 0;
+    // one field's windows live at a time: each field's sums are pinned
+    // (empty asm, no instructions) before the next field's LDS reads
+    row_field<T, VEC, FILT, 0>(reg[0], y, lc, c.ax, c.fd, rp, ru, rv);
+    pin_sums<T, VEC>(rp, ru, rv);
+    row_field<T, VEC, FILT, 1>(reg[1], y, lc, c.ax, c.fd, rp, ru, rv);
+    pin_sums<T, VEC>(rp, ru, rv);
+    row_field<T, VEC, FILT, 2>(reg[2], y, lc, c.ax, c.fd, rp, ru, rv);
+    const VecT<T, VEC> pc = *(const VecT<T, VEC> *)&reg[0][y][lc];
+    const VecT<T, VEC> uc = *(const VecT<T, VEC> *)&reg[1][y][lc];
+    const VecT<T, VEC> vc = *(const VecT<T, VEC> *)&reg[2][y][lc];
+    const VecT<T, VEC> pn = stage != 0 ? pn_ : pc;
+    const VecT<T, VEC> un = stage != 0 ? un_ : uc;
+    const VecT<T, VEC> vn = stage != 0 ? vn_ : vc;
+    all = true;
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+        const int col = gc + e;
+        if (c.in_sponge) {
+            const int sw = I.sponge_w;
+            const int eg = min(min(col, j), min(I.nx - 1 - col, I.ny - 1 - j));
+            if (eg < sw) {
+                const T fr = (T)(sw - eg) * c.sp_inv;
+                const T sg = c.sp_s * fr * fr;
+                rp[e] -= sg * pc.v[e];
+                ru[e] -= sg * uc.v[e];
+                rv[e] -= sg * vc.v[e];
+            }
+        }
+        if (c.has_src) {
+            const T xx = (T)(col - I.src_ic) * (T)I.h - (T)I.src_fx;
+            const T yy = (T)(j - I.src_jc) * (T)I.h - (T)I.src_fy;
+            rp[e] += c.amp * exp(-(T)I.src_b * (xx * xx + yy * yy));
+        }
+        po.v[e] = pn.v[e] + c.adt * rp[e];
+        uo.v[e] = un.v[e] + c.adt * ru[e];
+        vo.v[e] = vn.v[e] + c.adt * rv[e];
+        ok[e] = (col >= iv.x && col < iv.y) || (col >= iv.z && col < iv.w);
+        all = all && ok[e];
+    }
+}
+
+// Writes a row's new values at its fluid nodes (plane offset off of the
+// first node) in register set ob.
+template <typename T, int VEC>
+__device__ __forceinline__ void tile_store(const DevInst &I, int ob, unsigned off, const VecT<T, VEC> &po,
+                                           const VecT<T, VEC> &uo, const VecT<T, VEC> &vo, const bool (&ok)[VEC],
+                                           bool all)
+{
+    GLOBAL T *Po = gp<T>(I.f[ob][0]);
+    GLOBAL T *Uo = gp<T>(I.f[ob][1]);
+    GLOBAL T *Vo = gp<T>(I.f[ob][2]);
+    if (all) {
+        vst<T, VEC>(Po + off, po);
+        vst<T, VEC>(Uo + off, uo);
+        vst<T, VEC>(Vo + off, vo);
+    } else {
+#pragma unroll
+        for (int e = 0; e < VEC; ++e)
+            if (ok[e]) {
+                Po[off + e] = po.v[e];
+                Uo[off + e] = uo.v[e];
+                Vo[off + e] = vo.v[e];
+            }
+    }
+}
 
 // One tile: wk = {instance, first column, first row, +-(end row)}.
 template <typename T, int VEC, bool FILT, int TX, int TY>
 __device__ __forceinline__ void tile_body(const DevInst *__restrict__ insts, const int4 wk, int stage,
                                           const GhostDep *dep)
 {
-    constexpr int NT = 256;
-    constexpr int NCX = TX / VEC;                // column groups
-    constexpr int RG = NT / NCX;                 // rows in flight per pass
-    constexpr int R = TY + 10;                   // LDS rows of the read region
-    constexpr int LW = TX + 16;                  // LDS columns of the read region
-    constexpr int CW = LW / VEC;                 // 16-byte chunks per LDS row
-    constexpr int HC = 8 / VEC;                  // halo chunks per side
-    constexpr int NCH = R * CW;                  // chunks per field (region)
-    constexpr int QCW = TX / VEC;                // chunks per q^n row
-    constexpr int NQ = TY * QCW;                 // chunks per field (q^n block)
-    static_assert(sizeof(T) * VEC == 16, "16-byte chunks");
-    __shared__ alignas(16) T lds[3][R][LW];
+    using G = TileGeo<T, VEC, TX, TY>;
+    __shared__ alignas(16) T lds[3][G::R][G::LW];
     __shared__ alignas(16) T ldn[3][TY][TX];
     const DevInst &I = insts[wk.x];
-    if (!*gp<int>(I.active)) return;
+    if (!sload<int>(I.active)) return;
     const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
-    const int c0 = wk.y, r0 = wk.z;
-    const int r1 = wk.w < 0 ? -wk.w : wk.w;
-    const int ib = in_buf(stage), ob = out_buf(stage);
-    const int pitch = I.pitch;
-    const int org = I.org;
-    const int rowmax = I.ny + 4;                 // last allocated frame row
-
-    // ---- load phase: DMA into LDS, 64 chunks per wave instruction ----
-#pragma unroll
-    for (int f = 0; f < 3; ++f) {
-        const T *src = (const T *)I.f[ib][f];
-        for (int base = wave * 64; base < NCH; base += NT) {
-            const int q = base + lane;
-            const int row = q / CW, cc = q - (q / CW) * CW;
-            const int gr = r0 - 5 + row;
-            const bool halo_row = row < 5 || row >= TY + 5;
-            const bool ok = q < NCH && !(halo_row && (cc < HC || cc >= CW - HC)) && gr <= rowmax;
-            if (ok) dma16(src + (unsigned)(org + gr * pitch + (c0 - 8 + cc * VEC)), &lds[f][0][0] + base * VEC);
-        }
-    }
-    if (stage != 0) {
-#pragma unroll
-        for (int f = 0; f < 3; ++f) {
-            const T *src = (const T *)I.f[0][f];
-            for (int base = wave * 64; base < NQ; base += NT) {
-                const int q = base + lane;
-                const int row = q / QCW, cc = q - (q / QCW) * QCW;
-                const int gr = r0 + row;
-                if (q < NQ && gr <= rowmax)
-                    dma16(src + (unsigned)(org + gr * pitch + c0 + cc * VEC), &ldn[f][0][0] + base * VEC);
-            }
-        }
-    }
-    T ax[5], fd[6];
-    coefs<T>(I, ax, fd);
-    const T adt = (T)I.alpha_dt[stage];
-    const int sw = I.sponge_w;
-    // the sponge band and the source box are tested once per tile
-    const bool in_sponge = sw > 0 && (c0 < sw || r0 < sw || c0 + TX > I.nx - sw || r1 > I.ny - sw);
-    const T sp_inv = (T)I.sponge_inv, sp_s = (T)I.sponge_s;
-    const bool has_src = I.has_src && !(I.src_i1 < c0 || I.src_i0 >= c0 + TX) && !(I.src_j1 < r0 || I.src_j0 >= r1);
-    const T amp = has_src ? (T)gp<double>(I.amp)[stage] : (T)0;
-    GLOBAL T *Po = gp<T>(I.f[ob][0]);
-    GLOBAL T *Uo = gp<T>(I.f[ob][1]);
-    GLOBAL T *Vo = gp<T>(I.f[ob][2]);
-    if (dep && tid == 0) {
-        // while the copy is in flight: relaxed polls (an acquire load would
-        // invalidate this XCD's L2 on every poll), then one acquire fence
-        int polls = 0;
-        while (__hip_atomic_load(dep->count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < dep->need) {
-            if (++polls > dep->spin_limit) {
-                __hip_atomic_fetch_or(dep->error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                break;
-            }
-            __builtin_amdgcn_s_sleep(2);
-        }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    }
+    const TileCtx<T> c = tile_ctx<T, TX>(I, wk, stage);
+    tile_copy<T, VEC, TX, TY>(I, c, stage, lds, ldn);
+    // while the copy flies: this lane's first row ranges and its first patch
+    // entries
+    const int i0 = tid / G::NCX;
+    int4 iv = make_int4(0, 0, 0, 0);
+    if (i0 < TY && c.r0 + i0 < c.r1) iv = gp<int4>(I.iv)[c.r0 + i0];
+    int2 pre[2];
+    if (dep) patch_prefetch(dep->patch, dep->p0, dep->p1, pre);
     __builtin_amdgcn_s_waitcnt(0);               // this wave's DMA has landed in LDS
     __syncthreads();                             // ... and every other wave's
-    if (dep) {                                   // the ghost nodes as the ghost workgroups wrote them
-        const GLOBAL T *Pi = gp<T>(I.f[ib][0]);
-        const GLOBAL T *Ui = gp<T>(I.f[ib][1]);
-        const GLOBAL T *Vi = gp<T>(I.f[ib][2]);
-        for (int e = dep->p0 + tid; e < dep->p1; e += NT) {
-            const int2 pe = dep->patch[e];
-            (&lds[0][0][0])[pe.x] = Pi[pe.y];
-            (&lds[1][0][0])[pe.x] = Ui[pe.y];
-            (&lds[2][0][0])[pe.x] = Vi[pe.y];
-        }
+    if (dep) {                                   // this stage's ghost values over the copied ones
+        tile_patch<T, TX, TY>(I, stage_epoch(sload<long long>(I.step), stage), lds, *dep, pre);
         __syncthreads();
     }
-
-    // ---- compute phase: one row of VEC nodes at a time ----
-    const int cg = tid % NCX;
+    const int cg = tid % G::NCX;
     const int tc = cg * VEC;
-    const int lc = tc + 8;
-    const int gc = c0 + tc;
 #pragma unroll 1
-    for (int i = tid / NCX; i < TY; i += RG) {
-        const int j = r0 + i;
-        if (j >= r1) break;
-        const int y = i + 5;
-        T rp[VEC], ru[VEC], rv[VEC];
-#pragma unroll
-        for (int e = 0; e < VEC; ++e) rp[e] = ru[e] = rv[e] = 0;
-        // one field's windows live at a time: each field's sums are pinned
-        // (empty asm, no instructions) before the next field's LDS reads
-        row_field<T, VEC, FILT, 0>(lds[0], y, lc, ax, fd, rp, ru, rv);
-        pin_sums<T, VEC>(rp, ru, rv);
-        row_field<T, VEC, FILT, 1>(lds[1], y, lc, ax, fd, rp, ru, rv);
-        pin_sums<T, VEC>(rp, ru, rv);
-        row_field<T, VEC, FILT, 2>(lds[2], y, lc, ax, fd, rp, ru, rv);
-        const int4 iv = gp<int4>(I.iv)[j];
-        const VecT<T, VEC> pc = *(const VecT<T, VEC> *)&lds[0][y][lc];
-        const VecT<T, VEC> uc = *(const VecT<T, VEC> *)&lds[1][y][lc];
-        const VecT<T, VEC> vc = *(const VecT<T, VEC> *)&lds[2][y][lc];
-        VecT<T, VEC> pn = pc, un = uc, vn = vc;
+    for (int i = i0; i < TY; i += G::RG) {
+        const int j = c.r0 + i;
+        if (j >= c.r1) break;
+        if (i != i0) iv = gp<int4>(I.iv)[j];
+        VecT<T, VEC> pn{}, un{}, vn{};
         if (stage != 0) {
             pn = *(const VecT<T, VEC> *)&ldn[0][i][tc];
             un = *(const VecT<T, VEC> *)&ldn[1][i][tc];
@@ -657,45 +865,9 @@ __device__ __forceinline__ void tile_body(const DevInst *__restrict__ insts, con
         }
         VecT<T, VEC> po, uo, vo;
         bool ok[VEC];
-        bool all = true;
-#pragma unroll
-        for (int e = 0; e < VEC; ++e) {
-            const int col = gc + e;
-            if (in_sponge) {
-                const int eg = min(min(col, j), min(I.nx - 1 - col, I.ny - 1 - j));
-                if (eg < sw) {
-                    const T fr = (T)(sw - eg) * sp_inv;
-                    const T sg = sp_s * fr * fr;
-                    rp[e] -= sg * pc.v[e];
-                    ru[e] -= sg * uc.v[e];
-                    rv[e] -= sg * vc.v[e];
-                }
-            }
-            if (has_src) {
-                const T xx = (T)(col - I.src_ic) * (T)I.h - (T)I.src_fx;
-                const T yy = (T)(j - I.src_jc) * (T)I.h - (T)I.src_fy;
-                rp[e] += amp * exp(-(T)I.src_b * (xx * xx + yy * yy));
-            }
-            po.v[e] = pn.v[e] + adt * rp[e];
-            uo.v[e] = un.v[e] + adt * ru[e];
-            vo.v[e] = vn.v[e] + adt * rv[e];
-            ok[e] = (col >= iv.x && col < iv.y) || (col >= iv.z && col < iv.w);
-            all = all && ok[e];
-        }
-        const unsigned off = (unsigned)(org + j * pitch + gc);
-        if (all) {
-            vst<T, VEC>(Po + off, po);
-            vst<T, VEC>(Uo + off, uo);
-            vst<T, VEC>(Vo + off, vo);
-        } else {
-#pragma unroll
-            for (int e = 0; e < VEC; ++e)
-                if (ok[e]) {
-                    Po[off + e] = po.v[e];
-                    Uo[off + e] = uo.v[e];
-                    Vo[off + e] = vo.v[e];
-                }
-        }
+        bool all;
+        tile_row<T, VEC, FILT, TX, TY>(I, c, lds, stage, i, tc, iv, pn, un, vn, po, uo, vo, ok, all);
+        tile_store<T, VEC>(I, c.ob, (unsigned)(I.org + j * I.pitch + c.c0 + tc), po, uo, vo, ok, all);
     }
 }
 
@@ -716,19 +888,17 @@ __global__ __launch_bounds__(256) void k_tile(const DevInst *__restrict__ insts,
 }
 
 // One stage in one launch.  The first ncar workgroups each fill 256 / GL
-// ghosts (ghost fill and ADE update) before their own tile, then publish
-// with a release add on sync[stage]; no workgroups are added for the ghosts,
-// so a launch that fills the device in one wave still does.  Tiles whose
-// stencils read no ghost node run at once.  The others start their LDS copy,
-// wait until every ghost share has been published (relaxed polls, one
-// acquire fence) and then patch the ghost nodes they read (aux[w] = their
-// range in patch).  The ghost shares belong to the lowest workgroup ids and
-// no waiting tile has such an id (the host orders the work so), so they are
-// dispatched no later than any tile that waits for them and they wait for
-// nothing themselves; the wait is bounded by spin_limit polls all
-// the same, and a wait that runs out raises the error flag sync[4] instead
-// of hanging.  Block 0 clears the previous stage's counter, whose launch has
-// completed.
+// ghosts (ghost fill and ADE update) before their own tile and publish each
+// ghost value with this stage's epoch in the exchange words; no workgroups
+// are added for the ghosts, so a launch that fills the device in one wave
+// still does.  Tiles whose stencils read no ghost node run at once.  The
+// others start their LDS copy and then take the ghost values they read
+// (aux[k] = their range in patch) as soon as those carry the epoch.  The
+// ghost shares belong to the lowest workgroup ids and no waiting tile has
+// such an id (the host orders the work so), so they are dispatched no later
+// than any tile that waits for them and they wait for nothing themselves;
+// each wait is bounded by spin_limit polls all the same, and a wait that runs
+// out raises the error flag sync[4] instead of hanging.
 template <typename T, int VEC, bool FILT, int TX, int TY, int GL>
 __global__ __launch_bounds__(256) void k_stage(const DevInst *__restrict__ insts, const int4 *__restrict__ work1,
                                                int nwork1, const int4 *__restrict__ work2, int nwork2, int ncar,
@@ -737,13 +907,7 @@ __global__ __launch_bounds__(256) void k_stage(const DevInst *__restrict__ insts
 {
     const int tid = threadIdx.x;
     const int w = (int)blockIdx.x;
-    if (w == 0 && tid == 0)
-        __hip_atomic_store(&sync[(stage + 3) & 3], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (w < ncar) {
-        ghost_item<T, GL>(insts, work2, nwork2, w * (256 / GL) + tid / GL, tid % GL, stage);
-        __syncthreads();
-        if (tid == 0) __hip_atomic_fetch_add(&sync[stage], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    }
+    if (w < ncar) ghost_item<T, GL, true>(insts, work2, nwork2, w * (256 / GL) + tid / GL, tid % GL, stage);
     const int k = w - tile0;
     if (k < 0 || k >= nwork1) return;
     int4 wk = work1[k];
@@ -751,7 +915,7 @@ __global__ __launch_bounds__(256) void k_stage(const DevInst *__restrict__ insts
     if (wk.x & DEP_BIT) {
         wk.x &= DEP_BIT - 1;
         const int2 rg = aux[k];
-        const GhostDep dep{&sync[stage], &sync[4], ncar, spin_limit, patch, rg.x, rg.y};
+        const GhostDep dep{&sync[4], spin_limit, patch, rg.x, rg.y};
         tile_body<T, VEC, FILT, TX, TY>(insts, wk, stage, &dep);
     } else {
         tile_body<T, VEC, FILT, TX, TY>(insts, wk, stage, nullptr);
@@ -1056,7 +1220,8 @@ hipError_t launch_sample(int prec, const DevInst *insts, const int *ij, const do
 
 namespace lee {
 
-// plain device copy, 16 bytes per lane per iteration: the reference kernel of
+// plain device copy, one 16-byte chunk per lane (a grid-stride loop over
+// fewer workgroups measured 25% slower at 1 GiB): the reference kernel of
 // known traffic (2 x bytes) for calibrating hardware byte counters and the
 // achievable HBM rate
 __global__ __launch_bounds__(256) void k_copy(const uint4 *__restrict__ src, uint4 *__restrict__ dst, size_t n)
@@ -1069,7 +1234,7 @@ hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t s)
 {
     const size_t n = bytes / 16;
     if (n == 0) return hipSuccess;
-    const int nb = (int)std::min<size_t>((n + 255) / 256, 256 * 64);
+    const int nb = (int)std::min<size_t>((n + 255) / 256, (size_t)1 << 30);
     hipLaunchKernelGGL(k_copy, dim3(nb), dim3(256), 0, s, (const uint4 *)src, (uint4 *)dst, n);
     return hipGetLastError();
 }
