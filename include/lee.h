@@ -162,8 +162,12 @@ lee_status lee_init_fields(lee_instance *inst);
  */
 lee_status lee_rk_stage(lee_instance *inst, int32_t stage);
 
-/* n full steps by replaying a captured hipGraph of the step; asynchronous.
- * Requires that no partial step is pending (else LEE_E_STATE). */
+/* n full steps by replaying captured hipGraphs; asynchronous.  Requires that
+ * no partial step is pending (else LEE_E_STATE).  The steps go in runs (one
+ * captured graph each): the probes after each step but the last of a run are
+ * sampled by extra workgroups of the next step's second stage, and a run ends
+ * with the probes after its last step and one launch that advances the step
+ * counter, so a step costs its four stage launches. */
 lee_status lee_step_n(lee_instance *inst, int64_t n);
 
 /*
@@ -306,9 +310,9 @@ typedef struct {
 
 /*
  * Group n bound instances of the same precision and stencil into a batch
- * advanced by one launch per phase (ghost fill, sweep, step end) over a
- * flat work list spanning all members, captured in hipGraphs on the stream
- * of the first member.  The instance table lives in device memory
+ * advanced by one launch per phase (ghost fill and sweep, or one fused
+ * launch) over a flat work list spanning all members, captured in hipGraphs
+ * on the stream of the first member.  The instance table lives in device memory
  * owned by the batch (allocated by the library).  Members keep their own
  * step counters; lee_batch_set_budget lets finished members idle without
  * re-capturing.
@@ -326,8 +330,10 @@ lee_status lee_batch_add(lee_batch *b, lee_instance *inst);
 lee_status lee_batch_remove(lee_batch *b, lee_instance *inst);
 lee_status lee_batch_size(const lee_batch *b, int32_t *n);
 
-/* Per-member remaining step budget: a member advances only while its budget
- * is positive (budget decremented on device every step).  n entries. */
+/* Per-member step budget (n entries, synchronising): member k takes the next
+ * steps[k] steps and then idles (its fields, ADE states and step counter stay
+ * as they are) until a new budget is set.  lee_init_fields (and so
+ * lee_bind) makes an instance's budget unlimited. */
 lee_status lee_batch_set_budget(lee_batch *b, const int64_t *steps);
 
 /* n steps of every member with a positive budget; asynchronous. */

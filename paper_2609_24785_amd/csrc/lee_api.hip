@@ -16,10 +16,13 @@
 
 using namespace lee;
 
+constexpr int GRAPH_STEPS_DEFAULT = 16;            // measured: amortises the gap between graph launches
+constexpr int GRAPH_STEPS_MAX = 256;
+
 // Captured steps: `many` holds `per` consecutive steps, `one` a single step
 // for the remainder.  per == 0 launches every kernel eagerly.
 struct StepGraphs {
-    int per = 1;
+    int per = GRAPH_STEPS_DEFAULT;
     hipGraph_t gm = nullptr, g1 = nullptr;
     hipGraphExec_t em = nullptr, e1 = nullptr;
     void drop()
@@ -32,9 +35,6 @@ struct StepGraphs {
         gm = g1 = nullptr;
     }
 };
-constexpr int GRAPH_STEPS_DEFAULT = 16;            // measured: amortises the gap between graph launches
-constexpr int GRAPH_STEPS_MAX = 256;
-
 struct lee_instance {
     Host host;
     lee_tiling tl{};
@@ -55,7 +55,9 @@ struct lee_instance {
     size_t patch_cap = 0;
     int4 *d_work2 = nullptr;
     int nwork2 = 0;
-    int *d_sync = nullptr;          // fused-stage counters and error flag
+    int *d_sync = nullptr;          // fused-stage error flag
+    int2 *d_pwork = nullptr;        // (member, probe) pairs of the probe pass
+    std::vector<int2> up_pwork;
     int *d_sij = nullptr;
     double *d_sw = nullptr, *d_sout = nullptr;
     // host staging kept alive for asynchronous uploads
@@ -64,8 +66,7 @@ struct lee_instance {
     std::vector<int4> up_work1, up_iv;
     std::vector<int2> up_aux, up_patch;
     std::vector<int4> up_work2;
-    long long up_counters[3] = {0, LLONG_MAX, 1};
-    double up_amp[4] = {0, 0, 0, 0};
+    long long up_counters[2] = {0, LLONG_MAX};
     // sequencing
     StepGraphs graphs;
     int next_stage = 0;
@@ -101,7 +102,7 @@ size_t work1_capacity(const Host &h)
 }
 
 struct Layout {
-    size_t inst, planes[9], psi[3], iv, goff, cptr, coff, w4, gd, counters, amp, pij, pw, trace, dft, watch, xg,
+    size_t inst, planes[9], psi[3], iv, goff, cptr, coff, w4, gd, counters, pij, pw, pwork, trace, dft, watch, xg,
         work1, aux, patch, work2, sync, sij, sw, sout, total;
 };
 
@@ -129,10 +130,10 @@ Layout layout(const Host &h)
     L.coff = take(std::max<size_t>(nnz, 1) * 4);
     L.w4 = take(4 * std::max<size_t>(nnz, 1) * es);
     L.gd = take(4 * std::max<size_t>(G, 1) * es);
-    L.counters = take(3 * 8);
-    L.amp = take(4 * 8);
+    L.counters = take(2 * 8);
     L.pij = take(2 * std::max(h.np, 1) * 4);
     L.pw = take(16 * std::max(h.np, 1) * 8);
+    L.pwork = take(std::max(h.np, 1) * sizeof(int2));
     L.trace = take(std::max<size_t>((size_t)h.trace_cap * h.np * 3, 1) * 8);
     L.dft = take(2 * std::max(h.np, 1) * 8);
     L.watch = take(2 * std::max<size_t>((size_t)h.watch_cap, 1) * 8);
@@ -349,18 +350,19 @@ lee_status upload_work1(lee_instance *I)
 
 void drop_graph(lee_instance *I) { I->graphs.drop(); }
 
-// n steps on stream s through the captured graphs (or eagerly); issue_step
-// enqueues the launches of one step.
-lee_status run_steps(StepGraphs &G, hipStream_t s, int64_t n, const std::function<hipError_t()> &issue_step)
+// n steps on stream s through the captured graphs (or eagerly); issue_run(k)
+// enqueues one run of k steps (the launches of each step, then the run's
+// tail, which samples the probes after the last step and advances the step
+// counters).  Graphs hold runs of G.per steps and of one step.
+lee_status run_steps(StepGraphs &G, hipStream_t s, int64_t n, const std::function<hipError_t(int)> &issue_run)
 {
     if (s == nullptr || G.per == 0) {            // the legacy default stream cannot be captured
-        for (int64_t k = 0; k < n; ++k) HIPCHK(issue_step());
+        for (int64_t k = 0; k < n; k += 1 << 20) HIPCHK(issue_run((int)std::min<int64_t>(n - k, 1 << 20)));
         return LEE_OK;
     }
     auto capture = [&](int steps, hipGraph_t &g, hipGraphExec_t &ex) -> lee_status {
         HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        hipError_t e = hipSuccess;
-        for (int k = 0; k < steps && e == hipSuccess; ++k) e = issue_step();
+        hipError_t e = issue_run(steps);
         hipGraph_t cg = nullptr;
         hipError_t e2 = hipStreamEndCapture(s, &cg);
         if (e != hipSuccess) {
@@ -390,10 +392,11 @@ lee_status run_steps(StepGraphs &G, hipStream_t s, int64_t n, const std::functio
 int graph_steps_from(int32_t v) { return v == 0 ? GRAPH_STEPS_DEFAULT : (v < 0 ? 0 : v); }
 
 hipError_t sweep(int prec, bool filt, const lee_tiling &t, const DevInst *insts, const int4 *work, int nwork,
-                 int stage, int blocks, hipStream_t s)
+                 int stage, int slot, int blocks, hipStream_t s)
 {
-    if (t.kind == LEE_SWEEP_TILE) return launch_tile(prec, filt, t.cols, t.rows, insts, work, nwork, stage, blocks, s);
-    return launch_sweep(prec, t.vec, filt, t.waves, insts, work, nwork, stage, blocks, s);
+    if (t.kind == LEE_SWEEP_TILE)
+        return launch_tile(prec, filt, t.cols, t.rows, insts, work, nwork, stage, slot, blocks, s);
+    return launch_sweep(prec, t.vec, filt, t.waves, insts, work, nwork, stage, slot, blocks, s);
 }
 
 bool fused(const lee_tiling &t) { return t.kind == LEE_SWEEP_TILE && t.fused; }
@@ -403,11 +406,12 @@ bool fused(const lee_tiling &t) { return t.kind == LEE_SWEEP_TILE && t.fused; }
 // fused launch (s0, s1).
 hipError_t stage_launches(int prec, bool filt, const lee_tiling &t, const DevInst *insts, const int4 *work1,
                           int nwork1, const int2 *aux, const int2 *patch, int tile0, const int4 *work2, int nwork2,
-                          int *sync, int stage, int blocks, hipStream_t s, hipEvent_t *ev = nullptr)
+                          int *sync, int stage, int slot, ProbePass pp, int blocks, hipStream_t s,
+                          hipEvent_t *ev = nullptr)
 {
     hipError_t e = hipSuccess;
     if (ev) hipEventRecord(ev[0], s);
-    if (!fused(t)) e = launch_ghost(prec, insts, work2, nwork2, stage, s);
+    if (!fused(t)) e = launch_ghost(prec, insts, work2, nwork2, stage, slot, pp, s);
     if (ev) {
         hipEventRecord(ev[1], s);
         hipEventRecord(ev[2], s);
@@ -415,21 +419,46 @@ hipError_t stage_launches(int prec, bool filt, const lee_tiling &t, const DevIns
     if (e != hipSuccess) return e;
     if (fused(t))
         e = launch_stage(prec, filt, t.cols, t.rows, insts, work1, nwork1, aux, patch, tile0, work2, nwork2, stage,
-                         sync, SPIN_LIMIT, s);
+                         slot, sync, SPIN_LIMIT, pp, s);
     else
-        e = sweep(prec, filt, t, insts, work1, nwork1, stage, blocks, s);
+        e = sweep(prec, filt, t, insts, work1, nwork1, stage, slot, blocks, s);
     if (ev) hipEventRecord(ev[3], s);
     return e;
 }
 
-hipError_t issue_stage(lee_instance *I, int stage, hipEvent_t *ev = nullptr)
+// The probe pass a stage launch carries: in the second stage of every step
+// of a run but the first, the probes after the previous step (buffer 0 holds
+// its result through the first three stages).
+ProbePass probe_pass(const int2 *pw, int np, int stage, int slot)
+{
+    if (stage == 1 && slot >= 1) return ProbePass{pw, np, slot - 1};
+    return ProbePass{pw, 0, 0};
+}
+
+// Stage `stage` of step `slot` of the current run.
+hipError_t issue_stage(lee_instance *I, int stage, int slot)
 {
     const int prec = I->host.d.precision;
-    hipError_t e = stage_launches(prec, I->host.d.filter_sigma > 0.0, I->tl, I->d_inst, I->d_work1, I->nwork1,
-                                  I->d_aux, I->d_patch, I->tile0, I->d_work2, I->nwork2, I->d_sync, stage, 0,
-                                  I->stream, ev);
-    if (e != hipSuccess) return e;
-    if (stage == 3) e = launch_step_end(prec, I->d_inst, 1, I->stream);
+    return stage_launches(prec, I->host.d.filter_sigma > 0.0, I->tl, I->d_inst, I->d_work1, I->nwork1, I->d_aux,
+                          I->d_patch, I->tile0, I->d_work2, I->nwork2, I->d_sync, stage, slot,
+                          probe_pass(I->d_pwork, I->host.np, stage, slot), 0, I->stream);
+}
+
+// The tail of a run of n steps: the probes after its last step, then the
+// step counter.
+hipError_t issue_tail(lee_instance *I, int n)
+{
+    hipError_t e = launch_probe(I->host.d.precision, I->d_inst, ProbePass{I->d_pwork, I->host.np, n - 1}, I->stream);
+    if (e == hipSuccess) e = launch_advance(I->d_inst, 1, n, I->stream);
+    return e;
+}
+
+hipError_t issue_run(lee_instance *I, int n)
+{
+    hipError_t e = hipSuccess;
+    for (int j = 0; j < n && e == hipSuccess; ++j)
+        for (int l = 0; l < 4 && e == hipSuccess; ++l) e = issue_stage(I, l, j);
+    if (e == hipSuccess) e = issue_tail(I, n);
     return e;
 }
 
@@ -624,9 +653,7 @@ lee_status lee_bind(lee_instance *I, void *dev_ptr, size_t bytes, void *hip_stre
     D.w4 = b + L.w4;
     D.gd = b + L.gd;
     D.step = (long long *)(b + L.counters);
-    D.budget = D.step + 1;
-    D.active = (int *)(D.step + 2);
-    D.amp = (double *)(b + L.amp);
+    D.stop = D.step + 1;
     D.pij = (const int *)(b + L.pij);
     D.pw = (const double *)(b + L.pw);
     D.trace = (double *)(b + L.trace);
@@ -710,9 +737,13 @@ lee_status lee_bind(lee_instance *I, void *dev_ptr, size_t bytes, void *hip_stre
         HIPCHK(hipMemcpyAsync((void *)D.coff, I->up_coff.data(), nnz * 4, hipMemcpyHostToDevice, s));
         HIPCHK(hipMemcpyAsync((void *)D.w4, I->up_w4.data(), I->up_w4.size(), hipMemcpyHostToDevice, s));
     }
+    I->d_pwork = (int2 *)(b + L.pwork);
+    I->up_pwork.resize(h.np);
+    for (int k = 0; k < h.np; ++k) I->up_pwork[k] = make_int2(0, k);
     if (h.np) {
         HIPCHK(hipMemcpyAsync((void *)D.pij, h.probe_ij.data(), 2 * h.np * 4, hipMemcpyHostToDevice, s));
         HIPCHK(hipMemcpyAsync((void *)D.pw, h.probe_w.data(), 16 * h.np * 8, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(I->d_pwork, I->up_pwork.data(), h.np * sizeof(int2), hipMemcpyHostToDevice, s));
     }
     I->d_inst = (DevInst *)(b + L.inst);
     HIPCHK(hipMemcpyAsync(I->d_inst, &I->dev, sizeof(DevInst), hipMemcpyHostToDevice, s));
@@ -750,13 +781,9 @@ lee_status lee_init_fields(lee_instance *I)
     HIPCHK(launch_fill_bytes(I->base + L.watch, 2 * std::max<size_t>((size_t)h.watch_cap, 1) * 8, s));
     HIPCHK(launch_fill_bytes(I->base + L.xg, xg_bytes(h), s));
     HIPCHK(launch_fill_bytes(I->base + L.sync, SYNC_INTS * sizeof(int), s));
-    I->up_counters[0] = 0;
-    I->up_counters[1] = LLONG_MAX;
-    I->up_counters[2] = 1;   // active flag lives in the low word of the third slot
+    I->up_counters[0] = 0;                       // first step of the next run
+    I->up_counters[1] = LLONG_MAX;               // no stop
     HIPCHK(hipMemcpyAsync(I->dev.step, I->up_counters, sizeof(I->up_counters), hipMemcpyHostToDevice, s));
-    for (int l = 0; l < 4; ++l)        // stage amplitudes of step 0
-        I->up_amp[l] = I->dev.has_src ? I->dev.src_a * std::sin(I->dev.src_om * (I->dev.c_stage[l] * I->dev.dt)) : 0.0;
-    HIPCHK(hipMemcpyAsync(I->dev.amp, I->up_amp, sizeof(I->up_amp), hipMemcpyHostToDevice, s));
     HIPCHK(launch_init_ic(prec, I->d_inst, h.d.nx, h.d.ny, h.d.ic_kind, h.d.ic, s));
     I->next_stage = 0;
     I->steps_issued = 0;
@@ -768,7 +795,8 @@ lee_status lee_rk_stage(lee_instance *I, int32_t stage)
     if (!I || !I->bound) return fail(LEE_E_STATE, "instance not bound");
     if (stage < 0 || stage > 3) return fail(LEE_E_ARG, "stage must be 0..3");
     if (stage != I->next_stage) return fail(LEE_E_STATE, "stages must be issued in order 0, 1, 2, 3");
-    HIPCHK(issue_stage(I, stage));
+    HIPCHK(issue_stage(I, stage, 0));
+    if (stage == 3) HIPCHK(issue_tail(I, 1));
     I->next_stage = (stage + 1) & 3;
     if (stage == 3) ++I->steps_issued;
     return LEE_OK;
@@ -780,11 +808,7 @@ lee_status lee_step_n(lee_instance *I, int64_t n)
     if (n < 0) return fail(LEE_E_ARG, "n < 0");
     if (I->next_stage != 0) return fail(LEE_E_STATE, "a partial step is pending");
     if (n == 0) return LEE_OK;
-    lee_status st = run_steps(I->graphs, I->stream, n, [I]() {
-        hipError_t e = hipSuccess;
-        for (int l = 0; l < 4 && e == hipSuccess; ++l) e = issue_stage(I, l);
-        return e;
-    });
+    lee_status st = run_steps(I->graphs, I->stream, n, [I](int k) { return issue_run(I, k); });
     if (st != LEE_OK) return st;
     I->steps_issued += n;
     return LEE_OK;
@@ -1005,7 +1029,8 @@ lee_status lee_time_kernels(lee_instance *I, int64_t n, double *sweep_us, double
     auto ghosts = [&]() -> hipError_t {
         hipError_t e = hipSuccess;
         for (int64_t k = 0; k < 4 * n && e == hipSuccess; ++k)
-            e = launch_ghost(prec, I->d_inst, I->d_work2, I->nwork2, (int)(k & 3), I->stream);
+            e = launch_ghost(prec, I->d_inst, I->d_work2, I->nwork2, (int)(k & 3), 0, ProbePass{nullptr, 0, 0},
+                             I->stream);
         return e;
     };
     auto sweeps = [&]() -> hipError_t {
@@ -1013,18 +1038,13 @@ lee_status lee_time_kernels(lee_instance *I, int64_t n, double *sweep_us, double
         for (int64_t k = 0; k < 4 * n && e == hipSuccess; ++k) {
             const int l = (int)(k & 3);
             e = fused(I->tl) ? launch_stage(prec, filt, I->tl.cols, I->tl.rows, I->d_inst, I->d_work1, I->nwork1,
-                                            I->d_aux, I->d_patch, I->tile0, I->d_work2, I->nwork2, l, I->d_sync,
-                                            SPIN_LIMIT, I->stream)
-                             : sweep(prec, filt, I->tl, I->d_inst, I->d_work1, I->nwork1, l, 0, I->stream);
+                                            I->d_aux, I->d_patch, I->tile0, I->d_work2, I->nwork2, l, 0, I->d_sync,
+                                            SPIN_LIMIT, ProbePass{nullptr, 0, 0}, I->stream)
+                             : sweep(prec, filt, I->tl, I->d_inst, I->d_work1, I->nwork1, l, 0, 0, I->stream);
         }
         return e;
     };
-    auto steps = [&]() -> hipError_t {
-        hipError_t e = hipSuccess;
-        for (int64_t k = 0; k < n && e == hipSuccess; ++k)
-            for (int l = 0; l < 4 && e == hipSuccess; ++l) e = issue_stage(I, l);
-        return e;
-    };
+    auto steps = [&]() -> hipError_t { return issue_run(I, (int)std::min<int64_t>(n, 1 << 20)); };
     double out[3] = {0, 0, 0};
     lee_status st = time_runs(I->stream, {ghosts, sweeps, steps}, out);
     lee_status st2 = lee_init_fields(I);
@@ -1080,7 +1100,11 @@ struct lee_batch {
     size_t aux_cap = 0, patch_cap = 0;
     int tile0 = 0;
     std::vector<int4> up_work2;
-    std::vector<long long> up_budget;      // (budget, active) pairs
+    int2 *d_pwork = nullptr;               // (member, probe) pairs of the probe pass
+    size_t pwork_cap = 0;
+    int npwork = 0;
+    std::vector<int2> up_pwork;
+    std::vector<long long> up_budget;      // stop steps being uploaded
     StepGraphs graphs;
 };
 
@@ -1102,15 +1126,23 @@ void batch_build_work1(lee_batch *B)
     B->nwork1 = (int)B->up_work1.size();
 }
 
-hipError_t batch_issue_stage(lee_batch *B, int stage, hipEvent_t *ev = nullptr)
+hipError_t batch_issue_stage(lee_batch *B, int stage, int slot)
 {
     int blocks = 0;
     const int per = B->tl.kind == LEE_SWEEP_MARCH ? B->tl.waves : 1;
     if (B->pblocks > 0) blocks = std::min(B->pblocks, (B->nwork1 + per - 1) / per);
-    hipError_t e = stage_launches(B->prec, B->filt, B->tl, B->d_table, B->d_work1, B->nwork1, B->d_aux, B->d_patch,
-                                  B->tile0, B->d_work2, B->nwork2, B->d_sync, stage, blocks, B->stream, ev);
-    if (e != hipSuccess) return e;
-    if (stage == 3) e = launch_step_end(B->prec, B->d_table, (int)B->members.size(), B->stream);
+    return stage_launches(B->prec, B->filt, B->tl, B->d_table, B->d_work1, B->nwork1, B->d_aux, B->d_patch,
+                          B->tile0, B->d_work2, B->nwork2, B->d_sync, stage, slot,
+                          probe_pass(B->d_pwork, B->npwork, stage, slot), blocks, B->stream);
+}
+
+hipError_t batch_issue_run(lee_batch *B, int n)
+{
+    hipError_t e = hipSuccess;
+    for (int j = 0; j < n && e == hipSuccess; ++j)
+        for (int l = 0; l < 4 && e == hipSuccess; ++l) e = batch_issue_stage(B, l, j);
+    if (e == hipSuccess) e = launch_probe(B->prec, B->d_table, ProbePass{B->d_pwork, B->npwork, n - 1}, B->stream);
+    if (e == hipSuccess) e = launch_advance(B->d_table, (int)B->members.size(), n, B->stream);
     return e;
 }
 
@@ -1140,12 +1172,15 @@ lee_status batch_rebuild(lee_batch *B)
     const size_t n = B->members.size();
     B->up_table.clear();
     B->up_work2.clear();
+    B->up_pwork.clear();
     for (size_t k = 0; k < n; ++k) {
         const lee_instance *I = B->members[k];
         B->up_table.push_back(I->dev);
         for (int g = 0; g < (int)I->host.gidx.size(); ++g)
             B->up_work2.push_back(make_int4((int)k, g, I->host.cptr[g], I->host.cptr[g + 1]));
+        for (int p = 0; p < I->host.np; ++p) B->up_pwork.push_back(make_int2((int)k, p));
     }
+    B->npwork = (int)B->up_pwork.size();
     batch_build_work1(B);
     B->nwork2 = (int)B->up_work2.size();
     HIPCHK(grow(B->d_table, B->table_cap, n, B->stream));
@@ -1153,6 +1188,10 @@ lee_status batch_rebuild(lee_batch *B)
     HIPCHK(grow(B->d_work2, B->work2_cap, B->up_work2.size(), B->stream));
     HIPCHK(grow(B->d_aux, B->aux_cap, B->up_aux.size(), B->stream));
     HIPCHK(grow(B->d_patch, B->patch_cap, B->up_patch.size(), B->stream));
+    HIPCHK(grow(B->d_pwork, B->pwork_cap, B->up_pwork.size(), B->stream));
+    if (B->npwork)
+        HIPCHK(hipMemcpyAsync(B->d_pwork, B->up_pwork.data(), B->npwork * sizeof(int2), hipMemcpyHostToDevice,
+                              B->stream));
     if (n)
         HIPCHK(hipMemcpyAsync(B->d_table, B->up_table.data(), n * sizeof(DevInst), hipMemcpyHostToDevice,
                               B->stream));
@@ -1191,6 +1230,9 @@ void batch_free(lee_batch *B)
     if (B->d_sync) hipFree(B->d_sync);
     if (B->d_aux) hipFree(B->d_aux);
     if (B->d_patch) hipFree(B->d_patch);
+    if (B->d_pwork) hipFree(B->d_pwork);
+    B->d_pwork = nullptr;
+    B->pwork_cap = 0;
     B->d_sync = nullptr;
     B->d_aux = B->d_patch = nullptr;
     B->table_cap = B->work1_cap = B->work2_cap = B->aux_cap = B->patch_cap = 0;
@@ -1289,12 +1331,16 @@ lee_status lee_batch_set_budget(lee_batch *B, const int64_t *steps)
 {
     if (!B || !steps) return fail(LEE_E_ARG, "null argument");
     const size_t n = B->members.size();
-    B->up_budget.assign(2 * n, 0);
-    for (size_t k = 0; k < n; ++k) {
+    for (size_t k = 0; k < n; ++k)
         if (steps[k] < 0) return fail(LEE_E_ARG, "negative budget");
-        B->up_budget[2 * k] = steps[k];
-        B->up_budget[2 * k + 1] = steps[k] > 0 ? 1 : 0;
-        HIPCHK(hipMemcpyAsync(B->members[k]->dev.budget, &B->up_budget[2 * k], 16, hipMemcpyHostToDevice, B->stream));
+    // each member stops `steps` steps after the ones it has completed
+    B->up_budget.assign(n, 0);
+    HIPCHK(hipStreamSynchronize(B->stream));
+    for (size_t k = 0; k < n; ++k)
+        HIPCHK(hipMemcpy(&B->up_budget[k], B->members[k]->dev.step, 8, hipMemcpyDeviceToHost));
+    for (size_t k = 0; k < n; ++k) {
+        B->up_budget[k] += steps[k];
+        HIPCHK(hipMemcpyAsync(B->members[k]->dev.stop, &B->up_budget[k], 8, hipMemcpyHostToDevice, B->stream));
     }
     HIPCHK(hipStreamSynchronize(B->stream));
     return LEE_OK;
@@ -1305,11 +1351,7 @@ lee_status lee_batch_step_n(lee_batch *B, int64_t n)
     if (!B) return fail(LEE_E_ARG, "null batch");
     if (n < 0) return fail(LEE_E_ARG, "n < 0");
     if (n == 0 || B->members.empty()) return LEE_OK;
-    lee_status st = run_steps(B->graphs, B->stream, n, [B]() {
-        hipError_t e = hipSuccess;
-        for (int l = 0; l < 4 && e == hipSuccess; ++l) e = batch_issue_stage(B, l);
-        return e;
-    });
+    lee_status st = run_steps(B->graphs, B->stream, n, [B](int k) { return batch_issue_run(B, k); });
     if (st != LEE_OK) return st;
     for (auto *I : B->members) I->steps_issued += n;   // upper bound; budgets may idle members
     return LEE_OK;
@@ -1326,7 +1368,8 @@ lee_status lee_batch_time_kernels(lee_batch *B, int64_t n, double *sweep_us, dou
     auto ghosts = [&]() -> hipError_t {
         hipError_t e = hipSuccess;
         for (int64_t k = 0; k < 4 * n && e == hipSuccess; ++k)
-            e = launch_ghost(B->prec, B->d_table, B->d_work2, B->nwork2, (int)(k & 3), B->stream);
+            e = launch_ghost(B->prec, B->d_table, B->d_work2, B->nwork2, (int)(k & 3), 0, ProbePass{nullptr, 0, 0},
+                             B->stream);
         return e;
     };
     auto sweeps = [&]() -> hipError_t {
@@ -1334,18 +1377,14 @@ lee_status lee_batch_time_kernels(lee_batch *B, int64_t n, double *sweep_us, dou
         for (int64_t k = 0; k < 4 * n && e == hipSuccess; ++k) {
             const int l = (int)(k & 3);
             e = fused(B->tl) ? launch_stage(B->prec, B->filt, B->tl.cols, B->tl.rows, B->d_table, B->d_work1,
-                                            B->nwork1, B->d_aux, B->d_patch, B->tile0, B->d_work2, B->nwork2, l,
-                                            B->d_sync, SPIN_LIMIT, B->stream)
-                             : sweep(B->prec, B->filt, B->tl, B->d_table, B->d_work1, B->nwork1, l, blocks, B->stream);
+                                            B->nwork1, B->d_aux, B->d_patch, B->tile0, B->d_work2, B->nwork2, l, 0,
+                                            B->d_sync, SPIN_LIMIT, ProbePass{nullptr, 0, 0}, B->stream)
+                             : sweep(B->prec, B->filt, B->tl, B->d_table, B->d_work1, B->nwork1, l, 0, blocks,
+                                     B->stream);
         }
         return e;
     };
-    auto steps = [&]() -> hipError_t {
-        hipError_t e = hipSuccess;
-        for (int64_t k = 0; k < n && e == hipSuccess; ++k)
-            for (int l = 0; l < 4 && e == hipSuccess; ++l) e = batch_issue_stage(B, l);
-        return e;
-    };
+    auto steps = [&]() -> hipError_t { return batch_issue_run(B, (int)std::min<int64_t>(n, 1 << 20)); };
     double out[3] = {0, 0, 0};
     lee_status st = time_runs(B->stream, {ghosts, sweeps, steps}, out);
     for (auto *I : B->members) {

@@ -23,10 +23,8 @@ struct DevInst {
     const int *coff;        // cloud plane offsets (from the plane start)
     const void *w4;         // 4 weights per cloud entry (T)
     const void *gd;         // per ghost: n_x, n_y, beta_D, beta_N (T)
-    long long *step;        // completed steps
-    double *amp;            // source amplitude a sin(omega t_l) of the 4 stages of the next step
-    long long *budget;      // remaining steps; the member idles at 0
-    int *active;            // 1 while budget > 0
+    long long *step;        // first step of the current run (completed steps between runs)
+    long long *stop;        // the member takes the steps below this one
     const int *pij;         // probe stencil origins
     const double *pw;       // probe weights, 16 per probe
     double *trace;          // ring of trace_cap steps x np x 3
@@ -58,26 +56,41 @@ struct DevInst {
     double ade[4];
 };
 
+// Probe sampling carried by a launch: the (member, probe) pairs pw[0, np),
+// for step *step + rel of each member that took that step (np = 0: none).
+struct ProbePass {
+    const int2 *pw;
+    int np;
+    int rel;
+};
+
+// Stage launches act on step *step + slot of each member (slot = the step's
+// place in the current run).
 hipError_t launch_sweep(int prec, int vec, bool filt, int waves, const DevInst *insts, const int4 *work,
-                        int nwork, int stage, int blocks, hipStream_t s);
+                        int nwork, int stage, int slot, int blocks, hipStream_t s);
 bool tile_shape_supported(int prec, int tx, int ty);
 hipError_t launch_tile(int prec, bool filt, int tx, int ty, const DevInst *insts, const int4 *work, int nwork,
-                       int stage, int blocks, hipStream_t s);
+                       int stage, int slot, int blocks, hipStream_t s);
 // One launch for a stage with the tile sweep: the first ceil(nwork2 / 16)
 // workgroups fill 16 ghosts each, tile k runs in workgroup tile0 + k (the
 // caller keeps dependent tiles out of the carrier workgroups).  Items flagged
 // with TILE_DEP_BIT wait for the ghost values they read and patch them in:
 // aux[k] = [begin, end) in patch, whose entries are (LDS element index in the
 // tile's copy, ghost index * 3 + field).  sync[4] is the error flag raised by
-// a wait that runs out of polls (zero before first use).
+// a wait that runs out of polls (zero before first use).  The probe pass
+// runs in extra workgroups after the tiles.
 hipError_t launch_stage(int prec, bool filt, int tx, int ty, const DevInst *insts, const int4 *work1, int nwork1,
                         const int2 *aux, const int2 *patch, int tile0, const int4 *work2, int nwork2, int stage,
-                        int *sync, int spin_limit, hipStream_t s);
+                        int slot, int *sync, int spin_limit, ProbePass pp, hipStream_t s);
 constexpr int TILE_DEP_BIT = 1 << 30;
 constexpr int SYNC_INTS = 8;
 constexpr int SPIN_LIMIT = 1 << 20;             // polls before a ghost wait gives up (about a second)
-hipError_t launch_ghost(int prec, const DevInst *insts, const int4 *work, int nwork, int stage, hipStream_t s);
-hipError_t launch_step_end(int prec, const DevInst *insts, int ninst, hipStream_t s);
+// The ghost fill of a stage, with the probe pass in extra workgroups.
+hipError_t launch_ghost(int prec, const DevInst *insts, const int4 *work, int nwork, int stage, int slot,
+                        ProbePass pp, hipStream_t s);
+hipError_t launch_probe(int prec, const DevInst *insts, ProbePass pp, hipStream_t s);
+// After a run of n steps: *step += n for every member, held at *stop.
+hipError_t launch_advance(const DevInst *insts, int ninst, int n, hipStream_t s);
 hipError_t launch_fill(int prec, void *p, size_t n, hipStream_t s);
 hipError_t launch_fill_bytes(void *p, size_t bytes, hipStream_t s);
 hipError_t launch_init_ic(int prec, const DevInst *insts, int nx, int ny, int kind, const double *c,

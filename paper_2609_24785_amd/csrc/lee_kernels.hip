@@ -20,7 +20,9 @@
 //               neighbours); alternate runs march in opposite directions so
 //               that vertically adjacent runs read their shared halo rows at
 //               about the same time (L2 reuse).
-//   k_step_end  step counter, per-member budget, probe sampling and DFT.
+//   probes      sampling of the 8- or 360-point probe sets and their DFT, in
+//               extra workgroups of a later stage launch (k_probe at the end
+//               of a run); k_advance moves the step counters.
 //
 // No matrix cores: the stage is a stencil over three fields, bound by memory
 // traffic and, within a one-wave launch, by the vector ALU (about 110 FP32
@@ -82,6 +84,19 @@ __device__ __forceinline__ void wave_lds_sync()
 __device__ __forceinline__ int in_buf(int stage) { return stage == 0 ? 0 : (stage == 2 ? 2 : 1); }
 __device__ __forceinline__ int out_buf(int stage) { return stage == 0 ? 1 : (stage == 1 ? 2 : (stage == 2 ? 1 : 0)); }
 
+// Steps of a run: the launches of the run's step `slot` act on step
+// *I.step + slot of each member (*I.step is advanced only between runs), and
+// a member takes the steps below *I.stop.
+__device__ __forceinline__ long long step_at(const DevInst &I, int slot) { return *(const GLOBAL long long *)I.step + slot; }
+__device__ __forceinline__ bool takes(const DevInst &I, long long s) { return s < *(const GLOBAL long long *)I.stop; }
+
+// Monopole amplitude a sin(omega t) at stage l of step s, t = (s + c_l) dt
+// (FP64).
+__device__ __forceinline__ double src_amp(const DevInst &I, long long s, int stage)
+{
+    return I.src_a * sin(I.src_om * (((double)s + I.c_stage[stage]) * I.dt));
+}
+
 // ---------------------------------------------------------------------------
 // ghost fill + ADE
 
@@ -114,7 +129,7 @@ __device__ __forceinline__ void xg_put(GLOBAL unsigned long long *w, T v, unsign
 // PUB (fused launches) the ghost values also go to the exchange words I.xg.
 template <typename T, int GL, bool PUB = false>
 __device__ __forceinline__ void ghost_item(const DevInst *__restrict__ insts, const int4 *__restrict__ work,
-                                           int nwork, int gid, int sub, int stage)
+                                           int nwork, int gid, int sub, int stage, int slot)
 {
     if (gid >= nwork) return;                       // whole GL-lane groups leave together
     const int4 wk = work[gid];                      // instance, ghost, cloud entries [z, w)
@@ -126,7 +141,8 @@ __device__ __forceinline__ void ghost_item(const DevInst *__restrict__ insts, co
     GLOBAL T *V = gp<T>(I.f[ib][2]);
     // independent loads first (member flag, ghost data, ADE states, cloud
     // offsets and weights); the field values are the only dependent round trip
-    const int active = *gp<int>(I.active);
+    const long long step = step_at(I, slot);
+    const bool active = takes(I, step);
     const VecT<T, 4> gdv = vld<T, 4>(gp<T>(I.gd) + 4 * (size_t)g);
     const VecT<T, 2> psv = vld<T, 2>(gp<T>(I.psi[ib]) + 2 * (size_t)g);
     const VecT<T, 2> psn = vld<T, 2>(gp<T>(I.psi[0]) + 2 * (size_t)g);
@@ -185,7 +201,7 @@ __device__ __forceinline__ void ghost_item(const DevInst *__restrict__ insts, co
     // steps 4-5: Neumann for p (dp/dn = +du_n/dt in the wall-to-fluid frame),
     // Dirichlet for u.n (= -u_n), free for u.t
     if (stage == 0 && g == I.watch_g && I.watch_cap > 0) {   // recording only
-        double *wr = I.watch + 2 * (*I.step % I.watch_cap);
+        double *wr = I.watch + 2 * (step % I.watch_cap);
         wr[0] = (double)a0;
         wr[1] = (double)Un;
     }
@@ -199,7 +215,7 @@ __device__ __forceinline__ void ghost_item(const DevInst *__restrict__ insts, co
     V[go] = vg;
     if (PUB) {
         constexpr int NW = sizeof(T) / 4;
-        const unsigned ep = stage_epoch(*gp<long long>(I.step), stage);
+        const unsigned ep = stage_epoch(step, stage);
         GLOBAL unsigned long long *x = gp<unsigned long long>(I.xg) + (size_t)g * 3 * NW;
         xg_put<T>(x, pg, ep);
         xg_put<T>(x + NW, ug, ep);
@@ -213,12 +229,82 @@ __device__ __forceinline__ void ghost_item(const DevInst *__restrict__ insts, co
     }
 }
 
+// ---------------------------------------------------------------------------
+// probes
+
+// One probe per 16-lane group (pid), one stencil weight per lane: the
+// bicubic value of p, u, v of q^n (Sec. 4.1 probes) at the end of the
+// sampled step, into the trace ring, and the running DFT of p over the
+// window [dft_start, dft_start + dft_count) (FP64).  Valid while buffer 0
+// holds that step's result: in the first three stages of the next step, or
+// after the step.
+template <typename T>
+__device__ __forceinline__ void probe_item(const DevInst *__restrict__ insts, const ProbePass &pp, int pid, int sub)
+{
+    if (pid >= pp.np) return;                       // whole 16-lane groups leave together
+    const int2 q = pp.pw[pid];
+    const DevInst &I = insts[q.x];
+    const int k = q.y;
+    const long long s = step_at(I, pp.rel);
+    if (s < 0 || !takes(I, s)) return;
+    const int i0 = I.pij[2 * k], j0 = I.pij[2 * k + 1];
+    const int a = sub & 3, b = sub >> 2;
+    const double w = I.pw[16 * (size_t)k + sub];
+    const long off = (long)I.org + (long)(j0 + b) * I.pitch + (i0 + a);
+    double ap = w * (double)gp<T>(I.f[0][0])[off];
+    double au = w * (double)gp<T>(I.f[0][1])[off];
+    double av = w * (double)gp<T>(I.f[0][2])[off];
+#pragma unroll
+    for (int m = 8; m >= 1; m >>= 1) {
+        ap += __shfl_xor(ap, m, 16);
+        au += __shfl_xor(au, m, 16);
+        av += __shfl_xor(av, m, 16);
+    }
+    if (sub != 0) return;
+    if (I.trace_cap > 0) {
+        double *tr = I.trace + ((size_t)(s % I.trace_cap) * I.np + k) * 3;
+        tr[0] = ap;
+        tr[1] = au;
+        tr[2] = av;
+    }
+    if (I.dft_count > 0 && s >= I.dft_start && s < I.dft_start + I.dft_count) {   // sum p exp(-i omega t)
+        const double t = (double)(s + 1) * I.dt;
+        I.dft[2 * k] += ap * cos(I.dft_omega * t);
+        I.dft[2 * k + 1] -= ap * sin(I.dft_omega * t);
+    }
+}
+
+// Ghost fill of a stage (16 ghosts per workgroup), then the probe pass in
+// the workgroups after them.
 template <typename T, int GL>
 __global__ __launch_bounds__(256) void k_ghost(const DevInst *__restrict__ insts,
-                                               const int4 *__restrict__ work, int nwork, int stage)
+                                               const int4 *__restrict__ work, int nwork, int stage, int slot,
+                                               ProbePass pp)
 {
-    ghost_item<T, GL>(insts, work, nwork, (int)((blockIdx.x * blockDim.x + threadIdx.x) / GL),
-                      (int)(threadIdx.x % GL), stage);
+    const int nbg = (nwork * GL + 255) / 256;
+    const int b = (int)blockIdx.x;
+    if (b < nbg)
+        ghost_item<T, GL>(insts, work, nwork, (int)((b * blockDim.x + threadIdx.x) / GL), (int)(threadIdx.x % GL),
+                          stage, slot);
+    else
+        probe_item<T>(insts, pp, (b - nbg) * 16 + (int)threadIdx.x / 16, (int)threadIdx.x % 16);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_probe(const DevInst *__restrict__ insts, ProbePass pp)
+{
+    probe_item<T>(insts, pp, (int)blockIdx.x * 16 + (int)threadIdx.x / 16, (int)threadIdx.x % 16);
+}
+
+// After a run of n steps: each member's first step of the next run, held at
+// its stop step.
+__global__ void k_advance(const DevInst *__restrict__ insts, int ninst, int n)
+{
+    const int k = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (k >= ninst) return;
+    const DevInst &I = insts[k];
+    const long long b = *I.step, e = *I.stop;
+    if (b < e) *I.step = b + n < e ? b + n : e;
 }
 
 // ---------------------------------------------------------------------------
@@ -241,7 +327,7 @@ __device__ __forceinline__ void load_row(T (&dst)[3][VEC], const GLOBAL T *p, co
 
 template <typename T, int VEC, bool FILT, int WPB>
 __global__ __launch_bounds__(64 * WPB) void k_sweep(const DevInst *__restrict__ insts,
-                                                    const int4 *__restrict__ work, int nwork, int stage)
+                                                    const int4 *__restrict__ work, int nwork, int stage, int slot)
 {
     constexpr int NL = 64 * VEC;                 // loaded columns per strip
     constexpr int KM = (5 + VEC - 1) / VEC;      // LDS chunks left of the lane's own
@@ -256,7 +342,8 @@ __global__ __launch_bounds__(64 * WPB) void k_sweep(const DevInst *__restrict__ 
         const int4 wk = work[w];
         if (wk.x < 0) continue;                   // idle slot of the XCD-aware order
         const DevInst &I = insts[wk.x];
-        if (!*gp<int>(I.active)) continue;        // uniform per wave
+        const long long step = step_at(I, slot);
+        if (!takes(I, step)) continue;            // uniform per wave
         const int c0 = wk.y;                      // first output column
         const int r0 = wk.z;
         const int dir = wk.w < 0 ? -1 : 1;
@@ -288,7 +375,7 @@ __global__ __launch_bounds__(64 * WPB) void k_sweep(const DevInst *__restrict__ 
         const T ydir = (T)dir;
         const bool has_src = I.has_src && !(I.src_i1 < c0 || I.src_i0 >= c0 + NL - 16) &&
                              !(I.src_j1 < r0 || I.src_j0 >= r1);
-        const T amp = has_src ? (T)gp<double>(I.amp)[stage] : (T)0;
+        const T amp = has_src ? (T)src_amp(I, step, stage) : (T)0;
         const int sw = I.sponge_w;
 
         T q[11][3][VEC];
@@ -617,7 +704,7 @@ struct TileCtx {
 };
 
 template <typename T, int TX>
-__device__ __forceinline__ TileCtx<T> tile_ctx(const DevInst &I, const int4 wk, int stage)
+__device__ __forceinline__ TileCtx<T> tile_ctx(const DevInst &I, const int4 wk, int stage, long long step)
 {
     TileCtx<T> c;
     c.c0 = wk.y;
@@ -633,7 +720,7 @@ __device__ __forceinline__ TileCtx<T> tile_ctx(const DevInst &I, const int4 wk, 
     c.sp_inv = (T)I.sponge_inv;
     c.sp_s = (T)I.sponge_s;
     c.has_src = I.has_src && !(I.src_i1 < c.c0 || I.src_i0 >= c.c0 + TX) && !(I.src_j1 < c.r0 || I.src_j0 >= c.r1);
-    c.amp = c.has_src ? (T)sload<double>(I.amp + stage) : (T)0;
+    c.amp = c.has_src ? (T)src_amp(I, step, stage) : (T)0;
     return c;
 }
 
@@ -826,16 +913,17 @@ __device__ __forceinline__ void tile_store(const DevInst &I, int ob, unsigned of
 
 // One tile: wk = {instance, first column, first row, +-(end row)}.
 template <typename T, int VEC, bool FILT, int TX, int TY>
-__device__ __forceinline__ void tile_body(const DevInst *__restrict__ insts, const int4 wk, int stage,
+__device__ __forceinline__ void tile_body(const DevInst *__restrict__ insts, const int4 wk, int stage, int slot,
                                           const GhostDep *dep)
 {
     using G = TileGeo<T, VEC, TX, TY>;
     __shared__ alignas(16) T lds[3][G::R][G::LW];
     __shared__ alignas(16) T ldn[3][TY][TX];
     const DevInst &I = insts[wk.x];
-    if (!sload<int>(I.active)) return;
+    const long long step = sload<long long>(I.step) + slot;
+    if (step >= sload<long long>(I.stop)) return;
     const int tid = threadIdx.x;
-    const TileCtx<T> c = tile_ctx<T, TX>(I, wk, stage);
+    const TileCtx<T> c = tile_ctx<T, TX>(I, wk, stage, step);
     tile_copy<T, VEC, TX, TY>(I, c, stage, lds, ldn);
     // while the copy flies: this lane's first row ranges and its first patch
     // entries
@@ -847,7 +935,7 @@ __device__ __forceinline__ void tile_body(const DevInst *__restrict__ insts, con
     __builtin_amdgcn_s_waitcnt(0);               // this wave's DMA has landed in LDS
     __syncthreads();                             // ... and every other wave's
     if (dep) {                                   // this stage's ghost values over the copied ones
-        tile_patch<T, TX, TY>(I, stage_epoch(sload<long long>(I.step), stage), lds, *dep, pre);
+        tile_patch<T, TX, TY>(I, stage_epoch(step, stage), lds, *dep, pre);
         __syncthreads();
     }
     const int cg = tid % G::NCX;
@@ -877,14 +965,14 @@ constexpr int DEP_BIT = TILE_DEP_BIT;
 
 template <typename T, int VEC, bool FILT, int TX, int TY>
 __global__ __launch_bounds__(256) void k_tile(const DevInst *__restrict__ insts, const int4 *__restrict__ work,
-                                              int nwork, int stage)
+                                              int nwork, int stage, int slot)
 {
     const int w = blockIdx.x;
     if (w >= nwork) return;
     int4 wk = work[w];
     if (wk.x < 0) return;
     wk.x &= DEP_BIT - 1;
-    tile_body<T, VEC, FILT, TX, TY>(insts, wk, stage, nullptr);
+    tile_body<T, VEC, FILT, TX, TY>(insts, wk, stage, slot, nullptr);
 }
 
 // One stage in one launch.  The first ncar workgroups each fill 256 / GL
@@ -898,16 +986,22 @@ __global__ __launch_bounds__(256) void k_tile(const DevInst *__restrict__ insts,
 // such an id (the host orders the work so), so they are dispatched no later
 // than any tile that waits for them and they wait for nothing themselves;
 // each wait is bounded by spin_limit polls all the same, and a wait that runs
-// out raises the error flag sync[4] instead of hanging.
+// out raises the error flag sync[4] instead of hanging.  The probe pass, if
+// any, runs in the workgroups after the tiles (tend and up).
 template <typename T, int VEC, bool FILT, int TX, int TY, int GL>
 __global__ __launch_bounds__(256) void k_stage(const DevInst *__restrict__ insts, const int4 *__restrict__ work1,
                                                int nwork1, const int4 *__restrict__ work2, int nwork2, int ncar,
-                                               int tile0, int stage, int *sync, int spin_limit,
-                                               const int2 *__restrict__ aux, const int2 *__restrict__ patch)
+                                               int tile0, int tend, int stage, int slot, int *sync, int spin_limit,
+                                               const int2 *__restrict__ aux, const int2 *__restrict__ patch,
+                                               ProbePass pp)
 {
     const int tid = threadIdx.x;
     const int w = (int)blockIdx.x;
-    if (w < ncar) ghost_item<T, GL, true>(insts, work2, nwork2, w * (256 / GL) + tid / GL, tid % GL, stage);
+    if (w >= tend) {
+        probe_item<T>(insts, pp, (w - tend) * 16 + tid / 16, tid % 16);
+        return;
+    }
+    if (w < ncar) ghost_item<T, GL, true>(insts, work2, nwork2, w * (256 / GL) + tid / GL, tid % GL, stage, slot);
     const int k = w - tile0;
     if (k < 0 || k >= nwork1) return;
     int4 wk = work1[k];
@@ -916,65 +1010,9 @@ __global__ __launch_bounds__(256) void k_stage(const DevInst *__restrict__ insts
         wk.x &= DEP_BIT - 1;
         const int2 rg = aux[k];
         const GhostDep dep{&sync[4], spin_limit, patch, rg.x, rg.y};
-        tile_body<T, VEC, FILT, TX, TY>(insts, wk, stage, &dep);
+        tile_body<T, VEC, FILT, TX, TY>(insts, wk, stage, slot, &dep);
     } else {
-        tile_body<T, VEC, FILT, TX, TY>(insts, wk, stage, nullptr);
-    }
-}
-
-// ---------------------------------------------------------------------------
-// end of step: counters, probes, DFT
-
-template <typename T>
-__global__ __launch_bounds__(256) void k_step_end(const DevInst *__restrict__ insts)
-{
-    const DevInst &I = insts[blockIdx.x];
-    if (!*I.active) return;
-    const long long step = *I.step;                 // index of the step just completed
-    const T *P = (const T *)I.f[0][0];
-    const T *U = (const T *)I.f[0][1];
-    const T *V = (const T *)I.f[0][2];
-    const long pitch = I.pitch;
-    const bool in_dft = I.dft_count > 0 && step >= I.dft_start && step < I.dft_start + I.dft_count;
-    double cs = 0, sn = 0;
-    if (in_dft) {
-        const double t = (double)(step + 1) * I.dt;
-        cs = cos(I.dft_omega * t);
-        sn = sin(I.dft_omega * t);
-    }
-    for (int k = threadIdx.x; k < I.np; k += blockDim.x) {
-        const int i0 = I.pij[2 * k], j0 = I.pij[2 * k + 1];
-        const double *w = I.pw + 16 * (size_t)k;
-        double ap = 0, au = 0, av = 0;
-        for (int b = 0; b < 4; ++b)
-            for (int a = 0; a < 4; ++a) {
-                const long off = (long)I.org + (long)(j0 + b) * pitch + (i0 + a);
-                const double ww = w[b * 4 + a];
-                ap += ww * (double)P[off];
-                au += ww * (double)U[off];
-                av += ww * (double)V[off];
-            }
-        if (I.trace_cap > 0) {
-            double *tr = I.trace + ((size_t)(step % I.trace_cap) * I.np + k) * 3;
-            tr[0] = ap;
-            tr[1] = au;
-            tr[2] = av;
-        }
-        if (in_dft) {                               // sum p exp(-i omega t)
-            I.dft[2 * k] += ap * cs;
-            I.dft[2 * k + 1] -= ap * sn;
-        }
-    }
-    if (I.has_src && threadIdx.x < 4) {           // stage amplitudes of the next step, FP64
-        const double t = ((double)(step + 1) + I.c_stage[threadIdx.x]) * I.dt;
-        I.amp[threadIdx.x] = I.src_a * sin(I.src_om * t);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        *I.step = step + 1;
-        const long long b = *I.budget - 1;
-        *I.budget = b;
-        *I.active = b > 0 ? 1 : 0;
+        tile_body<T, VEC, FILT, TX, TY>(insts, wk, stage, slot, nullptr);
     }
 }
 
@@ -1033,41 +1071,41 @@ __global__ void k_sample(const DevInst *__restrict__ insts, const int *__restric
 // launch wrappers
 
 template <typename T, int VEC, bool FILT, int WPB>
-static hipError_t launch_sweep_t(const DevInst *insts, const int4 *work, int nwork, int stage, int blocks,
+static hipError_t launch_sweep_t(const DevInst *insts, const int4 *work, int nwork, int stage, int slot, int blocks,
                                  hipStream_t s)
 {
     const int nb = blocks > 0 ? blocks : (nwork + WPB - 1) / WPB;
-    hipLaunchKernelGGL((k_sweep<T, VEC, FILT, WPB>), dim3(nb), dim3(64 * WPB), 0, s, insts, work, nwork, stage);
+    hipLaunchKernelGGL((k_sweep<T, VEC, FILT, WPB>), dim3(nb), dim3(64 * WPB), 0, s, insts, work, nwork, stage, slot);
     return hipGetLastError();
 }
 
 template <typename T, int VEC, bool FILT>
-static hipError_t launch_sweep_w(const DevInst *insts, const int4 *work, int nwork, int stage, int waves,
+static hipError_t launch_sweep_w(const DevInst *insts, const int4 *work, int nwork, int stage, int slot, int waves,
                                  int blocks, hipStream_t s)
 {
-    if (waves == 4) return launch_sweep_t<T, VEC, FILT, 4>(insts, work, nwork, stage, blocks, s);
-    if (waves == 2) return launch_sweep_t<T, VEC, FILT, 2>(insts, work, nwork, stage, blocks, s);
-    return launch_sweep_t<T, VEC, FILT, 1>(insts, work, nwork, stage, blocks, s);
+    if (waves == 4) return launch_sweep_t<T, VEC, FILT, 4>(insts, work, nwork, stage, slot, blocks, s);
+    if (waves == 2) return launch_sweep_t<T, VEC, FILT, 2>(insts, work, nwork, stage, slot, blocks, s);
+    return launch_sweep_t<T, VEC, FILT, 1>(insts, work, nwork, stage, slot, blocks, s);
 }
 
 hipError_t launch_sweep(int prec, int vec, bool filt, int waves, const DevInst *insts, const int4 *work,
-                        int nwork, int stage, int blocks, hipStream_t s)
+                        int nwork, int stage, int slot, int blocks, hipStream_t s)
 {
     if (nwork <= 0) return hipSuccess;
     if (prec == LEE_F32) {
-        if (vec == 4) return filt ? launch_sweep_w<float, 4, true>(insts, work, nwork, stage, waves, blocks, s)
-                                  : launch_sweep_w<float, 4, false>(insts, work, nwork, stage, waves, blocks, s);
-        return filt ? launch_sweep_w<float, 2, true>(insts, work, nwork, stage, waves, blocks, s)
-                    : launch_sweep_w<float, 2, false>(insts, work, nwork, stage, waves, blocks, s);
+        if (vec == 4) return filt ? launch_sweep_w<float, 4, true>(insts, work, nwork, stage, slot, waves, blocks, s)
+                                  : launch_sweep_w<float, 4, false>(insts, work, nwork, stage, slot, waves, blocks, s);
+        return filt ? launch_sweep_w<float, 2, true>(insts, work, nwork, stage, slot, waves, blocks, s)
+                    : launch_sweep_w<float, 2, false>(insts, work, nwork, stage, slot, waves, blocks, s);
     }
-    return filt ? launch_sweep_w<double, 2, true>(insts, work, nwork, stage, waves, blocks, s)
-                : launch_sweep_w<double, 2, false>(insts, work, nwork, stage, waves, blocks, s);
+    return filt ? launch_sweep_w<double, 2, true>(insts, work, nwork, stage, slot, waves, blocks, s)
+                : launch_sweep_w<double, 2, false>(insts, work, nwork, stage, slot, waves, blocks, s);
 }
 
 
 constexpr int GHOST_LANES = 16;                  // lanes per ghost
 
-// Fused launch arguments (the ghost part and the tile offset).
+// Fused launch arguments (the ghost part, the tile offset, the probe pass).
 struct FuseArgs {
     const int4 *work2;
     int nwork2;
@@ -1076,20 +1114,25 @@ struct FuseArgs {
     const int2 *aux;
     const int2 *patch;
     int tile0;
+    ProbePass pp;
 };
 
 template <typename T, int VEC, bool FILT, int TX, int TY>
-static hipError_t launch_tile_t(const DevInst *insts, const int4 *work, int nwork, int stage, const FuseArgs *fa,
-                                hipStream_t s)
+static hipError_t launch_tile_t(const DevInst *insts, const int4 *work, int nwork, int stage, int slot,
+                                const FuseArgs *fa, hipStream_t s)
 {
     if (!fa) {
-        hipLaunchKernelGGL((k_tile<T, VEC, FILT, TX, TY>), dim3(nwork), dim3(256), 0, s, insts, work, nwork, stage);
+        hipLaunchKernelGGL((k_tile<T, VEC, FILT, TX, TY>), dim3(nwork), dim3(256), 0, s, insts, work, nwork, stage,
+                           slot);
     } else {
-        // the first ncar workgroups carry 256 / GHOST_LANES ghosts each
+        // the first ncar workgroups carry 256 / GHOST_LANES ghosts each; the
+        // probe pass takes 16 probes per workgroup after the tiles
         const int ncar = (fa->nwork2 * GHOST_LANES + 255) / 256;
-        hipLaunchKernelGGL((k_stage<T, VEC, FILT, TX, TY, GHOST_LANES>), dim3(std::max(ncar, fa->tile0 + nwork)),
-                           dim3(256), 0, s, insts, work, nwork, fa->work2, fa->nwork2, ncar, fa->tile0, stage,
-                           fa->sync, fa->spin_limit, fa->aux, fa->patch);
+        const int tend = std::max(ncar, fa->tile0 + nwork);
+        const int nbp = (fa->pp.np + 15) / 16;
+        hipLaunchKernelGGL((k_stage<T, VEC, FILT, TX, TY, GHOST_LANES>), dim3(tend + nbp), dim3(256), 0, s, insts,
+                           work, nwork, fa->work2, fa->nwork2, ncar, fa->tile0, tend, stage, slot, fa->sync,
+                           fa->spin_limit, fa->aux, fa->patch, fa->pp);
     }
     return hipGetLastError();
 }
@@ -1097,22 +1140,25 @@ static hipError_t launch_tile_t(const DevInst *insts, const int4 *work, int nwor
 // supported tile shapes (columns x rows)
 template <typename T, int VEC, bool FILT>
 static hipError_t launch_tile_v(int tx, int ty, const DevInst *insts, const int4 *work, int nwork, int stage,
-                                const FuseArgs *fa, hipStream_t s)
+                                int slot, const FuseArgs *fa, hipStream_t s)
 {
     constexpr bool F4 = sizeof(T) == 4;
     if (tx == 128) {
-        if (ty == 4) return launch_tile_t<T, VEC, FILT, 128, 4>(insts, work, nwork, stage, fa, s);
-        if (ty == 8) return launch_tile_t<T, VEC, FILT, 128, 8>(insts, work, nwork, stage, fa, s);
-        if (ty == 16) return launch_tile_t<T, VEC, FILT, 128, 16>(insts, work, nwork, stage, fa, s);
-        if (F4 && ty == 32) return launch_tile_t<T, VEC, FILT, 128, (F4 ? 32 : 16)>(insts, work, nwork, stage, fa, s);
+        if (ty == 4) return launch_tile_t<T, VEC, FILT, 128, 4>(insts, work, nwork, stage, slot, fa, s);
+        if (ty == 8) return launch_tile_t<T, VEC, FILT, 128, 8>(insts, work, nwork, stage, slot, fa, s);
+        if (ty == 16) return launch_tile_t<T, VEC, FILT, 128, 16>(insts, work, nwork, stage, slot, fa, s);
+        if (F4 && ty == 32)
+            return launch_tile_t<T, VEC, FILT, 128, (F4 ? 32 : 16)>(insts, work, nwork, stage, slot, fa, s);
     } else if (tx == 256) {
-        if (ty == 4) return launch_tile_t<T, VEC, FILT, 256, 4>(insts, work, nwork, stage, fa, s);
-        if (F4 && ty == 8) return launch_tile_t<T, VEC, FILT, 256, (F4 ? 8 : 4)>(insts, work, nwork, stage, fa, s);
-        if (F4 && ty == 16) return launch_tile_t<T, VEC, FILT, 256, (F4 ? 16 : 4)>(insts, work, nwork, stage, fa, s);
+        if (ty == 4) return launch_tile_t<T, VEC, FILT, 256, 4>(insts, work, nwork, stage, slot, fa, s);
+        if (F4 && ty == 8)
+            return launch_tile_t<T, VEC, FILT, 256, (F4 ? 8 : 4)>(insts, work, nwork, stage, slot, fa, s);
+        if (F4 && ty == 16)
+            return launch_tile_t<T, VEC, FILT, 256, (F4 ? 16 : 4)>(insts, work, nwork, stage, slot, fa, s);
     } else if (tx == 64) {
-        if (ty == 8) return launch_tile_t<T, VEC, FILT, 64, 8>(insts, work, nwork, stage, fa, s);
-        if (ty == 16) return launch_tile_t<T, VEC, FILT, 64, 16>(insts, work, nwork, stage, fa, s);
-        if (ty == 32) return launch_tile_t<T, VEC, FILT, 64, 32>(insts, work, nwork, stage, fa, s);
+        if (ty == 8) return launch_tile_t<T, VEC, FILT, 64, 8>(insts, work, nwork, stage, slot, fa, s);
+        if (ty == 16) return launch_tile_t<T, VEC, FILT, 64, 16>(insts, work, nwork, stage, slot, fa, s);
+        if (ty == 32) return launch_tile_t<T, VEC, FILT, 64, 32>(insts, work, nwork, stage, slot, fa, s);
     }
     return hipErrorInvalidValue;
 }
@@ -1128,48 +1174,64 @@ bool tile_shape_supported(int prec, int tx, int ty)
 
 
 hipError_t launch_tile(int prec, bool filt, int tx, int ty, const DevInst *insts, const int4 *work, int nwork,
-                       int stage, int blocks, hipStream_t s)
+                       int stage, int slot, int blocks, hipStream_t s)
 {
     (void)blocks;                                // one workgroup per tile
     if (nwork <= 0) return hipSuccess;
     if (prec == LEE_F32)
-        return filt ? launch_tile_v<float, 4, true>(tx, ty, insts, work, nwork, stage, nullptr, s)
-                    : launch_tile_v<float, 4, false>(tx, ty, insts, work, nwork, stage, nullptr, s);
-    return filt ? launch_tile_v<double, 2, true>(tx, ty, insts, work, nwork, stage, nullptr, s)
-                : launch_tile_v<double, 2, false>(tx, ty, insts, work, nwork, stage, nullptr, s);
+        return filt ? launch_tile_v<float, 4, true>(tx, ty, insts, work, nwork, stage, slot, nullptr, s)
+                    : launch_tile_v<float, 4, false>(tx, ty, insts, work, nwork, stage, slot, nullptr, s);
+    return filt ? launch_tile_v<double, 2, true>(tx, ty, insts, work, nwork, stage, slot, nullptr, s)
+                : launch_tile_v<double, 2, false>(tx, ty, insts, work, nwork, stage, slot, nullptr, s);
 }
 
 hipError_t launch_stage(int prec, bool filt, int tx, int ty, const DevInst *insts, const int4 *work1, int nwork1,
                         const int2 *aux, const int2 *patch, int tile0, const int4 *work2, int nwork2, int stage,
-                        int *sync, int spin_limit, hipStream_t s)
+                        int slot, int *sync, int spin_limit, ProbePass pp, hipStream_t s)
 {
-    if (nwork2 <= 0) return launch_tile(prec, filt, tx, ty, insts, work1, nwork1, stage, 0, s);
-    const FuseArgs fa{work2, nwork2, sync, spin_limit, aux, patch, tile0};
+    if (nwork2 <= 0) {                           // no ghosts: the plain sweep, then the probes
+        hipError_t e = launch_tile(prec, filt, tx, ty, insts, work1, nwork1, stage, slot, 0, s);
+        if (e == hipSuccess && pp.np > 0) e = launch_probe(prec, insts, pp, s);
+        return e;
+    }
+    const FuseArgs fa{work2, nwork2, sync, spin_limit, aux, patch, tile0, pp};
     if (prec == LEE_F32)
-        return filt ? launch_tile_v<float, 4, true>(tx, ty, insts, work1, nwork1, stage, &fa, s)
-                    : launch_tile_v<float, 4, false>(tx, ty, insts, work1, nwork1, stage, &fa, s);
-    return filt ? launch_tile_v<double, 2, true>(tx, ty, insts, work1, nwork1, stage, &fa, s)
-                : launch_tile_v<double, 2, false>(tx, ty, insts, work1, nwork1, stage, &fa, s);
+        return filt ? launch_tile_v<float, 4, true>(tx, ty, insts, work1, nwork1, stage, slot, &fa, s)
+                    : launch_tile_v<float, 4, false>(tx, ty, insts, work1, nwork1, stage, slot, &fa, s);
+    return filt ? launch_tile_v<double, 2, true>(tx, ty, insts, work1, nwork1, stage, slot, &fa, s)
+                : launch_tile_v<double, 2, false>(tx, ty, insts, work1, nwork1, stage, slot, &fa, s);
 }
 
-hipError_t launch_ghost(int prec, const DevInst *insts, const int4 *work, int nwork, int stage, hipStream_t s)
+hipError_t launch_ghost(int prec, const DevInst *insts, const int4 *work, int nwork, int stage, int slot,
+                        ProbePass pp, hipStream_t s)
 {
-    if (nwork <= 0) return hipSuccess;
     constexpr int GL = GHOST_LANES;
-    const int nb = (nwork * GL + 255) / 256;
+    const int nb = (std::max(nwork, 0) * GL + 255) / 256 + (pp.np + 15) / 16;
+    if (nb == 0) return hipSuccess;
     if (prec == LEE_F32)
-        hipLaunchKernelGGL((k_ghost<float, GL>), dim3(nb), dim3(256), 0, s, insts, work, nwork, stage);
+        hipLaunchKernelGGL((k_ghost<float, GL>), dim3(nb), dim3(256), 0, s, insts, work, std::max(nwork, 0), stage,
+                           slot, pp);
     else
-        hipLaunchKernelGGL((k_ghost<double, GL>), dim3(nb), dim3(256), 0, s, insts, work, nwork, stage);
+        hipLaunchKernelGGL((k_ghost<double, GL>), dim3(nb), dim3(256), 0, s, insts, work, std::max(nwork, 0),
+                           stage, slot, pp);
     return hipGetLastError();
 }
 
-hipError_t launch_step_end(int prec, const DevInst *insts, int ninst, hipStream_t s)
+hipError_t launch_probe(int prec, const DevInst *insts, ProbePass pp, hipStream_t s)
 {
+    if (pp.np <= 0) return hipSuccess;
+    const int nb = (pp.np + 15) / 16;
     if (prec == LEE_F32)
-        hipLaunchKernelGGL((k_step_end<float>), dim3(ninst), dim3(256), 0, s, insts);
+        hipLaunchKernelGGL((k_probe<float>), dim3(nb), dim3(256), 0, s, insts, pp);
     else
-        hipLaunchKernelGGL((k_step_end<double>), dim3(ninst), dim3(256), 0, s, insts);
+        hipLaunchKernelGGL((k_probe<double>), dim3(nb), dim3(256), 0, s, insts, pp);
+    return hipGetLastError();
+}
+
+hipError_t launch_advance(const DevInst *insts, int ninst, int n, hipStream_t s)
+{
+    if (ninst <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_advance, dim3((ninst + 255) / 256), dim3(256), 0, s, insts, ninst, n);
     return hipGetLastError();
 }
 
