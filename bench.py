@@ -238,8 +238,9 @@ def run(args):
             "graph_steps": ch32["graph_steps"],
             "tuning_from": "table" if ch32.get("cached") else "trials",
             "tuned_step_us": {"f32": ch32["step_us"], "f64": ch64["step_us"]},
-            "launch": "hipGraphs of captured steps; a step is 4 x (ghost fill + ADE, stage sweep; one launch "
-                      "when fused) + step end; configuration from the autotuner",
+            "launch": "hipGraphs of captured runs of steps; a step is 4 x (ghost fill + ADE, stage sweep; one "
+                      "launch when fused), probes riding in the next step's second stage, and a run ends with a "
+                      "probe launch and a step-counter launch; configuration from the autotuner",
         },
         "fp64_value": r64["value"],
         "fp64_ms_per_step": 1000.0 * r64["wall"] / r64["steps"],
