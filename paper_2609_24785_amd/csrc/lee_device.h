@@ -79,14 +79,16 @@ hipError_t launch_tile(int prec, bool filt, int tx, int ty, const DevInst *insts
 // tile's copy, ghost index * 3 + field).  sync[4] is the error flag raised by
 // a wait that runs out of polls (zero before first use).  The probe pass
 // runs in extra workgroups after the tiles.
-hipError_t launch_stage(int prec, bool filt, int tx, int ty, const DevInst *insts, const int4 *work1, int nwork1,
-                        const int2 *aux, const int2 *patch, int tile0, const int4 *work2, int nwork2, int stage,
-                        int slot, int *sync, int spin_limit, ProbePass pp, hipStream_t s);
+// ninst: entries of the instance table (1 lets the ghost fill read its
+// record with scalar loads).
+hipError_t launch_stage(int prec, bool filt, int tx, int ty, const DevInst *insts, int ninst, const int4 *work1,
+                        int nwork1, const int2 *aux, const int2 *patch, int tile0, const int4 *work2, int nwork2,
+                        int stage, int slot, int *sync, int spin_limit, ProbePass pp, hipStream_t s);
 constexpr int TILE_DEP_BIT = 1 << 30;
 constexpr int SYNC_INTS = 8;
 constexpr int SPIN_LIMIT = 1 << 20;             // polls before a ghost wait gives up (about a second)
 // The ghost fill of a stage, with the probe pass in extra workgroups.
-hipError_t launch_ghost(int prec, const DevInst *insts, const int4 *work, int nwork, int stage, int slot,
+hipError_t launch_ghost(int prec, const DevInst *insts, int ninst, const int4 *work, int nwork, int stage, int slot,
                         ProbePass pp, hipStream_t s);
 hipError_t launch_probe(int prec, const DevInst *insts, ProbePass pp, hipStream_t s);
 // After a run of n steps: *step += n for every member, held at *stop.

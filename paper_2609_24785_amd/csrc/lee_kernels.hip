@@ -127,13 +127,16 @@ __device__ __forceinline__ void xg_put(GLOBAL unsigned long long *w, T v, unsign
 
 // One ghost per GL-lane group (gid); sub is the lane within the group.  With
 // PUB (fused launches) the ghost values also go to the exchange words I.xg.
-template <typename T, int GL, bool PUB = false>
+// With ONE the launch has a single instance: its record is read with scalar
+// loads at once, instead of after the work item names it, which takes one
+// dependent round trip off the ghost fill.
+template <typename T, int GL, bool PUB = false, bool ONE = false>
 __device__ __forceinline__ void ghost_item(const DevInst *__restrict__ insts, const int4 *__restrict__ work,
                                            int nwork, int gid, int sub, int stage, int slot)
 {
     if (gid >= nwork) return;                       // whole GL-lane groups leave together
     const int4 wk = work[gid];                      // instance, ghost, cloud entries [z, w)
-    const DevInst &I = insts[wk.x];
+    const DevInst &I = insts[ONE ? 0 : wk.x];
     const int g = wk.y;
     const int ib = in_buf(stage), ob = out_buf(stage);
     GLOBAL T *P = gp<T>(I.f[ib][0]);
@@ -276,7 +279,7 @@ __device__ __forceinline__ void probe_item(const DevInst *__restrict__ insts, co
 
 // Ghost fill of a stage (16 ghosts per workgroup), then the probe pass in
 // the workgroups after them.
-template <typename T, int GL>
+template <typename T, int GL, bool ONE>
 __global__ __launch_bounds__(256) void k_ghost(const DevInst *__restrict__ insts,
                                                const int4 *__restrict__ work, int nwork, int stage, int slot,
                                                ProbePass pp)
@@ -284,8 +287,8 @@ __global__ __launch_bounds__(256) void k_ghost(const DevInst *__restrict__ insts
     const int nbg = (nwork * GL + 255) / 256;
     const int b = (int)blockIdx.x;
     if (b < nbg)
-        ghost_item<T, GL>(insts, work, nwork, (int)((b * blockDim.x + threadIdx.x) / GL), (int)(threadIdx.x % GL),
-                          stage, slot);
+        ghost_item<T, GL, false, ONE>(insts, work, nwork, (int)((b * blockDim.x + threadIdx.x) / GL),
+                                      (int)(threadIdx.x % GL), stage, slot);
     else
         probe_item<T>(insts, pp, (b - nbg) * 16 + (int)threadIdx.x / 16, (int)threadIdx.x % 16);
 }
@@ -988,7 +991,7 @@ __global__ __launch_bounds__(256) void k_tile(const DevInst *__restrict__ insts,
 // each wait is bounded by spin_limit polls all the same, and a wait that runs
 // out raises the error flag sync[4] instead of hanging.  The probe pass, if
 // any, runs in the workgroups after the tiles (tend and up).
-template <typename T, int VEC, bool FILT, int TX, int TY, int GL>
+template <typename T, int VEC, bool FILT, int TX, int TY, int GL, bool ONE>
 __global__ __launch_bounds__(256) void k_stage(const DevInst *__restrict__ insts, const int4 *__restrict__ work1,
                                                int nwork1, const int4 *__restrict__ work2, int nwork2, int ncar,
                                                int tile0, int tend, int stage, int slot, int *sync, int spin_limit,
@@ -1001,7 +1004,8 @@ __global__ __launch_bounds__(256) void k_stage(const DevInst *__restrict__ insts
         probe_item<T>(insts, pp, (w - tend) * 16 + tid / 16, tid % 16);
         return;
     }
-    if (w < ncar) ghost_item<T, GL, true>(insts, work2, nwork2, w * (256 / GL) + tid / GL, tid % GL, stage, slot);
+    if (w < ncar)
+        ghost_item<T, GL, true, ONE>(insts, work2, nwork2, w * (256 / GL) + tid / GL, tid % GL, stage, slot);
     const int k = w - tile0;
     if (k < 0 || k >= nwork1) return;
     int4 wk = work1[k];
@@ -1115,6 +1119,7 @@ struct FuseArgs {
     const int2 *patch;
     int tile0;
     ProbePass pp;
+    bool one;                                    // a single instance
 };
 
 template <typename T, int VEC, bool FILT, int TX, int TY>
@@ -1130,9 +1135,14 @@ static hipError_t launch_tile_t(const DevInst *insts, const int4 *work, int nwor
         const int ncar = (fa->nwork2 * GHOST_LANES + 255) / 256;
         const int tend = std::max(ncar, fa->tile0 + nwork);
         const int nbp = (fa->pp.np + 15) / 16;
-        hipLaunchKernelGGL((k_stage<T, VEC, FILT, TX, TY, GHOST_LANES>), dim3(tend + nbp), dim3(256), 0, s, insts,
-                           work, nwork, fa->work2, fa->nwork2, ncar, fa->tile0, tend, stage, slot, fa->sync,
-                           fa->spin_limit, fa->aux, fa->patch, fa->pp);
+        if (fa->one)
+            hipLaunchKernelGGL((k_stage<T, VEC, FILT, TX, TY, GHOST_LANES, true>), dim3(tend + nbp), dim3(256), 0, s,
+                               insts, work, nwork, fa->work2, fa->nwork2, ncar, fa->tile0, tend, stage, slot,
+                               fa->sync, fa->spin_limit, fa->aux, fa->patch, fa->pp);
+        else
+            hipLaunchKernelGGL((k_stage<T, VEC, FILT, TX, TY, GHOST_LANES, false>), dim3(tend + nbp), dim3(256), 0,
+                               s, insts, work, nwork, fa->work2, fa->nwork2, ncar, fa->tile0, tend, stage, slot,
+                               fa->sync, fa->spin_limit, fa->aux, fa->patch, fa->pp);
     }
     return hipGetLastError();
 }
@@ -1185,16 +1195,16 @@ hipError_t launch_tile(int prec, bool filt, int tx, int ty, const DevInst *insts
                 : launch_tile_v<double, 2, false>(tx, ty, insts, work, nwork, stage, slot, nullptr, s);
 }
 
-hipError_t launch_stage(int prec, bool filt, int tx, int ty, const DevInst *insts, const int4 *work1, int nwork1,
-                        const int2 *aux, const int2 *patch, int tile0, const int4 *work2, int nwork2, int stage,
-                        int slot, int *sync, int spin_limit, ProbePass pp, hipStream_t s)
+hipError_t launch_stage(int prec, bool filt, int tx, int ty, const DevInst *insts, int ninst, const int4 *work1,
+                        int nwork1, const int2 *aux, const int2 *patch, int tile0, const int4 *work2, int nwork2,
+                        int stage, int slot, int *sync, int spin_limit, ProbePass pp, hipStream_t s)
 {
     if (nwork2 <= 0) {                           // no ghosts: the plain sweep, then the probes
         hipError_t e = launch_tile(prec, filt, tx, ty, insts, work1, nwork1, stage, slot, 0, s);
         if (e == hipSuccess && pp.np > 0) e = launch_probe(prec, insts, pp, s);
         return e;
     }
-    const FuseArgs fa{work2, nwork2, sync, spin_limit, aux, patch, tile0, pp};
+    const FuseArgs fa{work2, nwork2, sync, spin_limit, aux, patch, tile0, pp, ninst == 1};
     if (prec == LEE_F32)
         return filt ? launch_tile_v<float, 4, true>(tx, ty, insts, work1, nwork1, stage, slot, &fa, s)
                     : launch_tile_v<float, 4, false>(tx, ty, insts, work1, nwork1, stage, slot, &fa, s);
@@ -1202,18 +1212,26 @@ hipError_t launch_stage(int prec, bool filt, int tx, int ty, const DevInst *inst
                 : launch_tile_v<double, 2, false>(tx, ty, insts, work1, nwork1, stage, slot, &fa, s);
 }
 
-hipError_t launch_ghost(int prec, const DevInst *insts, const int4 *work, int nwork, int stage, int slot,
-                        ProbePass pp, hipStream_t s)
+template <typename T>
+static void launch_ghost_t(bool one, const DevInst *insts, const int4 *work, int nwork, int stage, int slot,
+                           ProbePass pp, int nb, hipStream_t s)
 {
     constexpr int GL = GHOST_LANES;
-    const int nb = (std::max(nwork, 0) * GL + 255) / 256 + (pp.np + 15) / 16;
+    if (one)
+        hipLaunchKernelGGL((k_ghost<T, GL, true>), dim3(nb), dim3(256), 0, s, insts, work, nwork, stage, slot, pp);
+    else
+        hipLaunchKernelGGL((k_ghost<T, GL, false>), dim3(nb), dim3(256), 0, s, insts, work, nwork, stage, slot, pp);
+}
+
+hipError_t launch_ghost(int prec, const DevInst *insts, int ninst, const int4 *work, int nwork, int stage, int slot,
+                        ProbePass pp, hipStream_t s)
+{
+    const int nb = (std::max(nwork, 0) * GHOST_LANES + 255) / 256 + (pp.np + 15) / 16;
     if (nb == 0) return hipSuccess;
     if (prec == LEE_F32)
-        hipLaunchKernelGGL((k_ghost<float, GL>), dim3(nb), dim3(256), 0, s, insts, work, std::max(nwork, 0), stage,
-                           slot, pp);
+        launch_ghost_t<float>(ninst == 1, insts, work, std::max(nwork, 0), stage, slot, pp, nb, s);
     else
-        hipLaunchKernelGGL((k_ghost<double, GL>), dim3(nb), dim3(256), 0, s, insts, work, std::max(nwork, 0),
-                           stage, slot, pp);
+        launch_ghost_t<double>(ninst == 1, insts, work, std::max(nwork, 0), stage, slot, pp, nb, s);
     return hipGetLastError();
 }
 
