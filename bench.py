@@ -83,7 +83,7 @@ def _kernel_name(tiling: dict, prec: str) -> str:
     t = "float, 4" if prec == "f32" else "double, 2"
     if tiling["kind"] == "tile":
         k = "k_stage" if tiling.get("fused") else "k_tile"
-        extra = ", 16" if tiling.get("fused") else ""
+        extra = ", 16, true" if tiling.get("fused") else ""     # one instance per launch
         return f"lee::{k}<{t}, true, {tiling['cols']}, {tiling['rows']}{extra}>"
     return f"lee::k_sweep<{t.split(',')[0]}, {tiling['vec']}, true, {tiling['waves']}>"
 
