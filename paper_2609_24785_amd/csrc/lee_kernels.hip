@@ -597,6 +597,8 @@ __device__ __forceinline__ void row_field(const T (*lds)[LW], int y, int lc, con
     constexpr int KM = (5 + VEC - 1) / VEC;
     constexpr int KP = (VEC + 4) / VEC;
     constexpr int XW = (KM + 1 + KP) * VEC;
+    static_assert(KM * VEC - 5 == VEC - 1 && KM * VEC + VEC + 4 == (KM + KP) * VEC,
+                  "x +- 5 reaches one element of each outermost chunk");
     T yw[11][VEC];
 #pragma unroll
     for (int k = 0; k < 11; ++k) {
@@ -611,6 +613,16 @@ __device__ __forceinline__ void row_field(const T (*lds)[LW], int y, int lc, con
             if (k == 0) {                        // the centre chunk is the y window's
 #pragma unroll
                 for (int e = 0; e < VEC; ++e) xw[KM * VEC + e] = yw[5][e];
+                continue;
+            }
+            // of the outermost chunks only the element next to the inner
+            // ones is in reach (x +- 5): one LDS element instead of a chunk
+            if (k == -KM) {
+                xw[VEC - 1] = lds[y][lc - KM * VEC + VEC - 1];
+                continue;
+            }
+            if (k == KP) {
+                xw[(KM + KP) * VEC] = lds[y][lc + KP * VEC];
                 continue;
             }
             const VecT<T, VEC> a = lds16<T, VEC>(&lds[y][lc + k * VEC]);
