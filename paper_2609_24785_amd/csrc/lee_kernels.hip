@@ -680,7 +680,7 @@ struct GhostDep {
 // Shape of a cols x rows tile (TX x TY): NCX column groups of VEC nodes, RG
 // rows in flight per pass of 256 lanes, an LDS read region of R rows x LW
 // columns (CW 16-byte chunks per row, HC halo chunks per side; NCH chunks per
-// field) and a q^n block of NQ chunks per field.
+// field).
 template <typename T, int VEC, int TX, int TY>
 struct TileGeo {
     static constexpr int NT = 256;
@@ -691,8 +691,6 @@ struct TileGeo {
     static constexpr int CW = LW / VEC;
     static constexpr int HC = 8 / VEC;
     static constexpr int NCH = R * CW;
-    static constexpr int QCW = TX / VEC;
-    static constexpr int NQ = TY * QCW;
     static_assert(sizeof(T) * VEC == 16, "16-byte chunks");
 };
 
@@ -742,11 +740,12 @@ __device__ __forceinline__ TileCtx<T> tile_ctx(const DevInst &I, const int4 wk, 
 // Starts the LDS copy of a tile: the read region of the stage input (rows
 // r0 - 5 .. r0 + TY + 4, columns c0 - 8 .. c0 + TX + 7, the halo rows without
 // their corner chunks, no row past the allocated frame) into reg, 64 chunks
-// per wave instruction, and, when qn is given and the stage is not the first,
-// the q^n block into qn.
+// per wave instruction.  q^n is not staged in LDS: each lane reads its own
+// q^n chunks into registers while its row's arithmetic runs, which keeps the
+// workgroup's LDS at the read region alone (one more resident workgroup per
+// CU for FP32 64x16 and 128x8 and FP64 64x8).
 template <typename T, int VEC, int TX, int TY>
-__device__ __forceinline__ void tile_copy(const DevInst &I, const TileCtx<T> &c, int stage,
-                                          T (*reg)[TY + 10][TX + 16], T (*qn)[TY][TX])
+__device__ __forceinline__ void tile_copy(const DevInst &I, const TileCtx<T> &c, T (*reg)[TY + 10][TX + 16])
 {
     using G = TileGeo<T, VEC, TX, TY>;
     const int tid = threadIdx.x;
@@ -763,19 +762,6 @@ __device__ __forceinline__ void tile_copy(const DevInst &I, const TileCtx<T> &c,
             const bool halo_row = row < 5 || row >= TY + 5;
             const bool ok = q < G::NCH && !(halo_row && (cc < G::HC || cc >= G::CW - G::HC)) && gr <= rowmax;
             if (ok) dma16(src + (unsigned)(org + gr * pitch + (c.c0 - 8 + cc * VEC)), &reg[f][0][0] + base * VEC);
-        }
-    }
-    if (qn && stage != 0) {
-#pragma unroll
-        for (int f = 0; f < 3; ++f) {
-            const T *src = (const T *)I.f[0][f];
-            for (int base = wave * 64; base < G::NQ; base += G::NT) {
-                const int q = base + lane;
-                const int row = q / G::QCW, cc = q - (q / G::QCW) * G::QCW;
-                const int gr = c.r0 + row;
-                if (q < G::NQ && gr <= rowmax)
-                    dma16(src + (unsigned)(org + gr * pitch + c.c0 + cc * VEC), &qn[f][0][0] + base * VEC);
-            }
         }
     }
 }
@@ -933,13 +919,12 @@ __device__ __forceinline__ void tile_body(const DevInst *__restrict__ insts, con
 {
     using G = TileGeo<T, VEC, TX, TY>;
     __shared__ alignas(16) T lds[3][G::R][G::LW];
-    __shared__ alignas(16) T ldn[3][TY][TX];
     const DevInst &I = insts[wk.x];
     const long long step = sload<long long>(I.step) + slot;
     if (step >= sload<long long>(I.stop)) return;
     const int tid = threadIdx.x;
     const TileCtx<T> c = tile_ctx<T, TX>(I, wk, stage, step);
-    tile_copy<T, VEC, TX, TY>(I, c, stage, lds, ldn);
+    tile_copy<T, VEC, TX, TY>(I, c, lds);
     // while the copy flies: this lane's first row ranges and its first patch
     // entries
     const int i0 = tid / G::NCX;
@@ -961,10 +946,11 @@ __device__ __forceinline__ void tile_body(const DevInst *__restrict__ insts, con
         if (j >= c.r1) break;
         if (i != i0) iv = gp<int4>(I.iv)[j];
         VecT<T, VEC> pn{}, un{}, vn{};
-        if (stage != 0) {
-            pn = *(const VecT<T, VEC> *)&ldn[0][i][tc];
-            un = *(const VecT<T, VEC> *)&ldn[1][i][tc];
-            vn = *(const VecT<T, VEC> *)&ldn[2][i][tc];
+        if (stage != 0) {                        // in flight during the row's arithmetic
+            const unsigned qo = (unsigned)(I.org + j * I.pitch + c.c0 + tc);
+            pn = vld<T, VEC>(gp<T>(I.f[0][0]) + qo);
+            un = vld<T, VEC>(gp<T>(I.f[0][1]) + qo);
+            vn = vld<T, VEC>(gp<T>(I.f[0][2]) + qo);
         }
         VecT<T, VEC> po, uo, vo;
         bool ok[VEC];
