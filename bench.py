@@ -278,6 +278,7 @@ def run(args):
         cpu_rate = r32["fluid"] * 4.0 * args.cpu_steps / (t1 - t0)
         from paper_2609_24785_amd.lee import Instance
         g = Instance(case, "f32", trace_capacity=1)
+        _apply(g, ch32)                                 # the configuration timed above
         g.step_n(args.cpu_steps)
         g.synchronize()
         out["cpu_baseline"] = {
@@ -287,6 +288,7 @@ def run(args):
         }
         out["fp32_vs_oracle_rel_l2"] = _max_rel_l2(g.fields(), s.fields(), mask)
         out["fp32_vs_oracle_steps"] = args.cpu_steps
+        out["fp32_vs_oracle_tiling"] = g.get_tiling()
         g.close()
     print(json.dumps(out), flush=True)
     return 0

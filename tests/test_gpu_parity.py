@@ -30,12 +30,14 @@ def _say(*a):
     sys.stdout.flush()
 
 
-def _compare(case, steps, prec, tol, tiling=None):
+def _compare(case, steps, prec, tol, tiling=None, graph_steps=None):
     Instance, _ = _lee()
     _say(f"[parity] {case.name} {case.nx}x{case.ny} steps={steps} prec={prec} tiling={tiling}")
     inst = Instance(case, prec)
     if tiling:
         inst.set_tiling(**tiling)
+    if graph_steps:
+        inst.set_graph_steps(graph_steps)
     inst.step_n(steps)
     inst.synchronize()
     p, u, v = inst.fields()
@@ -106,18 +108,17 @@ def test_tilings_agree_fp64(tiling):
     _compare(case, 30, "f64", 1e-9, tiling=tiling)
 
 
-@pytest.mark.parametrize("prec", ["f32", "f64"])
-def test_fused_stage_equals_two_launches_bitwise(prec):
+@pytest.mark.parametrize("prec,cols,rows", [("f32", 64, 16), ("f32", 128, 8), ("f64", 64, 8), ("f64", 64, 16)])
+def test_fused_stage_equals_two_launches_bitwise(prec, cols, rows):
     """The fused launch (ghost workgroups first, dependent tiles waiting) gives
     the same bits as a ghost launch followed by a sweep launch."""
     Instance, _ = _lee()
-    rows = 16 if prec == "f32" else 8
     for case in (lc.small_cylinder(160, 20), lc.flat_wall_201(20), lc.cylinder_pulse_1024(20)):
-        _say(f"[fused] {case.name} {case.nx}x{case.ny} {prec}")
+        _say(f"[fused] {case.name} {case.nx}x{case.ny} {prec} {cols}x{rows}")
         a = Instance(case, prec)
         b = Instance(case, prec)
-        a.set_tiling("tile", cols=64, rows=rows, fused=1)
-        b.set_tiling("tile", cols=64, rows=rows, fused=0)
+        a.set_tiling("tile", cols=cols, rows=rows, fused=1)
+        b.set_tiling("tile", cols=cols, rows=rows, fused=0)
         a.step_n(20)
         b.step_n(20)
         a.synchronize()
@@ -197,3 +198,16 @@ def test_cylinder_1024_full_size_fp32():
     """The benchmark workload at full size (1024^2, default tiling) for 100 steps."""
     case = lc.cylinder_pulse_1024(100)
     _compare(case, 100, "f32", 1e-4)
+
+
+@pytest.mark.parametrize("prec,tol", [("f32", 1e-4), ("f64", 1e-9)])
+def test_cylinder_1024_full_size_benchmark_configuration(prec, tol):
+    """The benchmark workload at full size in the launch configuration the
+    benchmark times (the shipped tuning table's choice: tile shape, fused
+    form, steps per graph) for 100 steps, against the oracle."""
+    from paper_2609_24785_amd import tune
+    case = lc.cylinder_pulse_1024(100)
+    choice = tune.tune_case(case, prec, tune.TuneCache(None))
+    _say(f"[parity] benchmark configuration {prec}: {choice}")
+    inst, _ = _compare(case, 100, prec, tol, tiling=choice["tiling"], graph_steps=choice["graph_steps"])
+    inst.close()
