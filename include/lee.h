@@ -323,12 +323,22 @@ lee_status lee_batch_create(lee_instance *const *v, int32_t n, const lee_batch_o
 /* Membership: add a bound instance (same precision, filter setting and
  * device; its own stream is synchronised first) or remove one (the batch's
  * stream is synchronised first).  The device table and work lists are
- * rebuilt and the captured graphs dropped; the next lee_batch_step_n
- * captures again.  A batch may become empty (stepping it is then a no-op).
- * Budgets are per position: set them again after a membership change. */
+ * rebuilt in place: every list is padded with idle entries to a device
+ * capacity and the launches cover the capacities, so the captured graphs
+ * are kept.  Only a list that outgrows its capacity (capacities grow by
+ * at least a quarter) or shrinks below three quarters of it drops them
+ * (the capacities are then trimmed to the lists), and the next
+ * lee_batch_step_n captures again.  In the fused form the ghost-fill workgroups of a batch come before
+ * all tiles, sized by the ghost capacity.  A
+ * batch may become empty (stepping it is then a no-op).  Budgets are per
+ * position: set them again after a membership change. */
 lee_status lee_batch_add(lee_batch *b, lee_instance *inst);
 lee_status lee_batch_remove(lee_batch *b, lee_instance *inst);
 lee_status lee_batch_size(const lee_batch *b, int32_t *n);
+
+/* Number of step graphs the batch has captured so far (each run length
+ * captured counts once); it grows only when graphs had to be dropped. */
+lee_status lee_batch_graph_captures(const lee_batch *b, int64_t *n);
 
 /* Per-member step budget (n entries, synchronising): member k takes the next
  * steps[k] steps and then idles (its fields, ADE states and step counter stay

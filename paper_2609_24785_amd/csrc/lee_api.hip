@@ -23,6 +23,7 @@ constexpr int GRAPH_STEPS_MAX = 256;
 // for the remainder.  per == 0 launches every kernel eagerly.
 struct StepGraphs {
     int per = GRAPH_STEPS_DEFAULT;
+    int64_t captures = 0;           // graphs captured so far
     hipGraph_t gm = nullptr, g1 = nullptr;
     hipGraphExec_t em = nullptr, e1 = nullptr;
     void drop()
@@ -187,18 +188,20 @@ std::vector<int> xcd_slots(size_t n_items, int per_unit)
 // tiles wait for them, so no dependent tile may sit in a carrier slot: such
 // tiles are swapped with the first later plain tile (or idle slot) of the
 // same residue mod 8, which keeps them on their XCD.  If too few plain tiles
-// exist, the tiles start after ncar dedicated carrier workgroups instead.
+// exist, or when `dedicated` asks for it (batches: the first tile workgroup
+// then depends on the ghost capacity alone and stays put across membership
+// changes), the tiles start after ncar dedicated carrier workgroups instead.
 // Returns the id of the first tile workgroup (0 or ncar rounded up to 8).
 int order_work(const std::vector<int4> &items, const std::vector<std::vector<int2>> &patches, int per_unit,
-               int ncar, std::vector<int4> &out, std::vector<int2> &aux, std::vector<int2> &patch)
+               int ncar, bool dedicated, std::vector<int4> &out, std::vector<int2> &aux, std::vector<int2> &patch)
 {
     out.clear();
     aux.clear();
     patch.clear();
     std::vector<int> slots = xcd_slots(items.size(), per_unit);
     auto dep = [&](int k) { return k >= 0 && (items[k].x & TILE_DEP_BIT); };
-    int tile0 = 0;
-    if (ncar > 0) {
+    int tile0 = dedicated && ncar > 0 ? (ncar + 7) / 8 * 8 : 0;
+    if (ncar > 0 && tile0 == 0) {
         int next[8];
         for (int r = 0; r < 8; ++r) next[r] = ncar + ((r - ncar % 8) + 8) % 8;   // first slot >= ncar of residue r
         for (int b = 0; b < std::min<int>(ncar, (int)slots.size()) && tile0 == 0; ++b) {
@@ -333,7 +336,7 @@ lee_status upload_work1(lee_instance *I)
     std::vector<int4> items;
     std::vector<std::vector<int2>> patches;
     build_items(I->host, 0, I->tl, items, &patches);
-    I->tile0 = order_work(items, patches, per_unit_of(I->tl), carriers_for(I->tl, I->host.gidx.size()),
+    I->tile0 = order_work(items, patches, per_unit_of(I->tl), carriers_for(I->tl, I->host.gidx.size()), false,
                           I->up_work1, I->up_aux, I->up_patch);
     if (I->up_work1.size() > I->work1_cap) return fail(LEE_E_ARG, "tiling produces too many work items");
     if (I->up_patch.size() > I->patch_cap) return fail(LEE_E_ARG, "tiling produces too many ghost patches");
@@ -372,6 +375,7 @@ lee_status run_steps(StepGraphs &G, hipStream_t s, int64_t n, const std::functio
         if (e2 != hipSuccess) return hip_fail(e2, "hipStreamEndCapture");
         g = cg;
         HIPCHK(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
+        ++G.captures;
         return LEE_OK;
     };
     const int64_t full = G.per > 1 ? n / G.per : 0;
@@ -1105,6 +1109,8 @@ struct lee_batch {
     int npwork = 0;
     std::vector<int2> up_pwork;
     std::vector<long long> up_budget;      // stop steps being uploaded
+    long long *d_idle = nullptr;           // step and stop counters of the idle table entries (0, 0)
+    DevInst idle{};                        // table entry past the members
     StepGraphs graphs;
 };
 
@@ -1112,18 +1118,32 @@ namespace {
 
 void batch_drop_graph(lee_batch *B) { B->graphs.drop(); }
 
+// Frees the table and work lists (the caller has synchronised the stream).
+void batch_release_lists(lee_batch *B)
+{
+    auto rel = [](auto *&p, size_t &cap) {
+        if (p) hipFree(p);
+        p = nullptr;
+        cap = 0;
+    };
+    rel(B->d_table, B->table_cap);
+    rel(B->d_work1, B->work1_cap);
+    rel(B->d_work2, B->work2_cap);
+    rel(B->d_aux, B->aux_cap);
+    rel(B->d_patch, B->patch_cap);
+    rel(B->d_pwork, B->pwork_cap);
+}
+
 // The sweep work list over all members, in XCD-aware order, with the ghost
-// patches of the fused form.
+// patches of the fused form.  The carriers are those of the padded ghost
+// list (work2_cap items), which is what the launches see.
 void batch_build_work1(lee_batch *B)
 {
     std::vector<int4> items;
     std::vector<std::vector<int2>> patches;
     for (size_t k = 0; k < B->members.size(); ++k) build_items(B->members[k]->host, (int)k, B->tl, items, &patches);
-    size_t G = 0;
-    for (auto *I : B->members) G += I->host.gidx.size();
-    B->tile0 = order_work(items, patches, per_unit_of(B->tl), carriers_for(B->tl, G), B->up_work1, B->up_aux,
-                          B->up_patch);
-    B->nwork1 = (int)B->up_work1.size();
+    B->tile0 = order_work(items, patches, per_unit_of(B->tl), carriers_for(B->tl, B->work2_cap), true,
+                          B->up_work1, B->up_aux, B->up_patch);
 }
 
 hipError_t batch_issue_stage(lee_batch *B, int stage, int slot)
@@ -1131,7 +1151,7 @@ hipError_t batch_issue_stage(lee_batch *B, int stage, int slot)
     int blocks = 0;
     const int per = B->tl.kind == LEE_SWEEP_MARCH ? B->tl.waves : 1;
     if (B->pblocks > 0) blocks = std::min(B->pblocks, (B->nwork1 + per - 1) / per);
-    return stage_launches(B->prec, B->filt, B->tl, B->d_table, (int)B->members.size(), B->d_work1, B->nwork1,
+    return stage_launches(B->prec, B->filt, B->tl, B->d_table, 0, B->d_work1, B->nwork1,
                           B->d_aux, B->d_patch,
                           B->tile0, B->d_work2, B->nwork2, B->d_sync, stage, slot,
                           probe_pass(B->d_pwork, B->npwork, stage, slot), blocks, B->stream);
@@ -1143,18 +1163,19 @@ hipError_t batch_issue_run(lee_batch *B, int n)
     for (int j = 0; j < n && e == hipSuccess; ++j)
         for (int l = 0; l < 4 && e == hipSuccess; ++l) e = batch_issue_stage(B, l, j);
     if (e == hipSuccess) e = launch_probe(B->prec, B->d_table, ProbePass{B->d_pwork, B->npwork, n - 1}, B->stream);
-    if (e == hipSuccess) e = launch_advance(B->d_table, (int)B->members.size(), n, B->stream);
+    if (e == hipSuccess) e = launch_advance(B->d_table, (int)B->table_cap, n, B->stream);
     return e;
 }
 
-// Grows a device array to hold n elements (synchronising before it frees the
-// old one, which queued kernels may still read).
+// Grows a device array to hold n elements, with a quarter more room once it
+// has held some (synchronising before it frees the old one, which queued
+// kernels may still read).
 template <typename T>
 hipError_t grow(T *&p, size_t &cap, size_t n, hipStream_t s)
 {
     n = std::max<size_t>(n, 1);
     if (n <= cap) return hipSuccess;
-    const size_t want = std::max(n, 2 * cap);
+    const size_t want = cap ? std::max(n, cap + cap / 4) : n;
     hipError_t e = hipStreamSynchronize(s);
     if (e != hipSuccess) return e;
     if (p) hipFree(p);
@@ -1165,11 +1186,21 @@ hipError_t grow(T *&p, size_t &cap, size_t n, hipStream_t s)
     return e;
 }
 
-// Instance table and both work lists from the member list, uploaded on the
-// batch's stream; the captured graphs are dropped.
-lee_status batch_rebuild(lee_batch *B)
+// Instance table and work lists from the member list, uploaded on the
+// batch's stream.  Every list is padded with idle entries to its device
+// capacity, and the launches cover the capacities, so the captured graphs
+// stay valid across membership changes: they are dropped only when a list
+// outgrows its capacity (capacities grow by at least a quarter; the fused
+// form's carriers follow the ghost capacity), when a sweep or ghost list
+// falls below three quarters of its capacity, or when `drop` is set; then
+// every capacity is trimmed to the current lists (no idle workgroups).
+lee_status batch_rebuild(lee_batch *B, bool drop = false)
 {
-    batch_drop_graph(B);
+    if (drop) {
+        HIPCHK(hipStreamSynchronize(B->stream));
+        batch_drop_graph(B);
+        batch_release_lists(B);
+    }
     const size_t n = B->members.size();
     B->up_table.clear();
     B->up_work2.clear();
@@ -1181,30 +1212,42 @@ lee_status batch_rebuild(lee_batch *B)
             B->up_work2.push_back(make_int4((int)k, g, I->host.cptr[g], I->host.cptr[g + 1]));
         for (int p = 0; p < I->host.np; ++p) B->up_pwork.push_back(make_int2((int)k, p));
     }
-    B->npwork = (int)B->up_pwork.size();
-    batch_build_work1(B);
-    B->nwork2 = (int)B->up_work2.size();
+    const void *before[6] = {B->d_table, B->d_work1, B->d_work2, B->d_aux, B->d_patch, B->d_pwork};
+    const int tile0_before = B->tile0;
     HIPCHK(grow(B->d_table, B->table_cap, n, B->stream));
-    HIPCHK(grow(B->d_work1, B->work1_cap, B->up_work1.size(), B->stream));
     HIPCHK(grow(B->d_work2, B->work2_cap, B->up_work2.size(), B->stream));
-    HIPCHK(grow(B->d_aux, B->aux_cap, B->up_aux.size(), B->stream));
-    HIPCHK(grow(B->d_patch, B->patch_cap, B->up_patch.size(), B->stream));
     HIPCHK(grow(B->d_pwork, B->pwork_cap, B->up_pwork.size(), B->stream));
-    if (B->npwork)
-        HIPCHK(hipMemcpyAsync(B->d_pwork, B->up_pwork.data(), B->npwork * sizeof(int2), hipMemcpyHostToDevice,
-                              B->stream));
-    if (n)
-        HIPCHK(hipMemcpyAsync(B->d_table, B->up_table.data(), n * sizeof(DevInst), hipMemcpyHostToDevice,
-                              B->stream));
-    if (B->nwork1)
-        HIPCHK(hipMemcpyAsync(B->d_work1, B->up_work1.data(), B->nwork1 * sizeof(int4), hipMemcpyHostToDevice,
-                              B->stream));
-    if (B->nwork2)
-        HIPCHK(hipMemcpyAsync(B->d_work2, B->up_work2.data(), B->nwork2 * sizeof(int4), hipMemcpyHostToDevice,
-                              B->stream));
-    if (!B->up_aux.empty())
-        HIPCHK(hipMemcpyAsync(B->d_aux, B->up_aux.data(), B->up_aux.size() * sizeof(int2), hipMemcpyHostToDevice,
-                              B->stream));
+    batch_build_work1(B);
+    // lists far below their capacities would launch many idle workgroups in
+    // every stage: trim them (new graphs) instead
+    auto sparse = [](size_t used, size_t cap) { return cap > 256 && 4 * used < 3 * cap; };
+    if (!drop && (sparse(B->up_work1.size(), B->work1_cap) || sparse(B->up_work2.size(), B->work2_cap)))
+        return batch_rebuild(B, true);
+    HIPCHK(grow(B->d_work1, B->work1_cap, B->up_work1.size(), B->stream));
+    HIPCHK(grow(B->d_aux, B->aux_cap, B->work1_cap, B->stream));
+    HIPCHK(grow(B->d_patch, B->patch_cap, B->up_patch.size(), B->stream));
+    const void *after[6] = {B->d_table, B->d_work1, B->d_work2, B->d_aux, B->d_patch, B->d_pwork};
+    for (int k = 0; k < 6; ++k) drop = drop || before[k] != after[k];
+    drop = drop || B->tile0 != tile0_before;
+    if (drop) batch_drop_graph(B);             // after a trim the pointers have changed as well
+    B->up_table.resize(B->table_cap, B->idle);
+    B->up_work1.resize(B->work1_cap, make_int4(-1, 0, 0, 1));
+    B->up_aux.resize(B->work1_cap, make_int2(0, 0));
+    B->up_work2.resize(B->work2_cap, make_int4(-1, 0, 0, 0));
+    B->up_pwork.resize(B->pwork_cap, make_int2(-1, 0));
+    B->nwork1 = (int)B->work1_cap;
+    B->nwork2 = (int)B->work2_cap;
+    B->npwork = (int)B->pwork_cap;
+    HIPCHK(hipMemcpyAsync(B->d_table, B->up_table.data(), B->table_cap * sizeof(DevInst), hipMemcpyHostToDevice,
+                          B->stream));
+    HIPCHK(hipMemcpyAsync(B->d_work1, B->up_work1.data(), B->work1_cap * sizeof(int4), hipMemcpyHostToDevice,
+                          B->stream));
+    HIPCHK(hipMemcpyAsync(B->d_aux, B->up_aux.data(), B->work1_cap * sizeof(int2), hipMemcpyHostToDevice,
+                          B->stream));
+    HIPCHK(hipMemcpyAsync(B->d_work2, B->up_work2.data(), B->work2_cap * sizeof(int4), hipMemcpyHostToDevice,
+                          B->stream));
+    HIPCHK(hipMemcpyAsync(B->d_pwork, B->up_pwork.data(), B->pwork_cap * sizeof(int2), hipMemcpyHostToDevice,
+                          B->stream));
     if (!B->up_patch.empty())
         HIPCHK(hipMemcpyAsync(B->d_patch, B->up_patch.data(), B->up_patch.size() * sizeof(int2),
                               hipMemcpyHostToDevice, B->stream));
@@ -1225,21 +1268,11 @@ lee_status member_ok(const lee_batch *B, const lee_instance *I)
 void batch_free(lee_batch *B)
 {
     batch_drop_graph(B);
-    if (B->d_table) hipFree(B->d_table);
-    if (B->d_work1) hipFree(B->d_work1);
-    if (B->d_work2) hipFree(B->d_work2);
+    batch_release_lists(B);
     if (B->d_sync) hipFree(B->d_sync);
-    if (B->d_aux) hipFree(B->d_aux);
-    if (B->d_patch) hipFree(B->d_patch);
-    if (B->d_pwork) hipFree(B->d_pwork);
-    B->d_pwork = nullptr;
-    B->pwork_cap = 0;
+    if (B->d_idle) hipFree(B->d_idle);
+    B->d_idle = nullptr;
     B->d_sync = nullptr;
-    B->d_aux = B->d_patch = nullptr;
-    B->table_cap = B->work1_cap = B->work2_cap = B->aux_cap = B->patch_cap = 0;
-    B->d_table = nullptr;
-    B->d_work1 = nullptr;
-    B->d_work2 = nullptr;
 }
 
 }  // namespace
@@ -1282,6 +1315,10 @@ lee_status lee_batch_create(lee_instance *const *v, int32_t n, const lee_batch_o
     if (B->pblocks > 0) B->pblocks = (B->pblocks + 7) / 8 * 8;   // keep the XCD pattern
     hipError_t e = hipMalloc(&B->d_sync, SYNC_INTS * sizeof(int));
     if (e == hipSuccess) e = launch_fill_bytes(B->d_sync, SYNC_INTS * sizeof(int), B->stream);
+    if (e == hipSuccess) e = hipMalloc(&B->d_idle, 2 * sizeof(long long));
+    if (e == hipSuccess) e = launch_fill_bytes(B->d_idle, 2 * sizeof(long long), B->stream);
+    B->idle.step = B->d_idle;
+    B->idle.stop = B->d_idle ? B->d_idle + 1 : nullptr;
     if (e != hipSuccess) {
         batch_free(B);
         delete B;
@@ -1319,6 +1356,13 @@ lee_status lee_batch_remove(lee_batch *B, lee_instance *I)
     HIPCHK(hipStreamSynchronize(B->stream));      // no queued step may still use it
     B->members.erase(it);
     return batch_rebuild(B);
+}
+
+lee_status lee_batch_graph_captures(const lee_batch *B, int64_t *n)
+{
+    if (!B || !n) return fail(LEE_E_ARG, "null argument");
+    *n = B->graphs.captures;
+    return LEE_OK;
 }
 
 lee_status lee_batch_size(const lee_batch *B, int32_t *n)
@@ -1369,7 +1413,7 @@ lee_status lee_batch_time_kernels(lee_batch *B, int64_t n, double *sweep_us, dou
     auto ghosts = [&]() -> hipError_t {
         hipError_t e = hipSuccess;
         for (int64_t k = 0; k < 4 * n && e == hipSuccess; ++k)
-            e = launch_ghost(B->prec, B->d_table, (int)B->members.size(), B->d_work2, B->nwork2, (int)(k & 3), 0,
+            e = launch_ghost(B->prec, B->d_table, 0, B->d_work2, B->nwork2, (int)(k & 3), 0,
                              ProbePass{nullptr, 0, 0}, B->stream);
         return e;
     };
@@ -1377,8 +1421,7 @@ lee_status lee_batch_time_kernels(lee_batch *B, int64_t n, double *sweep_us, dou
         hipError_t e = hipSuccess;
         for (int64_t k = 0; k < 4 * n && e == hipSuccess; ++k) {
             const int l = (int)(k & 3);
-            e = fused(B->tl) ? launch_stage(B->prec, B->filt, B->tl.cols, B->tl.rows, B->d_table,
-                                            (int)B->members.size(), B->d_work1,
+            e = fused(B->tl) ? launch_stage(B->prec, B->filt, B->tl.cols, B->tl.rows, B->d_table, 0, B->d_work1,
                                             B->nwork1, B->d_aux, B->d_patch, B->tile0, B->d_work2, B->nwork2, l, 0,
                                             B->d_sync, SPIN_LIMIT, ProbePass{nullptr, 0, 0}, B->stream)
                              : sweep(B->prec, B->filt, B->tl, B->d_table, B->d_work1, B->nwork1, l, 0, blocks,
@@ -1412,7 +1455,7 @@ lee_status lee_batch_set_tiling(lee_batch *B, const lee_tiling *t)
     if (!tiling_valid(B->prec, *t)) return fail(LEE_E_ARG, "unsupported tiling");
     HIPCHK(hipStreamSynchronize(B->stream));     // the old lists may still be read
     B->tl = *t;
-    return batch_rebuild(B);
+    return batch_rebuild(B, true);
 }
 
 lee_status lee_batch_get_tiling(const lee_batch *B, lee_tiling *t)

@@ -57,7 +57,8 @@ struct DevInst {
 };
 
 // Probe sampling carried by a launch: the (member, probe) pairs pw[0, np),
-// for step *step + rel of each member that took that step (np = 0: none).
+// for step *step + rel of each member that took that step (np = 0: none;
+// member -1: an idle entry).
 struct ProbePass {
     const int2 *pw;
     int np;
@@ -79,8 +80,10 @@ hipError_t launch_tile(int prec, bool filt, int tx, int ty, const DevInst *insts
 // tile's copy, ghost index * 3 + field).  sync[4] is the error flag raised by
 // a wait that runs out of polls (zero before first use).  The probe pass
 // runs in extra workgroups after the tiles.
-// ninst: entries of the instance table (1 lets the ghost fill read its
-// record with scalar loads).
+// ninst: 1 for a single instance (the ghost fill reads its record with
+// scalar loads), any other value for a table indexed by the work items.
+// Work items with instance -1 (ghost and sweep lists) are idle, so a batch
+// can pad its lists to fixed capacities.
 hipError_t launch_stage(int prec, bool filt, int tx, int ty, const DevInst *insts, int ninst, const int4 *work1,
                         int nwork1, const int2 *aux, const int2 *patch, int tile0, const int4 *work2, int nwork2,
                         int stage, int slot, int *sync, int spin_limit, ProbePass pp, hipStream_t s);
@@ -91,7 +94,8 @@ constexpr int SPIN_LIMIT = 1 << 20;             // polls before a ghost wait giv
 hipError_t launch_ghost(int prec, const DevInst *insts, int ninst, const int4 *work, int nwork, int stage, int slot,
                         ProbePass pp, hipStream_t s);
 hipError_t launch_probe(int prec, const DevInst *insts, ProbePass pp, hipStream_t s);
-// After a run of n steps: *step += n for every member, held at *stop.
+// After a run of n steps: *step += n for each of the ninst table entries,
+// held at *stop.
 hipError_t launch_advance(const DevInst *insts, int ninst, int n, hipStream_t s);
 hipError_t launch_fill(int prec, void *p, size_t n, hipStream_t s);
 hipError_t launch_fill_bytes(void *p, size_t bytes, hipStream_t s);

@@ -136,6 +136,7 @@ __device__ __forceinline__ void ghost_item(const DevInst *__restrict__ insts, co
 {
     if (gid >= nwork) return;                       // whole GL-lane groups leave together
     const int4 wk = work[gid];                      // instance, ghost, cloud entries [z, w)
+    if (!ONE && wk.x < 0) return;                   // an idle item of a padded list
     const DevInst &I = insts[ONE ? 0 : wk.x];
     const int g = wk.y;
     const int ib = in_buf(stage), ob = out_buf(stage);
@@ -246,6 +247,7 @@ __device__ __forceinline__ void probe_item(const DevInst *__restrict__ insts, co
 {
     if (pid >= pp.np) return;                       // whole 16-lane groups leave together
     const int2 q = pp.pw[pid];
+    if (q.x < 0) return;                            // an idle item of a padded list
     const DevInst &I = insts[q.x];
     const int k = q.y;
     const long long s = step_at(I, pp.rel);

@@ -284,6 +284,13 @@ class Batch:
         check(self.lib.lee_batch_size(self._h, ctypes.byref(n)), "lee_batch_size")
         return n.value
 
+    def graph_captures(self) -> int:
+        """Step graphs captured so far (membership changes keep them unless
+        a device list outgrows its capacity)."""
+        n = ctypes.c_int64()
+        check(self.lib.lee_batch_graph_captures(self._h, ctypes.byref(n)), "lee_batch_graph_captures")
+        return n.value
+
     def set_budget(self, steps: Sequence[int]):
         a = np.ascontiguousarray(np.asarray(steps, dtype=np.int64))
         check(self.lib.lee_batch_set_budget(self._h, _ptr(a)), "lee_batch_set_budget")

@@ -77,3 +77,40 @@ def test_batch_budgets_idle_finished_members():
         m.synchronize()
         for x, y in zip(m.fields(), ref):
             assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("prec,fused", [("f32", 0), ("f32", 1), ("f64", 1)])
+def test_membership_changes_keep_graphs(prec, fused):
+    """A member leaves and joins again between runs: the batch keeps its
+    captured graphs (its padded lists still fit their capacities), and every
+    member matches a solo run of the same number of steps bit for bit."""
+    Instance, Batch = _lee()
+    cases = _members()[:4]
+    rows = 16 if prec == "f32" else 8
+    steps = [24, 16, 24, 24]                 # member 1 sits out the middle run
+    print(f"[batch] membership {prec} fused={fused}", flush=True)
+    solo = []
+    for c, n in zip(cases, steps):
+        i = Instance(c, prec)
+        i.set_tiling("tile", cols=64, rows=rows, fused=0)
+        i.step_n(n)
+        i.synchronize()
+        solo.append(i.fields())
+    mem = [Instance(c, prec) for c in cases]
+    b = Batch(mem, tiling=dict(kind="tile", cols=64, rows=rows, fused=fused), graph_steps=4)
+    b.step_n(8)
+    b.synchronize()
+    captured = b.graph_captures()
+    assert captured >= 1
+    b.remove(mem[1])
+    assert len(b) == 3
+    b.step_n(8)
+    b.add(mem[1])
+    assert len(b) == 4
+    b.step_n(8)
+    b.synchronize()
+    assert b.graph_captures() == captured
+    for m, ref in zip(mem, solo):
+        m.synchronize()
+        for x, y in zip(m.fields(), ref):
+            assert np.array_equal(x, y)
