@@ -28,7 +28,7 @@ _SHAPES = {
     "f32": [(64, 16), (64, 8), (64, 32), (128, 8), (128, 16)],
     "f64": [(64, 8), (64, 16), (128, 4), (128, 8)],
 }
-GRAPH_STEPS = (16,)
+GRAPH_STEPS = (16, 32)      # trial runs are whole graphs of either length
 
 
 def candidates(precision: str) -> List[dict]:
@@ -53,23 +53,31 @@ def cache_key(arch: str, precision: str, cls: str) -> str:
     return f"{arch.split(':')[0]}|{precision}|{cls}"
 
 
-def select(measure: Callable[[dict], float], cands: Iterable[dict]) -> Tuple[dict, List[dict]]:
+def select(measure: Callable[[dict], float], cands: Iterable[dict], rounds: int = 3) -> Tuple[dict, List[dict]]:
     """Time every candidate with measure (microseconds per step; it may raise,
-    which rejects the candidate) and return the fastest and the table."""
-    table = []
+    which rejects the candidate) in `rounds` interleaved passes, keep each
+    candidate's best time (candidates a few per cent apart are otherwise
+    ordered by run-to-run noise), and return the fastest and the table."""
+    cands = list(cands)
+    table = [dict(c, step_us=None, trials=[]) for c in cands]
+    for _ in range(max(int(rounds), 1)):
+        for row, c in zip(table, cands):
+            if "error" in row:
+                continue
+            try:
+                us = float(measure(c))
+            except Exception as e:        # a configuration the device rejects
+                row.update(step_us=None, error=str(e))
+                continue
+            if not math.isfinite(us) or us <= 0.0:
+                row.update(step_us=None, error="no time")
+                continue
+            row["trials"].append(us)
+            row["step_us"] = min(row["trials"])
     best = None
-    for c in cands:
-        try:
-            us = float(measure(c))
-        except Exception as e:            # a configuration the device rejects
-            table.append(dict(c, step_us=None, error=str(e)))
-            continue
-        if not math.isfinite(us) or us <= 0.0:
-            table.append(dict(c, step_us=None, error="no time"))
-            continue
-        table.append(dict(c, step_us=us))
-        if best is None or us < best["step_us"]:
-            best = dict(c, step_us=us)
+    for row, c in zip(table, cands):
+        if row["step_us"] is not None and "error" not in row and (best is None or row["step_us"] < best["step_us"]):
+            best = dict(c, step_us=row["step_us"])
     if best is None:
         raise RuntimeError("no candidate configuration ran")
     return best, table
@@ -131,7 +139,7 @@ def _apply(target, choice: dict) -> None:
     target.set_graph_steps(choice["graph_steps"])
 
 
-def tune_instance(inst, cache: Optional[TuneCache] = None, steps: int = 48, warmup: int = 16,
+def tune_instance(inst, cache: Optional[TuneCache] = None, steps: int = 64, warmup: int = 32,
                   cands: Optional[Sequence[dict]] = None) -> dict:
     """Pick and apply the fastest configuration for a bound instance, then
     reset it to its initial condition.  Returns the choice (with its time and,
@@ -166,7 +174,7 @@ def tune_case(case, precision: str = "f32", cache: Optional[TuneCache] = None, *
         inst.close()
 
 
-def tune_batch(batch, cache: Optional[TuneCache] = None, steps: int = 16, warmup: int = 4,
+def tune_batch(batch, cache: Optional[TuneCache] = None, steps: int = 32, warmup: int = 32,
                cands: Optional[Sequence[dict]] = None) -> dict:
     """Pick and apply the fastest configuration for a batch, then reset every
     member to its initial condition (budgets become unlimited)."""

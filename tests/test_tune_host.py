@@ -42,6 +42,23 @@ def test_select_takes_the_fastest_and_skips_failures():
         tune.select(lambda c: float("inf"), cands)
 
 
+def test_select_keeps_each_candidates_best_round():
+    """Rounds are interleaved and each candidate keeps its best time, so one
+    slow trial does not decide the order."""
+    cands = [{"tiling": {"cols": c}, "graph_steps": 16} for c in (1, 2)]
+    seq = {1: iter([4.0, 9.0, 9.0]), 2: iter([5.0, 3.5, 6.0])}
+    calls = []
+
+    def measure(c):
+        calls.append(c["tiling"]["cols"])
+        return next(seq[c["tiling"]["cols"]])
+
+    best, table = tune.select(measure, cands, rounds=3)
+    assert calls == [1, 2, 1, 2, 1, 2]
+    assert best["tiling"]["cols"] == 2 and best["step_us"] == 3.5
+    assert table[0]["trials"] == [4.0, 9.0, 9.0] and table[0]["step_us"] == 4.0
+
+
 def test_size_class_groups_nearby_problems():
     a = tune.size_class(1_045_359, 855)
     assert a == tune.size_class(1_000_000, 830)
