@@ -24,7 +24,8 @@ Also reported: the oracle on the host cores over a bounded sample of the
 benchmark workload.
 
 Other modes: --extras (a second JSON line: the flat-wall case against the
-oracle, the 4096^2 monopole case, and the batch of 256 uneven instances),
+oracle, the 4096^2 monopole case, the benchmark workload with the paper's
+7-point stencils and no filter, and the batch of 256 uneven instances),
 --serve (the served request stream: Poisson arrivals, continuous batching,
 admission by HBM budget; throughput and p50/p99 latency),
 --profile-run (a short fixed sequence for rocprofv3), and
@@ -326,6 +327,24 @@ def extras(args):
         rm["inst"].close()
         torch.cuda.empty_cache()
     out["monopole_4096"] = dict(steps=args.mono_steps, unit=UNIT, **mres)
+
+    # the benchmark workload in the paper's own scheme: 7-point DRP stencils
+    # (H = 3) and no selective filter; FP64 is checked against the oracle
+    print("[extras] cylinder pulse 1024^2, 7-point DRP without filter", file=sys.stderr, flush=True)
+    pm_steps = 500
+    pm = lc.cylinder_pulse_1024(pm_steps).replace(H=3, filter_sigma=0.0)
+    pres = {}
+    for prec in ("f32", "f64"):
+        ch = tune.tune_case(pm, prec, cache)
+        rp = _timed(pm, prec, pm_steps, 0, ch)
+        pres[prec] = {"value": rp["value"], "ms_per_step": 1000.0 * rp["wall"] / rp["steps"],
+                      "tiling": ch["tiling"]}
+        if prec == "f64":
+            s = osv.OracleSolver(pm)
+            s.run(pm_steps)
+            pres[prec]["rel_l2_vs_oracle"] = _max_rel_l2(rp["inst"].fields(), s.fields(), s.fluid)
+        rp["inst"].close()
+    out["cylinder_pulse_1024_7pt"] = dict(steps=pm_steps, unit=UNIT, **pres)
 
     print(f"[extras] batch of {args.batch_size} uneven instances", file=sys.stderr, flush=True)
     gen = lc.batch_candidates(steps=args.batch_steps)
