@@ -45,13 +45,20 @@ class Wall:
 
 @dataclass(frozen=True)
 class Impedance:
-    """Wall condition. kind: "rigid" or "msd" (mass M, resistance R, stiffness K
-    per unit area, Sec. 2.5)."""
+    """Wall condition. kind: "rigid", "msd" (mass M, resistance R, stiffness K
+    per unit area, Sec. 2.5) or "poles": a wall admittance given in the
+    multi-pole form of Sec. 2.3 (eq. Yrational) without a direct term,
+    real = ((lambda_k, A_k), ...) for the real poles and
+    pairs = ((alpha_k, beta_k, B_k, C_k), ...) for the pole pairs
+    s_k = alpha_k +- i beta_k with residues B_k +- i C_k (at most 8 states:
+    one per real pole, two per pair)."""
 
     kind: str = "rigid"
     R: float = 0.0
     M: float = 0.0
     K: float = 0.0
+    real: tuple = ()
+    pairs: tuple = ()
 
 
 @dataclass(frozen=True)

@@ -12,7 +12,14 @@ s_{1,2} = -R/(2M) +- sqrt((R/2M)^2 - K/M).
   dPhi_k/dt = lambda_k Phi_k + p, u_n = sum_k A_k Phi_k, A_k the residues of Y;
 * critical damping (double pole): rejected, the partial fractions divide by
   s1 - s2 (reading for the tolerance: |disc| <= 1e-9 K/M);
-* rigid wall (Sec. 2.4): all residues zero, u_n = 0, nothing is advanced.
+* rigid wall (Sec. 2.4): all residues zero, u_n = 0, nothing is advanced;
+* general multi-pole admittance (Sec. 2.3, eqs. Yrational, ADEgeneral,
+  unGeneral) with no direct term: one state Phi_k per real pole,
+  dPhi_k/dt = lambda_k Phi_k + p, and two per pole pair,
+  dPsi1/dt = alpha Psi1 - beta Psi2 + p, dPsi2/dt = alpha Psi2 + beta Psi1;
+  u_n = sum_k A_k Phi_k + sum_k 2 (B_k Psi1_k - C_k Psi2_k).  Every pole must
+  lie in the open left half-plane; a direct term Y_inf is not supported
+  (its Neumann datum would need dp_BP/dt).
 
 Stability reading: the ADE is advanced by the same RK4 as the field, so its
 poles must satisfy |R4(dt s_k)| <= 1 with R4 the RK4 amplification polynomial
@@ -20,8 +27,13 @@ poles must satisfy |R4(dt s_k)| <= 1 with R4 the RK4 amplification polynomial
 
 u_n is counted positive from the fluid into the wall (Sec. 2.3).
 
+Every kind is handed to the time stepper as one dense linear system
+dPsi/dt = A Psi + f p_BP, u_n = c . Psi, with ns = len(f) states per ghost.
+
 Parity: pinned in tests by the frequency response c (i w - A)^-1 f = 1/Z(i w)
-in both regimes, the closed-form step response, and the pole eigenvalues.
+in both regimes, the closed-form step response, and the pole eigenvalues; the
+multi-pole form by c (i w - A)^-1 f against eq. Yrational evaluated directly
+and by the MSD written as poles, which must step exactly like the MSD kinds.
 """
 from __future__ import annotations
 
@@ -31,6 +43,7 @@ from dataclasses import dataclass
 from lee_cases import Impedance
 
 CRITICAL_TOL = 1e-9
+MAX_STATES = 8
 
 
 class ImpedanceError(ValueError):
@@ -39,7 +52,7 @@ class ImpedanceError(ValueError):
 
 @dataclass(frozen=True)
 class ADE:
-    kind: str          # "rigid" | "complex" | "real"
+    kind: str          # "rigid" | "complex" | "real" | "poles"
     a: float = 0.0     # complex: s1 = -a + i b
     b: float = 0.0
     B1: float = 0.0
@@ -48,9 +61,29 @@ class ADE:
     lam2: float = 0.0
     A1: float = 0.0
     A2: float = 0.0
+    real: tuple = ()   # poles: ((lambda_k, A_k), ...)
+    pairs: tuple = ()  # poles: ((alpha_k, beta_k, B_k, C_k), ...)
 
     def matrices(self):
         """(A, f, c) with dPsi/dt = A Psi + f p, u_n = c . Psi."""
+        if self.kind == "poles":
+            n = len(self.real) + 2 * len(self.pairs)
+            A = [[0.0] * n for _ in range(n)]
+            f = [0.0] * n
+            c = [0.0] * n
+            i = 0
+            for lam, a in self.real:            # eq. ADEgeneral (a)
+                A[i][i] = lam
+                f[i] = 1.0
+                c[i] = a
+                i += 1
+            for al, be, B, C in self.pairs:     # eqs. ADEgeneral (b), (c)
+                A[i][i], A[i][i + 1] = al, -be
+                A[i + 1][i], A[i + 1][i + 1] = be, al
+                f[i] = 1.0
+                c[i], c[i + 1] = 2.0 * B, -2.0 * C
+                i += 2
+            return A, f, c
         if self.kind == "complex":
             return ([[-self.a, -self.b], [self.b, -self.a]], [1.0, 0.0],
                     [2.0 * self.B1, -2.0 * self.C1])
@@ -59,6 +92,11 @@ class ADE:
         return ([[0.0, 0.0], [0.0, 0.0]], [0.0, 0.0], [0.0, 0.0])
 
     def poles(self):
+        if self.kind == "poles":
+            out = [complex(lam) for lam, _ in self.real]
+            for al, be, _, _ in self.pairs:
+                out += [complex(al, be), complex(al, -be)]
+            return out
         if self.kind == "complex":
             return [complex(-self.a, self.b), complex(-self.a, -self.b)]
         if self.kind == "real":
@@ -70,9 +108,36 @@ def rk4_poly(z: complex) -> complex:
     return 1 + z + z * z / 2 + z ** 3 / 6 + z ** 4 / 24
 
 
+def admittance(imp: Impedance, s: complex) -> complex:
+    """Eq. Yrational at the complex frequency s, term by term (no direct term)."""
+    y = 0j
+    for lam, a in imp.real:
+        y += a / (s - lam)
+    for al, be, B, C in imp.pairs:
+        q, sk = complex(B, C), complex(al, be)
+        y += q / (s - sk) + q.conjugate() / (s - sk.conjugate())
+    return y
+
+
 def ade_from_impedance(imp: Impedance, dt: float) -> ADE:
     if imp.kind == "rigid":
         return ADE("rigid")
+    if imp.kind == "poles":
+        n = len(imp.real) + 2 * len(imp.pairs)
+        if n == 0 or n > MAX_STATES:
+            raise ImpedanceError("between 1 and 8 auxiliary states")
+        vals = [x for t in imp.real for x in t] + [x for t in imp.pairs for x in t]
+        if any(len(t) != 2 for t in imp.real) or any(len(t) != 4 for t in imp.pairs) or \
+                not all(math.isfinite(float(x)) for x in vals):
+            raise ImpedanceError("pole terms")
+        if any(lam >= 0.0 for lam, _ in imp.real) or any(al >= 0.0 or be <= 0.0 for al, be, _, _ in imp.pairs):
+            raise ImpedanceError("poles must lie in the open left half-plane (beta > 0 for a pair)")
+        ade = ADE("poles", real=tuple((float(l), float(a)) for l, a in imp.real),
+                  pairs=tuple(tuple(float(x) for x in t) for t in imp.pairs))
+        for s in ade.poles():
+            if abs(rk4_poly(dt * s)) > 1.0:
+                raise ImpedanceError("ADE pole outside the RK4 stability region")
+        return ade
     R, M, K = imp.R, imp.M, imp.K
     if not (R > 0.0 and M > 0.0 and K > 0.0):
         raise ImpedanceError("M, R, K must be positive")

@@ -6,7 +6,8 @@
  * ghost by ghost:
  *   1. least-squares read-out of p, u, v at P_0..P_4 (W from the Python side);
  *      p_BP = p(P_0);
- *   2. ADE derivative dPsi/dt = A Psi^(l-1) + f p_BP (Sec. 2.5 / eq. ADEgeneral);
+ *   2. ADE derivative dPsi/dt = A Psi^(l-1) + f p_BP (Sec. 2.5 / eq. ADEgeneral;
+ *      ns states per ghost, one dense system for every impedance kind);
  *   3. u_n,BP = c.Psi^(l-1) and du_n,BP/dt = c.dPsi/dt (eqs. ADE-un, ADE-dpdn);
  *   4. boundary data in the frame of the immersed-boundary normal n (wall to
  *      fluid): u.n = -u_n,BP (u_n counts positive into the wall) and
@@ -54,8 +55,10 @@ typedef struct {
     const double *W;            /* nnz*5 */
     const double *lag;          /* G*5  Lagrange l_i(-r) */
     const double *bir;          /* G*5  Birkhoff mu_i(-r) */
-    int ade_kind;               /* 0 rigid, 1 complex pair, 2 real poles */
-    double ade[4];              /* complex: a, b, B1, C1; real: l1, l2, A1, A2 */
+    int ade_ns;                 /* auxiliary states per ghost (1..8) */
+    double ade_A[64];           /* dPsi/dt = A Psi + f p_BP, A row-major ns x ns in an 8 x 8 array */
+    double ade_f[8];
+    double ade_c[8];            /* u_n,BP = c . Psi */
     int watch_g;                /* ghost whose p_BP and u_n,BP are recorded (-1: none) */
 } oc_case;
 
@@ -98,20 +101,18 @@ static void fill_ghosts(const oc_case *c, double *p, double *u, double *v,
         }
         double pBP = fp[0];
         /* steps 2-3: ADE derivative, wall velocity and its time derivative */
-        double s1 = psi_in[2 * g], s2 = psi_in[2 * g + 1];
-        double d1 = 0.0, d2 = 0.0, U = 0.0, Ud = 0.0;
-        if (c->ade_kind == 1) {
-            double a = c->ade[0], b = c->ade[1], B1 = c->ade[2], C1 = c->ade[3];
-            d1 = -a * s1 - b * s2 + pBP;
-            d2 = -a * s2 + b * s1;
-            U = 2.0 * B1 * s1 - 2.0 * C1 * s2;
-            Ud = 2.0 * B1 * d1 - 2.0 * C1 * d2;
-        } else if (c->ade_kind == 2) {
-            double l1 = c->ade[0], l2 = c->ade[1], A1 = c->ade[2], A2 = c->ade[3];
-            d1 = l1 * s1 + pBP;
-            d2 = l2 * s2 + pBP;
-            U = A1 * s1 + A2 * s2;
-            Ud = A1 * d1 + A2 * d2;
+        const int ns = c->ade_ns;
+        const double *sg = psi_in + (long long)ns * g;
+        double d[8], U = 0.0, Ud = 0.0;
+        for (i = 0; i < ns; ++i) {
+            double acc = c->ade_f[i] * pBP;
+            int j;
+            for (j = 0; j < ns; ++j) acc += c->ade_A[8 * i + j] * sg[j];
+            d[i] = acc;
+        }
+        for (i = 0; i < ns; ++i) {
+            U += c->ade_c[i] * sg[i];
+            Ud += c->ade_c[i] * d[i];
         }
         /* steps 4-5: boundary data in the IBM frame and 1-D extrapolation */
         const double *L = c->lag + 5 * g, *B = c->bir + 5 * g;
@@ -131,8 +132,8 @@ static void fill_ghosts(const oc_case *c, double *p, double *u, double *v,
         p[q] = pg;
         u[q] = nx * ung - ny * utg;
         v[q] = ny * ung + nx * utg;
-        psi_out[2 * g] = psi_n[2 * g] + alpha * c->dt * d1;
-        psi_out[2 * g + 1] = psi_n[2 * g + 1] + alpha * c->dt * d2;
+        for (i = 0; i < ns; ++i)
+            psi_out[(long long)ns * g + i] = psi_n[(long long)ns * g + i] + alpha * c->dt * d[i];
     }
 }
 
@@ -218,11 +219,12 @@ int oc_run(const oc_case *c, double *p, double *u, double *v, double *psi,
     const long long sy = c->nx + 2 * c->F;
     const long long n = sy * (long long)(c->ny + 2 * c->F);
     double *buf = (double *)calloc((size_t)(6 * n), sizeof(double));
-    double *psb = (double *)calloc((size_t)(4 * (c->G > 0 ? c->G : 1)), sizeof(double));
+    const long long npsi = (long long)c->ade_ns * (c->G > 0 ? c->G : 1);
+    double *psb = (double *)calloc((size_t)(2 * npsi), sizeof(double));
     if (!buf || !psb) { free(buf); free(psb); return -1; }
     double *S[3] = {buf, buf + n, buf + 2 * n};      /* stage value q^(l-1) */
     double *T[3] = {buf + 3 * n, buf + 4 * n, buf + 5 * n}; /* stage output */
-    double *psS = psb, *psT = psb + 2 * (c->G > 0 ? c->G : 1);
+    double *psS = psb, *psT = psb + npsi;
     int s, l, k;
     for (s = 0; s < nsteps; ++s) {
         for (l = 0; l < 4; ++l) {
@@ -237,7 +239,7 @@ int oc_run(const oc_case *c, double *p, double *u, double *v, double *psi,
         memcpy(p, S[0], (size_t)n * sizeof(double));
         memcpy(u, S[1], (size_t)n * sizeof(double));
         memcpy(v, S[2], (size_t)n * sizeof(double));
-        if (c->G > 0) memcpy(psi, psS, (size_t)(2 * c->G) * sizeof(double));
+        if (c->G > 0) memcpy(psi, psS, (size_t)c->ade_ns * c->G * sizeof(double));
         for (k = 0; k < np; ++k) {
             double acc[3] = {0, 0, 0};
             int a, b;

@@ -42,7 +42,8 @@ class _OcCase(ctypes.Structure):
         ("gidx", ctypes.c_void_p), ("gnx", ctypes.c_void_p), ("gny", ctypes.c_void_p),
         ("cptr", ctypes.c_void_p), ("cidx", ctypes.c_void_p), ("W", ctypes.c_void_p),
         ("lag", ctypes.c_void_p), ("bir", ctypes.c_void_p),
-        ("ade_kind", ctypes.c_int), ("ade", ctypes.c_double * 4),
+        ("ade_ns", ctypes.c_int), ("ade_A", ctypes.c_double * 64), ("ade_f", ctypes.c_double * 8),
+        ("ade_c", ctypes.c_double * 8),
         ("watch_g", ctypes.c_int),
     ]
 
@@ -114,7 +115,8 @@ class OracleSolver:
         self.p = np.zeros(self.shape)
         self.u = np.zeros(self.shape)
         self.v = np.zeros(self.shape)
-        self.psi = np.zeros(max(2 * G, 2))
+        self.ns = len(self.ade.matrices()[1])        # auxiliary states per ghost
+        self.psi = np.zeros(max(self.ns * G, self.ns))
         self.step = 0
         self.watch_g = -1
         self.watch_trace = np.zeros((0, 2))
@@ -186,18 +188,13 @@ class OracleSolver:
         s.gidx, s.gnx, s.gny = keep[1].ctypes.data, keep[2].ctypes.data, keep[3].ctypes.data
         s.cptr, s.cidx, s.W = keep[4].ctypes.data, keep[5].ctypes.data, keep[6].ctypes.data
         s.lag, s.bir = keep[7].ctypes.data, keep[8].ctypes.data
-        ade = self.ade
-        if ade.kind == "complex":
-            s.ade_kind = 1
-            vals = (ade.a, ade.b, ade.B1, ade.C1)
-        elif ade.kind == "real":
-            s.ade_kind = 2
-            vals = (ade.lam1, ade.lam2, ade.A1, ade.A2)
-        else:
-            s.ade_kind = 0
-            vals = (0.0, 0.0, 0.0, 0.0)
-        for k in range(4):
-            s.ade[k] = vals[k]
+        A, f, cv = self.ade.matrices()
+        s.ade_ns = len(f)
+        for i in range(len(f)):
+            s.ade_f[i] = f[i]
+            s.ade_c[i] = cv[i]
+            for j in range(len(f)):
+                s.ade_A[8 * i + j] = A[i][j]
         s.watch_g = -1
         return s
 

@@ -72,13 +72,15 @@ def msd_Z(omega, R, M, K):
     return R + 1j * (M * omega - K / omega)
 
 
-def flat_reflection(F, s_w, s_m, t, R, M, K, n_fft=1 << 16, dt_fft=None, t_span=None):
+def flat_reflection(F, s_w, s_m, t, R, M, K, n_fft=1 << 16, dt_fft=None, t_span=None, Y=None):
     """App. A.  F(xi): incident profile along the normal coordinate s (fluid at
     s < s_w), p_i = F(s - t).  The signal seen at the wall
     sig(tau) = F(s_w - tau) is filtered by R_c(omega) = (Z - 1)/(Z + 1) with
     Z = R + i (M omega - K / omega) (e^{+i omega t} convention: the FFT of a
     real signal uses exp(-i omega t)), and the pressure at s_m is
-    F(s_m - t) + r(t - (s_w - s_m))."""
+    F(s_m - t) + r(t - (s_w - s_m)).  With an admittance function Y(s) (the
+    Laplace variable s = i omega) the wall impedance is Z = 1 / Y instead,
+    R_c = (1 - Y) / (1 + Y)."""
     if dt_fft is None:
         dt_fft = 0.01
     tau = (np.arange(n_fft) - n_fft // 4) * dt_fft
@@ -86,7 +88,10 @@ def flat_reflection(F, s_w, s_m, t, R, M, K, n_fft=1 << 16, dt_fft=None, t_span=
     S = np.fft.rfft(sig)
     om = 2 * np.pi * np.fft.rfftfreq(n_fft, dt_fft)
     Rc = np.ones_like(om, dtype=complex)
-    if M > 0 or K > 0 or R > 0:
+    if Y is not None:
+        y = np.array([Y(1j * w) for w in om])
+        Rc = (1 - y) / (1 + y)
+    elif M > 0 or K > 0 or R > 0:
         with np.errstate(divide="ignore", invalid="ignore"):
             Z = msd_Z(om, R, M, K)
             Rc = (Z - 1) / (Z + 1)

@@ -88,6 +88,17 @@ def test_small_cylinder_matches_oracle(prec, tol):
     _compare(lc.small_cylinder(96, 60), 60, prec, tol)
 
 
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-9), ("f32", 1e-4)])
+def test_paper_scheme_matches_oracle(prec, tol):
+    """The paper's own scheme: 7-point DRP stencils (H = 3, three ghost
+    layers) and no selective filter, on the reduced cylinder (impedance wall)
+    and the flat wall, fused and two-launch."""
+    for fused in (1, 0):
+        t = dict(kind="tile", cols=64, rows=16 if prec == "f32" else 8, fused=fused)
+        _compare(lc.small_cylinder(96, 60, filter_sigma=0.0, H=3), 60, prec, tol, tiling=t)
+        _compare(lc.flat_wall_201(60).replace(H=3, filter_sigma=0.0), 60, prec, tol, tiling=t)
+
+
 TILINGS_F32 = [dict(kind="tile", cols=64, rows=16, fused=0), dict(kind="march", vec=2, rows=4, waves=1), dict(kind="march", vec=2, rows=16, waves=2),
                dict(kind="march", vec=4, rows=8, waves=4), dict(kind="march", vec=4, rows=64, waves=1)] + \
               [dict(kind="tile", cols=c, rows=r) for c in (64, 128, 256) for r in (4, 8, 16, 32)

@@ -117,9 +117,27 @@ def _packet_case(imp, h=0.5, ang=30.0):
                    ic=lc.Packet(src[0], src[1], -nxw, -nyw, 1.0, alpha, k), probes=(mic,))
 
 
+# a broadband wall in the multi-pole form of Sec. 2.3: a relaxation term and
+# two resonances, the first at the packet's frequency
+MULTIPOLE = lc.Impedance("poles", real=((-0.5, 0.3),),
+                         pairs=((-0.3, 2 * math.pi / 8.0, 0.2, 0.05), (-1.5, 1.2, 0.1, -0.04)))
+
+
+def _admittance(imp, s):
+    """Eq. Yrational term by term (no direct term)."""
+    y = 0j
+    for lam, a in imp.real:
+        y += a / (s - lam)
+    for al, be, b, c in imp.pairs:
+        q, sk = complex(b, c), complex(al, be)
+        y += q / (s - sk) + q.conjugate() / (s - sk.conjugate())
+    return y
+
+
 @pytest.mark.parametrize("imp", [lc.Impedance("msd", R=0.5, M=1.0, K=1.0 * (2 * math.pi / 8.0) ** 2),
                                  lc.Impedance("msd", R=2.0, M=0.5, K=0.2),
-                                 lc.Impedance("rigid")], ids=["resonant", "real-poles", "rigid"])
+                                 lc.Impedance("rigid"), MULTIPOLE],
+                         ids=["resonant", "real-poles", "rigid", "multi-pole"])
 def test_impedance_wall_plane_packet(imp):
     """App. A: p(s_m, t) = F(s_m - t) + r(t - (s_w - s_m)), r = R_c * signal at the wall."""
     case = _packet_case(imp)
@@ -136,12 +154,15 @@ def test_impedance_wall_plane_packet(imp):
 
     t = (np.arange(steps) + 1) * case.dt
     R, M, K = (imp.R, imp.M, imp.K) if imp.kind == "msd" else (0.0, 0.0, 0.0)
-    ref = refsol.flat_reflection(F, 0.0, sm, t, R, M, K, dt_fft=0.05)
+    Y = (lambda s: _admittance(imp, s)) if imp.kind == "poles" else None
+    if Y is not None:                                  # a passive wall: Re Y(i w) >= 0
+        assert min(Y(1j * w).real for w in np.linspace(0.0, 20.0, 401)) >= 0.0
+    ref = refsol.flat_reflection(F, 0.0, sm, t, R, M, K, dt_fft=0.05, Y=Y)
     win = t > 30.0 * case.h                            # incident and reflected parts
     err = np.sqrt(np.mean((tr[win, 0, 0] - ref[win]) ** 2)) / np.sqrt(np.mean(ref[win] ** 2))
     assert err < 2e-2, err
     # and the reflected part really differs from a rigid wall unless rigid
-    if imp.kind == "msd":
+    if imp.kind != "rigid":
         rig = refsol.flat_reflection(F, 0.0, sm, t, 0.0, 0.0, 0.0, dt_fft=0.05)
         far = np.sqrt(np.mean((rig[win] - ref[win]) ** 2)) / np.sqrt(np.mean(ref[win] ** 2))
         assert far > 10 * err

@@ -327,3 +327,85 @@ def test_ade_rejections():
         ade_mod.ade_from_impedance(lc.FLAT_IMPEDANCE_LITERAL, 0.5)
     ade_mod.ade_from_impedance(lc.FLAT_IMPEDANCE_GRID, 0.5)
     assert ade_mod.ade_from_impedance(lc.Impedance("rigid"), 0.5).matrices()[2] == [0.0, 0.0]
+
+
+# A broadband admittance in the multi-pole form of Sec. 2.3: one relaxation
+# term and two resonances (5 states), all poles in the left half-plane.
+MULTIPOLE = lc.Impedance("poles", real=((-0.5, 0.3),),
+                         pairs=((-0.3, 2 * math.pi / 8.0, 0.2, 0.05), (-1.5, 1.2, 0.1, -0.04)))
+
+
+def _rational(imp, s):
+    """Eq. Yrational written out term by term (no direct term)."""
+    y = 0j
+    for lam, a in imp.real:
+        y += a / (s - lam)
+    for al, be, b, c in imp.pairs:
+        q = complex(b, c)
+        sk = complex(al, be)
+        y += q / (s - sk) + np.conj(q) / (s - np.conj(sk))
+    return y
+
+
+def test_multipole_transfer_function_is_the_rational_admittance():
+    """c (s - A)^-1 f of the auxiliary system (eqs. ADEgeneral, unGeneral)
+    equals eq. Yrational at every s off the poles, seeded random terms too."""
+    rng = np.random.default_rng(2609)
+    imps = [MULTIPOLE]
+    for _ in range(4):
+        nr, npr = int(rng.integers(0, 3)), int(rng.integers(1, 3))
+        imps.append(lc.Impedance("poles", real=tuple((-rng.uniform(0.1, 5), rng.normal()) for _ in range(nr)),
+                                 pairs=tuple((-rng.uniform(0.1, 5), rng.uniform(0.1, 9), rng.normal(), rng.normal())
+                                             for _ in range(npr))))
+    for imp in imps:
+        a = ade_mod.ade_from_impedance(imp, dt=1e-3)
+        A, f, c = (np.array(x, dtype=float) for x in a.matrices())
+        assert len(f) == len(imp.real) + 2 * len(imp.pairs)
+        for s in (0.3j, 1.0j, 7.0j, 40.0j, 0.5 + 2.0j):
+            H = c @ np.linalg.solve(s * np.eye(len(f)) - A, f)
+            Y = _rational(imp, s)
+            assert abs(H - Y) < 1e-12 * max(abs(Y), 1e-3), (imp, s)
+        want = sorted([complex(l) for l, _ in imp.real] +
+                      [complex(al, sg * be) for al, be, _, _ in imp.pairs for sg in (1, -1)],
+                      key=lambda z: (z.real, z.imag))
+        got = sorted(np.linalg.eigvals(A), key=lambda z: (z.real, z.imag))
+        assert np.allclose(got, want, rtol=1e-12)
+
+
+def test_msd_written_as_poles_steps_like_the_msd():
+    """The mass-spring-damper admittance expanded in partial fractions (its
+    poles are the roots of M s^2 + R s + K, the residues s_k / (M (s_k - s_j)))
+    is the N = 2 or M = 1 case of eq. Yrational: the oracle steps it exactly
+    like the MSD kinds, in both regimes."""
+    base = lc.small_cylinder(64, 12)
+    for R, M, K in ((0.5, 0.1, 10.0), (2.0, 0.1, 1.0)):
+        s1, s2 = np.roots([M, R, K])
+        if abs(s1.imag) > 0:
+            s1 = s1 if s1.imag > 0 else s2
+            q = s1 / (M * (s1 - np.conj(s1)))
+            poles = lc.Impedance("poles", pairs=((s1.real, s1.imag, q.real, q.imag),))
+        else:
+            l1, l2 = sorted([s1.real, s2.real], reverse=True)
+            poles = lc.Impedance("poles", real=((l1, l1 / (M * (l1 - l2))), (l2, l2 / (M * (l2 - l1)))))
+        runs = []
+        for imp in (lc.Impedance("msd", R=R, M=M, K=K), poles):
+            s = OracleSolver(base.replace(impedance=imp))
+            tr = s.run(12)
+            runs.append((s.fields(), s.psi.copy(), tr))
+        (fa, pa, ta), (fb, pb, tb) = runs
+        for x, y in zip(fa, fb):
+            assert np.abs(x - y).max() <= 1e-13 * np.abs(x).max()
+        assert np.abs(pa - pb).max() <= 1e-12 * max(np.abs(pa).max(), 1e-30)
+        assert np.abs(ta - tb).max() <= 1e-13 * np.abs(ta).max()
+
+
+def test_multipole_rejections():
+    with pytest.raises(ade_mod.ImpedanceError):       # a pole in the right half-plane
+        ade_mod.ade_from_impedance(lc.Impedance("poles", real=((0.5, 1.0),)), 1e-3)
+    with pytest.raises(ade_mod.ImpedanceError):       # more than 8 states
+        ade_mod.ade_from_impedance(lc.Impedance("poles", pairs=((-1.0, 1.0, 0.1, 0.0),) * 5), 1e-3)
+    with pytest.raises(ade_mod.ImpedanceError):       # no term at all
+        ade_mod.ade_from_impedance(lc.Impedance("poles"), 1e-3)
+    with pytest.raises(ade_mod.ImpedanceError):       # dt * lambda outside the RK4 region
+        ade_mod.ade_from_impedance(lc.Impedance("poles", real=((-100.0, 1.0),)), 0.05)
+    ade_mod.ade_from_impedance(MULTIPOLE, 0.25)
