@@ -65,6 +65,12 @@ typedef int32_t lee_status;
 
 #define LEE_Z_RIGID 0       /* Y -> 0: u_n = 0, dp/dn = 0 (Sec. 2.4) */
 #define LEE_Z_MSD 1         /* Z = M s + R + K / s (Sec. 2.5) */
+#define LEE_Z_POLES 2       /* Y(s) = sum_k A_k / (s - lambda_k)
+                               + sum_k [q_k / (s - s_k) + conj(q_k) / (s - conj(s_k))],
+                               the multi-pole form of Sec. 2.3 (eq. Yrational) without a
+                               direct term; one auxiliary state per real pole and two per
+                               pair (eq. ADEgeneral), at most LEE_ADE_MAX_STATES */
+#define LEE_ADE_MAX_STATES 8
 
 /* Problem description (Sec. 2.1-2.2, 3.1, 4).  dt = cfl * h (c0 = 1). */
 typedef struct {
@@ -86,8 +92,16 @@ typedef struct {
 } lee_case_desc;
 
 typedef struct {
-    int32_t kind;            /* LEE_Z_RIGID or LEE_Z_MSD */
-    double R, M, K;          /* resistance, mass, stiffness per unit area (all > 0) */
+    int32_t kind;            /* LEE_Z_RIGID, LEE_Z_MSD or LEE_Z_POLES */
+    double R, M, K;          /* LEE_Z_MSD: resistance, mass, stiffness per unit area (all > 0) */
+    /* LEE_Z_POLES: n_real real poles lambda_k < 0 with residues A_k, and n_pair
+       pole pairs s_k = alpha_k +- i beta_k (alpha_k < 0, beta_k > 0) with
+       residues B_k +- i C_k; 1 <= n_real + 2 n_pair <= LEE_ADE_MAX_STATES */
+    int32_t n_real;
+    double real_pole[LEE_ADE_MAX_STATES], real_res[LEE_ADE_MAX_STATES];
+    int32_t n_pair;
+    double pair_alpha[LEE_ADE_MAX_STATES / 2], pair_beta[LEE_ADE_MAX_STATES / 2];
+    double pair_B[LEE_ADE_MAX_STATES / 2], pair_C[LEE_ADE_MAX_STATES / 2];
 } lee_impedance;
 
 typedef struct {
@@ -98,8 +112,9 @@ typedef struct {
     double r_min, r_max;     /* range of r = d / h */
     double w_l1_max;         /* largest 1-norm of a composite weight row */
     int64_t fluid_nodes;     /* nodes advanced per stage */
-    int32_t ade_kind;        /* 0 rigid, 1 complex pole pair, 2 two real poles */
-    double poles[4];         /* re s1, im s1, re s2, im s2 */
+    int32_t ade_kind;        /* 0 rigid, 1 complex pole pair, 2 two real poles, 3 multi-pole */
+    double poles[4];         /* re s1, im s1, re s2, im s2 (multi-pole: the first two poles) */
+    int32_t ade_states;      /* auxiliary states per ghost (2, or n_real + 2 n_pair) */
 } lee_ghost_summary;
 
 typedef struct lee_instance lee_instance;
@@ -129,7 +144,12 @@ lee_status lee_setup_grid(const lee_case_desc *d, lee_instance **out);
  * back to degree 3, 2, 1, else zero; clouds cut by the domain edge are zero.
  * ADE: poles and residues of Y = 1/Z (Sec. 2.5); critical damping ->
  * LEE_E_CRITICAL_DAMPING; a pole outside the RK4 stability region or a wall
- * coupling gain h/M > 2 -> LEE_E_ADE_STIFF.  opt_out may be NULL.
+ * coupling gain h/M > 2 -> LEE_E_ADE_STIFF.  LEE_Z_POLES: the given terms
+ * (Sec. 2.3); a pole off the open left half-plane, a pair with beta <= 0,
+ * a non-finite value or a state count outside 1..8 -> LEE_E_ARG; a pole
+ * outside the RK4 region or a coupling gain h (sum A_k + 2 sum B_k) > 2
+ * (the limit of s Y(s), 1/M for the MSD) -> LEE_E_ADE_STIFF.  opt_out may
+ * be NULL.
  * Must be called once, after lee_setup_grid and before lee_bind.
  */
 lee_status lee_build_ghosts(lee_instance *inst, const lee_impedance *z, int32_t degree,
@@ -213,7 +233,9 @@ lee_status lee_get_fields(lee_instance *inst, double *p, double *u, double *v);
 /* Synchronising: overwrite q^n at fluid nodes from ny * nx doubles. */
 lee_status lee_set_fields(lee_instance *inst, const double *p, const double *u, const double *v);
 
-/* Synchronising: ADE states after the last full step, out[2g + {0,1}]. */
+/* Synchronising: ADE states after the last full step, out[n g + k] with n
+ * the summary's ade_states (states in the order of the real poles, then
+ * each pair's two). */
 lee_status lee_get_ade_states(lee_instance *inst, double *out);
 
 /* Completed steps: the device's step counter once the stream is idle

@@ -14,7 +14,7 @@ STATUS = {0: "LEE_OK", -1: "LEE_E_ARG", -2: "LEE_E_GEOMETRY", -3: "LEE_E_CRITICA
           -8: "LEE_E_STATE", -9: "LEE_E_PROBE"}
 F32, F64 = 0, 1
 WALL = {"none": 0, "line": 1, "circle": 2}
-Z_RIGID, Z_MSD = 0, 1
+Z_RIGID, Z_MSD, Z_POLES = 0, 1, 2
 
 c_int32, c_int64, c_double, c_void_p, c_size_t = (ctypes.c_int32, ctypes.c_int64, ctypes.c_double,
                                                    ctypes.c_void_p, ctypes.c_size_t)
@@ -29,14 +29,22 @@ class CaseDesc(ctypes.Structure):
                 ("ic_kind", c_int32), ("ic", c_double * 7), ("src_kind", c_int32), ("src", c_double * 5)]
 
 
+ADE_MAX_STATES = 8
+
+
 class ImpedanceDesc(ctypes.Structure):
-    _fields_ = [("kind", c_int32), ("R", c_double), ("M", c_double), ("K", c_double)]
+    _fields_ = [("kind", c_int32), ("R", c_double), ("M", c_double), ("K", c_double),
+                ("n_real", c_int32), ("real_pole", c_double * ADE_MAX_STATES),
+                ("real_res", c_double * ADE_MAX_STATES), ("n_pair", c_int32),
+                ("pair_alpha", c_double * (ADE_MAX_STATES // 2)), ("pair_beta", c_double * (ADE_MAX_STATES // 2)),
+                ("pair_B", c_double * (ADE_MAX_STATES // 2)), ("pair_C", c_double * (ADE_MAX_STATES // 2))]
 
 
 class GhostSummary(ctypes.Structure):
     _fields_ = [("G", c_int32), ("nnz", c_int64), ("n_degraded", c_int32), ("n_cut", c_int32),
                 ("r_min", c_double), ("r_max", c_double), ("w_l1_max", c_double),
-                ("fluid_nodes", c_int64), ("ade_kind", c_int32), ("poles", c_double * 4)]
+                ("fluid_nodes", c_int64), ("ade_kind", c_int32), ("poles", c_double * 4),
+                ("ade_states", c_int32)]
 
 
 SWEEP_TILE, SWEEP_MARCH = 0, 1

@@ -124,7 +124,7 @@ Layout layout(const Host &h)
     const size_t G = h.gidx.size(), nnz = h.cidx.size();
     L.inst = take(sizeof(DevInst));
     for (int k = 0; k < 9; ++k) L.planes[k] = take(plane_elems(h) * es);
-    for (int k = 0; k < 3; ++k) L.psi[k] = take(2 * std::max<size_t>(G, 1) * es);
+    for (int k = 0; k < 3; ++k) L.psi[k] = take((size_t)h.ade_ns * std::max<size_t>(G, 1) * es);
     L.iv = take((size_t)h.d.ny * sizeof(int4));
     L.goff = take(std::max<size_t>(G, 1) * 4);
     L.cptr = take((G + 1) * 4);
@@ -720,6 +720,8 @@ lee_status lee_bind(lee_instance *I, void *dev_ptr, size_t bytes, void *hip_stre
     }
     D.ade_kind = h.ade_kind;
     for (int k = 0; k < 4; ++k) D.ade[k] = h.ade[k];
+    D.ade_ns = h.ade_ns;
+    std::memcpy(D.ade_st, h.ade_st, sizeof(D.ade_st));
 
     // uploads
     if (h.d.precision == LEE_F32)
@@ -779,7 +781,8 @@ lee_status lee_init_fields(lee_instance *I)
     hipStream_t s = I->stream;
     const int prec = h.d.precision;
     for (int k = 0; k < 9; ++k) HIPCHK(launch_fill(prec, I->base + L.planes[k], plane_elems(h), s));
-    for (int k = 0; k < 3; ++k) HIPCHK(launch_fill(prec, I->base + L.psi[k], 2 * std::max<size_t>(h.gidx.size(), 1), s));
+    for (int k = 0; k < 3; ++k)
+        HIPCHK(launch_fill(prec, I->base + L.psi[k], (size_t)h.ade_ns * std::max<size_t>(h.gidx.size(), 1), s));
     HIPCHK(launch_fill_bytes(I->base + L.trace, std::max<size_t>((size_t)h.trace_cap * h.np * 3, 1) * 8, s));
     HIPCHK(launch_fill_bytes(I->base + L.dft, 2 * std::max(h.np, 1) * 8, s));
     HIPCHK(launch_fill_bytes(I->base + L.watch, 2 * std::max<size_t>((size_t)h.watch_cap, 1) * 8, s));
@@ -927,7 +930,7 @@ lee_status lee_set_fields(lee_instance *I, const double *p, const double *u, con
 lee_status lee_get_ade_states(lee_instance *I, double *out)
 {
     if (!I || !I->bound || !out) return fail(LEE_E_ARG, "instance not bound or null output");
-    const size_t n = 2 * I->host.gidx.size();
+    const size_t n = (size_t)I->host.ade_ns * I->host.gidx.size();
     if (!n) return LEE_OK;
     if (I->host.d.precision == LEE_F32) {
         std::vector<float> t(n);

@@ -16,7 +16,7 @@ namespace lee {
 // around the domain hold 0.
 struct DevInst {
     void *f[3][3];          // [register set A, B, C][p, u, v]; A holds q^n
-    void *psi[3];           // ADE states per register set, 2 per ghost
+    void *psi[3];           // ADE states per register set, ade_ns per ghost
     const int4 *iv;         // per row: fluid columns [x, y) and [z, w)
     const int *goff;        // ghost plane offsets (from the plane start)
     const int *cptr;        // cloud CSR pointers (G + 1)
@@ -41,6 +41,7 @@ struct DevInst {
     int nx, ny, pitch, G;
     int org;                // element offset of node (0, 0) in a plane
     int sponge_w, has_src, ade_kind;
+    int ade_ns;             // auxiliary states per ghost (2 for kinds 0-2)
     int src_ic, src_jc;     // source's nearest node
     int src_i0, src_i1, src_j0, src_j1;  // node box outside which the source underflows
     double x0, y0, h, dt;
@@ -54,6 +55,8 @@ struct DevInst {
     double sponge_inv;      // 1 / sponge_w
     double src_a, src_b, src_om, src_fx, src_fy;
     double ade[4];
+    double ade_st[8][5];    // kind 3: per state a, bn, bp, f, c of
+                            // dX_k = a X_k + bn X_{k+1} + bp X_{k-1} + f p_BP, u_n = sum c X_k
 };
 
 // Probe sampling carried by a launch: the (member, probe) pairs pw[0, np),

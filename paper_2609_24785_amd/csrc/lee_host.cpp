@@ -303,6 +303,7 @@ lee_status host_build(Host *H, const lee_impedance *z, int degree, lee_ghost_sum
 
     // ---- ADE coefficients (Sec. 2.5) ----
     H->ade_kind = 0;
+    H->ade_ns = 2;
     std::fill(H->ade, H->ade + 4, 0.0);
     std::fill(H->poles, H->poles + 4, 0.0);
     if (z->kind == LEE_Z_MSD) {
@@ -341,6 +342,50 @@ lee_status host_build(Host *H, const lee_impedance *z, int degree, lee_ghost_sum
         if (h / M > 2.0)
             return fail(LEE_E_ADE_STIFF, "wall coupling gain h/M > 2: the Neumann ghost value feeds p_BP "
                                          "back with gain ~ mu_0 h / M and the coupled stage is unstable");
+    } else if (z->kind == LEE_Z_POLES) {
+        // multi-pole admittance (Sec. 2.3, eqs. Yrational, ADEgeneral, unGeneral):
+        // real poles first (one state each), then each pair's two states
+        const int nr = z->n_real, npr = z->n_pair;
+        if (nr < 0 || npr < 0 || nr + 2 * npr < 1 || nr + 2 * npr > LEE_ADE_MAX_STATES)
+            return fail(LEE_E_ARG, "a multi-pole wall needs 1 to 8 auxiliary states");
+        std::vector<std::complex<double>> all;
+        double gain = 0.0;                         // lim s Y(s) = sum A_k + 2 sum B_k
+        int k = 0;
+        for (int i = 0; i < nr; ++i, ++k) {
+            const double lam = z->real_pole[i], A = z->real_res[i];
+            if (!std::isfinite(lam) || !std::isfinite(A)) return fail(LEE_E_ARG, "non-finite pole or residue");
+            if (!(lam < 0.0)) return fail(LEE_E_ARG, "a real pole must be negative");
+            double *st = H->ade_st[k];
+            st[0] = lam; st[1] = 0.0; st[2] = 0.0; st[3] = 1.0; st[4] = A;
+            all.emplace_back(lam, 0.0);
+            gain += A;
+        }
+        for (int i = 0; i < npr; ++i, k += 2) {
+            const double al = z->pair_alpha[i], be = z->pair_beta[i], B = z->pair_B[i], C = z->pair_C[i];
+            if (!std::isfinite(al) || !std::isfinite(be) || !std::isfinite(B) || !std::isfinite(C))
+                return fail(LEE_E_ARG, "non-finite pole or residue");
+            if (!(al < 0.0) || !(be > 0.0)) return fail(LEE_E_ARG, "a pole pair needs alpha < 0 and beta > 0");
+            double *s1 = H->ade_st[k], *s2 = H->ade_st[k + 1];
+            // dPsi1 = alpha Psi1 - beta Psi2 + p, dPsi2 = alpha Psi2 + beta Psi1,
+            // u_n += 2 B Psi1 - 2 C Psi2
+            s1[0] = al; s1[1] = -be; s1[2] = 0.0; s1[3] = 1.0; s1[4] = 2.0 * B;
+            s2[0] = al; s2[1] = 0.0; s2[2] = be; s2[3] = 0.0; s2[4] = -2.0 * C;
+            all.emplace_back(al, be);
+            all.emplace_back(al, -be);
+            gain += 2.0 * B;
+        }
+        H->ade_kind = 3;
+        H->ade_ns = k;
+        for (int i = 0; i < 2 && i < (int)all.size(); ++i) {
+            H->poles[2 * i] = all[i].real();
+            H->poles[2 * i + 1] = all[i].imag();
+        }
+        for (const auto &s : all)
+            if (rk4_abs(H->dt * s) > 1.0)
+                return fail(LEE_E_ADE_STIFF, "an ADE pole lies outside the RK4 stability region at this dt");
+        if (h * std::fabs(gain) > 2.0)
+            return fail(LEE_E_ADE_STIFF, "wall coupling gain h (sum A + 2 sum B) > 2: the Neumann ghost value "
+                                         "feeds p_BP back and the coupled stage is unstable");
     } else if (z->kind != LEE_Z_RIGID) {
         return fail(LEE_E_ARG, "impedance kind");
     }
@@ -451,6 +496,7 @@ lee_status host_build(Host *H, const lee_impedance *z, int degree, lee_ghost_sum
         out->fluid_nodes = H->fluid_nodes;
         out->ade_kind = H->ade_kind;
         for (int q = 0; q < 4; ++q) out->poles[q] = H->poles[q];
+        out->ade_states = H->ade_ns;
     }
     return LEE_OK;
 }

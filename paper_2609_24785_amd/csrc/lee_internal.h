@@ -35,6 +35,10 @@ struct Host {
     // ADE (Sec. 2.5): kind 0 rigid, 1 complex pair, 2 real poles
     int ade_kind = 0;
     double ade[4] = {0, 0, 0, 0};      // complex: a, b, 2B1, -2C1 ; real: l1, l2, A1, A2
+    // kind 3 (multi-pole, Sec. 2.3): ns states, state k advanced as
+    // dX_k = a_k X_k + bn_k X_{k+1} + bp_k X_{k-1} + f_k p_BP, u_n = sum c_k X_k
+    int ade_ns = 2;
+    double ade_st[8][5] = {};          // per state: a, bn, bp, f, c
     double poles[4] = {0, 0, 0, 0};
     // recorded probes
     int np = 0;

@@ -148,8 +148,12 @@ __device__ __forceinline__ void ghost_item(const DevInst *__restrict__ insts, co
     const long long step = step_at(I, slot);
     const bool active = takes(I, step);
     const VecT<T, 4> gdv = vld<T, 4>(gp<T>(I.gd) + 4 * (size_t)g);
-    const VecT<T, 2> psv = vld<T, 2>(gp<T>(I.psi[ib]) + 2 * (size_t)g);
-    const VecT<T, 2> psn = vld<T, 2>(gp<T>(I.psi[0]) + 2 * (size_t)g);
+    // two states per ghost (kinds 0-2) are loaded at once; a multi-pole wall
+    // reads its states later (the pair at offset 0 is in bounds and unused)
+    const bool two = I.ade_kind == 1 || I.ade_kind == 2;
+    const size_t po = two ? 2 * (size_t)g : 0;
+    const VecT<T, 2> psv = vld<T, 2>(gp<T>(I.psi[ib]) + po);
+    const VecT<T, 2> psn = vld<T, 2>(gp<T>(I.psi[0]) + po);
     const GLOBAL T *w4 = gp<T>(I.w4);
     const GLOBAL int *coff = gp<int>(I.coff);
     const int go = gp<int>(I.goff)[g];
@@ -202,6 +206,27 @@ __device__ __forceinline__ void ghost_item(const DevInst *__restrict__ insts, co
         Un = c1 * s1 + c2 * s2;
         Ud = c1 * d1 + c2 * d2;
     }
+    // multi-pole wall (Sec. 2.3, eqs. ADEgeneral, unGeneral): each state is
+    // coupled to at most its neighbours (a pair's two states)
+    T x[8], dx[8];
+    if (I.ade_kind == 3) {
+        const int ns = I.ade_ns;
+        const GLOBAL T *xin = gp<T>(I.psi[ib]) + (size_t)ns * g;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) x[k] = k < ns ? xin[k] : (T)0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const double *st = I.ade_st[k];
+            T d = (T)st[0] * x[k] + (T)st[3] * a0;
+            if (k + 1 < 8) d += (T)st[1] * x[k + 1];
+            if (k > 0) d += (T)st[2] * x[k - 1];
+            dx[k] = d;
+            if (k < ns) {
+                Un += (T)st[4] * x[k];
+                Ud += (T)st[4] * d;
+            }
+        }
+    }
     // steps 4-5: Neumann for p (dp/dn = +du_n/dt in the wall-to-fluid frame),
     // Dirichlet for u.n (= -u_n), free for u.t
     if (stage == 0 && g == I.watch_g && I.watch_cap > 0) {   // recording only
@@ -225,11 +250,19 @@ __device__ __forceinline__ void ghost_item(const DevInst *__restrict__ insts, co
         xg_put<T>(x + NW, ug, ep);
         xg_put<T>(x + 2 * NW, vg, ep);
     }
-    if (I.ade_kind != 0) {
+    if (two) {
         GLOBAL T *psi_out = gp<T>(I.psi[ob]);
         const T adt = (T)I.alpha_dt[stage];
         psi_out[2 * g] = psn.v[0] + adt * d1;
         psi_out[2 * g + 1] = psn.v[1] + adt * d2;
+    } else if (I.ade_kind == 3) {
+        const int ns = I.ade_ns;
+        GLOBAL T *xout = gp<T>(I.psi[ob]) + (size_t)ns * g;
+        const GLOBAL T *xn = gp<T>(I.psi[0]) + (size_t)ns * g;
+        const T adt = (T)I.alpha_dt[stage];
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            if (k < ns) xout[k] = xn[k] + adt * dx[k];
     }
 }
 

@@ -68,6 +68,15 @@ def impedance_desc(imp) -> ImpedanceDesc:
     z = ImpedanceDesc()
     if imp.kind == "rigid":
         z.kind = _lib.Z_RIGID
+    elif imp.kind == "poles":
+        z.kind = _lib.Z_POLES
+        if len(imp.real) > _lib.ADE_MAX_STATES or len(imp.pairs) > _lib.ADE_MAX_STATES // 2:
+            raise LeeError(-1, "impedance_desc", "too many pole terms")
+        z.n_real, z.n_pair = len(imp.real), len(imp.pairs)
+        for k, (lam, a) in enumerate(imp.real):
+            z.real_pole[k], z.real_res[k] = lam, a
+        for k, (al, be, b, c) in enumerate(imp.pairs):
+            z.pair_alpha[k], z.pair_beta[k], z.pair_B[k], z.pair_C[k] = al, be, b, c
     else:
         z.kind = _lib.Z_MSD
         z.R, z.M, z.K = imp.R, imp.M, imp.K
@@ -163,9 +172,11 @@ class Instance:
         check(self.lib.lee_set_fields(self._h, *(_ptr(a) for a in arrs)), "lee_set_fields")
 
     def ade_states(self):
-        out = np.zeros(2 * self.summary.G)
+        """Auxiliary states after the last full step, one row per ghost."""
+        ns = max(int(self.summary.ade_states), 1)
+        out = np.zeros(ns * self.summary.G)
         check(self.lib.lee_get_ade_states(self._h, _ptr(out)), "lee_get_ade_states")
-        return out.reshape(-1, 2)
+        return out.reshape(-1, ns)
 
     def probe(self, xy: Sequence[Sequence[float]]):
         xy = np.ascontiguousarray(np.asarray(xy, dtype=np.float64).reshape(-1, 2))

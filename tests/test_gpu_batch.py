@@ -30,6 +30,8 @@ def _members():
         lc.small_cylinder(128, 20, impedance=lc.Impedance("rigid")),
         lc.flat_wall_201(20),
         lc.small_cylinder(224, 20).replace(ny=97, y0=-3.5, probes=((2.5, 0.0),)),
+        lc.small_cylinder(112, 20, impedance=lc.Impedance("poles", real=((-0.5, 0.3),),
+                                                          pairs=((-0.3, 0.8, 0.2, 0.05),))),
     ]
 
 

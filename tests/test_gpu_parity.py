@@ -88,6 +88,26 @@ def test_small_cylinder_matches_oracle(prec, tol):
     _compare(lc.small_cylinder(96, 60), 60, prec, tol)
 
 
+MULTIPOLE = lc.Impedance("poles", real=((-0.5, 0.3),),
+                         pairs=((-0.3, 2 * math.pi / 8.0, 0.2, 0.05), (-1.5, 1.2, 0.1, -0.04)))
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-9), ("f32", 1e-4)])
+def test_multipole_wall_matches_oracle(prec, tol):
+    """A broadband wall in the multi-pole form of Sec. 2.3 (a relaxation term
+    and two resonances, five auxiliary states per ghost), fused and
+    two-launch; FP64 also compares the auxiliary states."""
+    case = lc.small_cylinder(96, 60).replace(impedance=MULTIPOLE)
+    for fused in (1, 0):
+        t = dict(kind="tile", cols=64, rows=16 if prec == "f32" else 8, fused=fused)
+        inst, ora = _compare(case, 60, prec, tol, tiling=t)
+        got = inst.ade_states()
+        assert got.shape == (len(ora.gidx), 5)
+        want = ora.psi.reshape(-1, 5)
+        assert np.abs(got - want).max() <= tol * np.abs(want).max()
+        inst.close()
+
+
 @pytest.mark.parametrize("prec,tol", [("f64", 1e-9), ("f32", 1e-4)])
 def test_paper_scheme_matches_oracle(prec, tol):
     """The paper's own scheme: 7-point DRP stencils (H = 3, three ghost

@@ -148,3 +148,28 @@ def test_watched_ghost_choice_matches_oracle():
         from paper_2609_24785_amd.lee import Instance
         inst = Instance(case, "f32", bind=False, watch=(xy[0], xy[1], 10))
         assert inst.watch_g == OracleSolver(case).set_watch(*xy)
+
+
+def test_multipole_wall_set_up_and_rejections():
+    """A multi-pole wall (Sec. 2.3): state count and poles in the summary,
+    and the set-up checks of lee_build_ghosts."""
+    from paper_2609_24785_amd._lib import LeeError
+    base = lc.small_cylinder(96)
+    imp = lc.Impedance("poles", real=((-0.5, 0.3),), pairs=((-0.3, 0.8, 0.2, 0.05), (-1.5, 1.2, 0.1, -0.04)))
+    inst = _host_instance(base.replace(impedance=imp))
+    s = inst.summary
+    assert s.ade_kind == 3 and s.ade_states == 5
+    assert list(s.poles) == [-0.5, 0.0, -0.3, 0.8]
+    assert _host_instance(base).summary.ade_states == 2
+    bad = [
+        (lc.Impedance("poles", real=((0.2, 1.0),)), -1),                       # right half-plane
+        (lc.Impedance("poles", pairs=((-1.0, -2.0, 0.1, 0.0),)), -1),          # beta <= 0
+        (lc.Impedance("poles", real=((-1.0, 0.1),) * 3, pairs=((-1.0, 1.0, 0.01, 0.0),) * 3), -1),  # 9 states
+        (lc.Impedance("poles"), -1),                                           # no term
+        (lc.Impedance("poles", real=((-1e4, 1e-3),)), -4),                     # outside the RK4 region
+        (lc.Impedance("poles", real=((-1.0, 20.0),)), -4),                     # coupling gain h * 20 > 2
+    ]
+    for z, status in bad:
+        with pytest.raises(LeeError) as e:
+            _host_instance(base.replace(impedance=z))
+        assert e.value.status == status, z
