@@ -25,7 +25,8 @@ benchmark workload.
 
 Other modes: --extras (a second JSON line: the flat-wall case against the
 oracle, the 4096^2 monopole case, the benchmark workload with the paper's
-7-point stencils and no filter, and the batch of 256 uneven instances),
+7-point stencils and no filter and with a multi-pole wall, and the batch of
+256 uneven instances),
 --serve (the served request stream: Poisson arrivals, continuous batching,
 admission by HBM budget; throughput and p50/p99 latency),
 --profile-run (a short fixed sequence for rocprofv3), and
@@ -84,7 +85,7 @@ def _kernel_name(tiling: dict, prec: str) -> str:
     t = "float, 4" if prec == "f32" else "double, 2"
     if tiling["kind"] == "tile":
         k = "k_stage" if tiling.get("fused") else "k_tile"
-        extra = ", 16, true" if tiling.get("fused") else ""     # one instance per launch
+        extra = ", 16, 1" if tiling.get("fused") else ""        # ghost-fill variant: one instance
         return f"lee::{k}<{t}, true, {tiling['cols']}, {tiling['rows']}{extra}>"
     return f"lee::k_sweep<{t.split(',')[0]}, {tiling['vec']}, true, {tiling['waves']}>"
 
@@ -345,6 +346,25 @@ def extras(args):
             pres[prec]["rel_l2_vs_oracle"] = _max_rel_l2(rp["inst"].fields(), s.fields(), s.fluid)
         rp["inst"].close()
     out["cylinder_pulse_1024_7pt"] = dict(steps=pm_steps, unit=UNIT, **pres)
+
+    # the benchmark workload with a broadband multi-pole wall (Sec. 2.3): two
+    # relaxation terms and three resonances, eight auxiliary states per ghost
+    print("[extras] cylinder pulse 1024^2, multi-pole wall", file=sys.stderr, flush=True)
+    mp = lc.cylinder_pulse_1024(pm_steps).replace(impedance=lc.Impedance(
+        "poles", real=((-5.0, 8.0), (-40.0, 4.0)),
+        pairs=((-12.5, 18.5, 12.0, -8.0), (-3.0, 30.0, 2.0, 1.0), (-20.0, 60.0, 1.5, 0.5))))
+    mres = {}
+    for prec in ("f32", "f64"):
+        ch = tune.tune_case(mp, prec, cache)
+        rp = _timed(mp, prec, pm_steps, 0, ch)
+        mres[prec] = {"value": rp["value"], "ms_per_step": 1000.0 * rp["wall"] / rp["steps"],
+                      "tiling": ch["tiling"]}
+        if prec == "f64":
+            s = osv.OracleSolver(mp)
+            s.run(pm_steps)
+            mres[prec]["rel_l2_vs_oracle"] = _max_rel_l2(rp["inst"].fields(), s.fields(), s.fluid)
+        rp["inst"].close()
+    out["cylinder_pulse_1024_multipole"] = dict(steps=pm_steps, unit=UNIT, ade_states=8, **mres)
 
     print(f"[extras] batch of {args.batch_size} uneven instances", file=sys.stderr, flush=True)
     gen = lc.batch_candidates(steps=args.batch_steps)

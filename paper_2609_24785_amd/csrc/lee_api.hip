@@ -408,22 +408,22 @@ bool fused(const lee_tiling &t) { return t.kind == LEE_SWEEP_TILE && t.fused; }
 // The ghost fill and sweep of one stage: one fused launch, or two launches.
 // Events, when given, bracket the ghost launch (g0, g1) and the sweep or
 // fused launch (s0, s1).
-hipError_t stage_launches(int prec, bool filt, const lee_tiling &t, const DevInst *insts, int ninst,
+hipError_t stage_launches(int prec, bool filt, const lee_tiling &t, const DevInst *insts, int ninst, bool poles,
                           const int4 *work1, int nwork1, const int2 *aux, const int2 *patch, int tile0,
                           const int4 *work2, int nwork2, int *sync, int stage, int slot, ProbePass pp, int blocks,
                           hipStream_t s, hipEvent_t *ev = nullptr)
 {
     hipError_t e = hipSuccess;
     if (ev) hipEventRecord(ev[0], s);
-    if (!fused(t)) e = launch_ghost(prec, insts, ninst, work2, nwork2, stage, slot, pp, s);
+    if (!fused(t)) e = launch_ghost(prec, insts, ninst, poles, work2, nwork2, stage, slot, pp, s);
     if (ev) {
         hipEventRecord(ev[1], s);
         hipEventRecord(ev[2], s);
     }
     if (e != hipSuccess) return e;
     if (fused(t))
-        e = launch_stage(prec, filt, t.cols, t.rows, insts, ninst, work1, nwork1, aux, patch, tile0, work2, nwork2,
-                         stage, slot, sync, SPIN_LIMIT, pp, s);
+        e = launch_stage(prec, filt, t.cols, t.rows, insts, ninst, poles, work1, nwork1, aux, patch, tile0, work2,
+                         nwork2, stage, slot, sync, SPIN_LIMIT, pp, s);
     else
         e = sweep(prec, filt, t, insts, work1, nwork1, stage, slot, blocks, s);
     if (ev) hipEventRecord(ev[3], s);
@@ -443,7 +443,8 @@ ProbePass probe_pass(const int2 *pw, int np, int stage, int slot)
 hipError_t issue_stage(lee_instance *I, int stage, int slot)
 {
     const int prec = I->host.d.precision;
-    return stage_launches(prec, I->host.d.filter_sigma > 0.0, I->tl, I->d_inst, 1, I->d_work1, I->nwork1, I->d_aux,
+    return stage_launches(prec, I->host.d.filter_sigma > 0.0, I->tl, I->d_inst, 1, I->host.ade_kind == 3,
+                          I->d_work1, I->nwork1, I->d_aux,
                           I->d_patch, I->tile0, I->d_work2, I->nwork2, I->d_sync, stage, slot,
                           probe_pass(I->d_pwork, I->host.np, stage, slot), 0, I->stream);
 }
@@ -1036,7 +1037,8 @@ lee_status lee_time_kernels(lee_instance *I, int64_t n, double *sweep_us, double
     auto ghosts = [&]() -> hipError_t {
         hipError_t e = hipSuccess;
         for (int64_t k = 0; k < 4 * n && e == hipSuccess; ++k)
-            e = launch_ghost(prec, I->d_inst, 1, I->d_work2, I->nwork2, (int)(k & 3), 0, ProbePass{nullptr, 0, 0},
+            e = launch_ghost(prec, I->d_inst, 1, I->host.ade_kind == 3, I->d_work2, I->nwork2, (int)(k & 3), 0,
+                             ProbePass{nullptr, 0, 0},
                              I->stream);
         return e;
     };
@@ -1044,7 +1046,8 @@ lee_status lee_time_kernels(lee_instance *I, int64_t n, double *sweep_us, double
         hipError_t e = hipSuccess;
         for (int64_t k = 0; k < 4 * n && e == hipSuccess; ++k) {
             const int l = (int)(k & 3);
-            e = fused(I->tl) ? launch_stage(prec, filt, I->tl.cols, I->tl.rows, I->d_inst, 1, I->d_work1, I->nwork1,
+            e = fused(I->tl) ? launch_stage(prec, filt, I->tl.cols, I->tl.rows, I->d_inst, 1, I->host.ade_kind == 3,
+                                            I->d_work1, I->nwork1,
                                             I->d_aux, I->d_patch, I->tile0, I->d_work2, I->nwork2, l, 0, I->d_sync,
                                             SPIN_LIMIT, ProbePass{nullptr, 0, 0}, I->stream)
                              : sweep(prec, filt, I->tl, I->d_inst, I->d_work1, I->nwork1, l, 0, 0, I->stream);
@@ -1113,6 +1116,7 @@ struct lee_batch {
     std::vector<int2> up_pwork;
     std::vector<long long> up_budget;      // stop steps being uploaded
     long long *d_idle = nullptr;           // step and stop counters of the idle table entries (0, 0)
+    bool poles = false;                    // some member has a multi-pole wall
     DevInst idle{};                        // table entry past the members
     StepGraphs graphs;
 };
@@ -1154,7 +1158,7 @@ hipError_t batch_issue_stage(lee_batch *B, int stage, int slot)
     int blocks = 0;
     const int per = B->tl.kind == LEE_SWEEP_MARCH ? B->tl.waves : 1;
     if (B->pblocks > 0) blocks = std::min(B->pblocks, (B->nwork1 + per - 1) / per);
-    return stage_launches(B->prec, B->filt, B->tl, B->d_table, 0, B->d_work1, B->nwork1,
+    return stage_launches(B->prec, B->filt, B->tl, B->d_table, 0, B->poles, B->d_work1, B->nwork1,
                           B->d_aux, B->d_patch,
                           B->tile0, B->d_work2, B->nwork2, B->d_sync, stage, slot,
                           probe_pass(B->d_pwork, B->npwork, stage, slot), blocks, B->stream);
@@ -1231,6 +1235,10 @@ lee_status batch_rebuild(lee_batch *B, bool drop = false)
     HIPCHK(grow(B->d_patch, B->patch_cap, B->up_patch.size(), B->stream));
     const void *after[6] = {B->d_table, B->d_work1, B->d_work2, B->d_aux, B->d_patch, B->d_pwork};
     for (int k = 0; k < 6; ++k) drop = drop || before[k] != after[k];
+    bool poles = false;
+    for (const auto *I : B->members) poles = poles || I->host.ade_kind == 3;
+    drop = drop || poles != B->poles;               // another ghost-fill variant
+    B->poles = poles;
     drop = drop || B->tile0 != tile0_before;
     if (drop) batch_drop_graph(B);             // after a trim the pointers have changed as well
     B->up_table.resize(B->table_cap, B->idle);
@@ -1416,7 +1424,7 @@ lee_status lee_batch_time_kernels(lee_batch *B, int64_t n, double *sweep_us, dou
     auto ghosts = [&]() -> hipError_t {
         hipError_t e = hipSuccess;
         for (int64_t k = 0; k < 4 * n && e == hipSuccess; ++k)
-            e = launch_ghost(B->prec, B->d_table, 0, B->d_work2, B->nwork2, (int)(k & 3), 0,
+            e = launch_ghost(B->prec, B->d_table, 0, B->poles, B->d_work2, B->nwork2, (int)(k & 3), 0,
                              ProbePass{nullptr, 0, 0}, B->stream);
         return e;
     };
@@ -1424,7 +1432,8 @@ lee_status lee_batch_time_kernels(lee_batch *B, int64_t n, double *sweep_us, dou
         hipError_t e = hipSuccess;
         for (int64_t k = 0; k < 4 * n && e == hipSuccess; ++k) {
             const int l = (int)(k & 3);
-            e = fused(B->tl) ? launch_stage(B->prec, B->filt, B->tl.cols, B->tl.rows, B->d_table, 0, B->d_work1,
+            e = fused(B->tl) ? launch_stage(B->prec, B->filt, B->tl.cols, B->tl.rows, B->d_table, 0, B->poles,
+                                            B->d_work1,
                                             B->nwork1, B->d_aux, B->d_patch, B->tile0, B->d_work2, B->nwork2, l, 0,
                                             B->d_sync, SPIN_LIMIT, ProbePass{nullptr, 0, 0}, B->stream)
                              : sweep(B->prec, B->filt, B->tl, B->d_table, B->d_work1, B->nwork1, l, 0, blocks,

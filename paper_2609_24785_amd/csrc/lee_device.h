@@ -85,17 +85,21 @@ hipError_t launch_tile(int prec, bool filt, int tx, int ty, const DevInst *insts
 // runs in extra workgroups after the tiles.
 // ninst: 1 for a single instance (the ghost fill reads its record with
 // scalar loads), any other value for a table indexed by the work items.
+// poles: some instance of the launch has a multi-pole wall (ADE kind 3);
+// only then is the ghost fill's multi-pole code compiled in.
 // Work items with instance -1 (ghost and sweep lists) are idle, so a batch
 // can pad its lists to fixed capacities.
-hipError_t launch_stage(int prec, bool filt, int tx, int ty, const DevInst *insts, int ninst, const int4 *work1,
-                        int nwork1, const int2 *aux, const int2 *patch, int tile0, const int4 *work2, int nwork2,
-                        int stage, int slot, int *sync, int spin_limit, ProbePass pp, hipStream_t s);
+hipError_t launch_stage(int prec, bool filt, int tx, int ty, const DevInst *insts, int ninst, bool poles,
+                        const int4 *work1, int nwork1, const int2 *aux, const int2 *patch, int tile0,
+                        const int4 *work2, int nwork2, int stage, int slot, int *sync, int spin_limit, ProbePass pp,
+                        hipStream_t s);
 constexpr int TILE_DEP_BIT = 1 << 30;
 constexpr int SYNC_INTS = 8;
 constexpr int SPIN_LIMIT = 1 << 20;             // polls before a ghost wait gives up (about a second)
-// The ghost fill of a stage, with the probe pass in extra workgroups.
-hipError_t launch_ghost(int prec, const DevInst *insts, int ninst, const int4 *work, int nwork, int stage, int slot,
-                        ProbePass pp, hipStream_t s);
+// The ghost fill of a stage, with the probe pass in extra workgroups (ninst,
+// poles and work as for launch_stage).
+hipError_t launch_ghost(int prec, const DevInst *insts, int ninst, bool poles, const int4 *work, int nwork,
+                        int stage, int slot, ProbePass pp, hipStream_t s);
 hipError_t launch_probe(int prec, const DevInst *insts, ProbePass pp, hipStream_t s);
 // After a run of n steps: *step += n for each of the ninst table entries,
 // held at *stop.

@@ -125,15 +125,22 @@ __device__ __forceinline__ void xg_put(GLOBAL unsigned long long *w, T v, unsign
     }
 }
 
+// Variants of the ghost fill (flags): GV_ONE, a single instance instead of a
+// table of them; GV_POLES, some wall of the launch is multi-pole (without it
+// every wall is rigid or mass-spring-damper, two auxiliary states per ghost).
+constexpr int GV_TABLE = 0, GV_ONE = 1, GV_POLES = 2;
+
 // One ghost per GL-lane group (gid); sub is the lane within the group.  With
 // PUB (fused launches) the ghost values also go to the exchange words I.xg.
-// With ONE the launch has a single instance: its record is read with scalar
-// loads at once, instead of after the work item names it, which takes one
-// dependent round trip off the ghost fill.
-template <typename T, int GL, bool PUB = false, bool ONE = false>
+// With GV_ONE the launch has a single instance: its record is read with
+// scalar loads at once, instead of after the work item names it, which takes
+// one dependent round trip off the ghost fill.  Only GV_POLES carries the
+// multi-pole code, so the other variants keep their registers and schedule.
+template <typename T, int GL, bool PUB = false, int GV = GV_TABLE>
 __device__ __forceinline__ void ghost_item(const DevInst *__restrict__ insts, const int4 *__restrict__ work,
                                            int nwork, int gid, int sub, int stage, int slot)
 {
+    constexpr bool ONE = (GV & GV_ONE) != 0, MP = (GV & GV_POLES) != 0;
     if (gid >= nwork) return;                       // whole GL-lane groups leave together
     const int4 wk = work[gid];                      // instance, ghost, cloud entries [z, w)
     if (!ONE && wk.x < 0) return;                   // an idle item of a padded list
@@ -148,12 +155,23 @@ __device__ __forceinline__ void ghost_item(const DevInst *__restrict__ insts, co
     const long long step = step_at(I, slot);
     const bool active = takes(I, step);
     const VecT<T, 4> gdv = vld<T, 4>(gp<T>(I.gd) + 4 * (size_t)g);
-    // two states per ghost (kinds 0-2) are loaded at once; a multi-pole wall
-    // reads its states later (the pair at offset 0 is in bounds and unused)
-    const bool two = I.ade_kind == 1 || I.ade_kind == 2;
-    const size_t po = two ? 2 * (size_t)g : 0;
+    // two states per ghost (kinds 0-2) as one pair each; a multi-pole wall's
+    // ns states separately (then the pair at offset 0 is in bounds and unused)
+    const bool two = MP ? (I.ade_kind == 1 || I.ade_kind == 2) : I.ade_kind != 0;
+    const size_t po = (!MP || two) ? 2 * (size_t)g : 0;
     const VecT<T, 2> psv = vld<T, 2>(gp<T>(I.psi[ib]) + po);
     const VecT<T, 2> psn = vld<T, 2>(gp<T>(I.psi[0]) + po);
+    T x[8], xn[8];
+    if (MP && I.ade_kind == 3) {
+        const int ns = I.ade_ns;
+        const GLOBAL T *xin = gp<T>(I.psi[ib]) + (size_t)ns * g;
+        const GLOBAL T *xq = gp<T>(I.psi[0]) + (size_t)ns * g;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            x[k] = k < ns ? xin[k] : (T)0;
+            xn[k] = k < ns ? xq[k] : (T)0;
+        }
+    }
     const GLOBAL T *w4 = gp<T>(I.w4);
     const GLOBAL int *coff = gp<int>(I.coff);
     const int go = gp<int>(I.goff)[g];
@@ -208,12 +226,9 @@ __device__ __forceinline__ void ghost_item(const DevInst *__restrict__ insts, co
     }
     // multi-pole wall (Sec. 2.3, eqs. ADEgeneral, unGeneral): each state is
     // coupled to at most its neighbours (a pair's two states)
-    T x[8], dx[8];
-    if (I.ade_kind == 3) {
+    T dx[8];
+    if (MP && I.ade_kind == 3) {
         const int ns = I.ade_ns;
-        const GLOBAL T *xin = gp<T>(I.psi[ib]) + (size_t)ns * g;
-#pragma unroll
-        for (int k = 0; k < 8; ++k) x[k] = k < ns ? xin[k] : (T)0;
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             const double *st = I.ade_st[k];
@@ -255,10 +270,9 @@ __device__ __forceinline__ void ghost_item(const DevInst *__restrict__ insts, co
         const T adt = (T)I.alpha_dt[stage];
         psi_out[2 * g] = psn.v[0] + adt * d1;
         psi_out[2 * g + 1] = psn.v[1] + adt * d2;
-    } else if (I.ade_kind == 3) {
+    } else if (MP && I.ade_kind == 3) {
         const int ns = I.ade_ns;
         GLOBAL T *xout = gp<T>(I.psi[ob]) + (size_t)ns * g;
-        const GLOBAL T *xn = gp<T>(I.psi[0]) + (size_t)ns * g;
         const T adt = (T)I.alpha_dt[stage];
 #pragma unroll
         for (int k = 0; k < 8; ++k)
@@ -314,7 +328,7 @@ __device__ __forceinline__ void probe_item(const DevInst *__restrict__ insts, co
 
 // Ghost fill of a stage (16 ghosts per workgroup), then the probe pass in
 // the workgroups after them.
-template <typename T, int GL, bool ONE>
+template <typename T, int GL, int GV>
 __global__ __launch_bounds__(256) void k_ghost(const DevInst *__restrict__ insts,
                                                const int4 *__restrict__ work, int nwork, int stage, int slot,
                                                ProbePass pp)
@@ -322,7 +336,7 @@ __global__ __launch_bounds__(256) void k_ghost(const DevInst *__restrict__ insts
     const int nbg = (nwork * GL + 255) / 256;
     const int b = (int)blockIdx.x;
     if (b < nbg)
-        ghost_item<T, GL, false, ONE>(insts, work, nwork, (int)((b * blockDim.x + threadIdx.x) / GL),
+        ghost_item<T, GL, false, GV>(insts, work, nwork, (int)((b * blockDim.x + threadIdx.x) / GL),
                                       (int)(threadIdx.x % GL), stage, slot);
     else
         probe_item<T>(insts, pp, (b - nbg) * 16 + (int)threadIdx.x / 16, (int)threadIdx.x % 16);
@@ -1024,7 +1038,7 @@ __global__ __launch_bounds__(256) void k_tile(const DevInst *__restrict__ insts,
 // each wait is bounded by spin_limit polls all the same, and a wait that runs
 // out raises the error flag sync[4] instead of hanging.  The probe pass, if
 // any, runs in the workgroups after the tiles (tend and up).
-template <typename T, int VEC, bool FILT, int TX, int TY, int GL, bool ONE>
+template <typename T, int VEC, bool FILT, int TX, int TY, int GL, int GV>
 __global__ __launch_bounds__(256) void k_stage(const DevInst *__restrict__ insts, const int4 *__restrict__ work1,
                                                int nwork1, const int4 *__restrict__ work2, int nwork2, int ncar,
                                                int tile0, int tend, int stage, int slot, int *sync, int spin_limit,
@@ -1038,7 +1052,7 @@ __global__ __launch_bounds__(256) void k_stage(const DevInst *__restrict__ insts
         return;
     }
     if (w < ncar)
-        ghost_item<T, GL, true, ONE>(insts, work2, nwork2, w * (256 / GL) + tid / GL, tid % GL, stage, slot);
+        ghost_item<T, GL, true, GV>(insts, work2, nwork2, w * (256 / GL) + tid / GL, tid % GL, stage, slot);
     const int k = w - tile0;
     if (k < 0 || k >= nwork1) return;
     int4 wk = work1[k];
@@ -1152,7 +1166,7 @@ struct FuseArgs {
     const int2 *patch;
     int tile0;
     ProbePass pp;
-    bool one;                                    // a single instance
+    int gv;                                      // ghost-fill variant (GV_*)
 };
 
 template <typename T, int VEC, bool FILT, int TX, int TY>
@@ -1168,13 +1182,21 @@ static hipError_t launch_tile_t(const DevInst *insts, const int4 *work, int nwor
         const int ncar = (fa->nwork2 * GHOST_LANES + 255) / 256;
         const int tend = std::max(ncar, fa->tile0 + nwork);
         const int nbp = (fa->pp.np + 15) / 16;
-        if (fa->one)
-            hipLaunchKernelGGL((k_stage<T, VEC, FILT, TX, TY, GHOST_LANES, true>), dim3(tend + nbp), dim3(256), 0, s,
-                               insts, work, nwork, fa->work2, fa->nwork2, ncar, fa->tile0, tend, stage, slot,
+        if (fa->gv == GV_ONE)
+            hipLaunchKernelGGL((k_stage<T, VEC, FILT, TX, TY, GHOST_LANES, GV_ONE>), dim3(tend + nbp), dim3(256), 0,
+                               s, insts, work, nwork, fa->work2, fa->nwork2, ncar, fa->tile0, tend, stage, slot,
+                               fa->sync, fa->spin_limit, fa->aux, fa->patch, fa->pp);
+        else if (fa->gv == (GV_ONE | GV_POLES))
+            hipLaunchKernelGGL((k_stage<T, VEC, FILT, TX, TY, GHOST_LANES, GV_ONE | GV_POLES>), dim3(tend + nbp),
+                               dim3(256), 0, s, insts, work, nwork, fa->work2, fa->nwork2, ncar, fa->tile0, tend,
+                               stage, slot, fa->sync, fa->spin_limit, fa->aux, fa->patch, fa->pp);
+        else if (fa->gv == GV_POLES)
+            hipLaunchKernelGGL((k_stage<T, VEC, FILT, TX, TY, GHOST_LANES, GV_POLES>), dim3(tend + nbp), dim3(256),
+                               0, s, insts, work, nwork, fa->work2, fa->nwork2, ncar, fa->tile0, tend, stage, slot,
                                fa->sync, fa->spin_limit, fa->aux, fa->patch, fa->pp);
         else
-            hipLaunchKernelGGL((k_stage<T, VEC, FILT, TX, TY, GHOST_LANES, false>), dim3(tend + nbp), dim3(256), 0,
-                               s, insts, work, nwork, fa->work2, fa->nwork2, ncar, fa->tile0, tend, stage, slot,
+            hipLaunchKernelGGL((k_stage<T, VEC, FILT, TX, TY, GHOST_LANES, GV_TABLE>), dim3(tend + nbp), dim3(256),
+                               0, s, insts, work, nwork, fa->work2, fa->nwork2, ncar, fa->tile0, tend, stage, slot,
                                fa->sync, fa->spin_limit, fa->aux, fa->patch, fa->pp);
     }
     return hipGetLastError();
@@ -1228,16 +1250,19 @@ hipError_t launch_tile(int prec, bool filt, int tx, int ty, const DevInst *insts
                 : launch_tile_v<double, 2, false>(tx, ty, insts, work, nwork, stage, slot, nullptr, s);
 }
 
-hipError_t launch_stage(int prec, bool filt, int tx, int ty, const DevInst *insts, int ninst, const int4 *work1,
-                        int nwork1, const int2 *aux, const int2 *patch, int tile0, const int4 *work2, int nwork2,
-                        int stage, int slot, int *sync, int spin_limit, ProbePass pp, hipStream_t s)
+static int ghost_variant(int ninst, bool poles) { return (ninst == 1 ? GV_ONE : GV_TABLE) | (poles ? GV_POLES : 0); }
+
+hipError_t launch_stage(int prec, bool filt, int tx, int ty, const DevInst *insts, int ninst, bool poles,
+                        const int4 *work1, int nwork1, const int2 *aux, const int2 *patch, int tile0,
+                        const int4 *work2, int nwork2, int stage, int slot, int *sync, int spin_limit, ProbePass pp,
+                        hipStream_t s)
 {
     if (nwork2 <= 0) {                           // no ghosts: the plain sweep, then the probes
         hipError_t e = launch_tile(prec, filt, tx, ty, insts, work1, nwork1, stage, slot, 0, s);
         if (e == hipSuccess && pp.np > 0) e = launch_probe(prec, insts, pp, s);
         return e;
     }
-    const FuseArgs fa{work2, nwork2, sync, spin_limit, aux, patch, tile0, pp, ninst == 1};
+    const FuseArgs fa{work2, nwork2, sync, spin_limit, aux, patch, tile0, pp, ghost_variant(ninst, poles)};
     if (prec == LEE_F32)
         return filt ? launch_tile_v<float, 4, true>(tx, ty, insts, work1, nwork1, stage, slot, &fa, s)
                     : launch_tile_v<float, 4, false>(tx, ty, insts, work1, nwork1, stage, slot, &fa, s);
@@ -1246,25 +1271,32 @@ hipError_t launch_stage(int prec, bool filt, int tx, int ty, const DevInst *inst
 }
 
 template <typename T>
-static void launch_ghost_t(bool one, const DevInst *insts, const int4 *work, int nwork, int stage, int slot,
+static void launch_ghost_t(int gv, const DevInst *insts, const int4 *work, int nwork, int stage, int slot,
                            ProbePass pp, int nb, hipStream_t s)
 {
     constexpr int GL = GHOST_LANES;
-    if (one)
-        hipLaunchKernelGGL((k_ghost<T, GL, true>), dim3(nb), dim3(256), 0, s, insts, work, nwork, stage, slot, pp);
+    if (gv == GV_ONE)
+        hipLaunchKernelGGL((k_ghost<T, GL, GV_ONE>), dim3(nb), dim3(256), 0, s, insts, work, nwork, stage, slot, pp);
+    else if (gv == (GV_ONE | GV_POLES))
+        hipLaunchKernelGGL((k_ghost<T, GL, GV_ONE | GV_POLES>), dim3(nb), dim3(256), 0, s, insts, work, nwork, stage,
+                           slot, pp);
+    else if (gv == GV_POLES)
+        hipLaunchKernelGGL((k_ghost<T, GL, GV_POLES>), dim3(nb), dim3(256), 0, s, insts, work, nwork, stage, slot,
+                           pp);
     else
-        hipLaunchKernelGGL((k_ghost<T, GL, false>), dim3(nb), dim3(256), 0, s, insts, work, nwork, stage, slot, pp);
+        hipLaunchKernelGGL((k_ghost<T, GL, GV_TABLE>), dim3(nb), dim3(256), 0, s, insts, work, nwork, stage, slot,
+                           pp);
 }
 
-hipError_t launch_ghost(int prec, const DevInst *insts, int ninst, const int4 *work, int nwork, int stage, int slot,
-                        ProbePass pp, hipStream_t s)
+hipError_t launch_ghost(int prec, const DevInst *insts, int ninst, bool poles, const int4 *work, int nwork,
+                        int stage, int slot, ProbePass pp, hipStream_t s)
 {
     const int nb = (std::max(nwork, 0) * GHOST_LANES + 255) / 256 + (pp.np + 15) / 16;
     if (nb == 0) return hipSuccess;
     if (prec == LEE_F32)
-        launch_ghost_t<float>(ninst == 1, insts, work, std::max(nwork, 0), stage, slot, pp, nb, s);
+        launch_ghost_t<float>(ghost_variant(ninst, poles), insts, work, std::max(nwork, 0), stage, slot, pp, nb, s);
     else
-        launch_ghost_t<double>(ninst == 1, insts, work, std::max(nwork, 0), stage, slot, pp, nb, s);
+        launch_ghost_t<double>(ghost_variant(ninst, poles), insts, work, std::max(nwork, 0), stage, slot, pp, nb, s);
     return hipGetLastError();
 }
 
