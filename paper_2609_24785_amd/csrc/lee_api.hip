@@ -231,10 +231,11 @@ int order_work(const std::vector<int4> &items, const std::vector<std::vector<int
     return tile0;
 }
 
-// Workgroups that carry the ghost fill of a fused launch (16 ghosts each).
+// Workgroups that carry the ghost fill of a fused launch (8 ghosts each: 32
+// lanes per ghost).
 int carriers_for(const lee_tiling &t, size_t nwork2)
 {
-    return (t.kind == LEE_SWEEP_TILE && t.fused) ? (int)((nwork2 + 15) / 16) : 0;
+    return (t.kind == LEE_SWEEP_TILE && t.fused) ? (int)((nwork2 + 7) / 8) : 0;
 }
 
 bool tiling_valid(int prec, const lee_tiling &t)

@@ -75,8 +75,8 @@ hipError_t launch_sweep(int prec, int vec, bool filt, int waves, const DevInst *
 bool tile_shape_supported(int prec, int tx, int ty);
 hipError_t launch_tile(int prec, bool filt, int tx, int ty, const DevInst *insts, const int4 *work, int nwork,
                        int stage, int slot, int blocks, hipStream_t s);
-// One launch for a stage with the tile sweep: the first ceil(nwork2 / 16)
-// workgroups fill 16 ghosts each, tile k runs in workgroup tile0 + k (the
+// One launch for a stage with the tile sweep: the first ceil(nwork2 / 8)
+// workgroups fill 8 ghosts each, tile k runs in workgroup tile0 + k (the
 // caller keeps dependent tiles out of the carrier workgroups).  Items flagged
 // with TILE_DEP_BIT wait for the ghost values they read and patch them in:
 // aux[k] = [begin, end) in patch, whose entries are (LDS element index in the

@@ -178,7 +178,7 @@ __device__ __forceinline__ void ghost_item(const DevInst *__restrict__ insts, co
     const T nx = gdv.v[0], ny = gdv.v[1];
     T a0 = 0, aF = 0, aD = 0, aN = 0;
     const int e0 = wk.z, e1 = wk.w;
-    constexpr int MAXE = 4;                         // entries per lane per pass
+    constexpr int MAXE = 2;                         // entries per lane per pass (64 per pass at GL = 32)
     for (int base = e0; base < e1; base += GL * MAXE) {
         int off[MAXE];
         VecT<T, 4> w[MAXE];
@@ -326,7 +326,7 @@ __device__ __forceinline__ void probe_item(const DevInst *__restrict__ insts, co
     }
 }
 
-// Ghost fill of a stage (16 ghosts per workgroup), then the probe pass in
+// Ghost fill of a stage (256 / GL ghosts per workgroup), then the probe pass in
 // the workgroups after them.
 template <typename T, int GL, int GV>
 __global__ __launch_bounds__(256) void k_ghost(const DevInst *__restrict__ insts,
@@ -1154,7 +1154,7 @@ hipError_t launch_sweep(int prec, int vec, bool filt, int waves, const DevInst *
 }
 
 
-constexpr int GHOST_LANES = 16;                  // lanes per ghost
+constexpr int GHOST_LANES = 32;                  // lanes per ghost (8 ghosts per workgroup)
 
 // Fused launch arguments (the ghost part, the tile offset, the probe pass).
 struct FuseArgs {
