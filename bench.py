@@ -85,7 +85,7 @@ def _kernel_name(tiling: dict, prec: str) -> str:
     t = "float, 4" if prec == "f32" else "double, 2"
     if tiling["kind"] == "tile":
         k = "k_stage" if tiling.get("fused") else "k_tile"
-        extra = ", 32, 1" if tiling.get("fused") else ""        # lanes per ghost, one-instance variant
+        extra = ", 32, 1" if tiling.get("fused") else ""        # lanes per ghost (fused), one-instance variant
         return f"lee::{k}<{t}, true, {tiling['cols']}, {tiling['rows']}{extra}>"
     return f"lee::k_sweep<{t.split(',')[0]}, {tiling['vec']}, true, {tiling['waves']}>"
 

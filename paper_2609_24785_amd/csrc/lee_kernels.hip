@@ -178,7 +178,7 @@ __device__ __forceinline__ void ghost_item(const DevInst *__restrict__ insts, co
     const T nx = gdv.v[0], ny = gdv.v[1];
     T a0 = 0, aF = 0, aD = 0, aN = 0;
     const int e0 = wk.z, e1 = wk.w;
-    constexpr int MAXE = 2;                         // entries per lane per pass (64 per pass at GL = 32)
+    constexpr int MAXE = 64 / GL;                   // entries per lane per pass: 64 per ghost
     for (int base = e0; base < e1; base += GL * MAXE) {
         int off[MAXE];
         VecT<T, 4> w[MAXE];
@@ -1154,7 +1154,12 @@ hipError_t launch_sweep(int prec, int vec, bool filt, int waves, const DevInst *
 }
 
 
-constexpr int GHOST_LANES = 32;                  // lanes per ghost (8 ghosts per workgroup)
+// Lanes per ghost: 32 in the fused stage, whose ghost-carrying workgroups
+// are on the launch's critical path (8 ghosts each, shorter per-lane load
+// chains), 16 in the separate ghost launch, which batches fill with many
+// ghosts (16 per workgroup, fewer idle lanes).
+constexpr int GHOST_LANES_FUSED = 32;
+constexpr int GHOST_LANES = 16;
 
 // Fused launch arguments (the ghost part, the tile offset, the probe pass).
 struct FuseArgs {
@@ -1177,27 +1182,28 @@ static hipError_t launch_tile_t(const DevInst *insts, const int4 *work, int nwor
         hipLaunchKernelGGL((k_tile<T, VEC, FILT, TX, TY>), dim3(nwork), dim3(256), 0, s, insts, work, nwork, stage,
                            slot);
     } else {
-        // the first ncar workgroups carry 256 / GHOST_LANES ghosts each; the
-        // probe pass takes 16 probes per workgroup after the tiles
-        const int ncar = (fa->nwork2 * GHOST_LANES + 255) / 256;
+        // the first ncar workgroups carry 256 / GHOST_LANES_FUSED ghosts each;
+        // the probe pass takes 16 probes per workgroup after the tiles
+        const int ncar = (fa->nwork2 * GHOST_LANES_FUSED + 255) / 256;
         const int tend = std::max(ncar, fa->tile0 + nwork);
         const int nbp = (fa->pp.np + 15) / 16;
+        constexpr int GL = GHOST_LANES_FUSED;
         if (fa->gv == GV_ONE)
-            hipLaunchKernelGGL((k_stage<T, VEC, FILT, TX, TY, GHOST_LANES, GV_ONE>), dim3(tend + nbp), dim3(256), 0,
+            hipLaunchKernelGGL((k_stage<T, VEC, FILT, TX, TY, GL, GV_ONE>), dim3(tend + nbp), dim3(256), 0, s, insts,
+                               work, nwork, fa->work2, fa->nwork2, ncar, fa->tile0, tend, stage, slot, fa->sync,
+                               fa->spin_limit, fa->aux, fa->patch, fa->pp);
+        else if (fa->gv == (GV_ONE | GV_POLES))
+            hipLaunchKernelGGL((k_stage<T, VEC, FILT, TX, TY, GL, GV_ONE | GV_POLES>), dim3(tend + nbp), dim3(256), 0,
                                s, insts, work, nwork, fa->work2, fa->nwork2, ncar, fa->tile0, tend, stage, slot,
                                fa->sync, fa->spin_limit, fa->aux, fa->patch, fa->pp);
-        else if (fa->gv == (GV_ONE | GV_POLES))
-            hipLaunchKernelGGL((k_stage<T, VEC, FILT, TX, TY, GHOST_LANES, GV_ONE | GV_POLES>), dim3(tend + nbp),
-                               dim3(256), 0, s, insts, work, nwork, fa->work2, fa->nwork2, ncar, fa->tile0, tend,
-                               stage, slot, fa->sync, fa->spin_limit, fa->aux, fa->patch, fa->pp);
         else if (fa->gv == GV_POLES)
-            hipLaunchKernelGGL((k_stage<T, VEC, FILT, TX, TY, GHOST_LANES, GV_POLES>), dim3(tend + nbp), dim3(256),
-                               0, s, insts, work, nwork, fa->work2, fa->nwork2, ncar, fa->tile0, tend, stage, slot,
-                               fa->sync, fa->spin_limit, fa->aux, fa->patch, fa->pp);
+            hipLaunchKernelGGL((k_stage<T, VEC, FILT, TX, TY, GL, GV_POLES>), dim3(tend + nbp), dim3(256), 0, s, insts,
+                               work, nwork, fa->work2, fa->nwork2, ncar, fa->tile0, tend, stage, slot, fa->sync,
+                               fa->spin_limit, fa->aux, fa->patch, fa->pp);
         else
-            hipLaunchKernelGGL((k_stage<T, VEC, FILT, TX, TY, GHOST_LANES, GV_TABLE>), dim3(tend + nbp), dim3(256),
-                               0, s, insts, work, nwork, fa->work2, fa->nwork2, ncar, fa->tile0, tend, stage, slot,
-                               fa->sync, fa->spin_limit, fa->aux, fa->patch, fa->pp);
+            hipLaunchKernelGGL((k_stage<T, VEC, FILT, TX, TY, GL, GV_TABLE>), dim3(tend + nbp), dim3(256), 0, s, insts,
+                               work, nwork, fa->work2, fa->nwork2, ncar, fa->tile0, tend, stage, slot, fa->sync,
+                               fa->spin_limit, fa->aux, fa->patch, fa->pp);
     }
     return hipGetLastError();
 }
