@@ -176,37 +176,65 @@ __device__ __forceinline__ void ghost_item(const DevInst *__restrict__ insts, co
     const GLOBAL int *coff = gp<int>(I.coff);
     const int go = gp<int>(I.goff)[g];
     const T nx = gdv.v[0], ny = gdv.v[1];
-    T a0 = 0, aF = 0, aD = 0, aN = 0;
+    // The four sums follow one layout whatever GL is, so both launch forms
+    // give the same bits: 32 virtual lanes, virtual lane v adding entries
+    // v and v + 32 of every 64-entry pass in that order, then a butterfly
+    // over the 32 virtual lanes.  A lane carries R = 32 / GL of them
+    // (virtual lanes sub and sub + 16 when GL = 16).
+    constexpr int VL = 32;
+    constexpr int R = VL / GL;
+    static_assert(GL == 16 || GL == 32, "16 or 32 lanes per ghost");
+    T c0[R], cF[R], cD[R], cN[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) c0[r] = cF[r] = cD[r] = cN[r] = 0;
     const int e0 = wk.z, e1 = wk.w;
-    constexpr int MAXE = 64 / GL;                   // entries per lane per pass: 64 per ghost
-    for (int base = e0; base < e1; base += GL * MAXE) {
-        int off[MAXE];
-        VecT<T, 4> w[MAXE];
+    for (int base = e0; base < e1; base += 2 * VL) {
+        int off[R][2];
+        VecT<T, 4> w[R][2];
 #pragma unroll
-        for (int k = 0; k < MAXE; ++k) {
-            const int e = base + sub + k * GL;
-            const bool ok = e < e1;
-            off[k] = ok ? coff[e] : -1;
-            if (ok) w[k] = vld<T, 4>(w4 + 4 * (size_t)e);
-            else w[k] = VecT<T, 4>{{0, 0, 0, 0}};
-        }
+        for (int r = 0; r < R; ++r)
 #pragma unroll
-        for (int k = 0; k < MAXE; ++k) {
-            if (off[k] < 0) continue;
-            const T p = P[off[k]], u = U[off[k]], v = V[off[k]];
-            a0 += w[k].v[0] * p;
-            aN += w[k].v[3] * p;
-            aD += w[k].v[2] * (nx * u + ny * v);
-            aF += w[k].v[1] * (-ny * u + nx * v);
-        }
+            for (int k = 0; k < 2; ++k) {
+                const int e = base + sub + r * GL + k * VL;
+                const bool ok = e < e1;
+                off[r][k] = ok ? coff[e] : -1;
+                if (ok) w[r][k] = vld<T, 4>(w4 + 4 * (size_t)e);
+                else w[r][k] = VecT<T, 4>{{0, 0, 0, 0}};
+            }
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                if (off[r][k] < 0) continue;
+                const int o = off[r][k];
+                const T p = P[o], u = U[o], v = V[o];
+                c0[r] += w[r][k].v[0] * p;
+                cN[r] += w[r][k].v[3] * p;
+                cD[r] += w[r][k].v[2] * (nx * u + ny * v);
+                cF[r] += w[r][k].v[1] * (-ny * u + nx * v);
+            }
+    }
+    // the first butterfly step pairs virtual lanes v and v + 16
+    T s0 = c0[0], sF = cF[0], sD = cD[0], sN = cN[0];
+    if constexpr (R == 2) {
+        s0 = c0[0] + c0[1];
+        sF = cF[0] + cF[1];
+        sD = cD[0] + cD[1];
+        sN = cN[0] + cN[1];
+    } else {
+        s0 += __shfl_xor(s0, 16, GL);
+        sF += __shfl_xor(sF, 16, GL);
+        sD += __shfl_xor(sD, 16, GL);
+        sN += __shfl_xor(sN, 16, GL);
     }
 #pragma unroll
-    for (int m = GL / 2; m >= 1; m >>= 1) {
-        a0 += __shfl_xor(a0, m, GL);
-        aF += __shfl_xor(aF, m, GL);
-        aD += __shfl_xor(aD, m, GL);
-        aN += __shfl_xor(aN, m, GL);
+    for (int m = 8; m >= 1; m >>= 1) {
+        s0 += __shfl_xor(s0, m, GL);
+        sF += __shfl_xor(sF, m, GL);
+        sD += __shfl_xor(sD, m, GL);
+        sN += __shfl_xor(sN, m, GL);
     }
+    const T a0 = s0, aF = sF, aD = sD, aN = sN;
     if (sub != 0 || !active) return;
     // steps 2-3: ADE derivative, wall normal velocity and its time derivative
     T d1 = 0, d2 = 0, Un = 0, Ud = 0;
