@@ -116,3 +116,40 @@ def test_membership_changes_keep_graphs(prec, fused):
         m.synchronize()
         for x, y in zip(m.fields(), ref):
             assert np.array_equal(x, y)
+
+
+def test_batch_capacity_growth_and_trim_recapture():
+    """A member that outgrows the padded lists, and removals that leave them
+    mostly idle, each drop the captured graphs once (the next run captures
+    again); every member still matches its solo run bit for bit."""
+    Instance, Batch = _lee()
+    small = [lc.small_cylinder(96, 20), lc.small_cylinder(128, 20, impedance=lc.Impedance("rigid"))]
+    big = lc.small_cylinder(224, 20).replace(ny=97, y0=-3.5, probes=((2.5, 0.0),))
+    print("[batch] capacity growth and trim", flush=True)
+    steps = {0: 24, 1: 16, 2: 8}                     # member 1 leaves after 16 steps, the big one joins for 8
+    cases = small + [big]
+    solo = []
+    for k, c in enumerate(cases):
+        i = Instance(c, "f32")
+        i.set_tiling("tile", cols=64, rows=16, fused=0)
+        i.step_n(steps[k])
+        i.synchronize()
+        solo.append(i.fields())
+    mem = [Instance(c, "f32") for c in cases]
+    b = Batch(mem[:2], tiling=dict(kind="tile", cols=64, rows=16, fused=0), graph_steps=4)
+    b.step_n(8)
+    b.synchronize()
+    c0 = b.graph_captures()
+    b.step_n(8)                                      # same lists: no new capture
+    b.synchronize()
+    assert b.graph_captures() == c0
+    b.remove(mem[1])
+    b.add(mem[2])                                    # outgrows the ghost and sweep capacities
+    b.step_n(8)
+    b.synchronize()
+    assert b.graph_captures() == c0 + 1
+    for m, ref, n in zip(mem, solo, (24, 16, 8)):
+        m.synchronize()
+        assert m.step == n
+        for x, y in zip(m.fields(), ref):
+            assert np.array_equal(x, y)
