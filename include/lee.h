@@ -295,6 +295,18 @@ lee_status lee_set_graph_steps(lee_instance *inst, int32_t steps);
 lee_status lee_get_tiling(const lee_instance *inst, lee_tiling *t);
 
 /*
+ * Bound on the polls of a fused stage's wait for each ghost value it reads
+ * (the ghost values of the stage's carrier workgroups, Coupling section):
+ * polls > 0 sets the bound (default 2^20, about a second), 0 restores the
+ * default.  polls < 0 is for testing the error path: every wait then looks
+ * for a tag that is never published, gives up after -polls polls and raises
+ * the error flag, so the next lee_synchronize reports LEE_E_DEVICE (the
+ * results of such stages are not valid; every kernel still ends).
+ * Invalidates the captured graphs.
+ */
+lee_status lee_set_ghost_wait(lee_instance *inst, int32_t polls);
+
+/*
  * Measurement (synchronising, on the bound stream).  Runs, each bracketed by
  * one pair of HIP events: 4n ghost launches (stages 0..3 in turn), 4n sweep
  * launches (the fused launch when the tiling is fused), then n eager steps.

@@ -90,6 +90,7 @@ SIGNATURES = {
     "lee_set_watch": (c_int32, [c_void_p, c_double, c_double, c_int64, ctypes.POINTER(c_int32)]),
     "lee_watch_traces": (c_int32, [c_void_p, c_void_p, c_int64, ctypes.POINTER(c_int64)]),
     "lee_set_graph_steps": (c_int32, [c_void_p, c_int32]),
+    "lee_set_ghost_wait": (c_int32, [c_void_p, c_int32]),
     "lee_batch_synchronize": (c_int32, [c_void_p]),
     "lee_batch_add": (c_int32, [c_void_p, c_void_p]),
     "lee_batch_remove": (c_int32, [c_void_p, c_void_p]),

@@ -72,6 +72,7 @@ struct lee_instance {
     StepGraphs graphs;
     int next_stage = 0;
     int64_t steps_issued = 0;
+    int spin = SPIN_LIMIT;          // polls per ghost-value wait (negative: test mode)
 };
 
 namespace {
@@ -412,7 +413,7 @@ bool fused(const lee_tiling &t) { return t.kind == LEE_SWEEP_TILE && t.fused; }
 hipError_t stage_launches(int prec, bool filt, const lee_tiling &t, const DevInst *insts, int ninst, bool poles,
                           const int4 *work1, int nwork1, const int2 *aux, const int2 *patch, int tile0,
                           const int4 *work2, int nwork2, int *sync, int stage, int slot, ProbePass pp, int blocks,
-                          hipStream_t s, hipEvent_t *ev = nullptr)
+                          hipStream_t s, hipEvent_t *ev = nullptr, int spin = SPIN_LIMIT)
 {
     hipError_t e = hipSuccess;
     if (ev) hipEventRecord(ev[0], s);
@@ -424,7 +425,7 @@ hipError_t stage_launches(int prec, bool filt, const lee_tiling &t, const DevIns
     if (e != hipSuccess) return e;
     if (fused(t))
         e = launch_stage(prec, filt, t.cols, t.rows, insts, ninst, poles, work1, nwork1, aux, patch, tile0, work2,
-                         nwork2, stage, slot, sync, SPIN_LIMIT, pp, s);
+                         nwork2, stage, slot, sync, spin, pp, s);
     else
         e = sweep(prec, filt, t, insts, work1, nwork1, stage, slot, blocks, s);
     if (ev) hipEventRecord(ev[3], s);
@@ -447,7 +448,7 @@ hipError_t issue_stage(lee_instance *I, int stage, int slot)
     return stage_launches(prec, I->host.d.filter_sigma > 0.0, I->tl, I->d_inst, 1, I->host.ade_kind == 3,
                           I->d_work1, I->nwork1, I->d_aux,
                           I->d_patch, I->tile0, I->d_work2, I->nwork2, I->d_sync, stage, slot,
-                          probe_pass(I->d_pwork, I->host.np, stage, slot), 0, I->stream);
+                          probe_pass(I->d_pwork, I->host.np, stage, slot), 0, I->stream, nullptr, I->spin);
 }
 
 // The tail of a run of n steps: the probes after its last step, then the
@@ -832,6 +833,14 @@ lee_status lee_set_graph_steps(lee_instance *I, int32_t steps)
     return LEE_OK;
 }
 
+lee_status lee_set_ghost_wait(lee_instance *I, int32_t polls)
+{
+    if (!I) return fail(LEE_E_ARG, "null instance");
+    drop_graph(I);
+    I->spin = polls == 0 ? SPIN_LIMIT : polls;
+    return LEE_OK;
+}
+
 lee_status lee_set_tiling(lee_instance *I, const lee_tiling *t)
 {
     if (!I || !t) return fail(LEE_E_ARG, "null argument");
@@ -1050,7 +1059,7 @@ lee_status lee_time_kernels(lee_instance *I, int64_t n, double *sweep_us, double
             e = fused(I->tl) ? launch_stage(prec, filt, I->tl.cols, I->tl.rows, I->d_inst, 1, I->host.ade_kind == 3,
                                             I->d_work1, I->nwork1,
                                             I->d_aux, I->d_patch, I->tile0, I->d_work2, I->nwork2, l, 0, I->d_sync,
-                                            SPIN_LIMIT, ProbePass{nullptr, 0, 0}, I->stream)
+                                            I->spin, ProbePass{nullptr, 0, 0}, I->stream)
                              : sweep(prec, filt, I->tl, I->d_inst, I->d_work1, I->nwork1, l, 0, 0, I->stream);
         }
         return e;

@@ -857,18 +857,21 @@ __device__ __forceinline__ void patch_prefetch(const int2 *__restrict__ patch, i
 // One ghost value of the current stage from its exchange words: relaxed
 // agent-scope atomic loads, repeated while a word carries another epoch (at
 // most spin_limit polls, then the error flag is raised and the value is not
-// valid).
+// valid).  A negative spin_limit (testing the error path from the host)
+// waits -spin_limit polls for a tag no carrier ever publishes.
 template <typename T>
 __device__ __forceinline__ T xg_get(const GLOBAL unsigned long long *w, unsigned epoch, int spin_limit, int *error)
 {
     constexpr int NW = sizeof(T) / 4;
+    const unsigned want = spin_limit < 0 ? ~epoch : epoch;   // epochs are small: ~epoch never appears
+    const int limit = spin_limit < 0 ? -spin_limit : spin_limit;
     unsigned long long b = 0;
 #pragma unroll
     for (int k = 0; k < NW; ++k) {
         unsigned long long v = __hip_atomic_load(w + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         int polls = 0;
-        while ((unsigned)(v >> 32) != epoch) {
-            if (++polls > spin_limit) {
+        while ((unsigned)(v >> 32) != want) {
+            if (++polls > limit) {
                 __hip_atomic_fetch_or(error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 break;
             }

@@ -238,6 +238,11 @@ class Instance:
         """Steps per captured hipGraph (0: built-in default, < 0: eager launches)."""
         check(self.lib.lee_set_graph_steps(self._h, steps), "lee_set_graph_steps")
 
+    def set_ghost_wait(self, polls: int):
+        """Bound on a fused stage's polls per ghost value (0: default; < 0:
+        every wait fails after -polls polls, for testing the error path)."""
+        check(self.lib.lee_set_ghost_wait(self._h, polls), "lee_set_ghost_wait")
+
     def get_tiling(self) -> dict:
         t = Tiling()
         check(self.lib.lee_get_tiling(self._h, ctypes.byref(t)), "lee_get_tiling")

@@ -242,3 +242,27 @@ def test_cylinder_1024_full_size_benchmark_configuration(prec, tol):
     _say(f"[parity] benchmark configuration {prec}: {choice}")
     inst, _ = _compare(case, 100, prec, tol, tiling=choice["tiling"], graph_steps=choice["graph_steps"])
     inst.close()
+
+
+def test_spent_ghost_wait_is_reported_not_hung():
+    """The fused stage's waits for ghost values are bounded: forced from the
+    host to look for a tag no carrier publishes, every wait gives up after a
+    few polls, every kernel ends, and lee_synchronize reports LEE_E_DEVICE.
+    The two-launch form has no such wait."""
+    from paper_2609_24785_amd._lib import LeeError
+    Instance, _ = _lee()
+    case = lc.small_cylinder(96, 4)
+    a = Instance(case, "f32")
+    a.set_tiling("tile", cols=64, rows=16, fused=1)
+    a.set_ghost_wait(-4)
+    a.step_n(2)
+    with pytest.raises(LeeError) as e:
+        a.synchronize()
+    assert e.value.status == -7
+    a.close()
+    b = Instance(case, "f32")
+    b.set_tiling("tile", cols=64, rows=16, fused=0)
+    b.set_ghost_wait(-4)
+    b.step_n(2)
+    b.synchronize()
+    b.close()
