@@ -366,6 +366,47 @@ def extras(args):
         rp["inst"].close()
     out["cylinder_pulse_1024_multipole"] = dict(steps=pm_steps, unit=UNIT, ade_states=8, **mres)
 
+    # spectral stability of the step map (abstract): assembled on the GPU for
+    # coarse cylinders and checked against the oracle's assembly; the growth
+    # per step of the worst mode of the benchmark grid by power iteration
+    print("[extras] spectral analysis", file=sys.stderr, flush=True)
+    import numpy as np
+    from oracle import spectral as osp
+    from paper_2609_24785_amd import stability
+    scan = []
+    for d in (0.0, 0.25, 0.49):
+        sc = lc.coarse_cylinder(28, 4.0, d, 0.5 * d)
+        inst = Instance(sc, "f64")
+        t0 = time.perf_counter()
+        G = stability.step_matrix(inst)
+        t_gpu = time.perf_counter() - t0
+        inst.close()
+        t0 = time.perf_counter()
+        R = osp.step_matrix(sc)
+        t_cpu = time.perf_counter() - t0
+        scan.append({"shift": [d, 0.5 * d], "states": int(G.shape[0]),
+                     "spectral_radius": stability.spectral_radius(G),
+                     "spectral_radius_oracle": osp.spectral_radius(R),
+                     "max_abs_diff_vs_oracle": float(np.abs(G - R).max()),
+                     "gpu_columns_per_s": G.shape[0] / t_gpu, "oracle_columns_per_s": R.shape[0] / t_cpu})
+    bench_case = lc.cylinder_pulse_1024(10).replace(ic=None, probes=())
+    power = {}
+    for prec in ("f32", "f64"):
+        inst = Instance(bench_case, prec)
+        ch = tune.tune_case(bench_case, prec, cache)
+        inst.set_tiling(**ch["tiling"])
+        inst.set_graph_steps(ch["graph_steps"])
+        n = stability.StatePacker(inst).n
+        x0 = np.random.default_rng(2609).standard_normal(n)
+        t0 = time.perf_counter()
+        est, logs = stability.power_growth(inst, x0, args.power_steps, chunk=100)
+        wall = time.perf_counter() - t0
+        inst.close()
+        power[prec] = {"growth_per_step": est, "over_4000_steps": est ** 4000,
+                       "last_chunk_growth": float(np.exp((logs[-1] - logs[-2]) / 100)),
+                       "steps": args.power_steps, "wall_s": wall}
+    out["spectral"] = {"coarse_cylinder_28_rc4_f64": scan, "benchmark_grid_power_iteration": power}
+
     print(f"[extras] batch of {args.batch_size} uneven instances", file=sys.stderr, flush=True)
     gen = lc.batch_candidates(steps=args.batch_steps)
     members, rejected = [], 0
@@ -529,6 +570,7 @@ def main():
     ap.add_argument("--kernel-steps", type=int, default=200)
     ap.add_argument("--cpu-steps", type=int, default=2000)
     ap.add_argument("--mono-steps", type=int, default=200)
+    ap.add_argument("--power-steps", type=int, default=4000, help="power-iteration steps on the benchmark grid (--extras)")
     ap.add_argument("--extras", action="store_true", help="the other configurations, as a second JSON line")
     ap.add_argument("--batch-size", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=2000)

@@ -238,6 +238,13 @@ lee_status lee_set_fields(lee_instance *inst, const double *p, const double *u, 
  * each pair's two). */
 lee_status lee_get_ade_states(lee_instance *inst, double *out);
 
+/* Synchronising: overwrite the ADE states that the next step starts from
+ * with in[n g + k], the layout lee_get_ade_states returns; nothing to do for
+ * a rigid wall.  With lee_set_fields this sets the whole state of the scheme
+ * (Sec. 2.3: the auxiliary states are part of the unknowns), as a linear
+ * analysis of the step map needs. */
+lee_status lee_set_ade_states(lee_instance *inst, const double *in);
+
 /* Completed steps: the device's step counter once the stream is idle
  * (synchronising; budgets of a batch may have idled the instance); before
  * lee_bind, 0.  Reports a spent fused-stage wait as lee_synchronize does. */

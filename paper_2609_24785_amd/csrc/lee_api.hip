@@ -955,6 +955,24 @@ lee_status lee_get_ade_states(lee_instance *I, double *out)
     return LEE_OK;
 }
 
+lee_status lee_set_ade_states(lee_instance *I, const double *in)
+{
+    if (!I || !I->bound || !in) return fail(LEE_E_ARG, "instance not bound or null input");
+    if (I->next_stage != 0) return fail(LEE_E_STATE, "a partial step is pending");
+    const size_t n = (size_t)I->host.ade_ns * I->host.gidx.size();
+    if (!n) return LEE_OK;
+    if (I->host.d.precision == LEE_F32) {
+        std::vector<float> t(n);
+        for (size_t k = 0; k < n; ++k) t[k] = (float)in[k];
+        HIPCHK(hipMemcpyAsync(I->dev.psi[0], t.data(), n * 4, hipMemcpyHostToDevice, I->stream));
+        HIPCHK(hipStreamSynchronize(I->stream));
+    } else {
+        HIPCHK(hipMemcpyAsync(I->dev.psi[0], in, n * 8, hipMemcpyHostToDevice, I->stream));
+        HIPCHK(hipStreamSynchronize(I->stream));
+    }
+    return LEE_OK;
+}
+
 lee_status lee_probe(lee_instance *I, int32_t np, const double *xy, double *out)
 {
     if (!I || !I->bound) return fail(LEE_E_STATE, "instance not bound");

@@ -178,6 +178,15 @@ class Instance:
         check(self.lib.lee_get_ade_states(self._h, _ptr(out)), "lee_get_ade_states")
         return out.reshape(-1, ns)
 
+    def set_ade_states(self, x):
+        """Overwrite the auxiliary states the next step starts from (rows per
+        ghost, as ade_states() returns them)."""
+        ns = max(int(self.summary.ade_states), 1)
+        a = np.ascontiguousarray(np.asarray(x, dtype=np.float64).reshape(-1))
+        if a.size != ns * self.summary.G:
+            raise ValueError(f"expected {ns * self.summary.G} auxiliary states, got {a.size}")
+        check(self.lib.lee_set_ade_states(self._h, _ptr(a)), "lee_set_ade_states")
+
     def probe(self, xy: Sequence[Sequence[float]]):
         xy = np.ascontiguousarray(np.asarray(xy, dtype=np.float64).reshape(-1, 2))
         out = np.zeros((len(xy), 3))
