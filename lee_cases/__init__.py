@@ -294,25 +294,6 @@ def small_cylinder(n: int = 96, steps: int = 40, impedance: Optional[Impedance] 
     )
 
 
-def tilted_wall(angle_deg: float, n: int = 32, offset: float = 0.0,
-                impedance: Optional[Impedance] = None, H: int = 5,
-                filter_sigma: float = 0.2) -> Case:
-    """A small square grid (dx = 1, n nodes a side, centred on the origin)
-    cut by a straight wall at angle_deg to the x axis, passing `offset` grid
-    units from the origin along its normal; fluid on the side the normal
-    points to.  No initial field, no source, no sponge: the outer frame is
-    the zero frame of the solver.  Used for the spectral scan over the wall
-    angle, down to the wall lying along a grid line (angle 0)."""
-    nx_, ny_ = line_normal(angle_deg)
-    c0 = -0.5 * (n - 1)
-    return Case(
-        nx=n, ny=n, x0=c0, y0=c0, h=1.0, H=H, cfl=0.5, filter_sigma=filter_sigma,
-        wall=Wall("line", offset * nx_, offset * ny_, nx_, ny_),
-        impedance=impedance if impedance is not None else Impedance(),
-        steps=0, name=f"tilted-wall-{n}-{angle_deg:g}-{offset:g}",
-    )
-
-
 def coarse_cylinder(n: int = 28, rc: float = 4.0, dx: float = 0.0, dy: float = 0.0,
                     impedance: Optional[Impedance] = None, H: int = 5,
                     filter_sigma: float = 0.2) -> Case:
