@@ -120,6 +120,8 @@ class Case:
     steps: int = 0
     probes: Tuple[Tuple[float, float], ...] = ()
     dft_steps: int = 0             # running DFT over the final dft_steps steps
+    radiation: bool = False        # radiation condition in the outer band of H nodes
+    rad_center: Tuple[float, float] = (0.0, 0.0)   # its centre (x, y)
     name: str = ""
 
     @property
@@ -308,6 +310,25 @@ def coarse_cylinder(n: int = 28, rc: float = 4.0, dx: float = 0.0, dy: float = 0
         wall=Wall("circle", dx, dy, rc=rc),
         impedance=impedance if impedance is not None else Impedance(),
         steps=0, name=f"coarse-cylinder-{n}-{rc:g}-{dx:g}-{dy:g}",
+    )
+
+
+def radiating_cylinder(n: int = 96, steps: int = 120, impedance: Optional[Impedance] = None,
+                       H: int = 5, filter_sigma: float = 0.2) -> Case:
+    """A reduced cylinder-pulse case truncated by the radiation condition
+    instead of the zero frame (Sec. 4.2 uses non-reflecting conditions on
+    all four sides): n x (n + 7) nodes on [-8, 8) in x, cylinder r_c = 1.3,
+    pulse (a = 1e-3, w = 0.5) at (3, 1), radiation centre at the origin."""
+    h = 16.0 / n
+    return Case(
+        nx=n, ny=n + 7, x0=-8.0, y0=-8.0 - 3 * h, h=h, H=H, cfl=0.5,
+        filter_sigma=filter_sigma,
+        wall=Wall("circle", 0.3 * h, 0.3 * h, rc=1.3),
+        impedance=impedance if impedance is not None else Impedance("msd", R=0.5, M=0.1, K=10.0),
+        ic=Pulse(3.0, 1.0, 1e-3, 0.5), steps=steps,
+        probes=((5.0, 0.0), (0.0, 6.5), (-7.5, -7.0)),
+        radiation=True, rad_center=(0.0, 0.0),
+        name=f"radiating-cylinder-{n}",
     )
 
 

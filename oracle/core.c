@@ -31,6 +31,15 @@
  * reading (the paper truncates its domains with radiation conditions instead):
  * its profile sigma(d) = sigma_max ((W - d) / W)^2 is parity unpinned; a test
  * checks only that it removes energy.
+ *
+ * Radiation condition (optional; Sec. 2.2 names one-sided stencils at the
+ * outer boundary, Sec. 4.1-4.2 the non-reflecting condition of Tam and Webb
+ * on it): at the fluid nodes closer than rad_w nodes to an edge of the
+ * domain, step 6 uses the far-field form of the LEE for outgoing waves
+ * without mean flow, dq/dt = -(dq/dr + q/(2r)) for q = p, u, v, with r and
+ * theta measured from a centre inside the domain and d/dr = cos(theta) d/dx
+ * + sin(theta) d/dy; the derivatives take 7 nodes inside the domain
+ * (central where possible, one-sided next to the edge) and no filter term.
  */
 #include <math.h>
 #include <stdlib.h>
@@ -60,6 +69,10 @@ typedef struct {
     double ade_f[8];
     double ade_c[8];            /* u_n,BP = c . Psi */
     int watch_g;                /* ghost whose p_BP and u_n,BP are recorded (-1: none) */
+    int rad_w;                  /* radiation band: nodes closer than rad_w to an edge (0 = none) */
+    double rad_xc, rad_yc;      /* centre of the radiation condition */
+    double rad_c[3];            /* central 7-point first derivative a_1..a_3 */
+    double rad_b[3][7];         /* one-sided 7-point first derivative at point m of 0..6 */
 } oc_case;
 
 static const double RK_ALPHA[4] = {0.25, 1.0 / 3.0, 0.5, 1.0};
@@ -149,6 +162,25 @@ static double sponge(const oc_case *c, int i, int j)
     return c->sponge_smax * f * f;
 }
 
+/* First derivative along one axis at a node i of n (stride between
+ * neighbours in the padded plane) from the 7 nearest nodes inside the
+ * domain: the central 7-point stencil where three nodes lie on either side,
+ * else the one-sided set with the node at place m of the seven (m nodes on
+ * the near side), mirrored at the far edge. */
+static double rad_deriv(const oc_case *c, const double *q, long long at, int i, int n, long long stride)
+{
+    int lo = i, hi = n - 1 - i, k;
+    double s = 0.0;
+    if (lo >= 3 && hi >= 3) {
+        for (k = 1; k <= 3; ++k) s += c->rad_c[k - 1] * (q[at + k * stride] - q[at - k * stride]);
+    } else if (lo < 3) {
+        for (k = 0; k < 7; ++k) s += c->rad_b[lo][k] * q[at + (k - lo) * stride];
+    } else {
+        for (k = 0; k < 7; ++k) s -= c->rad_b[hi][k] * q[at - (k - hi) * stride];
+    }
+    return s / c->h;
+}
+
 /* step 6: RHS at fluid nodes of the stage input (ps, us, vs) and the update */
 static void sweep(const oc_case *c, const double *p, const double *u, const double *v,
                   const double *ps, const double *us, const double *vs,
@@ -166,6 +198,20 @@ static void sweep(const oc_case *c, const double *p, const double *u, const doub
                 po[q] = 0.0; uo[q] = 0.0; vo[q] = 0.0;
                 continue;
             }
+            double rp, ru, rv;
+            int e = i;
+            if (j < e) e = j;
+            if (c->nx - 1 - i < e) e = c->nx - 1 - i;
+            if (c->ny - 1 - j < e) e = c->ny - 1 - j;
+            if (e < c->rad_w) {
+                /* radiation condition: (d/dt + d/dr + 1/(2r)) q = 0 for each
+                 * of p, u, v, r and theta about (rad_xc, rad_yc) */
+                double x = c->x0 + (double)i * c->h - c->rad_xc, y = c->y0 + (double)j * c->h - c->rad_yc;
+                double r = sqrt(x * x + y * y), ct = x / r, st = y / r, hr = 0.5 / r;
+                rp = -(ct * rad_deriv(c, ps, q, i, c->nx, 1) + st * rad_deriv(c, ps, q, j, c->ny, sy) + hr * ps[q]);
+                ru = -(ct * rad_deriv(c, us, q, i, c->nx, 1) + st * rad_deriv(c, us, q, j, c->ny, sy) + hr * us[q]);
+                rv = -(ct * rad_deriv(c, vs, q, i, c->nx, 1) + st * rad_deriv(c, vs, q, j, c->ny, sy) + hr * vs[q]);
+            } else {
             double dpdx = 0, dudx = 0, dpdy = 0, dvdy = 0;
             for (k = 1; k <= c->H; ++k) {
                 dpdx += c->a[k - 1] * (ps[q + k] - ps[q - k]);
@@ -174,9 +220,9 @@ static void sweep(const oc_case *c, const double *p, const double *u, const doub
                 dvdy += c->a[k - 1] * (vs[q + k * sy] - vs[q - k * sy]);
             }
             dpdx /= c->h; dudx /= c->h; dpdy /= c->h; dvdy /= c->h;
-            double rp = -(dudx + dvdy);
-            double ru = -dpdx;
-            double rv = -dpdy;
+            rp = -(dudx + dvdy);
+            ru = -dpdx;
+            rv = -dpdy;
             if (c->sigma_d > 0.0) {
                 double fp = 2.0 * c->d[0] * ps[q];
                 double fu = 2.0 * c->d[0] * us[q];
@@ -188,6 +234,7 @@ static void sweep(const oc_case *c, const double *p, const double *u, const doub
                 }
                 double s = c->sigma_d / c->dt;
                 rp -= s * fp; ru -= s * fu; rv -= s * fv;
+            }
             }
             double ss = sponge(c, i, j);
             if (ss != 0.0) {

@@ -36,6 +36,37 @@ RK_ALPHA = np.array([0.25, 1.0 / 3.0, 0.5, 1.0])
 RK_C = np.array([0.0, 0.25, 1.0 / 3.0, 0.5])
 
 
+def one_sided7(m: int):
+    """First-derivative weights at point m of seven unit-spaced points
+    0..6: the derivative of the degree-6 interpolant (exact rationals).  The
+    outer boundary's one-sided stencils (Sec. 2.2 names them without
+    printing them; reading: the maximal-order set on the same seven points)."""
+    from fractions import Fraction
+    pts = range(7)
+    w = []
+    for k in pts:
+        # l_k'(m) for the Lagrange basis polynomial l_k on points 0..6
+        den = Fraction(1)
+        for q in pts:
+            if q != k:
+                den *= (k - q)
+        tot = Fraction(0)
+        for skip in pts:
+            if skip == k:
+                continue
+            prod = Fraction(1)
+            for q in pts:
+                if q != k and q != skip:
+                    prod *= (m - q)
+            tot += prod
+        w.append(tot / den)
+    return w
+
+
+#: one-sided weights for m = 0, 1, 2 nodes on the near side (rows), FP64
+RAD_ONE_SIDED = np.array([[float(x) for x in one_sided7(m)] for m in range(3)])
+
+
 def drp(H: int) -> np.ndarray:
     """a_1..a_H of the central first-derivative stencil of half-width H."""
     if H == 3:

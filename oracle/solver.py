@@ -45,6 +45,8 @@ class _OcCase(ctypes.Structure):
         ("ade_ns", ctypes.c_int), ("ade_A", ctypes.c_double * 64), ("ade_f", ctypes.c_double * 8),
         ("ade_c", ctypes.c_double * 8),
         ("watch_g", ctypes.c_int),
+        ("rad_w", ctypes.c_int), ("rad_xc", ctypes.c_double), ("rad_yc", ctypes.c_double),
+        ("rad_c", ctypes.c_double * 3), ("rad_b", ctypes.c_double * 21),
     ]
 
 
@@ -83,11 +85,30 @@ def cubic_probe_weights(case: Case, fluid: np.ndarray, x: float, y: float):
     return i0, j0, np.outer(wy, wx)
 
 
+def _check_radiation(c: Case, fluid: np.ndarray):
+    """The radiation band (nodes closer than H to an edge) and every node its
+    stencils read (6 more) must be fluid, and the centre must lie at least
+    one grid step from every band node."""
+    reach = c.H + 6
+    edge = np.ones_like(fluid)
+    edge[reach:c.ny - reach, reach:c.nx - reach] = False
+    if c.nx <= 2 * reach or c.ny <= 2 * reach or not np.all(fluid[edge]):
+        raise ValueError("radiation condition: the wall comes within reach of the outer band")
+    jj, ii = np.nonzero(edge)
+    band = np.minimum(np.minimum(ii, jj), np.minimum(c.nx - 1 - ii, c.ny - 1 - jj)) < c.H
+    x = c.x0 + ii[band] * c.h - c.rad_center[0]
+    y = c.y0 + jj[band] * c.h - c.rad_center[1]
+    if np.min(np.hypot(x, y)) < c.h:
+        raise ValueError("radiation condition: centre too close to the outer band")
+
+
 class OracleSolver:
     def __init__(self, case: Case):
         self.case = case
         c = case
         self.fluid = geometry.fluid_mask(c)
+        if c.radiation:
+            _check_radiation(c, self.fluid)
         if c.wall.kind != "none":
             self.gidx = geometry.ghost_points(c, self.fluid)
         else:
@@ -196,6 +217,14 @@ class OracleSolver:
             for j in range(len(f)):
                 s.ade_A[8 * i + j] = A[i][j]
         s.watch_g = -1
+        if c.radiation:
+            s.rad_w = c.H
+            s.rad_xc, s.rad_yc = c.rad_center
+            for k in range(3):
+                s.rad_c[k] = schemes.DRP7[k]
+            for m in range(3):
+                for k in range(7):
+                    s.rad_b[7 * m + k] = schemes.RAD_ONE_SIDED[m, k]
         return s
 
     # ---- stepping ---------------------------------------------------------
