@@ -366,6 +366,23 @@ def extras(args):
         rp["inst"].close()
     out["cylinder_pulse_1024_multipole"] = dict(steps=pm_steps, unit=UNIT, ade_states=8, **mres)
 
+    # the benchmark workload truncated by the outer radiation condition
+    # instead of the zero frame; FP64 is checked against the oracle
+    print("[extras] cylinder pulse 1024^2, radiation condition", file=sys.stderr, flush=True)
+    rc = lc.cylinder_pulse_1024(pm_steps).replace(radiation=True, rad_center=(0.0, 0.0))
+    rres = {}
+    for prec in ("f32", "f64"):
+        ch = tune.tune_case(rc, prec, cache)
+        rp = _timed(rc, prec, pm_steps, 0, ch)
+        rres[prec] = {"value": rp["value"], "ms_per_step": 1000.0 * rp["wall"] / rp["steps"],
+                      "tiling": ch["tiling"]}
+        if prec == "f64":
+            s = osv.OracleSolver(rc)
+            s.run(pm_steps)
+            rres[prec]["rel_l2_vs_oracle"] = _max_rel_l2(rp["inst"].fields(), s.fields(), s.fluid)
+        rp["inst"].close()
+    out["cylinder_pulse_1024_radiation"] = dict(steps=pm_steps, unit=UNIT, **rres)
+
     # spectral stability of the step map (abstract): assembled on the GPU for
     # coarse cylinders and checked against the oracle's assembly; the growth
     # per step of the worst mode of the benchmark grid by power iteration

@@ -89,6 +89,18 @@ typedef struct {
     double ic[7];
     int32_t src_kind;        /* LEE_SRC_* */
     double src[5];
+    /* Outer boundary (Sec. 2.2: one-sided stencils at the domain edges;
+     * Sec. 4.1-4.2: the non-reflecting condition of Tam and Webb there).
+     * 0: a zero frame around the domain (plus the sponge, if any).  1: at
+     * the nodes closer than stencil_half nodes to an edge the stage solves
+     * dq/dt = -(dq/dr + q/(2r)) for p, u and v, r and theta measured from
+     * (rad_xc, rad_yc), with 7-node derivatives inside the domain (central
+     * where three nodes lie on each side, else the one-sided maximal-order
+     * set) and no filter term.  Requires every node within stencil_half + 6
+     * of an edge to be fluid and the centre at least h from every band node
+     * (else LEE_E_ARG); the tile sweeps only (LEE_SWEEP_MARCH -> LEE_E_ARG). */
+    int32_t radiation;
+    double rad_xc, rad_yc;
 } lee_case_desc;
 
 typedef struct {

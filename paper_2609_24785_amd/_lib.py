@@ -26,7 +26,8 @@ class CaseDesc(ctypes.Structure):
                 ("sponge_cells", c_int32), ("sponge_sigma", c_double), ("precision", c_int32),
                 ("wall_kind", c_int32), ("wall_cx", c_double), ("wall_cy", c_double),
                 ("wall_nx", c_double), ("wall_ny", c_double), ("wall_rc", c_double),
-                ("ic_kind", c_int32), ("ic", c_double * 7), ("src_kind", c_int32), ("src", c_double * 5)]
+                ("ic_kind", c_int32), ("ic", c_double * 7), ("src_kind", c_int32), ("src", c_double * 5),
+                ("radiation", c_int32), ("rad_xc", c_double), ("rad_yc", c_double)]
 
 
 ADE_MAX_STATES = 8

@@ -701,6 +701,32 @@ lee_status lee_bind(lee_instance *I, void *dev_ptr, size_t bytes, void *hip_stre
         D.alpha_dt[l] = ALPHA[l] * h.dt;
         D.c_stage[l] = CST[l];
     }
+    D.rad_w = h.d.radiation ? h.d.stencil_half : 0;
+    D.rad_xc = h.d.rad_xc;
+    D.rad_yc = h.d.rad_yc;
+    // window weights: place 3 the central 7-node set (-a3, -a2, -a1, 0, a1,
+    // a2, a3); any other place m the derivative at node m of the Lagrange basis
+    // on nodes 0..6, l_k'(m) = prod_{q != k, m} (m - q) / prod_{q != k} (k - q)
+    // for k != m and l_m'(m) = sum_{q != m} 1 / (m - q)
+    for (int m = 0; m < 7; ++m)
+        for (int k = 0; k < 7; ++k) {
+            double v = 0.0;
+            if (m == 3) {
+                v = k == 3 ? 0.0 : (k > 3 ? A3[k - 4] : -A3[2 - k]);
+            } else if (k == m) {
+                for (int q = 0; q < 7; ++q)
+                    if (q != m) v += 1.0 / (m - q);
+            } else {
+                double num = 1.0, den = 1.0;
+                for (int q = 0; q < 7; ++q) {
+                    if (q != k) den *= (k - q);
+                    if (q != k && q != m) num *= (m - q);
+                }
+                v = num / den;
+            }
+            D.rad_w7[m][k] = v / h.d.h;
+            D.rad_wf[m][k] = (float)D.rad_w7[m][k];
+        }
     D.sponge_w = h.d.sponge_cells;
     D.sponge_s = h.d.sponge_sigma;
     D.sponge_inv = h.d.sponge_cells > 0 ? 1.0 / h.d.sponge_cells : 0.0;
@@ -845,6 +871,8 @@ lee_status lee_set_tiling(lee_instance *I, const lee_tiling *t)
 {
     if (!I || !t) return fail(LEE_E_ARG, "null argument");
     if (!tiling_valid(I->host.d.precision, *t)) return fail(LEE_E_ARG, "unsupported tiling");
+    if (t->kind == LEE_SWEEP_MARCH && I->host.d.radiation)
+        return fail(LEE_E_ARG, "the march sweep has no radiation band; use a tile sweep");
     if (I->next_stage != 0) return fail(LEE_E_STATE, "a partial step is pending");
     I->tl = *t;
     drop_graph(I);
@@ -1301,6 +1329,8 @@ lee_status member_ok(const lee_batch *B, const lee_instance *I)
     if (I->host.d.precision != B->prec) return fail(LEE_E_ARG, "mixed precision");
     if ((I->host.d.filter_sigma > 0.0) != B->filt) return fail(LEE_E_ARG, "mixed filter on/off");
     if (I->device != B->device) return fail(LEE_E_ARG, "members on different devices");
+    if (I->host.d.radiation && B->tl.kind == LEE_SWEEP_MARCH)
+        return fail(LEE_E_ARG, "the march sweep has no radiation band");
     return LEE_OK;
 }
 
@@ -1493,6 +1523,9 @@ lee_status lee_batch_set_tiling(lee_batch *B, const lee_tiling *t)
 {
     if (!B || !t) return fail(LEE_E_ARG, "null argument");
     if (!tiling_valid(B->prec, *t)) return fail(LEE_E_ARG, "unsupported tiling");
+    if (t->kind == LEE_SWEEP_MARCH)
+        for (lee_instance *m : B->members)
+            if (m->host.d.radiation) return fail(LEE_E_ARG, "the march sweep has no radiation band");
     HIPCHK(hipStreamSynchronize(B->stream));     // the old lists may still be read
     B->tl = *t;
     return batch_rebuild(B, true);

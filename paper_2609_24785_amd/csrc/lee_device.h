@@ -57,6 +57,11 @@ struct DevInst {
     double ade[4];
     double ade_st[8][5];    // kind 3: per state a, bn, bp, f, c of
                             // dX_k = a X_k + bn X_{k+1} + bp X_{k-1} + f p_BP, u_n = sum c X_k
+    int rad_w;              // radiation band width (nodes closer than rad_w to an edge; 0 = none)
+    double rad_xc, rad_yc;  // its centre
+    double rad_w7[7][7];    // first-derivative weights / h on a 7-node window, node at place r:
+                            // r = 3 the central set a_k, else the one-sided maximal-order set
+    float rad_wf[7][7];
 };
 
 // Probe sampling carried by a launch: the (member, probe) pairs pw[0, np),

@@ -96,6 +96,22 @@ lee_status host_setup(const lee_case_desc *dp, Host *H)
             ++runs;
         }
     }
+    // radiation band: the band and everything its stencils read is fluid, and
+    // the centre keeps a grid step from every band node
+    if (d.radiation != 0) {
+        if (d.radiation != 1) return fail(LEE_E_ARG, "radiation must be 0 or 1");
+        const int W = d.stencil_half, reach = W + 6;
+        if (nx <= 2 * reach || ny <= 2 * reach) return fail(LEE_E_ARG, "radiation condition: grid too small");
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                const int e = std::min(std::min(i, j), std::min(nx - 1 - i, ny - 1 - j));
+                if (e >= reach) continue;
+                if (!H->fluid[(size_t)j * nx + i])
+                    return fail(LEE_E_ARG, "radiation condition: the wall comes within reach of the outer band");
+                if (e < W && std::hypot(node_x(d, i) - d.rad_xc, node_y(d, j) - d.rad_yc) < d.h)
+                    return fail(LEE_E_ARG, "radiation condition: centre too close to the outer band");
+            }
+    }
     // ghost points: solid nodes reached by a fluid node's stencil along x or y
     H->gidx.clear();
     if (d.wall_kind != LEE_WALL_NONE) {

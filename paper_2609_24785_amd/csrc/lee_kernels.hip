@@ -788,7 +788,7 @@ __device__ __forceinline__ T sload(const void *p)
 template <typename T>
 struct TileCtx {
     int c0, r0, r1, ib, ob;
-    bool in_sponge, has_src;
+    bool in_sponge, has_src, in_band;
     T adt, sp_inv, sp_s, amp;
     T ax[5], fd[6];
 };
@@ -809,6 +809,8 @@ __device__ __forceinline__ TileCtx<T> tile_ctx(const DevInst &I, const int4 wk, 
     c.in_sponge = sw > 0 && (c.c0 < sw || c.r0 < sw || c.c0 + TX > I.nx - sw || c.r1 > I.ny - sw);
     c.sp_inv = (T)I.sponge_inv;
     c.sp_s = (T)I.sponge_s;
+    const int rw = I.rad_w;
+    c.in_band = rw > 0 && (c.c0 < rw || c.r0 < rw || c.c0 + TX > I.nx - rw || c.r1 > I.ny - rw);
     c.has_src = I.has_src && !(I.src_i1 < c.c0 || I.src_i0 >= c.c0 + TX) && !(I.src_j1 < c.r0 || I.src_j0 >= c.r1);
     c.amp = c.has_src ? (T)src_amp(I, step, stage) : (T)0;
     return c;
@@ -963,6 +965,8 @@ __device__ __forceinline__ void tile_row(const DevInst &I, const TileCtx<T> &c, 
         uo.v[e] = un.v[e] + c.adt * ru[e];
         vo.v[e] = vn.v[e] + c.adt * rv[e];
         ok[e] = (col >= iv.x && col < iv.y) || (col >= iv.z && col < iv.w);
+        if (c.in_band && min(min(col, j), min(I.nx - 1 - col, I.ny - 1 - j)) < I.rad_w)
+            ok[e] = false;                       // the band pass writes these
         all = all && ok[e];
     }
 }
@@ -992,6 +996,93 @@ __device__ __forceinline__ void tile_store(const DevInst &I, int ob, unsigned of
     }
 }
 
+template <typename T>
+__device__ __forceinline__ T rad_w(const DevInst &I, int r, int k);
+template <>
+__device__ __forceinline__ float rad_w<float>(const DevInst &I, int r, int k) { return I.rad_wf[r][k]; }
+template <>
+__device__ __forceinline__ double rad_w<double>(const DevInst &I, int r, int k) { return I.rad_w7[r][k]; }
+
+// Place of a node in the 7-node window inside the domain along one axis
+// (node i of n): 3 (central) where three nodes lie on either side, else the
+// distance to the near edge, mirrored at the far one.
+__device__ __forceinline__ int rad_place(int i, int n)
+{
+    const int hi = n - 1 - i;
+    return i < 3 ? i : (hi < 3 ? 6 - hi : 3);
+}
+
+// Radiation band (the nodes closer than rad_w to an edge of the domain) in
+// the row pass: for the band nodes among a row's VEC nodes, the outgoing-
+// wave form of the LEE without mean flow replaces the interior right-hand
+// side, dq/dt = -(cos(theta) dq/dx + sin(theta) dq/dy + q/(2r)) for q = p, u,
+// v with r and theta about the instance's centre, no filter term, plus the
+// sponge and source terms of the row pass.  The 7-node windows come from the
+// tile's LDS copy of the stage input (x windows in the tile's own rows, y
+// windows in its columns between the halo rows); a y window that leaves the
+// copied rows (a one-row tile at the top edge) reads global memory.  wt holds
+// the window weights.  The whole band and every node it reads are fluid
+// (checked at set-up), so no ghost value is involved.
+template <typename T, int VEC, int TX, int TY>
+__device__ __forceinline__ void band_row(const DevInst &I, const TileCtx<T> &c, const T (*reg)[TY + 10][TX + 16],
+                                         const T (*wt)[7], int stage, int i, int tc, const VecT<T, VEC> &pn,
+                                         const VecT<T, VEC> &un, const VecT<T, VEC> &vn, VecT<T, VEC> &po,
+                                         VecT<T, VEC> &uo, VecT<T, VEC> &vo, bool (&ok)[VEC], bool &all)
+{
+    const int W = I.rad_w, nx = I.nx, ny = I.ny;
+    const int j = c.r0 + i;
+    const int ry = rad_place(j, ny);
+    const int y0 = j - ry - (c.r0 - 5);          // LDS row of the y window's first node
+    const bool ylds = y0 >= 0 && y0 + 6 < TY + 10;
+    all = true;
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+        const int col = c.c0 + tc + e;
+        const int eg = min(min(col, j), min(nx - 1 - col, ny - 1 - j));
+        if (col < nx && eg < W) {
+            const int rx = rad_place(col, nx);
+            const int lc = tc + e + 8;
+            const double x = I.x0 + col * I.h - I.rad_xc, y = I.y0 + j * I.h - I.rad_yc;
+            const double r = sqrt(x * x + y * y);
+            const T ct = (T)(x / r), st = (T)(y / r), hr = (T)(0.5 / r);
+            T sg = 0;
+            if (c.in_sponge && eg < I.sponge_w) {
+                const T fr = (T)(I.sponge_w - eg) * c.sp_inv;
+                sg = c.sp_s * fr * fr;
+            }
+            T out[3];
+#pragma unroll 1
+            for (int f = 0; f < 3; ++f) {
+                const T *row = &reg[f][i + 5][0];
+                T dx = 0, dy = 0;
+#pragma unroll
+                for (int k = 0; k < 7; ++k) dx += wt[rx][k] * row[lc - rx + k];
+                if (ylds) {
+#pragma unroll
+                    for (int k = 0; k < 7; ++k) dy += wt[ry][k] * reg[f][y0 + k][lc];
+                } else {
+                    const GLOBAL T *q = gp<T>(I.f[c.ib][f]) + (I.org + (j - ry) * I.pitch + col);
+#pragma unroll 1
+                    for (int k = 0; k < 7; ++k) dy += wt[ry][k] * q[k * I.pitch];
+                }
+                const T qc = row[lc];
+                T rq = -(ct * dx + st * dy + hr * qc) - sg * qc;
+                if (f == 0 && c.has_src) {
+                    const T xx = (T)(col - I.src_ic) * (T)I.h - (T)I.src_fx;
+                    const T yy = (T)(j - I.src_jc) * (T)I.h - (T)I.src_fy;
+                    rq += c.amp * exp(-(T)I.src_b * (xx * xx + yy * yy));
+                }
+                out[f] = c.adt * rq + (stage != 0 ? (f == 0 ? pn.v[e] : (f == 1 ? un.v[e] : vn.v[e])) : qc);
+            }
+            po.v[e] = out[0];
+            uo.v[e] = out[1];
+            vo.v[e] = out[2];
+            ok[e] = true;
+        }
+        all = all && ok[e];
+    }
+}
+
 // One tile: wk = {instance, first column, first row, +-(end row)}.
 template <typename T, int VEC, bool FILT, int TX, int TY>
 __device__ __forceinline__ void tile_body(const DevInst *__restrict__ insts, const int4 wk, int stage, int slot,
@@ -1005,6 +1096,8 @@ __device__ __forceinline__ void tile_body(const DevInst *__restrict__ insts, con
     const int tid = threadIdx.x;
     const TileCtx<T> c = tile_ctx<T, TX>(I, wk, stage, step);
     tile_copy<T, VEC, TX, TY>(I, c, lds);
+    __shared__ T wt[7][7];                       // radiation window weights (band tiles only)
+    if (c.in_band && tid < 49) wt[tid / 7][tid % 7] = rad_w<T>(I, tid / 7, tid % 7);
     // while the copy flies: this lane's first row ranges and its first patch
     // entries
     const int i0 = tid / G::NCX;
@@ -1036,8 +1129,10 @@ __device__ __forceinline__ void tile_body(const DevInst *__restrict__ insts, con
         bool ok[VEC];
         bool all;
         tile_row<T, VEC, FILT, TX, TY>(I, c, lds, stage, i, tc, iv, pn, un, vn, po, uo, vo, ok, all);
+        if (c.in_band) band_row<T, VEC, TX, TY>(I, c, lds, wt, stage, i, tc, pn, un, vn, po, uo, vo, ok, all);
         tile_store<T, VEC>(I, c.ob, (unsigned)(I.org + j * I.pitch + c.c0 + tc), po, uo, vo, ok, all);
     }
+
 }
 
 // Work items of the tile sweep: x = instance | DEP_BIT when the tile's read

@@ -61,6 +61,9 @@ def case_desc(case, precision: str = "f32") -> CaseDesc:
         d.src_kind = 1
         for k, v in enumerate((s.xs, s.ys, s.a, s.w, s.omega)):
             d.src[k] = v
+    if getattr(case, "radiation", False):
+        d.radiation = 1
+        d.rad_xc, d.rad_yc = case.rad_center
     return d
 
 

@@ -266,3 +266,50 @@ def test_spent_ghost_wait_is_reported_not_hung():
     b.step_n(2)
     b.synchronize()
     b.close()
+
+
+# the outer radiation condition in place of the zero frame: the band's
+# one-sided stencils and the outgoing-wave equation against the oracle, with
+# the pulse crossing the band (150 steps: t = 12.5, the pulse starts 5 from
+# the nearest edge)
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-9), ("f32", 1e-4)])
+@pytest.mark.parametrize("fused", [0, 1])
+@pytest.mark.parametrize("H,fs", [(5, 0.2), (3, 0.0)], ids=["11pt-filter", "paper-scheme"])
+def test_radiation_condition_matches_oracle(prec, tol, fused, H, fs):
+    case = lc.radiating_cylinder(96, 150, H=H, filter_sigma=fs)
+    cols = 128 if prec == "f32" else 64
+    _compare(case, 150, prec, tol, tiling=dict(kind="tile", cols=cols, rows=8, fused=fused))
+
+
+def test_radiation_condition_other_tile_shapes():
+    case = lc.radiating_cylinder(96, 150)
+    for cols, rows in ((64, 16), (256, 4)):
+        _compare(case, 150, "f32", 1e-4, tiling=dict(kind="tile", cols=cols, rows=rows, fused=1))
+    # 97 rows: the top tile holds one row, whose y windows leave the copied
+    # rows and are read from global memory
+    case = lc.radiating_cylinder(90, 150)
+    assert case.ny % 8 == 1 and case.ny % 16 == 1
+    for prec, tol, cols, rows in (("f64", 1e-9, 64, 8), ("f32", 1e-4, 128, 8), ("f32", 1e-4, 64, 16)):
+        _compare(case, 150, prec, tol, tiling=dict(kind="tile", cols=cols, rows=rows, fused=1))
+
+
+def test_radiation_batch_equals_solo_bitwise():
+    Instance, Batch = _lee()
+    cases = [lc.radiating_cylinder(96, 150), lc.radiating_cylinder(80, 150, impedance=lc.Impedance("rigid")),
+             lc.small_cylinder(96, 150)]
+    _say(f"[parity] radiation batch of {len(cases)}")
+    solo = []
+    for c in cases:
+        i = Instance(c, "f32")
+        i.set_tiling("tile", cols=128, rows=8, fused=0)
+        i.step_n(150)
+        i.synchronize()
+        solo.append(i.fields())
+        i.close()
+    mem = [Instance(c, "f32") for c in cases]
+    b = Batch(mem, tiling=dict(kind="tile", cols=128, rows=8, fused=1))
+    b.step_n(150)
+    b.synchronize()
+    for m, ref in zip(mem, solo):
+        for x, y in zip(m.fields(), ref):
+            assert np.array_equal(x, y)

@@ -173,3 +173,19 @@ def test_multipole_wall_set_up_and_rejections():
         with pytest.raises(LeeError) as e:
             _host_instance(base.replace(impedance=z))
         assert e.value.status == status, z
+
+
+def test_radiation_setup_and_rejections():
+    from paper_2609_24785_amd._lib import LeeError
+    c = lc.radiating_cylinder(96)
+    inst = _host_instance(c, "f32")
+    with pytest.raises(LeeError) as e:               # the march sweep has no band
+        inst.set_tiling("march", vec=4, rows=16)
+    assert e.value.status == -1
+    inst.set_tiling("tile", cols=128, rows=8, fused=1)
+    inst.close()
+    for bad in (c.replace(wall=lc.Wall("circle", 6.5, 0.0, rc=1.3)),        # wall within reach of the band
+                c.replace(rad_center=(-7.9, 0.0), wall=lc.Wall())):         # centre in the band
+        with pytest.raises(LeeError) as e:
+            _host_instance(bad)
+        assert e.value.status == -1
