@@ -1042,9 +1042,10 @@ __device__ __forceinline__ void band_row(const DevInst &I, const TileCtx<T> &c, 
         if (col < nx && eg < W) {
             const int rx = rad_place(col, nx);
             const int lc = tc + e + 8;
-            const double x = I.x0 + col * I.h - I.rad_xc, y = I.y0 + j * I.h - I.rad_yc;
-            const double r = sqrt(x * x + y * y);
-            const T ct = (T)(x / r), st = (T)(y / r), hr = (T)(0.5 / r);
+            // node position about the centre: the offsets in FP64, the rest in T
+            const T x = (T)(I.x0 - I.rad_xc) + (T)col * (T)I.h, y = (T)(I.y0 - I.rad_yc) + (T)j * (T)I.h;
+            const T ir = (T)1 / sqrt(x * x + y * y);
+            const T ct = x * ir, st = y * ir, hr = (T)0.5 * ir;
             T sg = 0;
             if (c.in_sponge && eg < I.sponge_w) {
                 const T fr = (T)(I.sponge_w - eg) * c.sp_inv;
