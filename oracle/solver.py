@@ -3,9 +3,12 @@ FP64) and advances it with the plain C core.  TEST INFRASTRUCTURE ONLY.
 
 Initial state (Sec. 2.1): q0 = [p0, u0, v0] at fluid nodes; ghost, solid and
 frame nodes and the auxiliary states start at zero.  The frame of F = 5
-nodes around the domain stays zero (reading: the paper's one-sided boundary
-stencils and non-reflecting conditions are not specified; an outer sponge
-layer, when enabled, absorbs outgoing waves).
+nodes around the domain stays zero.  Outer boundary: by default nothing more
+than that frame (plus an outer sponge layer when enabled); with
+case.radiation, the nodes closer than H to an edge solve the outgoing-wave
+equation with one-sided stencils (the paper names one-sided stencils and a
+non-reflecting condition on the outer boundary without printing either;
+the reading is stated in core.c).
 
 Sponge reading: sigma_s = sigma_max ((W - e) / W)^2 for a node e < W cells
 from the nearest domain edge, zero elsewhere.
