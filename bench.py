@@ -383,6 +383,24 @@ def extras(args):
         rp["inst"].close()
     out["cylinder_pulse_1024_radiation"] = dict(steps=pm_steps, unit=UNIT, **rres)
 
+    # the paper's own cylinder-pulse configuration (7-point scheme, no filter,
+    # radiation on all four sides, 301^2); FP64 is checked against the oracle
+    print("[extras] paper cylinder pulse 301^2", file=sys.stderr, flush=True)
+    pc_steps = 400
+    pc = lc.paper_cylinder_pulse(pc_steps)
+    pres = {}
+    for prec in ("f32", "f64"):
+        ch = tune.tune_case(pc, prec, cache)
+        rp = _timed(pc, prec, pc_steps, 0, ch)
+        pres[prec] = {"value": rp["value"], "ms_per_step": 1000.0 * rp["wall"] / rp["steps"],
+                      "tiling": ch["tiling"]}
+        if prec == "f64":
+            s = osv.OracleSolver(pc)
+            s.run(pc_steps)
+            pres[prec]["rel_l2_vs_oracle"] = _max_rel_l2(rp["inst"].fields(), s.fields(), s.fluid)
+        rp["inst"].close()
+    out["paper_cylinder_pulse_301"] = dict(steps=pc_steps, unit=UNIT, **pres)
+
     # spectral stability of the step map (abstract): assembled on the GPU for
     # coarse cylinders and checked against the oracle's assembly; the growth
     # per step of the worst mode of the benchmark grid by power iteration

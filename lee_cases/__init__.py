@@ -332,6 +332,24 @@ def radiating_cylinder(n: int = 96, steps: int = 120, impedance: Optional[Impeda
     )
 
 
+def paper_cylinder_pulse(steps: int = 400) -> Case:
+    """The paper's own cylinder-pulse configuration (Sec. 4.2): [-6, 6]^2 at
+    h = 0.04 (301^2 nodes), cylinder r_c = 0.5 at the origin, Gaussian pulse
+    of amplitude 1 and half-width 0.2 at (4, 0), mass-spring-damper wall
+    (M, K, R) = (0.025, 1.6, 0.2), CFL 0.5, the paper's scheme (7-point DRP,
+    no filter) and the non-reflecting condition on all four sides (centre at
+    the origin).  Probes on r = 2."""
+    return Case(
+        nx=301, ny=301, x0=-6.0, y0=-6.0, h=0.04, H=3, cfl=0.5, filter_sigma=0.0,
+        wall=Wall("circle", 0.0, 0.0, rc=0.5),
+        impedance=Impedance("msd", R=0.2, M=0.025, K=1.6),
+        ic=Pulse(4.0, 0.0, 1.0, 0.2), steps=steps,
+        probes=((2.0, 0.0), (0.0, 2.0), (-2.0, 0.0), (0.0, -2.0)),
+        radiation=True, rad_center=(0.0, 0.0),
+        name="paper-cylinder-pulse-301",
+    )
+
+
 def named(name: str) -> Case:
     table = {
         "flat-wall-201": flat_wall_201,

@@ -313,3 +313,13 @@ def test_radiation_batch_equals_solo_bitwise():
     for m, ref in zip(mem, solo):
         for x, y in zip(m.fields(), ref):
             assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-9), ("f32", 1e-4)])
+def test_paper_cylinder_pulse_configuration(prec, tol):
+    # the paper's own configuration: 7-point scheme, no filter, radiation on
+    # all four sides, its impedance; 200 steps take the pulse onto the wall
+    # and its front through the band
+    case = lc.paper_cylinder_pulse(200)
+    cols = 128 if prec == "f32" else 64
+    _compare(case, 200, prec, tol, tiling=dict(kind="tile", cols=cols, rows=8, fused=1))
