@@ -69,6 +69,31 @@ def test_step_matrix_matches_oracle(prec, name, z, H, fs):
         assert err <= 1e-4 * scale and fro <= 1e-5
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_step_matrix_with_radiation_band_matches_oracle(prec):
+    # the band's one-sided stencils and outgoing-wave equation are part of
+    # the step map too (28 x 31 nodes: the band and the 6 nodes it reads
+    # around a cylinder of radius 1.5)
+    Instance, stability = _mods()
+    n = 28
+    case = lc.Case(nx=n, ny=n + 3, x0=-0.5 * (n - 1), y0=-0.5 * (n - 1) - 1.0, h=1.0, H=5, cfl=0.5,
+                   filter_sigma=0.2, wall=lc.Wall("circle", 0.25, 0.125, rc=1.5), impedance=MSD,
+                   radiation=True, rad_center=(0.1, -0.2), name="cyl-24-radiation")
+    _say(f"[stability] step matrix {case.name} prec={prec}")
+    inst = Instance(case, prec)
+    G = stability.step_matrix(inst)
+    inst.close()
+    ref = osp.step_matrix(case)
+    scale = np.abs(ref).max()
+    err = np.abs(G - ref).max()
+    _say(f"[stability] n={G.shape[0]} max|dG|={err:.3e} (scale {scale:.3f})")
+    if prec == "f64":
+        assert err <= 1e-11 * scale
+        assert abs(stability.spectral_radius(G) - osp.spectral_radius(ref)) <= 1e-9
+    else:
+        assert err <= 1e-4 * scale
+
+
 @pytest.mark.parametrize("name,z,H,fs", CASES[:2], ids=[c[0] for c in CASES[:2]])
 def test_power_growth_matches_oracle(name, z, H, fs):
     Instance, stability = _mods()
