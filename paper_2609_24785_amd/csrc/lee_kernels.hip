@@ -1051,20 +1051,26 @@ __device__ __forceinline__ void band_row(const DevInst &I, const TileCtx<T> &c, 
                 const T fr = (T)(I.sponge_w - eg) * c.sp_inv;
                 sg = c.sp_s * fr * fr;
             }
+            T wx[7], wy[7];                      // this node's weights, read once for the three fields
+#pragma unroll
+            for (int k = 0; k < 7; ++k) {
+                wx[k] = wt[rx][k];
+                wy[k] = wt[ry][k];
+            }
             T out[3];
 #pragma unroll 1
             for (int f = 0; f < 3; ++f) {
                 const T *row = &reg[f][i + 5][0];
                 T dx = 0, dy = 0;
 #pragma unroll
-                for (int k = 0; k < 7; ++k) dx += wt[rx][k] * row[lc - rx + k];
+                for (int k = 0; k < 7; ++k) dx += wx[k] * row[lc - rx + k];
                 if (ylds) {
 #pragma unroll
-                    for (int k = 0; k < 7; ++k) dy += wt[ry][k] * reg[f][y0 + k][lc];
+                    for (int k = 0; k < 7; ++k) dy += wy[k] * reg[f][y0 + k][lc];
                 } else {
                     const GLOBAL T *q = gp<T>(I.f[c.ib][f]) + (I.org + (j - ry) * I.pitch + col);
 #pragma unroll 1
-                    for (int k = 0; k < 7; ++k) dy += wt[ry][k] * q[k * I.pitch];
+                    for (int k = 0; k < 7; ++k) dy += wy[k] * q[k * I.pitch];
                 }
                 const T qc = row[lc];
                 T rq = -(ct * dx + st * dy + hr * qc) - sg * qc;
