@@ -19,6 +19,15 @@
  *      with the DRP first derivative (eq. DRP_s), plus the selective-filter
  *      damping term, the outer sponge and the monopole source, and the stage
  *      update q^(l) = q^n + alpha_l dt RHS(q^(l-1)).
+ *
+ * Filter rows (a reading: the paper has no filter): along each axis a fluid
+ * node takes the widest centred filter row whose nodes are all fluid or
+ * outside the domain (the zero frame): the 11-point selective filter where
+ * five nodes on either side qualify, else the standard centred filter of
+ * half-width w (damping function sin^{2w}(k/2)) for the w nodes that do, and
+ * none next to the wall.  The filter so never reads a ghost value: the
+ * extrapolated values made the damping term feed a wall mode that grew as
+ * sigma_d / dt.  The half-widths come per node from the Python side.
  * The auxiliary states follow the same stage update,
  * Psi^(l) = Psi^n + alpha_l dt dPsi/dt.
  *
@@ -50,7 +59,6 @@ typedef struct {
     double h, dt, x0, y0;
     double a[5];            /* DRP a_1..a_H */
     double sigma_d;         /* filter strength, 0 = off */
-    double d[6];            /* filter d_0..d_5 */
     int sponge_w;
     double sponge_smax;
     int has_src;
@@ -73,6 +81,8 @@ typedef struct {
     double rad_xc, rad_yc;      /* centre of the radiation condition */
     double rad_c[3];            /* central 7-point first derivative a_1..a_3 */
     double rad_b[3][7];         /* one-sided 7-point first derivative at point m of 0..6 */
+    const unsigned char *fw;    /* per node, x then y: index of its filter row in frow */
+    double frow[36][11];        /* filter rows: weights of nodes -5..5 */
 } oc_case;
 
 static const double RK_ALPHA[4] = {0.25, 1.0 / 3.0, 0.5, 1.0};
@@ -224,13 +234,16 @@ static void sweep(const oc_case *c, const double *p, const double *u, const doub
             ru = -dpdx;
             rv = -dpdy;
             if (c->sigma_d > 0.0) {
-                double fp = 2.0 * c->d[0] * ps[q];
-                double fu = 2.0 * c->d[0] * us[q];
-                double fv = 2.0 * c->d[0] * vs[q];
-                for (k = 1; k <= 5; ++k) {
-                    fp += c->d[k] * (ps[q + k] + ps[q - k] + ps[q + k * sy] + ps[q - k * sy]);
-                    fu += c->d[k] * (us[q + k] + us[q - k] + us[q + k * sy] + us[q - k * sy]);
-                    fv += c->d[k] * (vs[q + k] + vs[q - k] + vs[q + k * sy] + vs[q - k * sy]);
+                /* selective-filter damping -(sigma_d/dt)(F_x + F_y)q, each
+                 * axis with the row of this node's half-width along it */
+                const long long lin = (long long)j * c->nx + i;
+                const double *wx = c->frow[c->fw[2 * lin]];
+                const double *wy = c->frow[c->fw[2 * lin + 1]];
+                double fp = 0.0, fu = 0.0, fv = 0.0;
+                for (k = -5; k <= 5; ++k) {
+                    fp += wx[k + 5] * ps[q + k] + wy[k + 5] * ps[q + k * sy];
+                    fu += wx[k + 5] * us[q + k] + wy[k + 5] * us[q + k * sy];
+                    fv += wx[k + 5] * vs[q + k] + wy[k + 5] * vs[q + k * sy];
                 }
                 double s = c->sigma_d / c->dt;
                 rp -= s * fp; ru -= s * fu; rv -= s * fv;

@@ -166,6 +166,30 @@ def clouds(case: Case, fluid: np.ndarray, gidx: np.ndarray, bx, by, nxv, nyv, k:
     return (np.asarray(ptr, dtype=np.int64), cat(idx).astype(np.int64), cat(xps), cat(yps), cut)
 
 
+def filter_widths(fluid: np.ndarray) -> np.ndarray:
+    """uint8[ny, nx, 2]: for each fluid node, the half-width (0..5) of its
+    filter row along x (index 0) and y (index 1): the largest w <= 5 such that
+    the nodes i - w .. i + w along that axis hold no non-fluid node inside
+    the domain (nodes past the domain edge are the zero frame and count as
+    available).  Zero at non-fluid nodes."""
+    ny, nx = fluid.shape
+    out = np.zeros((ny, nx, 2), dtype=np.uint8)
+    solid = ~fluid
+    for ax in (0, 1):
+        w = np.where(fluid, 5, 0).astype(np.int64)
+        for d in range(1, 6):
+            near = np.zeros_like(fluid)
+            if ax == 0:
+                near[:, d:] |= solid[:, :-d]      # non-fluid at (i - d, j)
+                near[:, :-d] |= solid[:, d:]      # non-fluid at (i + d, j)
+            else:
+                near[d:, :] |= solid[:-d, :]      # non-fluid at (i, j - d)
+                near[:-d, :] |= solid[d:, :]      # non-fluid at (i, j + d)
+            w = np.where(fluid & near, np.minimum(w, d - 1), w)
+        out[:, :, ax] = w
+    return out
+
+
 def row_intervals(fluid: np.ndarray):
     """Fluid column intervals per row (for reporting; the oracle itself uses the
     mask directly)."""

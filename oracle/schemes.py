@@ -12,6 +12,12 @@
   applied inside every stage as the damping term -(sigma_d/dt)(D_x + D_y) q.
   Pinned by D(0) = 0 (no damping of a constant) and D(pi) = 1 (full removal
   of the grid-scale mode).
+* centred_filter(w): near an immersed wall, where fewer than five fluid
+  nodes lie on one side of a node along an axis, that axis takes the
+  standard centred filter of the largest half-width w that fits in the fluid
+  (w = 0: none): D(k) = sin^{2w}(k/2), i.e. d_j = (-1)^j C(2w, w + j) / 4^w,
+  which is the maximal-order centred filter on 2w + 1 nodes with D(pi) = 1.
+  filter_rows() tabulates the row of every half-width 0..5.
 * RK: the four-stage low-storage Runge-Kutta (Sec. 2.2 cites a low-storage
   fourth-order scheme without printing it).  Reading: the two-register form
   q^(l) = q^n + alpha_l dt RHS(q^(l-1)), alpha = (1/4, 1/3, 1/2, 1), whose
@@ -31,6 +37,27 @@ DRP11 = np.array([0.872756993962, -0.286511173973, 0.090320001280,
 # 11-point selective filter (Bogey & Bailly 2004), d_0 .. d_5.
 FILTER11 = np.array([0.215044884112, -0.187772883589, 0.123755948787,
                      -0.059227575576, 0.018721609157, -0.002999540835])
+
+
+def centred_filter(w: int) -> np.ndarray:
+    """d_0..d_w of the standard centred filter of half-width w (w >= 1):
+    the coefficients of sin^{2w}(k/2) = ((1 - cos k) / 2)^w as
+    d_0 + 2 sum_j d_j cos(j k), i.e. d_j = (-1)^j C(2w, w + j) / 4^w."""
+    from math import comb
+    return np.array([(-1) ** j * comb(2 * w, w + j) / 4.0 ** w for j in range(w + 1)])
+
+
+def filter_rows() -> np.ndarray:
+    """rows[w, 5 + k]: weight of node i + k in the filter row of half-width
+    w at node i, for w = 0..5 (w = 5: FILTER11; w = 0: no filter)."""
+    rows = np.zeros((6, 11))
+    for w in range(1, 6):
+        d = FILTER11 if w == 5 else centred_filter(w)
+        rows[w, 5] = d[0]
+        for j in range(1, w + 1):
+            rows[w, 5 + j] = rows[w, 5 - j] = d[j]
+    return rows
+
 
 RK_ALPHA = np.array([0.25, 1.0 / 3.0, 0.5, 1.0])
 RK_C = np.array([0.0, 0.25, 1.0 / 3.0, 0.5])

@@ -10,6 +10,10 @@ equation with one-sided stencils (the paper names one-sided stencils and a
 non-reflecting condition on the outer boundary without printing either;
 the reading is stated in core.c).
 
+Filter rows: per node and axis, the widest centred filter row that reads no
+non-fluid node of the domain (geometry.filter_widths, schemes.filter_rows;
+the reading is stated in core.c).
+
 Sponge reading: sigma_s = sigma_max ((W - e) / W)^2 for a node e < W cells
 from the nearest domain edge, zero elsewhere.
 
@@ -37,7 +41,7 @@ class _OcCase(ctypes.Structure):
     _fields_ = [
         ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("F", ctypes.c_int), ("H", ctypes.c_int),
         ("h", ctypes.c_double), ("dt", ctypes.c_double), ("x0", ctypes.c_double), ("y0", ctypes.c_double),
-        ("a", ctypes.c_double * 5), ("sigma_d", ctypes.c_double), ("d", ctypes.c_double * 6),
+        ("a", ctypes.c_double * 5), ("sigma_d", ctypes.c_double),
         ("sponge_w", ctypes.c_int), ("sponge_smax", ctypes.c_double),
         ("has_src", ctypes.c_int), ("src_x", ctypes.c_double), ("src_y", ctypes.c_double),
         ("src_a", ctypes.c_double), ("src_b", ctypes.c_double), ("src_omega", ctypes.c_double),
@@ -50,6 +54,7 @@ class _OcCase(ctypes.Structure):
         ("watch_g", ctypes.c_int),
         ("rad_w", ctypes.c_int), ("rad_xc", ctypes.c_double), ("rad_yc", ctypes.c_double),
         ("rad_c", ctypes.c_double * 3), ("rad_b", ctypes.c_double * 21),
+        ("fw", ctypes.c_void_p), ("frow", ctypes.c_double * 396),
     ]
 
 
@@ -106,7 +111,9 @@ def _check_radiation(c: Case, fluid: np.ndarray):
 
 
 class OracleSolver:
-    def __init__(self, case: Case):
+    def __init__(self, case: Case, filter_rows: np.ndarray | None = None):
+        """filter_rows (tests only): rows[w, 5 + k] replacing the filter rows
+        of schemes.filter_rows(), to show what a different reading does."""
         self.case = case
         c = case
         self.fluid = geometry.fluid_mask(c)
@@ -146,6 +153,9 @@ class OracleSolver:
         self.watch_trace = np.zeros((0, 2))
         self._init_fields()
         self.probe_ij, self.probe_w = self._probes()
+        # per node and axis, the half-width of its filter row (schemes, geometry)
+        self.filter_w = geometry.filter_widths(self.fluid)
+        self.filter_rows = schemes.filter_rows() if filter_rows is None else np.asarray(filter_rows, float)
         self._keep = []
         self._cs = self._make_struct()
 
@@ -187,8 +197,9 @@ class OracleSolver:
         for k in range(5):
             s.a[k] = a[k] if k < len(a) else 0.0
         s.sigma_d = c.filter_sigma
-        for k in range(6):
-            s.d[k] = schemes.FILTER11[k]
+        rows = self.filter_rows.ravel()
+        for k in range(len(rows)):
+            s.frow[k] = rows[k]
         s.sponge_w = c.sponge_cells
         s.sponge_smax = c.sponge_sigma
         if isinstance(c.source, Monopole):
@@ -205,8 +216,10 @@ class OracleSolver:
                 np.ascontiguousarray(self.cidx, dtype=np.int64),
                 np.ascontiguousarray(self.W, dtype=np.float64),
                 np.ascontiguousarray(self.lag, dtype=np.float64),
-                np.ascontiguousarray(self.bir, dtype=np.float64)]
+                np.ascontiguousarray(self.bir, dtype=np.float64),
+                np.ascontiguousarray(self.filter_w.reshape(-1))]
         self._keep = keep
+        s.fw = keep[9].ctypes.data
         s.fluid = keep[0].ctypes.data
         s.G = len(self.gidx)
         s.gidx, s.gnx, s.gny = keep[1].ctypes.data, keep[2].ctypes.data, keep[3].ctypes.data

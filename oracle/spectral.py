@@ -34,9 +34,9 @@ from lee_cases import Case
 from .solver import F, OracleSolver
 
 
-def _solver(case: Case) -> OracleSolver:
+def _solver(case: Case, filter_rows=None) -> OracleSolver:
     # The analysis is of the homogeneous scheme: no source, no probes.
-    return OracleSolver(case.replace(ic=None, source=None, probes=(), dft_steps=0))
+    return OracleSolver(case.replace(ic=None, source=None, probes=(), dft_steps=0), filter_rows)
 
 
 def state_size(case: Case) -> int:
@@ -74,9 +74,10 @@ def _get(s: OracleSolver) -> np.ndarray:
     return out
 
 
-def step_matrix(case: Case) -> np.ndarray:
-    """G[n, n]: column k is one full step applied to the k-th unit state."""
-    s = _solver(case)
+def step_matrix(case: Case, filter_rows=None) -> np.ndarray:
+    """G[n, n]: column k is one full step applied to the k-th unit state
+    (filter_rows: see OracleSolver)."""
+    s = _solver(case, filter_rows)
     n = _layout(s)[2]
     G = np.empty((n, n))
     e = np.zeros(n)
