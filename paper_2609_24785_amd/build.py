@@ -3,6 +3,7 @@ so set-up predicates are reproducible), the kernels and the C ABI with hipcc."""
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
@@ -23,14 +24,16 @@ def _run(cmd):
 
 def build(verbose: bool = False) -> str:
     os.makedirs(OUT, exist_ok=True)
-    objs = []
     host_o = os.path.join(OUT, "lee_host.o")
-    _run(["g++", *HOST_FLAGS, "-c", os.path.join(CSRC, "lee_host.cpp"), "-o", host_o])
-    objs.append(host_o)
+    cmds = [["g++", *HOST_FLAGS, "-c", os.path.join(CSRC, "lee_host.cpp"), "-o", host_o]]
+    objs = [host_o]
     for src in ("lee_kernels.hip", "lee_api.hip"):
         o = os.path.join(OUT, src.replace(".hip", ".o"))
-        _run([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", o])
+        cmds.append([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", o])
         objs.append(o)
+    # the three translation units are independent: compile them side by side
+    with ThreadPoolExecutor(max_workers=len(cmds)) as pool:
+        list(pool.map(_run, cmds))
     tmp = LIB + ".tmp"
     _run([HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp, *objs])
     os.replace(tmp, LIB)

@@ -280,6 +280,9 @@ void default_tiling(lee_instance *I)
 // (LDS element index in the tile's copy, ghost index * 3 + field), and items
 // with any are flagged TILE_DEP_BIT.  The stencils of a tile read its own rows over the columns
 // [c0 - 5, c0 + cols + 5) and the 5 rows above and below over [c0, c0 + cols).
+// With the filter on, items whose stencils read a ghost node (in any launch
+// form) are flagged TILE_WALL_BIT: only their nodes can sit closer than five
+// nodes to the wall along an axis, where the filter row narrows.
 void build_items(const Host &h, int inst_id, const lee_tiling &t, std::vector<int4> &items,
                  std::vector<std::vector<int2>> *patches)
 {
@@ -288,10 +291,11 @@ void build_items(const Host &h, int inst_id, const lee_tiling &t, std::vector<in
     const int strips = (h.d.nx + ow - 1) / ow;
     const int tiles = (h.d.ny + rows - 1) / rows;
     const bool fused = t.kind == LEE_SWEEP_TILE && t.fused && patches;
+    const bool walls = h.d.filter_sigma > 0.0 && !h.gidx.empty();
     // ghost columns by row (ascending: the ghost list is sorted by linear
     // index) and the ghost index of each
     std::vector<std::vector<int>> grow_cols, grow_g;
-    if (fused) {
+    if (fused || walls) {
         grow_cols.resize(h.d.ny);
         grow_g.resize(h.d.ny);
         for (size_t g = 0; g < h.gidx.size(); ++g) {
@@ -312,19 +316,22 @@ void build_items(const Host &h, int inst_id, const lee_tiling &t, std::vector<in
             }
             if (!any) continue;
             std::vector<int2> pl;
-            if (fused) {
+            bool wall = false;
+            if (fused || walls) {
                 for (int j = std::max(0, r0 - 5); j < std::min(h.d.ny, r0 + rows + 5); ++j) {
                     const bool own = j >= r0 && j < r0 + rows;
                     const int lo = own ? c0 - 5 : c0, hi = own ? c0 + ow + 5 : c0 + ow;
                     const std::vector<int> &gc = grow_cols[j];
                     for (auto it = std::lower_bound(gc.begin(), gc.end(), lo); it != gc.end() && *it < hi; ++it) {
+                        wall = walls;
+                        if (!fused) break;
                         const int g = grow_g[j][it - gc.begin()];
                         for (int f = 0; f < 3; ++f)
                             pl.push_back(make_int2((j - (r0 - 5)) * LW + (*it - (c0 - 8)), 3 * g + f));
                     }
                 }
             }
-            const int flag = pl.empty() ? 0 : TILE_DEP_BIT;
+            const int flag = (pl.empty() ? 0 : TILE_DEP_BIT) | (wall ? TILE_WALL_BIT : 0);
             items.push_back(make_int4(inst_id | flag, c0, r0, (r & 1) ? -r1 : r1));
             if (patches) patches->push_back(std::move(pl));
         }
@@ -695,6 +702,24 @@ lee_status lee_bind(lee_instance *I, void *dev_ptr, size_t bytes, void *hip_stre
     for (int k = 1; k < 6; ++k) D.fd[k] = sd * FD[k];
     for (int k = 0; k < 5; ++k) D.axf[k] = (float)D.ax[k];
     for (int k = 0; k < 6; ++k) D.fdf[k] = (float)D.fd[k];
+    // near an immersed wall an axis of half-width w < 5 takes the standard
+    // centred filter of that half-width, whose damping function is
+    // ((1 - cos k) / 2)^w: its row is the w-fold convolution of the
+    // three-point row (-1/4, 1/2, -1/4); none for w = 0
+    for (int w = 0; w < 5; ++w) {
+        double row[11] = {0};                    // offsets -5..5
+        if (w > 0) {
+            row[5] = 1.0;
+            for (int c = 0; c < w; ++c) {
+                double nxt[11] = {0};
+                for (int k = 1; k < 10; ++k) nxt[k] = 0.5 * row[k] - 0.25 * (row[k - 1] + row[k + 1]);
+                std::memcpy(row, nxt, sizeof(row));
+            }
+        }
+        for (int j = 0; j < 6; ++j) D.fdw[w][j] = sd * (row[5 + j] - FD[j]);
+    }
+    for (int w = 0; w < 6; ++w)
+        for (int j = 0; j < 6; ++j) D.fdwf[w][j] = (float)D.fdw[w][j];
     static const double ALPHA[4] = {0.25, 1.0 / 3.0, 0.5, 1.0};
     static const double CST[4] = {0.0, 0.25, 1.0 / 3.0, 0.5};
     for (int l = 0; l < 4; ++l) {

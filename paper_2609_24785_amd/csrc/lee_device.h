@@ -49,6 +49,12 @@ struct DevInst {
     float axf[5];           // the same in FP32
     float fdf[6];           // fd in FP32
     double fd[6];           // (sigma_d / dt) * (2 d_0, d_1 .. d_5): damping of D_x + D_y
+    double fdw[6][6];       // per axis, a node whose filter row has half-width w < 5 (no
+                            // non-fluid node of the domain within w along that axis) takes
+                            // fd + fdw[w]: (sigma_d / dt) * (b_0 - d_0, b_1 - d_1, .., -d_5)
+                            // with b the standard centred filter of half-width w (none for
+                            // w = 0); row 5 is zero
+    float fdwf[6][6];       // the same in FP32
     double alpha_dt[4];     // alpha_l dt
     double c_stage[4];      // stage time offsets c_l (in steps)
     double sponge_s;
@@ -99,6 +105,10 @@ hipError_t launch_stage(int prec, bool filt, int tx, int ty, const DevInst *inst
                         const int4 *work2, int nwork2, int stage, int slot, int *sync, int spin_limit, ProbePass pp,
                         hipStream_t s);
 constexpr int TILE_DEP_BIT = 1 << 30;
+// Sweep items whose read region holds a ghost node (in either launch form):
+// their rows take the near-wall filter rows (fdw).
+constexpr int TILE_WALL_BIT = 1 << 29;
+constexpr int TILE_INST_MASK = TILE_WALL_BIT - 1;
 constexpr int SYNC_INTS = 8;
 constexpr int SPIN_LIMIT = 1 << 20;             // polls before a ghost wait gives up (about a second)
 // The ghost fill of a stage, with the probe pass in extra workgroups (ninst,

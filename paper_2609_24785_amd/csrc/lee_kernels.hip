@@ -388,6 +388,63 @@ __global__ void k_advance(const DevInst *__restrict__ insts, int ninst, int n)
 }
 
 // ---------------------------------------------------------------------------
+// the filter next to an immersed wall
+
+// Fluid intervals of a row outside the domain: every column counts as open
+// (the zero frame is not a wall).
+__device__ __forceinline__ int4 open_row() { return make_int4(-(1 << 30), 1 << 30, 0, 0); }
+
+__device__ __forceinline__ bool in_iv(const int4 iv, int col)
+{
+    return (col >= iv.x && col < iv.y) || (col >= iv.z && col < iv.w);
+}
+
+// Half-width (0..5) of the filter row along x of fluid node col of a row
+// with fluid intervals iv: the nodes up to w away on either side hold no
+// non-fluid node of the domain (an interval that reaches the domain edge is
+// open beyond it).
+__device__ __forceinline__ int x_width(const int4 iv, int col, int nx)
+{
+    const bool first = col >= iv.x && col < iv.y;
+    const int a = first ? iv.x : iv.z, b = first ? iv.y : iv.w;
+    const int lo = a == 0 ? 5 : min(col - a, 5);
+    const int hi = b == nx ? 5 : min(b - 1 - col, 5);
+    return min(lo, hi);
+}
+
+// The same along y for column col, with row(k) the intervals of row j + k.
+template <typename R>
+__device__ __forceinline__ int y_width(const R &row, int col)
+{
+    int w = 5;
+#pragma unroll
+    for (int k = 5; k >= 1; --k)
+        if (!in_iv(row(-k), col) || !in_iv(row(k), col)) w = k - 1;
+    return w;
+}
+
+// Change of one field's filter sum at a node whose rows have half-widths wx
+// and wy: sum over both axes of dw[w][0] q_0 + sum_k dw[w][k] (q_k + q_-k),
+// dw[w] being the half-width-w row minus the 11-point one (times sigma/dt;
+// zero for w = 5).  qx(k), qy(k): the field at offset k along x, y.
+template <typename T, typename QX, typename QY>
+__device__ __forceinline__ T wall_filter_delta(const T (*dw)[6], int wx, int wy, const QX &qx, const QY &qy)
+{
+    const T q0 = qx(0);
+    T d = dw[wx][0] * q0 + dw[wy][0] * q0;
+#pragma unroll
+    for (int k = 1; k <= 5; ++k) d += dw[wx][k] * (qx(k) + qx(-k)) + dw[wy][k] * (qy(k) + qy(-k));
+    return d;
+}
+
+template <typename T>
+__device__ __forceinline__ T fdw_at(const DevInst &I, int w, int k);
+template <>
+__device__ __forceinline__ float fdw_at<float>(const DevInst &I, int w, int k) { return I.fdwf[w][k]; }
+template <>
+__device__ __forceinline__ double fdw_at<double>(const DevInst &I, int w, int k) { return I.fdw[w][k]; }
+
+// ---------------------------------------------------------------------------
 // stage sweep
 
 template <typename T, int VEC>
@@ -421,7 +478,8 @@ __global__ __launch_bounds__(64 * WPB) void k_sweep(const DevInst *__restrict__ 
     for (int w = blockIdx.x * WPB + wv; w < nwork; w += gridDim.x * WPB) {
         const int4 wk = work[w];
         if (wk.x < 0) continue;                   // idle slot of the XCD-aware order
-        const DevInst &I = insts[wk.x];
+        const bool wall = FILT && (wk.x & TILE_WALL_BIT) != 0;
+        const DevInst &I = insts[wk.x & TILE_INST_MASK];
         const long long step = step_at(I, slot);
         if (!takes(I, step)) continue;            // uniform per wave
         const int c0 = wk.y;                      // first output column
@@ -539,6 +597,37 @@ __global__ __launch_bounds__(64 * WPB) void k_sweep(const DevInst *__restrict__ 
                             else if (f == 1) ru[e] -= fx;
                             else rv[e] -= fx;
                         }
+                    }
+                }
+                if (wall) {                      // nodes within five of the wall along an axis
+                    const int ny = I.ny;
+                    int4 rows[11];
+#pragma unroll
+                    for (int k = -5; k <= 5; ++k)
+                        rows[k + 5] = j + k >= 0 && j + k < ny ? int4(gp<int4>(I.iv)[j + k]) : open_row();
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) {
+                        const int col = col0 + e;
+                        if (!in_iv(iv, col)) continue;
+                        const int wx = x_width(iv, col, I.nx);
+                        const int wy = y_width([&](int k) { return rows[k + 5]; }, col);
+                        if (wx == 5 && wy == 5) continue;
+                        T dw[6][6];
+#pragma unroll
+                        for (int k = 0; k < 6; ++k) {
+                            dw[0][k] = fdw_at<T>(I, wx, k);
+                            dw[1][k] = fdw_at<T>(I, wy, k);
+                        }
+                        const T(*dwp)[6] = dw;
+                        T d[3];
+#pragma unroll
+                        for (int f = 0; f < 3; ++f) {
+                            d[f] = wall_filter_delta<T>(dwp, 0, 1, [&](int k) { return lds[f][lane * VEC + e + k]; },
+                                                        [&](int k) { return q[5 + k][f][e]; });
+                        }
+                        rp[e] -= d[0];
+                        ru[e] -= d[1];
+                        rv[e] -= d[2];
                     }
                 }
                 T ro[3][VEC];
@@ -788,15 +877,16 @@ __device__ __forceinline__ T sload(const void *p)
 template <typename T>
 struct TileCtx {
     int c0, r0, r1, ib, ob;
-    bool in_sponge, has_src, in_band;
+    bool in_sponge, has_src, in_band, wall;
     T adt, sp_inv, sp_s, amp;
     T ax[5], fd[6];
 };
 
 template <typename T, int TX>
-__device__ __forceinline__ TileCtx<T> tile_ctx(const DevInst &I, const int4 wk, int stage, long long step)
+__device__ __forceinline__ TileCtx<T> tile_ctx(const DevInst &I, const int4 wk, int stage, long long step, bool wall)
 {
     TileCtx<T> c;
+    c.wall = wall;
     c.c0 = wk.y;
     c.r0 = wk.z;
     c.r1 = wk.w < 0 ? -wk.w : wk.w;
@@ -917,6 +1007,7 @@ __device__ __forceinline__ void tile_patch(const DevInst &I, unsigned epoch, T (
 // new values and which of the nodes are fluid.
 template <typename T, int VEC, bool FILT, int TX, int TY>
 __device__ __forceinline__ void tile_row(const DevInst &I, const TileCtx<T> &c, const T (*reg)[TY + 10][TX + 16],
+                                         const T (*wfd)[6], const int4 *wiv,
                                          int stage, int i, int tc, const int4 iv, const VecT<T, VEC> &pn_,
                                          const VecT<T, VEC> &un_, const VecT<T, VEC> &vn_, VecT<T, VEC> &po,
                                          VecT<T, VEC> &uo, VecT<T, VEC> &vo, bool (&ok)[VEC], bool &all)
@@ -935,6 +1026,32 @@ __device__ __forceinline__ void tile_row(const DevInst &I, const TileCtx<T> &c, 
     row_field<T, VEC, FILT, 1>(reg[1], y, lc, c.ax, c.fd, rp, ru, rv);
     pin_sums<T, VEC>(rp, ru, rv);
     row_field<T, VEC, FILT, 2>(reg[2], y, lc, c.ax, c.fd, rp, ru, rv);
+    if (FILT && c.wall) {
+        // nodes within five of the wall along an axis: that axis takes the
+        // narrower centred row (wfd: its difference from the 11-point one),
+        // wiv[y + k] the intervals of row j + k
+        pin_sums<T, VEC>(rp, ru, rv);
+        const int4 own = wiv[y];
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+            const int col = gc + e;
+            if (!in_iv(own, col)) continue;
+            const int wx = x_width(own, col, I.nx);
+            const int wy = y_width([&](int k) { return wiv[y + k]; }, col);
+            if (wx == 5 && wy == 5) continue;
+            const int cx = lc + e;
+            T d[3];
+#pragma unroll
+            for (int f = 0; f < 3; ++f) {
+                const T(*L)[TX + 16] = reg[f];
+                d[f] = wall_filter_delta<T>(wfd, wx, wy, [&](int k) { return L[y][cx + k]; },
+                                            [&](int k) { return L[y + k][cx]; });
+            }
+            rp[e] -= d[0];
+            ru[e] -= d[1];
+            rv[e] -= d[2];
+        }
+    }
     const VecT<T, VEC> pc = *(const VecT<T, VEC> *)&reg[0][y][lc];
     const VecT<T, VEC> uc = *(const VecT<T, VEC> *)&reg[1][y][lc];
     const VecT<T, VEC> vc = *(const VecT<T, VEC> *)&reg[2][y][lc];
@@ -1093,7 +1210,7 @@ __device__ __forceinline__ void band_row(const DevInst &I, const TileCtx<T> &c, 
 // One tile: wk = {instance, first column, first row, +-(end row)}.
 template <typename T, int VEC, bool FILT, int TX, int TY>
 __device__ __forceinline__ void tile_body(const DevInst *__restrict__ insts, const int4 wk, int stage, int slot,
-                                          const GhostDep *dep)
+                                          const GhostDep *dep, bool wall)
 {
     using G = TileGeo<T, VEC, TX, TY>;
     __shared__ alignas(16) T lds[3][G::R][G::LW];
@@ -1101,10 +1218,19 @@ __device__ __forceinline__ void tile_body(const DevInst *__restrict__ insts, con
     const long long step = sload<long long>(I.step) + slot;
     if (step >= sload<long long>(I.stop)) return;
     const int tid = threadIdx.x;
-    const TileCtx<T> c = tile_ctx<T, TX>(I, wk, stage, step);
+    const TileCtx<T> c = tile_ctx<T, TX>(I, wk, stage, step, FILT && wall);
     tile_copy<T, VEC, TX, TY>(I, c, lds);
     __shared__ T wt[7][7];                       // radiation window weights (band tiles only)
     if (c.in_band && tid < 49) wt[tid / 7][tid % 7] = rad_w<T>(I, tid / 7, tid % 7);
+    // wall tiles: the near-wall filter rows and the fluid intervals of the
+    // copied rows (rows outside the domain are open)
+    __shared__ T wfd[6][6];
+    __shared__ int4 wiv[G::R];
+    if (c.wall) {
+        if (tid < 36) wfd[tid / 6][tid % 6] = fdw_at<T>(I, tid / 6, tid % 6);
+        const int row = c.r0 - 5 + tid;
+        if (tid < G::R) wiv[tid] = row >= 0 && row < I.ny ? int4(gp<int4>(I.iv)[row]) : open_row();
+    }
     // while the copy flies: this lane's first row ranges and its first patch
     // entries
     const int i0 = tid / G::NCX;
@@ -1135,15 +1261,16 @@ __device__ __forceinline__ void tile_body(const DevInst *__restrict__ insts, con
         VecT<T, VEC> po, uo, vo;
         bool ok[VEC];
         bool all;
-        tile_row<T, VEC, FILT, TX, TY>(I, c, lds, stage, i, tc, iv, pn, un, vn, po, uo, vo, ok, all);
+        tile_row<T, VEC, FILT, TX, TY>(I, c, lds, wfd, wiv, stage, i, tc, iv, pn, un, vn, po, uo, vo, ok, all);
         if (c.in_band) band_row<T, VEC, TX, TY>(I, c, lds, wt, stage, i, tc, pn, un, vn, po, uo, vo, ok, all);
         tile_store<T, VEC>(I, c.ob, (unsigned)(I.org + j * I.pitch + c.c0 + tc), po, uo, vo, ok, all);
     }
 
 }
 
-// Work items of the tile sweep: x = instance | DEP_BIT when the tile's read
-// region holds ghost nodes, -1 for an idle slot of the XCD-aware order.
+// Work items of the tile sweep: x = instance | DEP_BIT when a fused tile's
+// read region holds ghost nodes | TILE_WALL_BIT when it does in either form,
+// -1 for an idle slot of the XCD-aware order.
 constexpr int DEP_BIT = TILE_DEP_BIT;
 
 template <typename T, int VEC, bool FILT, int TX, int TY>
@@ -1154,8 +1281,9 @@ __global__ __launch_bounds__(256) void k_tile(const DevInst *__restrict__ insts,
     if (w >= nwork) return;
     int4 wk = work[w];
     if (wk.x < 0) return;
-    wk.x &= DEP_BIT - 1;
-    tile_body<T, VEC, FILT, TX, TY>(insts, wk, stage, slot, nullptr);
+    const bool wall = (wk.x & TILE_WALL_BIT) != 0;
+    wk.x &= TILE_INST_MASK;
+    tile_body<T, VEC, FILT, TX, TY>(insts, wk, stage, slot, nullptr, wall);
 }
 
 // One stage in one launch.  The first ncar workgroups each fill 256 / GL
@@ -1190,13 +1318,15 @@ __global__ __launch_bounds__(256) void k_stage(const DevInst *__restrict__ insts
     if (k < 0 || k >= nwork1) return;
     int4 wk = work1[k];
     if (wk.x < 0) return;
+    const bool wall = (wk.x & TILE_WALL_BIT) != 0;
     if (wk.x & DEP_BIT) {
-        wk.x &= DEP_BIT - 1;
+        wk.x &= TILE_INST_MASK;
         const int2 rg = aux[k];
         const GhostDep dep{&sync[4], spin_limit, patch, rg.x, rg.y};
-        tile_body<T, VEC, FILT, TX, TY>(insts, wk, stage, slot, &dep);
+        tile_body<T, VEC, FILT, TX, TY>(insts, wk, stage, slot, &dep, wall);
     } else {
-        tile_body<T, VEC, FILT, TX, TY>(insts, wk, stage, slot, nullptr);
+        wk.x &= TILE_INST_MASK;
+        tile_body<T, VEC, FILT, TX, TY>(insts, wk, stage, slot, nullptr, wall);
     }
 }
 
