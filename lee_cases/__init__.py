@@ -289,7 +289,7 @@ def small_cylinder(n: int = 96, steps: int = 40, impedance: Optional[Impedance] 
         nx=n, ny=n + 7, x0=-8.0, y0=-8.0 - 3 * h, h=h, H=H, cfl=0.5,
         filter_sigma=filter_sigma,
         wall=Wall("circle", 0.3 * h, 0.3 * h, rc=1.3),
-        impedance=impedance if impedance is not None else Impedance("msd", R=0.5, M=0.1, K=10.0),
+        impedance=impedance if impedance is not None else Impedance("msd", R=0.5, M=0.2, K=10.0),
         ic=Pulse(1.9, 0.4, 1e-3, 0.5), steps=steps,
         probes=((2.5, 0.0), (0.0, 2.5), (-3.0, -1.0)),
         name=f"small-cyl-{n}",
@@ -324,7 +324,7 @@ def radiating_cylinder(n: int = 96, steps: int = 120, impedance: Optional[Impeda
         nx=n, ny=n + 7, x0=-8.0, y0=-8.0 - 3 * h, h=h, H=H, cfl=0.5,
         filter_sigma=filter_sigma,
         wall=Wall("circle", 0.3 * h, 0.3 * h, rc=1.3),
-        impedance=impedance if impedance is not None else Impedance("msd", R=0.5, M=0.1, K=10.0),
+        impedance=impedance if impedance is not None else Impedance("msd", R=0.5, M=0.2, K=10.0),
         ic=Pulse(3.0, 1.0, 1e-3, 0.5), steps=steps,
         probes=((5.0, 0.0), (0.0, 6.5), (-7.5, -7.0)),
         radiation=True, rad_center=(0.0, 0.0),

@@ -25,6 +25,15 @@ Stability reading: the ADE is advanced by the same RK4 as the field, so its
 poles must satisfy |R4(dt s_k)| <= 1 with R4 the RK4 amplification polynomial
 (checked at set-up; a violating impedance is rejected).
 
+Coupling reading (the paper states none): the Neumann ghost value takes
+h du_n/dt, whose part c.f p_BP = lim_{s -> oo} s Y(s) p_BP (1/M for the MSD)
+feeds the boundary pressure straight back into the stencil.  With the
+selective filter on, spectral radii of the step map on coarse cylinders stay
+at the rigid wall's up to h lim sY = 1.5 and rise above it from about 1.6;
+such walls are rejected (check_coupling).  Without the filter the scheme
+carries the tangency growth of the wall itself, the coupling only adds to it
+smoothly, and nothing is rejected.
+
 u_n is counted positive from the fluid into the wall (Sec. 2.3).
 
 Every kind is handed to the time stepper as one dense linear system
@@ -117,6 +126,26 @@ def admittance(imp: Impedance, s: complex) -> complex:
         q, sk = complex(B, C), complex(al, be)
         y += q / (s - sk) + q.conjugate() / (s - sk.conjugate())
     return y
+
+
+COUPLING_MAX = 1.5
+
+
+def coupling_gain(imp: Impedance) -> float:
+    """lim_{s -> oo} s Y(s): 1/M for the MSD, sum A_k + 2 sum B_k for a
+    multi-pole admittance without direct term, 0 for a rigid wall."""
+    if imp.kind == "msd":
+        return 1.0 / imp.M
+    if imp.kind == "poles":
+        return sum(A for _, A in imp.real) + 2.0 * sum(B for _, _, B, _ in imp.pairs)
+    return 0.0
+
+
+def check_coupling(imp: Impedance, h: float, filtered: bool) -> None:
+    """Rejects a wall whose coupling gain h |lim sY| exceeds COUPLING_MAX
+    in the filtered scheme (see the coupling reading above)."""
+    if filtered and h * abs(coupling_gain(imp)) > COUPLING_MAX:
+        raise ImpedanceError("wall coupling gain h lim sY(s) > 1.5 with the filter on")
 
 
 def ade_from_impedance(imp: Impedance, dt: float) -> ADE:

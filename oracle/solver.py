@@ -142,6 +142,8 @@ class OracleSolver:
             self.lag = self.bir = np.zeros((0, 5))
             self.W = np.zeros((0, 5))
         self.ade = ade_mod.ade_from_impedance(c.impedance, c.dt) if G else ade_mod.ADE("rigid")
+        if G:
+            ade_mod.check_coupling(c.impedance, c.h, c.filter_sigma > 0.0)
         self.shape = (c.ny + 2 * F, c.nx + 2 * F)
         self.p = np.zeros(self.shape)
         self.u = np.zeros(self.shape)

@@ -26,14 +26,22 @@ struct StepGraphs {
     int64_t captures = 0;           // graphs captured so far
     hipGraph_t gm = nullptr, g1 = nullptr;
     hipGraphExec_t em = nullptr, e1 = nullptr;
+    int rest_len = 0;               // steps of the remainder graph (g1, e1)
+    void drop_rest()
+    {
+        if (e1) hipGraphExecDestroy(e1);
+        if (g1) hipGraphDestroy(g1);
+        e1 = nullptr;
+        g1 = nullptr;
+        rest_len = 0;
+    }
     void drop()
     {
         if (em) hipGraphExecDestroy(em);
-        if (e1) hipGraphExecDestroy(e1);
         if (gm) hipGraphDestroy(gm);
-        if (g1) hipGraphDestroy(g1);
-        em = e1 = nullptr;
-        gm = g1 = nullptr;
+        em = nullptr;
+        gm = nullptr;
+        drop_rest();
     }
 };
 struct lee_instance {
@@ -365,7 +373,9 @@ void drop_graph(lee_instance *I) { I->graphs.drop(); }
 // n steps on stream s through the captured graphs (or eagerly); issue_run(k)
 // enqueues one run of k steps (the launches of each step, then the run's
 // tail, which samples the probes after the last step and advances the step
-// counters).  Graphs hold runs of G.per steps and of one step.
+// counters).  Graphs hold runs of G.per steps and one run of the remainder
+// n mod G.per, kept for the next call of the same remainder (with G.per = 1,
+// one-step graphs).
 lee_status run_steps(StepGraphs &G, hipStream_t s, int64_t n, const std::function<hipError_t(int)> &issue_run)
 {
     if (s == nullptr || G.per == 0) {            // the legacy default stream cannot be captured
@@ -389,16 +399,20 @@ lee_status run_steps(StepGraphs &G, hipStream_t s, int64_t n, const std::functio
     };
     const int64_t full = G.per > 1 ? n / G.per : 0;
     const int64_t rest = n - full * G.per;
+    const int rlen = G.per > 1 ? (int)rest : 1;
+    const int64_t rlaunch = G.per > 1 ? (rest > 0 ? 1 : 0) : rest;
     if (full > 0 && !G.em) {
         lee_status st = capture(G.per, G.gm, G.em);
         if (st != LEE_OK) return st;
     }
-    if (rest > 0 && !G.e1) {
-        lee_status st = capture(1, G.g1, G.e1);
+    if (rlaunch > 0 && (!G.e1 || G.rest_len != rlen)) {
+        G.drop_rest();
+        lee_status st = capture(rlen, G.g1, G.e1);
         if (st != LEE_OK) return st;
+        G.rest_len = rlen;
     }
     for (int64_t k = 0; k < full; ++k) HIPCHK(hipGraphLaunch(G.em, s));
-    for (int64_t k = 0; k < rest; ++k) HIPCHK(hipGraphLaunch(G.e1, s));
+    for (int64_t k = 0; k < rlaunch; ++k) HIPCHK(hipGraphLaunch(G.e1, s));
     return LEE_OK;
 }
 

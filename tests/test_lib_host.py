@@ -110,7 +110,7 @@ def test_status_codes():
     assert e.value.status == -4                      # ADE pole outside the RK4 region
     with pytest.raises(LeeError) as e:
         _host_instance(base.replace(impedance=lc.Impedance("msd", R=0.5, M=0.02, K=10.0)))
-    assert e.value.status == -4                      # wall coupling gain h/M > 2
+    assert e.value.status == -4                      # wall coupling gain h/M > 1.5 (filter on)
     with pytest.raises(LeeError) as e:
         _host_instance(base.replace(H=3))            # the 11-point filter needs 5 ghost layers
     assert e.value.status == -1
@@ -120,6 +120,30 @@ def test_status_codes():
     with pytest.raises(LeeError) as e:               # probe inside the body
         _host_instance(base.replace(probes=((0.0, 0.0),)))
     assert e.value.status == -9
+
+
+def test_coupling_gain_rule_agrees_with_oracle():
+    # the library and the oracle accept and refuse the same walls: with the
+    # filter on, h lim sY(s) <= 1.5; without it, any gain
+    from oracle import ade as ade_mod
+    from paper_2609_24785_amd._lib import LeeError
+    base = lc.small_cylinder(96)                     # h = 1/6
+    h = base.h
+    for gain, fs, ok in ((1.4, 0.2, True), (1.6, 0.2, False), (1.6, 0.0, True)):
+        M = h / gain
+        imp = lc.Impedance("msd", R=2.0 * 0.3 * math.sqrt(M * M * 4.0), M=M, K=M * 4.0)
+        pol = lc.Impedance("poles", real=((-3.0, 0.5 * gain / h),), pairs=((-1.0, 2.0, 0.25 * gain / h, 0.1),))
+        for z in (imp, pol):
+            case = base.replace(impedance=z, filter_sigma=fs)
+            if ok:
+                _host_instance(case)
+                OracleSolver(case)
+            else:
+                with pytest.raises(LeeError) as e:
+                    _host_instance(case)
+                assert e.value.status == -4
+                with pytest.raises(ade_mod.ImpedanceError):
+                    OracleSolver(case)
 
 
 def test_unbound_calls_are_state_errors():

@@ -378,7 +378,7 @@ def test_msd_written_as_poles_steps_like_the_msd():
     is the N = 2 or M = 1 case of eq. Yrational: the oracle steps it exactly
     like the MSD kinds, in both regimes."""
     base = lc.small_cylinder(64, 12)
-    for R, M, K in ((0.5, 0.1, 10.0), (2.0, 0.1, 1.0)):
+    for R, M, K in ((0.5, 0.2, 10.0), (2.0, 0.2, 1.0)):
         s1, s2 = np.roots([M, R, K])
         if abs(s1.imag) > 0:
             s1 = s1 if s1.imag > 0 else s2

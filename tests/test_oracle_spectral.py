@@ -310,3 +310,27 @@ def test_filter_widths_brute_force():
     masks.append(geometry.fluid_mask(f)[60:110, 70:140])
     for m in masks:
         assert np.array_equal(geometry.filter_widths(m), _widths_brute(m))
+
+
+# ---------------------------------------------------------------------------
+# The wall coupling gain h lim sY(s) (1/M for the mass-spring-damper): with
+# the filter on, walls up to 1.5 step like the rigid wall; beyond it the
+# step map grows, which is why both sides refuse such walls.
+
+def _light_wall(gain, h=1.0):
+    M = h / gain
+    K = M * 0.09                                      # resonance 0.3 per unit time
+    return lc.Impedance("msd", R=2.0 * 0.3 * math.sqrt(K * M), M=M, K=K)
+
+
+def test_coupling_gain_limit(monkeypatch):
+    from oracle import ade as ade_mod
+    rigid = sp.spectral_radius(sp.step_matrix(_coarse(1, lc.Impedance(), 0.5)))
+    ok = sp.spectral_radius(sp.step_matrix(_coarse(1, _light_wall(1.4), 0.5)))
+    assert ok <= max(1.0, rigid) + 1e-9, (ok, rigid)
+    with pytest.raises(ade_mod.ImpedanceError):
+        sp.step_matrix(_coarse(1, _light_wall(1.6), 0.5))
+    # planted: the rule lifted, a wall of gain 2 grows
+    monkeypatch.setattr(ade_mod, "COUPLING_MAX", 10.0)
+    bad = sp.spectral_radius(sp.step_matrix(_coarse(1, _light_wall(2.0), 0.5)))
+    assert bad > 1.005, bad
