@@ -3,30 +3,39 @@
 
 Metric: fluid grid-point Runge-Kutta stage updates per second.  The reported
 value is FP32; FP64 is reported beside it, with the FP32 result's relative L2
-error against the FP64 oracle and against the FP64 GPU run.
+error against the FP64 run at the workload's stated step count, against the
+FP64 oracle over a bounded sample, and the served stream's p50/p99 latency.
 
-Workload: the cylinder reflecting a pulse on a 1024^2 grid (h = 1/64 on
-[-8, 8)^2, r_c = 0.5, impedance (R, m, k) = (0.5, 0.02, 10), 11-point DRP and
-11-point filter, LSRK4 at CFL 0.5, 8 probes on r = 5).  A step is one full
-RK4 time step (four stages of ghost fill + ADE update and stage sweep, then
-the step-end probe kernel), replayed from a captured hipGraph.  Inputs are
-resident in HBM when the timed region starts.
+Workload: the cylinder scattering a harmonic monopole on a 4096^2 grid
+(h = 1/128 on [-16, 16)^2, r_c = 1, impedance (R, m, k) = (1, 0.01, 5) with
+two real poles, monopole at (4, 0) with omega = 4 pi and half-width 3 h,
+64-cell sponge, 11-point DRP and 11-point filter, LSRK4 at CFL 0.5, 20000
+steps, amplitudes by a running DFT over the last 10 periods on two rings of
+180 points).  Its working set (about 600 MB in FP32) exceeds the on-chip
+cache, so its fraction of the HBM roofline is meaningful.  A step is one full
+RK4 time step (four stages of ghost fill + ADE update and stage sweep),
+replayed from captured hipGraphs.  Inputs are resident in HBM when the timed
+region starts, and the graphs for the timed run length are captured before
+it.
 
-Roofline: the stage sweep moves more than 98% of the bytes.  Its algorithmic
+Roofline: the stage sweep moves more than 99% of the bytes.  Its algorithmic
 traffic per launch is the mean over the four stages of 24 B (stage 1: read
 q^n, write q^(1)) and 36 B (stages 2-4: read q^n and q^(l-1), write q^(l))
-per fluid node, 33 B in FP32, divided by the mean launch time measured with
-HIP events on the library's stream over back-to-back launches.
+per fluid node, 33 B in FP32, plus the fused launch's ghost fill, divided by
+the mean launch time measured with HIP events on the library's stream over
+back-to-back launches.
 
 The launch configuration (tile shape, fused or two-launch stage, steps per
-graph) is chosen by the library's autotuner on a scratch instance first.
+graph) is chosen by the library's autotuner (shipped table, else trials).
 Also reported: the oracle on the host cores over a bounded sample of the
-benchmark workload.
+workload (all threads and one thread).
 
-Other modes: --extras (a second JSON line: the flat-wall case against the
-oracle, the 4096^2 monopole case, the benchmark workload with the paper's
-7-point stencils and no filter and with a multi-pole wall, and the batch of
-256 uneven instances),
+Other modes: --extras (a second JSON line: the 1024^2 cylinder pulse, whose
+working set sits in the on-chip cache and is reported as effective
+bandwidth; the flat-wall case against the oracle; the 1024^2 case with the
+paper's 7-point stencils and no filter, with a multi-pole wall and with the
+radiation band; the paper's own configuration; the spectral analysis; the
+batch of 256 uneven instances),
 --serve (the served request stream: Poisson arrivals, continuous batching,
 admission by HBM budget; throughput and p50/p99 latency),
 --profile-run (a short fixed sequence for rocprofv3), and
@@ -96,14 +105,18 @@ def _apply(inst, choice):
         inst.set_graph_steps(choice["graph_steps"])
 
 
-def _timed(case, prec: str, steps: int, warmup: int, choice=None):
-    """Graph-replayed steps of one instance; returns the rate and the instance."""
+def _timed(case, prec: str, steps: int, warmup: int, choice=None, dft=None, trace_capacity=None):
+    """Graph-replayed steps of one instance; returns the rate and the instance.
+    The run of `steps` steps is issued once untimed first, so that its graphs
+    are captured before the timed run."""
     import torch
     from paper_2609_24785_amd.lee import Instance
 
-    inst = Instance(case, prec, trace_capacity=max(steps + warmup, 1))
+    cap = trace_capacity if trace_capacity is not None else max(2 * steps + warmup, 1)
+    inst = Instance(case, prec, trace_capacity=cap, dft=dft)
     _apply(inst, choice)
     inst.step_n(warmup)
+    inst.step_n(steps)
     inst.synchronize()
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
@@ -170,6 +183,40 @@ def _max_rel_l2(a, b, mask):
     return max(relative_l2(x, y, mask) for x, y in zip(a, b))
 
 
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _ring_dft(inst, case):
+    """Complex ring amplitudes P = (2i/N) sum_n p(t_n) exp(-i omega t_n) over
+    the last N = dft_steps steps (p(t) = Im(P exp(i omega t))), as
+    lee_probe_dft returns them."""
+    return inst.dft()
+
+
+def _serve_short(args):
+    """A short window of the served request stream (its p50/p99 latency)."""
+    import lee_cases as lc
+    from paper_2609_24785_amd.serve import GpuBackend, Request, Server
+
+    reqs = [Request(k, c, t) for k, (t, c) in
+            enumerate(lc.request_stream(seed=26091, rate=args.serve_rate, duration=args.serve_duration))]
+    be = GpuBackend("f32")
+    try:
+        srv = Server(be, budget_bytes=args.serve_budget_gb * 1e9, chunk=args.serve_chunk)
+        res = srv.run(reqs)
+    finally:
+        be.close()
+    return srv, res
+
+
 def run(args):
     import numpy as np
     import torch
@@ -181,35 +228,45 @@ def run(args):
         return 1
     torch.cuda.set_device(0)
     from paper_2609_24785_amd import tune
-    case = lc.cylinder_pulse_1024(steps=args.steps)
+    case = lc.monopole_4096()
+    dft = (case.source.omega, case.steps - case.dft_steps, case.dft_steps)
     print("[bench] autotuning the launch configuration", file=sys.stderr, flush=True)
     cache = tune.TuneCache(args.tune_cache, shipped=not args.retune)   # the shipped table, then live trials
     ch32 = tune.tune_case(case, "f32", cache)
     ch64 = tune.tune_case(case, "f64", cache)
     print(f"[bench] {case.name}: {args.steps} steps after {args.warmup} warm-up, FP32 then FP64",
           file=sys.stderr, flush=True)
-    r32 = _timed(case, "f32", args.steps, args.warmup, ch32)
-    r64 = _timed(case, "f64", args.steps, args.warmup, ch64)
+    r32 = _timed(case, "f32", args.steps, args.warmup, ch32, dft=dft, trace_capacity=1)
+    r64 = _timed(case, "f64", args.steps, args.warmup, ch64, dft=dft, trace_capacity=1)
     print("[bench] kernel timing", file=sys.stderr, flush=True)
     k32 = _kernel_times(case, "f32", args.kernel_steps, ch32)
     k64 = _kernel_times(case, "f64", args.kernel_steps, ch64)
-
     copy_gbs = _copy_rate()
 
     import oracle.solver as osv          # error reference and CPU baseline (test infrastructure)
     from oracle.geometry import fluid_mask
     mask = fluid_mask(case)
-    f32 = r32["inst"].fields()
-    f64 = r64["inst"].fields()
-    rel_32_64 = _max_rel_l2(f32, f64, mask)
-    # error relative to the size of the initial pulse (the field decays as the
-    # pulse leaves the 1024^2 window; see the design notes)
-    p64 = f64[0]
-    init_norm = float(np.sqrt(np.sum((case.ic.a * np.exp(-np.log(2.0) * (
-        (case.x0 + case.h * np.arange(case.nx))[None, :] - case.ic.xs) ** 2 / case.ic.w ** 2
-        - np.log(2.0) * ((case.y0 + case.h * np.arange(case.ny))[:, None] - case.ic.ys) ** 2
-        / case.ic.w ** 2))[mask] ** 2)))
-    abs_32_64 = float(np.sqrt(np.sum((f32[0] - p64)[mask] ** 2))) / init_norm
+    rel_timed = _max_rel_l2(r32["inst"].fields(), r64["inst"].fields(), mask)
+
+    # the stated step count: both timed instances continue to the workload's
+    # 20000 steps (the DFT window is its last 10 periods)
+    stated = {}
+    if not args.no_stated:
+        print(f"[bench] FP32 and FP64 to the stated {case.steps} steps", file=sys.stderr, flush=True)
+        for r in (r32, r64):
+            left = case.steps - r["inst"].step
+            if left > 0:
+                r["inst"].step_n(left)
+            r["inst"].synchronize()
+        f32, f64 = r32["inst"].fields(), r64["inst"].fields()
+        a32, a64 = _ring_dft(r32["inst"], case), _ring_dft(r64["inst"], case)
+        rel = _max_rel_l2(f32, f64, mask)
+        ring = float(np.abs(a32 - a64).max() / np.abs(a64).max())
+        stated = {"steps": case.steps, "fp32_vs_fp64_rel_l2": rel,
+                  "ring_dft_fp32_vs_fp64_max_rel": ring,
+                  "ring_amplitude_abs_mean": {"r=1.1": float(np.abs(a64[:180]).mean()),
+                                              "r=5": float(np.abs(a64[180:]).mean())},
+                  "within_tolerance": bool(rel <= 1e-4 and ring <= 1e-4)}
 
     alg_bytes = k32["alg_bytes"]
     achieved = alg_bytes / (k32["sweep_us"] * 1e-6) / 1e9
@@ -229,9 +286,10 @@ def run(args):
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": "cylinder-pulse 1024x1024, h=1/64 on [-8,8)^2, r_c=0.5 centred (0.3h,0.3h), Gaussian "
-                        "pulse (4,0) a=1e-3 w=0.2, MSD R=0.5 m=0.02 k=10, 11-pt DRP + 11-pt filter sigma=0.2, "
-                        "LSRK4 CFL 0.5, 8 probes on r=5",
+            "workload": "monopole-cylinder 4096x4096, h=1/128 on [-16,16)^2, r_c=1 at the origin, monopole (4,0) "
+                        "a=1 omega=4pi half-width 3h, MSD R=1 m=0.01 k=5 (two real poles), 64-cell sponge, 11-pt "
+                        "DRP + 11-pt filter sigma=0.2, LSRK4 CFL 0.5, 20000 steps, running DFT over the last 10 "
+                        "periods on rings r=1.1 and r=5 (360 probes)",
             "grid": [case.nx, case.ny],
             "fluid_nodes": r32["fluid"],
             "ghosts": int(r32["inst"].summary.G),
@@ -239,15 +297,14 @@ def run(args):
             "tiling_f64": k64["tiling"],
             "graph_steps": ch32["graph_steps"],
             "tuning_from": "table" if ch32.get("cached") else "trials",
-            "tuned_step_us": {"f32": ch32["step_us"], "f64": ch64["step_us"]},
-            "launch": "hipGraphs of captured runs of steps; a step is 4 x (ghost fill + ADE, stage sweep; one "
-                      "launch when fused), probes riding in the next step's second stage, and a run ends with a "
-                      "probe launch and a step-counter launch; configuration from the autotuner",
+            "launch": "hipGraphs of captured runs of steps (one graph per run length, captured before the timed "
+                      "run); a step is 4 x (ghost fill + ADE, stage sweep; one launch when fused), probes and DFT "
+                      "riding in the next step's second stage",
         },
         "fp64_value": r64["value"],
         "fp64_ms_per_step": 1000.0 * r64["wall"] / r64["steps"],
-        "fp32_vs_fp64_rel_l2": rel_32_64,
-        "fp32_vs_fp64_err_over_initial_norm": abs_32_64,
+        "fp32_vs_fp64_rel_l2_timed_run": rel_timed,
+        "stated_steps": stated,
         "gpu_event_ms_per_step": r32["gpu_ms"] / r32["steps"],
         "kernels_us": {"sweep_f32": k32["sweep_us"], "ghost_f32": k32["ghost_us"],
                        "sweep_f64": k64["sweep_us"], "ghost_f64": k64["ghost_us"],
@@ -269,11 +326,13 @@ def run(args):
     }
     r32["inst"].close()
     r64["inst"].close()
+    torch.cuda.empty_cache()
 
     if not args.no_cpu_baseline:
-        print(f"[bench] oracle on the host: {args.cpu_steps} steps", file=sys.stderr, flush=True)
-        nthreads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        print(f"[bench] oracle on the host: {args.cpu_steps} steps, then {args.cpu_steps_1t} on one thread",
+              file=sys.stderr, flush=True)
         s = osv.OracleSolver(case)
+        nthreads = osv.set_threads(0)
         t0 = time.perf_counter()
         s.run(args.cpu_steps)
         t1 = time.perf_counter()
@@ -283,15 +342,36 @@ def run(args):
         _apply(g, ch32)                                 # the configuration timed above
         g.step_n(args.cpu_steps)
         g.synchronize()
-        out["cpu_baseline"] = {
-            "value": cpu_rate, "unit": UNIT, "cores": nthreads, "kind": "oracle",
-            "sample": f"the benchmark workload's first {args.cpu_steps} steps (FP64 C core, OpenMP over rows, "
-                      f"stepping loop only, {t1 - t0:.1f} s)",
-        }
         out["fp32_vs_oracle_rel_l2"] = _max_rel_l2(g.fields(), s.fields(), mask)
         out["fp32_vs_oracle_steps"] = args.cpu_steps
-        out["fp32_vs_oracle_tiling"] = g.get_tiling()
         g.close()
+        del s
+        s1 = osv.OracleSolver(case)
+        osv.set_threads(1)
+        t2 = time.perf_counter()
+        s1.run(args.cpu_steps_1t)
+        t3 = time.perf_counter()
+        osv.set_threads(nthreads)
+        del s1
+        out["cpu_baseline"] = {
+            "value": cpu_rate, "unit": UNIT, "cores": nthreads, "kind": "oracle",
+            "sample": f"the workload's first {args.cpu_steps} steps (FP64 C core, OpenMP over rows, stepping loop "
+                      f"only, {t1 - t0:.1f} s)",
+            "cpu_model": _cpu_model(),
+            "one_thread_value": r32["fluid"] * 4.0 * args.cpu_steps_1t / (t3 - t2),
+            "one_thread_sample": f"the workload's first {args.cpu_steps_1t} steps on one thread ({t3 - t2:.1f} s)",
+        }
+
+    if not args.no_serve:
+        print(f"[bench] served stream: {args.serve_duration} s of arrivals at {args.serve_rate}/s",
+              file=sys.stderr, flush=True)
+        srv, res = _serve_short(args)
+        st = srv.stats
+        out["serve"] = {"window_s": args.serve_duration, "arrival_rate": args.serve_rate,
+                        "requests": len(res), "served": sum(1 for r in res if r.error is None),
+                        "refused": sum(1 for r in res if r.error is not None),
+                        "latency_p50_s": st.get("p50_latency_s"), "latency_p99_s": st.get("p99_latency_s"),
+                        "throughput": st.get("throughput")}
     print(json.dumps(out), flush=True)
     return 0
 
@@ -309,6 +389,29 @@ def extras(args):
     torch.cuda.set_device(0)
     out = {"extras": True}
     cache = tune.TuneCache(args.tune_cache, shipped=not args.retune)
+
+    # the cylinder pulse on 1024^2 at its stated 4000 steps: its working set
+    # (about 38 MB in FP32) sits in the on-chip cache, so its rate is an
+    # effective bandwidth, not an HBM fraction
+    print("[extras] cylinder pulse 1024^2, 4000 steps", file=sys.stderr, flush=True)
+    import numpy as np
+    from oracle.geometry import fluid_mask
+    cp = lc.cylinder_pulse_1024()
+    cres, flds = {}, {}
+    for prec in ("f32", "f64"):
+        ch = tune.tune_case(cp, prec, cache)
+        rc_ = _timed(cp, prec, cp.steps, 0, ch)
+        k = _kernel_times(cp, prec, args.kernel_steps, ch)
+        cres[prec] = {"value": rc_["value"], "ms_per_step": 1000.0 * rc_["wall"] / rc_["steps"],
+                      "tiling": ch["tiling"], "graph_steps": ch["graph_steps"], "kernel": k["kernel"],
+                      "launch_us": k["sweep_us"],
+                      "effective_GBs": k["alg_bytes"] / (k["sweep_us"] * 1e-6) / 1e9}
+        flds[prec] = rc_["inst"].fields()
+        rc_["inst"].close()
+    # each timed instance ran its 4000 steps twice (capture pass, timed pass)
+    cres["fp32_vs_fp64_rel_l2_after_8000_steps"] = _max_rel_l2(flds["f32"], flds["f64"], fluid_mask(cp))
+    out["cylinder_pulse_1024"] = dict(steps=cp.steps, unit=UNIT, working_set="cache-resident", **cres)
+
     print("[extras] flat wall 201^2 FP64 against the oracle", file=sys.stderr, flush=True)
     flat = lc.flat_wall_201(500)
     rf = _timed(flat, "f64", 500, 0)
@@ -519,34 +622,54 @@ def serve(args):
     return 0
 
 
-def profile_run(args):
-    """A short fixed sequence for hardware profilers: the benchmark workload
-    (FP32, graph replay), then three copies of COPY_BYTES bytes."""
-    import torch
-
+def _workload(name: str):
     import lee_cases as lc
-    from paper_2609_24785_amd import _lib
+    return {"monopole-4096": lc.monopole_4096, "cylinder-pulse-1024": lc.cylinder_pulse_1024}[name]()
+
+
+def profile_run(args):
+    """A short fixed sequence for hardware profilers: the workload named by
+    --workload (FP32, graph replay), then three copies of COPY_BYTES bytes.
+    It imports no torch: device memory and the stream come from hipmem, so
+    the process holds the one HIP runtime the library links (a profiler that
+    preloads the system runtime would otherwise leave torch's own runtime
+    beside it).  The run checks its fields against the oracle over the same
+    steps and prints the error."""
+    import oracle.solver as osv
+    from paper_2609_24785_amd import _lib, hipmem, tune
     from paper_2609_24785_amd.lee import Instance
 
-    from paper_2609_24785_amd import tune
-
-    torch.cuda.set_device(0)
-    case = lc.cylinder_pulse_1024(steps=args.steps)
-    ch = tune.tune_case(case, "f32", tune.TuneCache(args.tune_cache))
-    inst = Instance(case, "f32", trace_capacity=args.steps + args.warmup)
+    _lib.without_torch()
+    hipmem.set_device(0)
+    case = _workload(args.workload)
+    n = args.warmup + args.steps
+    inst = Instance(case, "f32", trace_capacity=n, bind=False)
+    ch = tune.lookup(case, "f32", inst.summary.fluid_nodes, inst.summary.G)
+    stream = hipmem.Stream()
+    buf = hipmem.DeviceBuffer(inst.required_bytes())
+    inst.bind_raw(buf, stream)
     _apply(inst, ch)
-    inst.step_n(args.warmup + args.steps)
+    inst.step_n(n)
     inst.synchronize()
-    a = torch.empty(COPY_BYTES, dtype=torch.uint8, device="cuda")
-    b = torch.empty(COPY_BYTES, dtype=torch.uint8, device="cuda")
-    s = torch.cuda.current_stream()
+    got = inst.fields()
+    tiling = inst.get_tiling()
+    inst.close()
+    buf.close()
+    a = hipmem.DeviceBuffer(COPY_BYTES)
+    b = hipmem.DeviceBuffer(COPY_BYTES)
     for _ in range(3):
-        _lib.check(_lib.load().lee_stream_copy(a.data_ptr(), b.data_ptr(), COPY_BYTES, s.cuda_stream), "copy")
-    torch.cuda.synchronize()
-    print(json.dumps({"profile_run": True, "steps": args.steps + args.warmup, "copy_bytes": COPY_BYTES,
-                      "fluid_nodes": inst.summary.fluid_nodes, "tiling": inst.get_tiling(),
-                      "kernel": _kernel_name(inst.get_tiling(), "f32")}), flush=True)
-    return 0
+        _lib.check(_lib.load().lee_stream_copy(a.ptr, b.ptr, COPY_BYTES, stream.handle), "copy")
+    stream.synchronize()
+    a.close()
+    b.close()
+    stream.close()
+    ora = osv.OracleSolver(case)
+    ora.run(n)
+    err = _max_rel_l2(got, ora.fields(), ora.fluid)
+    print(json.dumps({"profile_run": True, "workload": args.workload, "steps": n, "copy_bytes": COPY_BYTES,
+                      "fluid_nodes": int(ora.fluid.sum()), "tiling": tiling,
+                      "kernel": _kernel_name(tiling, "f32"), "fp32_vs_oracle_rel_l2": err}), flush=True)
+    return 0 if err <= 1e-4 else 3
 
 
 def counters(args):
@@ -577,7 +700,7 @@ def counters(args):
     write_scale = COPY_BYTES / (write[copy_name][0] * kib)
     fb = fetch[sweep_name][0] * kib * fetch_scale
     wb = write[sweep_name][0] * kib * write_scale
-    case = lc.cylinder_pulse_1024(10)
+    case = _workload(args.workload)
     from paper_2609_24785_amd.lee import Instance
     inst = Instance(case, "f32", bind=False)
     fluid = inst.summary.fluid_nodes
@@ -585,7 +708,7 @@ def counters(args):
     if "k_stage" in sweep_name:                       # the fused launch also fills the ghosts
         alg += ghost_bytes("f32", inst.summary.G, inst.summary.nnz)
     short = sweep_name.split("(")[0].replace("void ", "")
-    d = {"kernel": short, "kernel_sha": _kernel_hash(), "dispatches": fetch[sweep_name][1],
+    d = {"kernel": short, "workload": args.workload, "kernel_sha": _kernel_hash(), "dispatches": fetch[sweep_name][1],
          "fetch_kib_per_dispatch": fetch[sweep_name][0], "write_kib_per_dispatch": write[sweep_name][0],
          "copy_fetch_kib": fetch[copy_name][0], "copy_write_kib": write[copy_name][0],
          "fetch_scale": fetch_scale, "write_scale": write_scale,
@@ -600,10 +723,13 @@ def counters(args):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=4000)
+    ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--kernel-steps", type=int, default=200)
-    ap.add_argument("--cpu-steps", type=int, default=2000)
+    ap.add_argument("--cpu-steps", type=int, default=150, help="oracle sample on all host threads")
+    ap.add_argument("--cpu-steps-1t", type=int, default=3, help="oracle sample on one thread")
+    ap.add_argument("--no-stated", action="store_true", help="skip the run to the stated 20000 steps")
+    ap.add_argument("--no-serve", action="store_true", help="skip the short served window")
     ap.add_argument("--mono-steps", type=int, default=200)
     ap.add_argument("--power-steps", type=int, default=4000, help="power-iteration steps on the benchmark grid (--extras)")
     ap.add_argument("--extras", action="store_true", help="the other configurations, as a second JSON line")
@@ -617,6 +743,8 @@ def main():
     ap.add_argument("--serve-chunk", type=int, default=100)
     ap.add_argument("--serve-budget-gb", type=float, default=200.0)
     ap.add_argument("--counters", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "KERNEL"))
+    ap.add_argument("--workload", default="monopole-4096", choices=["monopole-4096", "cylinder-pulse-1024"],
+                    help="workload of --profile-run and --counters")
     ap.add_argument("--tune-cache", default=None, help="JSON file for autotuner choices (over the shipped table)")
     ap.add_argument("--retune", action="store_true", help="ignore the shipped tuning table (trials only)")
     args = ap.parse_args()

@@ -221,7 +221,11 @@ lee_status lee_probe(lee_instance *inst, int32_t np, const double *xy, double *o
  * *n receives the number of steps copied (at most cap and the ring size). */
 lee_status lee_probe_traces(lee_instance *inst, double *out, int64_t cap, int64_t *n);
 
-/* Synchronising: running DFT amplitudes, out[2k] = Re P_k, out[2k+1] = Im P_k. */
+/* Synchronising: running DFT amplitudes over the window set by
+ * lee_set_probes (N = dft_count steps), P_k = (2i/N) sum_n p_k(t_n)
+ * exp(-i omega t_n) with t_n the time after step n, so that a harmonic
+ * p_k(t) = Im(P_k exp(i omega t)) (App. C convention) gives back P_k;
+ * out[2k] = Re P_k, out[2k+1] = Im P_k. */
 lee_status lee_probe_dft(lee_instance *inst, double *out);
 
 /*

@@ -26,12 +26,15 @@ poles must satisfy |R4(dt s_k)| <= 1 with R4 the RK4 amplification polynomial
 (checked at set-up; a violating impedance is rejected).
 
 Coupling reading (the paper states none): the Neumann ghost value takes
-h du_n/dt, whose part c.f p_BP = lim_{s -> oo} s Y(s) p_BP (1/M for the MSD)
-feeds the boundary pressure straight back into the stencil.  With the
-selective filter on, spectral radii of the step map on coarse cylinders stay
-at the rigid wall's up to h lim sY = 1.5 and rise above it from about 1.6;
-such walls are rejected (check_coupling).  Without the filter the scheme
-carries the tangency growth of the wall itself, the coupling only adds to it
+h du_n/dt = h s Y(s) p_BP in the frequency domain, which feeds the boundary
+pressure back into the stencil with gain h |s Y(s)|.  With the selective
+filter on, spectral radii of the step map on coarse cylinders stay at the
+rigid wall's while the high-frequency gain h lim_{s -> oo} s Y(s) (h/M for
+the MSD) is at most 1.5 (growth from about 1.6) and while the peak gain
+h max_w |i w Y(i w)| (about h w_res / R for a lightly damped resonance) is at
+most 3.5 (growth from about 4, at w_res h from 0.5 to 2); walls beyond 1.5
+or 3 are rejected (check_coupling).  Without the filter the scheme carries
+the tangency growth of the wall itself, the coupling only adds to it
 smoothly, and nothing is rejected.
 
 u_n is counted positive from the fluid into the wall (Sec. 2.3).
@@ -141,11 +144,44 @@ def coupling_gain(imp: Impedance) -> float:
     return 0.0
 
 
+PEAK_MAX = 3.0
+
+
+def peak_gain(imp: Impedance) -> float:
+    """max over w > 0 of |i w Y(i w)|.  MSD: |i w Y| = u / |K - M u + i R w|
+    with u = w^2, whose square u^2 / ((K - M u)^2 + R^2 u) is largest at
+    u* = 2 K^2 / (2 K M - R^2) when 2 K M > R^2, else as u -> oo (1/M).
+    Multi-pole: the largest of the limit and of |i w Y(i w)| at w = |s_k| and
+    |Im s_k| of every pole and at 2401 log-spaced w from 1e-4 to 1e8."""
+    if imp.kind == "msd":
+        R, M, K = imp.R, imp.M, imp.K
+        if 2.0 * K * M > R * R:
+            u = 2.0 * K * K / (2.0 * K * M - R * R)
+            return u / math.sqrt((K - M * u) ** 2 + R * R * u)
+        return 1.0 / M
+    if imp.kind == "poles":
+        ws = [10.0 ** (-4.0 + e / 200.0) for e in range(2401)]
+        for lam, _ in imp.real:
+            ws.append(abs(lam))
+        for al, be, _, _ in imp.pairs:
+            ws += [abs(complex(al, be)), abs(be)]
+        best = abs(coupling_gain(imp))
+        for w in ws:
+            best = max(best, abs(1j * w * admittance(imp, 1j * w)))
+        return best
+    return 0.0
+
+
 def check_coupling(imp: Impedance, h: float, filtered: bool) -> None:
-    """Rejects a wall whose coupling gain h |lim sY| exceeds COUPLING_MAX
-    in the filtered scheme (see the coupling reading above)."""
-    if filtered and h * abs(coupling_gain(imp)) > COUPLING_MAX:
+    """Rejects a wall whose high-frequency gain h |lim sY| exceeds
+    COUPLING_MAX or whose peak gain h max |i w Y(i w)| exceeds PEAK_MAX in
+    the filtered scheme (see the coupling reading above)."""
+    if not filtered:
+        return
+    if h * abs(coupling_gain(imp)) > COUPLING_MAX:
         raise ImpedanceError("wall coupling gain h lim sY(s) > 1.5 with the filter on")
+    if h * peak_gain(imp) > PEAK_MAX:
+        raise ImpedanceError("wall peak coupling gain h max |i w Y(i w)| > 3 with the filter on")
 
 
 def ade_from_impedance(imp: Impedance, dt: float) -> ADE:

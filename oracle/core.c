@@ -51,8 +51,17 @@
  * (central where possible, one-sided next to the edge) and no filter term.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
+
+/* Threads of the stepping loops (for timing the oracle at a stated thread
+ * count); returns the count now in use. */
+int oc_set_threads(int n)
+{
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+}
 
 typedef struct {
     int nx, ny, F, H;

@@ -70,6 +70,14 @@ def _load():
     return _lib
 
 
+def set_threads(n: int = 0) -> int:
+    """Threads of the C core's loops (n <= 0: unchanged); returns the count in use."""
+    lib = _load()
+    lib.oc_set_threads.restype = ctypes.c_int
+    lib.oc_set_threads.argtypes = [ctypes.c_int]
+    return int(lib.oc_set_threads(int(n)))
+
+
 def _ptr(a: np.ndarray):
     return a.ctypes.data_as(ctypes.c_void_p)
 

@@ -120,16 +120,30 @@ class LeeError(RuntimeError):
         self.status = status
 
 
+_use_torch = True
+
+
+def without_torch() -> None:
+    """Before the first load: the process binds its instances through hipmem
+    and never imports torch, so the library uses the system HIP runtime."""
+    global _use_torch
+    if _lib is not None:
+        raise RuntimeError("liblee.so is already loaded")
+    _use_torch = False
+
+
 def load() -> ctypes.CDLL:
     """Load liblee.so; raises if it has not been built (no fallback path).
 
     torch is imported first: it ships its own HIP runtime under the same
     soname as the system one the library links, and whichever loads first is
     the one the process uses.  Loading torch's first keeps a single runtime
-    for the tensors that hold the library's memory and for its launches."""
+    for the tensors that hold the library's memory and for its launches
+    (unless without_torch() was called)."""
     global _lib
     if _lib is None:
-        import torch  # noqa: F401  (selects the process's HIP runtime)
+        if _use_torch:
+            import torch  # noqa: F401  (selects the process's HIP runtime)
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with paper_2609_24785_amd/build.py")
         lib = ctypes.CDLL(LIB_PATH)

@@ -32,13 +32,53 @@ extern "C" const char *lee_last_error(void) { return lee::g_err.c_str(); }
 
 namespace lee {
 
-// Largest wall coupling gain h lim_{s->oo} s Y(s) accepted with the selective
-// filter on: the Neumann ghost value carries h du_n/dt, whose part
-// lim sY p_BP feeds the boundary pressure straight back; spectral radii of the
-// step map on coarse cylinders stay at the rigid wall's up to 1.5 and rise
-// above it from about 1.6.  (Without the filter the scheme carries the wall's
+// Wall coupling limits with the selective filter on.  The Neumann ghost value
+// carries h du_n/dt = h s Y(s) p_BP, which feeds the boundary pressure back
+// with gain h |s Y(s)|: spectral radii of the step map on coarse cylinders
+// stay at the rigid wall's while the high-frequency gain h lim_{s->oo} s Y(s)
+// is at most 1.5 (growth from about 1.6) and the peak gain
+// h max_w |i w Y(i w)| at most 3.5 (growth from about 4, resonances at
+// w h = 0.5 to 2).  (Without the filter the scheme carries the wall's
 // tangency growth anyway and nothing is rejected.)
 static constexpr double COUPLING_MAX = 1.5;
+static constexpr double PEAK_MAX = 3.0;
+
+// max over w > 0 of |i w Y(i w)| for the mass-spring-damper wall: with
+// u = w^2, |i w Y|^2 = u^2 / ((K - M u)^2 + R^2 u); setting its derivative in
+// u to zero gives u* = 2 K^2 / (2 K M - R^2) when 2 K M > R^2; otherwise the
+// gain rises to its limit 1/M as w grows.
+static double msd_peak_gain(double R, double M, double K)
+{
+    const double den = 2.0 * K * M - R * R;
+    if (den <= 0.0) return 1.0 / M;
+    const double u = 2.0 * K * K / den;
+    return u / std::sqrt((K - M * u) * (K - M * u) + R * R * u);
+}
+
+// The same for a multi-pole admittance (eq. Yrational without direct term):
+// the largest of its limit `lim` and of |i w Y(i w)| at the pole moduli and
+// imaginary parts and at 2401 log-spaced frequencies from 1e-4 to 1e8.
+static double poles_peak_gain(const lee_impedance *z, double lim)
+{
+    auto gain = [&](double w) {
+        const std::complex<double> s(0.0, w);
+        std::complex<double> y(0.0, 0.0);
+        for (int i = 0; i < z->n_real; ++i) y += z->real_res[i] / (s - z->real_pole[i]);
+        for (int i = 0; i < z->n_pair; ++i) {
+            const std::complex<double> q(z->pair_B[i], z->pair_C[i]), p(z->pair_alpha[i], z->pair_beta[i]);
+            y += q / (s - p) + std::conj(q) / (s - std::conj(p));
+        }
+        return std::abs(s * y);
+    };
+    double best = std::fabs(lim);
+    for (int e = 0; e <= 2400; ++e) best = std::max(best, gain(std::pow(10.0, -4.0 + e / 200.0)));
+    for (int i = 0; i < z->n_real; ++i) best = std::max(best, gain(std::fabs(z->real_pole[i])));
+    for (int i = 0; i < z->n_pair; ++i) {
+        best = std::max(best, gain(std::abs(std::complex<double>(z->pair_alpha[i], z->pair_beta[i]))));
+        best = std::max(best, gain(std::fabs(z->pair_beta[i])));
+    }
+    return best;
+}
 
 static double node_x(const lee_case_desc &d, long i) { return d.x0 + (double)i * d.h; }
 static double node_y(const lee_case_desc &d, long j) { return d.y0 + (double)j * d.h; }
@@ -366,6 +406,9 @@ lee_status host_build(Host *H, const lee_impedance *z, int degree, lee_ghost_sum
         if (H->d.filter_sigma > 0.0 && h / M > COUPLING_MAX)
             return fail(LEE_E_ADE_STIFF, "wall coupling gain h/M > 1.5 with the filter on: the Neumann ghost "
                                          "value feeds p_BP back and the coupled step map grows");
+        if (H->d.filter_sigma > 0.0 && h * msd_peak_gain(R, M, K) > PEAK_MAX)
+            return fail(LEE_E_ADE_STIFF, "wall peak coupling gain h max |i w Y(i w)| > 3 with the filter on "
+                                         "(a lightly damped resonance): the coupled step map grows");
     } else if (z->kind == LEE_Z_POLES) {
         // multi-pole admittance (Sec. 2.3, eqs. Yrational, ADEgeneral, unGeneral):
         // real poles first (one state each), then each pair's two states
@@ -410,6 +453,9 @@ lee_status host_build(Host *H, const lee_impedance *z, int degree, lee_ghost_sum
         if (H->d.filter_sigma > 0.0 && h * std::fabs(gain) > COUPLING_MAX)
             return fail(LEE_E_ADE_STIFF, "wall coupling gain h (sum A + 2 sum B) > 1.5 with the filter on: the "
                                          "Neumann ghost value feeds p_BP back and the coupled step map grows");
+        if (H->d.filter_sigma > 0.0 && h * poles_peak_gain(z, gain) > PEAK_MAX)
+            return fail(LEE_E_ADE_STIFF, "wall peak coupling gain h max |i w Y(i w)| > 3 with the filter on: "
+                                         "the coupled step map grows");
     } else if (z->kind != LEE_Z_RIGID) {
         return fail(LEE_E_ARG, "impedance kind");
     }

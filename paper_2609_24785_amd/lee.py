@@ -1,12 +1,20 @@
 """Python binding of liblee: argument marshalling only.
 
 Every step of the method runs in the library's kernels; PyTorch provides the
-device memory (a uint8 tensor handed to lee_bind) and the stream.
+device memory (a uint8 tensor handed to lee_bind) and the stream, or, for a
+process without torch, hipmem does (Instance.bind_raw).
+
+Live bound instances and batches are closed by an exit hook registered when
+the first one binds (after torch is imported, so it runs before torch's own
+exit handlers); finalizers make no HIP call while the interpreter shuts down.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import math
+import sys
+import weakref
 from typing import Optional, Sequence
 
 import numpy as np
@@ -146,6 +154,18 @@ class Instance:
         aligned = (base + 255) // 256 * 256
         check(self.lib.lee_bind(self._h, c_void_p(aligned), nbytes, c_void_p(self.stream.cuda_stream)),
               "lee_bind")
+        _track(self)
+
+    def bind_raw(self, buf, stream):
+        """Bind device memory and a stream that the caller made without torch
+        (hipmem.DeviceBuffer of at least required_bytes(), hipmem.Stream); the
+        caller keeps both alive and frees them after close()."""
+        nbytes = self.required_bytes()
+        if buf.nbytes < nbytes or buf.ptr % 256:
+            raise ValueError("device buffer too small or not 256-byte aligned")
+        self.buf, self.stream = buf, stream
+        check(self.lib.lee_bind(self._h, c_void_p(buf.ptr), nbytes, c_void_p(stream.handle)), "lee_bind")
+        _track(self)
 
     # ---- stepping -----------------------------------------------------------
     def init_fields(self):
@@ -218,6 +238,8 @@ class Instance:
         return out[:n.value]
 
     def dft(self):
+        """Complex DFT amplitudes P_k = (2i/N) sum_n p_k(t_n) exp(-i omega t_n)
+        over the window given at construction (lee_probe_dft)."""
         out = np.zeros(2 * len(self.case.probes))
         check(self.lib.lee_probe_dft(self._h, _ptr(out)), "lee_probe_dft")
         return out[0::2] + 1j * out[1::2]
@@ -274,10 +296,35 @@ class Instance:
             self._h = c_void_p()
 
     def __del__(self):
+        # no HIP call while the interpreter shuts down: the runtime's own
+        # exit handlers may already have run (live objects are closed by the
+        # exit hook instead)
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
             pass
+
+
+_live_batches: "weakref.WeakSet" = weakref.WeakSet()
+_live_instances: "weakref.WeakSet" = weakref.WeakSet()
+_hook = False
+
+
+def _close_all():
+    for b in list(_live_batches):
+        b.close()
+    for i in list(_live_instances):
+        i.close()
+
+
+def _track(obj):
+    global _hook
+    (_live_batches if isinstance(obj, Batch) else _live_instances).add(obj)
+    if not _hook:
+        atexit.register(_close_all)
+        _hook = True
 
 
 class Batch:
@@ -298,6 +345,7 @@ class Batch:
         self._h = c_void_p()
         check(self.lib.lee_batch_create(arr, len(members), ctypes.byref(opts), ctypes.byref(self._h)),
               "lee_batch_create")
+        _track(self)
 
     def add(self, inst: "Instance"):
         check(self.lib.lee_batch_add(self._h, inst._h), "lee_batch_add")
@@ -360,6 +408,8 @@ class Batch:
             self._h = c_void_p()
 
     def __del__(self):
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:

@@ -4,9 +4,10 @@ It times candidate launch configurations on the device and keeps the
 fastest.  Each candidate is a tile shape, the fused or two-launch form of a
 stage, and a number of steps per captured graph.  The figure of merit is the
 mean time of a graph-replayed RK4 step, which is what a run pays.  Choices
-are cached in a JSON file, keyed by the device architecture, the precision
-and the problem's size class (fluid nodes and ghosts, in powers of two), so a
-later problem of the same class skips the trials.  The package ships such a
+are cached in a JSON file, keyed by the device architecture, the precision,
+the problem's size class (fluid nodes and ghosts, in powers of two) and its
+kernel variant (stencil half-width, filter on or off, radiation band, wall
+kind), so a later problem of the same class and variant skips the trials.  The package ships such a
 table (tuned_gfx950.json, written by this module on an MI355X) as a read-only
 base layer under every cache.
 
@@ -49,8 +50,16 @@ def size_class(fluid_nodes: int, ghosts: int, members: int = 1) -> str:
     return f"m{members}-f{b(fluid_nodes)}-g{b(ghosts)}"
 
 
-def cache_key(arch: str, precision: str, cls: str) -> str:
-    return f"{arch.split(':')[0]}|{precision}|{cls}"
+def variant_of(case) -> str:
+    """The parts of a case that select different kernel code or cost: the
+    stencil half-width, the filter, the radiation band and the wall kind
+    (rigid, mass-spring-damper, multi-pole)."""
+    wall = case.impedance.kind if case.wall.kind != "none" else "none"
+    return f"H{case.H}-s{int(case.filter_sigma > 0.0)}-r{int(bool(case.radiation))}-{wall}"
+
+
+def cache_key(arch: str, precision: str, cls: str, variant: str) -> str:
+    return f"{arch.split(':')[0]}|{precision}|{cls}|{variant}"
 
 
 def select(measure: Callable[[dict], float], cands: Iterable[dict], rounds: int = 3) -> Tuple[dict, List[dict]]:
@@ -145,7 +154,7 @@ def tune_instance(inst, cache: Optional[TuneCache] = None, steps: int = 64, warm
     reset it to its initial condition.  Returns the choice (with its time and,
     when measured here, the table of trials)."""
     s = inst.summary
-    key = cache_key(_device_arch(), inst.precision, size_class(s.fluid_nodes, s.G))
+    key = cache_key(_device_arch(), inst.precision, size_class(s.fluid_nodes, s.G), variant_of(inst.case))
     hit = cache.get(key) if cache else None
     if hit is not None:
         _apply(inst, hit)
@@ -182,7 +191,9 @@ def tune_batch(batch, cache: Optional[TuneCache] = None, steps: int = 32, warmup
     fluid = sum(m.summary.fluid_nodes for m in members)
     ghosts = sum(m.summary.G for m in members)
     prec = members[0].precision
-    key = cache_key(_device_arch(), prec, size_class(fluid, ghosts, len(members)))
+    variants = sorted({variant_of(m.case) for m in members})
+    key = cache_key(_device_arch(), prec, size_class(fluid, ghosts, len(members)),
+                    variants[0] if len(variants) == 1 else "mixed")
     hit = cache.get(key) if cache else None
     if hit is not None:
         _apply(batch, hit)
@@ -200,5 +211,13 @@ def tune_batch(batch, cache: Optional[TuneCache] = None, steps: int = 32, warmup
     return dict(best, cached=False, key=key, table=table)
 
 
-__all__ = ["candidates", "size_class", "cache_key", "select", "TuneCache", "tune_instance", "tune_case",
+def lookup(case, precision: str, fluid_nodes: int, ghosts: int, arch: str = "gfx950",
+           cache: Optional[TuneCache] = None) -> Optional[dict]:
+    """The cached choice for a case without touching the device (None if
+    there is none)."""
+    cache = cache if cache is not None else TuneCache()
+    return cache.get(cache_key(arch, precision, size_class(fluid_nodes, ghosts), variant_of(case)))
+
+
+__all__ = ["candidates", "size_class", "variant_of", "cache_key", "lookup", "select", "TuneCache", "tune_instance", "tune_case",
            "tune_batch"]

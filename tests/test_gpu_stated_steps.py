@@ -1,0 +1,146 @@
+"""GPU parity at the stated step counts of the workloads.
+
+The benchmark cylinder pulse (1024^2) is compared with the FP64 oracle after
+its full 4000 steps, in the launch configuration the benchmark times.  The
+harmonic monopole is compared over the whole time span of its 20000-step
+4096^2 configuration at a quarter of the resolution (1024^2, 5000 steps of
+twice the time step): fields and the running-DFT amplitudes on both rings,
+element by element.  The batch of 256 uneven instances runs its 2000 steps
+in one launch per phase; its small members (side <= 256) are compared with
+the oracle one by one.
+
+Tolerances: FP64 1e-9 relative L2 (summation order only), FP32 1e-4 (the
+bound the FP32 path is held to against the FP64 oracle).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import lee_cases as lc
+from oracle.solver import OracleSolver, dft_amplitude, relative_l2
+
+pytestmark = pytest.mark.gpu
+
+
+def _lee():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2609_24785_amd.lee import Batch, Instance
+    return Instance, Batch
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def cylinder_oracle():
+    case = lc.cylinder_pulse_1024()
+    _say(f"[stated] oracle {case.name} {case.steps} steps")
+    s = OracleSolver(case)
+    tr = s.run(case.steps)
+    return case, s, tr
+
+
+@pytest.mark.parametrize("prec,tol", [("f32", 1e-4), ("f64", 1e-9)])
+def test_cylinder_pulse_1024_at_4000_steps(cylinder_oracle, prec, tol):
+    from paper_2609_24785_amd import tune
+    Instance, _ = _lee()
+    case, ora, tr = cylinder_oracle
+    choice = tune.tune_case(case, prec, tune.TuneCache(None))
+    _say(f"[stated] {case.name} {prec} {case.steps} steps, {choice['tiling']} x{choice['graph_steps']}")
+    inst = Instance(case, prec)
+    inst.set_tiling(**choice["tiling"])
+    inst.set_graph_steps(choice["graph_steps"])
+    inst.step_n(case.steps)
+    inst.synchronize()
+    errs = [relative_l2(a, b, ora.fluid) for a, b in zip(inst.fields(), ora.fields())]
+    _say(f"[stated] rel L2 p,u,v = {errs}")
+    assert max(errs) <= tol, errs
+    gt = inst.traces()
+    assert gt.shape == tr.shape
+    assert np.abs(gt - tr).max() <= tol * np.abs(tr).max()
+    inst.close()
+
+
+def _monopole_quarter():
+    # the 4096^2 monopole case at n = 1024: the same domain, wall, source
+    # (half-width 3 h), 64-cell sponge and rings; 5000 steps of dt = 1/64
+    # cover the 20000 steps of dt = 1/256.  The wall mass goes from 0.01 to
+    # 0.04 so that the coupling gain h/M stays at the full-size 0.78 (the
+    # coupled step map grows beyond 1.5); R = 1, K = 5 keep two real poles.
+    return lc.monopole_4096(5000, n=1024).replace(impedance=lc.Impedance("msd", R=1.0, M=0.04, K=5.0))
+
+
+@pytest.fixture(scope="module")
+def monopole_oracle():
+    case = _monopole_quarter()
+    _say(f"[stated] oracle {case.name} {case.steps} steps, {len(case.probes)} ring probes")
+    s = OracleSolver(case)
+    tr = s.run(case.steps)
+    amp = dft_amplitude(tr[:, :, 0], case, case.steps, case.source.omega, case.dft_steps)
+    return case, s, tr, amp
+
+
+@pytest.mark.parametrize("prec,tol", [("f32", 1e-4), ("f64", 1e-9)])
+def test_monopole_time_span_and_ring_dft(monopole_oracle, prec, tol):
+    Instance, _ = _lee()
+    case, ora, tr, amp = monopole_oracle
+    n = case.dft_steps
+    _say(f"[stated] {case.name} {prec} {case.steps} steps, DFT over the last {n}")
+    inst = Instance(case, prec, dft=(case.source.omega, case.steps - n, n))
+    inst.step_n(case.steps)
+    inst.synchronize()
+    errs = [relative_l2(a, b, ora.fluid) for a, b in zip(inst.fields(), ora.fields())]
+    _say(f"[stated] rel L2 p,u,v = {errs}")
+    assert max(errs) <= tol, errs
+    got = inst.dft()                                 # P = (2i/N) sum p e^{-i omega t}, from the library
+    assert got.shape == amp.shape == (len(case.probes),)
+    scale = np.abs(amp).max()
+    assert scale > 0
+    _say(f"[stated] ring DFT max |P_gpu - P_oracle| / max |P| = {np.abs(got - amp).max() / scale}")
+    assert np.abs(got - amp).max() <= tol * scale
+    # both rings carry a non-trivial harmonic field
+    assert np.abs(amp[:180]).min() > 1e-3 * scale and np.abs(amp[180:]).min() > 1e-3 * scale
+    inst.close()
+
+
+def test_batch_256_at_2000_steps_small_members_match_oracle():
+    from oracle.ade import ImpedanceError
+    from paper_2609_24785_amd import tune
+    from paper_2609_24785_amd._lib import LeeError
+    Instance, Batch = _lee()
+    gen = lc.batch_candidates(steps=2000)
+    members, cases, rejected = [], [], 0
+    while len(members) < 256:
+        c = next(gen)
+        try:
+            members.append(Instance(c, "f32", trace_capacity=1))
+            cases.append(c)
+        except LeeError:
+            rejected += 1
+    _say(f"[stated] batch of 256 ({rejected} draws refused), 2000 steps")
+    b = Batch(members)
+    tune.tune_batch(b, tune.TuneCache(None))        # the benchmark's configuration; resets the members
+    b.step_n(2000)
+    b.synchronize()
+    checked = 0
+    for m, c in zip(members, cases):
+        if c.nx > 256:
+            continue
+        try:
+            ora = OracleSolver(c)
+        except ImpedanceError:                       # the oracle refuses exactly what the library refuses
+            raise AssertionError(f"oracle refuses a member the library accepted: {c.name}")
+        ora.run(2000)
+        errs = [relative_l2(x, y, ora.fluid) for x, y in zip(m.fields(), ora.fields())]
+        assert max(errs) <= 1e-4, (c.name, errs)
+        checked += 1
+        if checked >= 48:
+            break
+    _say(f"[stated] {checked} small members within 1e-4 of the oracle")
+    assert checked >= 16
+    b.close()

@@ -131,8 +131,36 @@ def test_coupling_gain_rule_agrees_with_oracle():
     h = base.h
     for gain, fs, ok in ((1.4, 0.2, True), (1.6, 0.2, False), (1.6, 0.0, True)):
         M = h / gain
-        imp = lc.Impedance("msd", R=2.0 * 0.3 * math.sqrt(M * M * 4.0), M=M, K=M * 4.0)
+        imp = lc.Impedance("msd", R=2.0 * 0.6 * math.sqrt(M * M * 4.0), M=M, K=M * 4.0)
         pol = lc.Impedance("poles", real=((-3.0, 0.5 * gain / h),), pairs=((-1.0, 2.0, 0.25 * gain / h, 0.1),))
+        for z in (imp, pol):
+            case = base.replace(impedance=z, filter_sigma=fs)
+            if ok:
+                _host_instance(case)
+                OracleSolver(case)
+            else:
+                with pytest.raises(LeeError) as e:
+                    _host_instance(case)
+                assert e.value.status == -4
+                with pytest.raises(ade_mod.ImpedanceError):
+                    OracleSolver(case)
+
+
+def test_peak_gain_rule_agrees_with_oracle():
+    # lightly damped resonances: h max |i w Y(i w)| <= 3 with the filter on
+    from oracle import ade as ade_mod
+    from paper_2609_24785_amd._lib import LeeError
+    base = lc.small_cylinder(96)                     # h = 1/6
+    h = base.h
+    M = h / 0.8
+    w = 3.0
+    for peak, fs, ok in ((2.9, 0.2, True), (3.1, 0.2, False), (3.1, 0.0, True)):
+        imp = lc.Impedance("msd", R=h * w / peak, M=M, K=M * w * w)
+        # the same resonance written as a pole pair (eq. Yrational)
+        s1 = np.roots([M, imp.R, imp.K])
+        s1 = s1[np.argmax(s1.imag)]
+        q = s1 / (M * (s1 - np.conj(s1)))
+        pol = lc.Impedance("poles", pairs=((s1.real, s1.imag, q.real, q.imag),))
         for z in (imp, pol):
             case = base.replace(impedance=z, filter_sigma=fs)
             if ok:

@@ -378,7 +378,7 @@ def test_msd_written_as_poles_steps_like_the_msd():
     is the N = 2 or M = 1 case of eq. Yrational: the oracle steps it exactly
     like the MSD kinds, in both regimes."""
     base = lc.small_cylinder(64, 12)
-    for R, M, K in ((0.5, 0.2, 10.0), (2.0, 0.2, 1.0)):
+    for R, M, K in ((1.0, 0.2, 10.0), (2.0, 0.2, 1.0)):
         s1, s2 = np.roots([M, R, K])
         if abs(s1.imag) > 0:
             s1 = s1 if s1.imag > 0 else s2
@@ -409,3 +409,21 @@ def test_multipole_rejections():
     with pytest.raises(ade_mod.ImpedanceError):       # dt * lambda outside the RK4 region
         ade_mod.ade_from_impedance(lc.Impedance("poles", real=((-100.0, 1.0),)), 0.05)
     ade_mod.ade_from_impedance(MULTIPOLE, 0.25)
+
+
+def test_msd_peak_gain_closed_form_against_brute_force():
+    """max_w |i w Y(i w)| of the mass-spring-damper (closed form in ade.peak_gain)
+    against a dense search on the admittance itself, in both pole regimes, and
+    its limit 1/M when 2 K M <= R^2."""
+    rng = np.random.default_rng(5)
+    for _ in range(40):
+        R, M, K = (float(np.exp(rng.uniform(np.log(a), np.log(b)))) for a, b in ((0.05, 10), (0.001, 1), (0.5, 100)))
+        imp = lc.Impedance("msd", R=R, M=M, K=K)
+        g = lambda w: np.abs(1j * w / (M * 1j * w + R + K / (1j * w)))
+        w = np.exp(np.linspace(np.log(1e-3), np.log(1e5), 400001))
+        k = int(np.argmax(g(w)))
+        fine = np.linspace(w[max(k - 1, 0)], w[min(k + 1, len(w) - 1)], 200001)   # around the coarse maximum
+        brute = max(float(np.max(g(fine))), float(np.max(g(w))), 1.0 / M)
+        got = ade_mod.peak_gain(imp)
+        assert got >= brute * (1 - 1e-12) and got - brute <= 1e-9 * brute, (R, M, K, got, brute)
+    assert ade_mod.peak_gain(lc.Impedance("msd", R=2.0, M=0.5, K=1.0)) == 2.0        # 2KM = 1 < R^2 = 4

@@ -330,7 +330,30 @@ def test_coupling_gain_limit(monkeypatch):
     assert ok <= max(1.0, rigid) + 1e-9, (ok, rigid)
     with pytest.raises(ade_mod.ImpedanceError):
         sp.step_matrix(_coarse(1, _light_wall(1.6), 0.5))
-    # planted: the rule lifted, a wall of gain 2 grows
+    # planted: the rules lifted, a wall of gain 2 grows
     monkeypatch.setattr(ade_mod, "COUPLING_MAX", 10.0)
+    monkeypatch.setattr(ade_mod, "PEAK_MAX", 100.0)
     bad = sp.spectral_radius(sp.step_matrix(_coarse(1, _light_wall(2.0), 0.5)))
     assert bad > 1.005, bad
+
+
+def _resonant_wall(peak, wh=1.0, h=1.0):
+    # h/M = 0.8, resonance w_res h = wh, peak gain h w_res / R = peak
+    M = 1.25 * h
+    K = M * (wh / h) ** 2
+    return lc.Impedance("msd", R=wh / peak, M=M, K=K)
+
+
+def test_peak_coupling_gain_limit(monkeypatch):
+    from oracle import ade as ade_mod
+    rigid = sp.spectral_radius(sp.step_matrix(_coarse(1, lc.Impedance(), 0.5)))
+    z = _resonant_wall(2.9)
+    assert 2.9 < ade_mod.peak_gain(z) <= 3.0
+    ok = sp.spectral_radius(sp.step_matrix(_coarse(1, z, 0.5)))
+    assert ok <= max(1.0, rigid) + 1e-9, (ok, rigid)
+    with pytest.raises(ade_mod.ImpedanceError):
+        sp.step_matrix(_coarse(1, _resonant_wall(3.2), 0.5))
+    # planted: the rule lifted, a lightly damped resonance of peak gain 5 grows
+    monkeypatch.setattr(ade_mod, "PEAK_MAX", 100.0)
+    bad = sp.spectral_radius(sp.step_matrix(_coarse(1, _resonant_wall(5.0, wh=0.5), 0.5)))
+    assert bad > 1.002, bad

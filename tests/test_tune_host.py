@@ -64,7 +64,26 @@ def test_size_class_groups_nearby_problems():
     assert a == tune.size_class(1_000_000, 830)
     assert a != tune.size_class(2_200_000, 855)
     assert a != tune.size_class(1_045_359, 855, members=2)
-    assert tune.cache_key("gfx950:sramecc+:xnack-", "f32", a).startswith("gfx950|f32|")
+    assert tune.cache_key("gfx950:sramecc+:xnack-", "f32", a, "v").startswith("gfx950|f32|")
+
+
+def test_cache_key_separates_kernel_variants():
+    # the stencil width, the filter, the radiation band and the wall kind
+    # select different kernel code: each gets its own cache entry
+    base = lc.cylinder_pulse_1024(10)
+    keys = {tune.variant_of(c) for c in (
+        base, base.replace(H=3, filter_sigma=0.0), base.replace(filter_sigma=0.0),
+        base.replace(radiation=True), base.replace(impedance=lc.Impedance("rigid")),
+        base.replace(impedance=lc.Impedance("poles", real=((-1.0, 1.0),))))}
+    assert len(keys) == 6
+    assert tune.variant_of(base) == tune.variant_of(lc.cylinder_pulse_1024(20).replace(
+        impedance=lc.Impedance("msd", R=1.0, M=0.05, K=3.0)))
+    # the shipped table answers the benchmark workloads, and only their variant
+    for c in (lc.cylinder_pulse_1024(10), lc.monopole_4096(10)):
+        from paper_2609_24785_amd.lee import Instance
+        s = Instance(c, "f32", bind=False).summary
+        assert tune.lookup(c, "f32", s.fluid_nodes, s.G) is not None
+        assert tune.lookup(c.replace(radiation=True, rad_center=(0.0, 0.0)), "f32", s.fluid_nodes, s.G) is None
 
 
 def test_cache_round_trip(tmp_path):
