@@ -6,7 +6,7 @@ harmonic monopole is compared over the whole time span of its 20000-step
 4096^2 configuration at a quarter of the resolution (1024^2, 5000 steps of
 twice the time step): fields and the running-DFT amplitudes on both rings,
 element by element.  The batch of 256 uneven instances runs its 2000 steps
-in one launch per phase; its small members (side <= 256) are compared with
+in one launch per phase; four members of each grid side are compared with
 the oracle one by one.
 
 Tolerances: FP64 1e-9 relative L2 (summation order only), FP32 1e-4 (the
@@ -108,7 +108,15 @@ def test_monopole_time_span_and_ring_dft(monopole_oracle, prec, tol):
     inst.close()
 
 
-def test_batch_256_at_2000_steps_small_members_match_oracle():
+def test_batch_256_at_2000_steps_members_match_oracle():
+    """Four members of each side (128, 256, 512, 1024) against the oracle
+    after the batch's 2000 steps.  Where a member's field still holds at
+    least 1% of its initial norm, relative L2 <= 1e-4 per field.  Where the
+    pulse has left its grid (2000 steps are 125 time units at side 128, 62.5
+    at 256), what remains is mostly vortical: divergence-free velocity with
+    no pressure is a steady solution of the LEE and keeps whatever rounding
+    put into it while the pulse was large, so there the bound is 1e-6 of the
+    field's initial norm (FP32 rounds at about 6e-8 of the values it holds)."""
     from oracle.ade import ImpedanceError
     from paper_2609_24785_amd import tune
     from paper_2609_24785_amd._lib import LeeError
@@ -127,20 +135,28 @@ def test_batch_256_at_2000_steps_small_members_match_oracle():
     tune.tune_batch(b, tune.TuneCache(None))        # the benchmark's configuration; resets the members
     b.step_n(2000)
     b.synchronize()
-    checked = 0
+    taken = {128: 0, 256: 0, 512: 0, 1024: 0}
     for m, c in zip(members, cases):
-        if c.nx > 256:
+        if taken[c.nx] >= 4:
             continue
+        taken[c.nx] += 1
         try:
             ora = OracleSolver(c)
         except ImpedanceError:                       # the oracle refuses exactly what the library refuses
             raise AssertionError(f"oracle refuses a member the library accepted: {c.name}")
+        init = [np.linalg.norm(f[ora.fluid]) for f in ora.fields()]
         ora.run(2000)
-        errs = [relative_l2(x, y, ora.fluid) for x, y in zip(m.fields(), ora.fields())]
-        assert max(errs) <= 1e-4, (c.name, errs)
-        checked += 1
-        if checked >= 48:
-            break
-    _say(f"[stated] {checked} small members within 1e-4 of the oracle")
-    assert checked >= 16
+        ref = ora.fields()
+        got = m.fields()
+        for k, (x, y) in enumerate(zip(got, ref)):
+            nref = np.linalg.norm(y[ora.fluid])
+            err = np.linalg.norm((x - y)[ora.fluid])
+            scale = max(init[0], init[k])            # u, v start at zero: the pulse's pressure norm
+            _say(f"[stated] {c.name} field {k}: rel L2 {err / max(nref, 1e-300):.3e}, over initial norm "
+                 f"{err / scale:.3e}, final/initial {nref / scale:.3e}")
+            if nref >= 1e-2 * scale:
+                assert err <= 1e-4 * nref, (c.name, k)
+            else:
+                assert err <= 1e-6 * scale, (c.name, k)
+    assert all(v > 0 for v in taken.values()), taken
     b.close()
