@@ -422,6 +422,31 @@ lee_status lee_batch_time_kernels(lee_batch *b, int64_t n, double *sweep_us, dou
 
 void lee_batch_destroy(lee_batch *b);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): advance the
+ * bound instances v[0..n) together by `steps` steps, as lee_batch_step_n
+ * does for a batch of the same members (lee_batch_create(v, n) with this
+ * tiling, NULL for the batch default) -- the same kernels and the same per-node
+ * arithmetic, so the same fields bit for bit -- but with the instance table,
+ * the work lists and the error flag in a static device array of
+ * LEE_NOALLOC_SCRATCH_BYTES per GPU instead of memory the library allocates.
+ * Nothing is allocated on the device; the array is held by each GPU the
+ * library runs on until the process ends.  Members as for lee_batch_create
+ * (bound, same precision, filter setting and device, no partial step), run on
+ * v[0]'s stream as eager launches (no graphs); each member takes the steps
+ * below its budget (lee_batch_set_budget) as in a batch.  LEE_E_ARG when the
+ * members' table and lists need more than the array holds (n at most
+ * LEE_NOALLOC_MAX_MEMBERS).  The call waits until its lists are on the device
+ * and returns with the steps queued; a ghost wait that ran out is reported by
+ * lee_synchronize(v[0]).  Every call on a GPU shares that GPU's array, which
+ * keeps the last call's contents (the error flag is cleared at each call):
+ * calls that overlap on one GPU from different streams race.
+ */
+#define LEE_NOALLOC_SCRATCH_BYTES (16u << 20)
+#define LEE_NOALLOC_MAX_MEMBERS 1024
+lee_status lee_step_members_noalloc(lee_instance *const *v, int32_t n, const lee_tiling *tiling, int64_t steps);
+
 #ifdef __cplusplus
 }
 #endif

@@ -109,6 +109,7 @@ SIGNATURES = {
     "lee_batch_time_kernels": (c_int32, [c_void_p, c_int64, ctypes.POINTER(c_double), ctypes.POINTER(c_double),
                                          ctypes.POINTER(c_double)]),
     "lee_batch_destroy": (None, [c_void_p]),
+    "lee_step_members_noalloc": (c_int32, [ctypes.POINTER(c_void_p), c_int32, ctypes.POINTER(Tiling), c_int64]),
 }
 
 _lib = None

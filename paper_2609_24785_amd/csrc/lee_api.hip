@@ -9,6 +9,7 @@
 #include <cstring>
 #include <functional>
 #include <initializer_list>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1594,3 +1595,149 @@ void lee_batch_destroy(lee_batch *B)
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// members stepped together without allocating: the batch's instance table,
+// work lists and error flag in a static device array
+
+// In host code this name is a host-side stand-in, not a device address: only
+// the address hipGetSymbolAddress returns (per device) may reach a kernel or
+// a copy.
+static __device__ __align__(256) unsigned char scratch[LEE_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int SCRATCH_DEVICES = 64;
+std::mutex g_scratch_mu;
+unsigned char *g_scratch_ptr[SCRATCH_DEVICES] = {};
+
+// The array's address on device dev, looked up once per device with that
+// device current.
+lee_status scratch_on(int dev, unsigned char **out)
+{
+    if (dev < 0 || dev >= SCRATCH_DEVICES) return fail(LEE_E_ARG, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        int cur = -1;
+        HIPCHK(hipGetDevice(&cur));
+        if (cur != dev) HIPCHK(hipSetDevice(dev));
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != dev) hipSetDevice(cur);
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        g_scratch_ptr[dev] = (unsigned char *)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return LEE_OK;
+}
+
+// Host staging of the lists, kept between calls of a thread.
+struct NoAllocStaging {
+    std::vector<DevInst> table;
+    std::vector<int4> items, work1, work2;
+    std::vector<std::vector<int2>> patches;
+    std::vector<int2> aux, patch, pwork;
+};
+thread_local NoAllocStaging g_noalloc;
+
+}  // namespace
+
+extern "C" lee_status lee_step_members_noalloc(lee_instance *const *v, int32_t n, const lee_tiling *tiling,
+                                               int64_t steps)
+{
+    if (!v || n <= 0 || n > LEE_NOALLOC_MAX_MEMBERS || steps < 0) return fail(LEE_E_ARG, "member list or steps");
+    for (int k = 0; k < n; ++k) {
+        if (!v[k] || !v[k]->bound) return fail(LEE_E_STATE, "every member must be bound");
+        if (v[k]->next_stage != 0) return fail(LEE_E_STATE, "a member has a partial step pending");
+        if (v[k]->host.d.precision != v[0]->host.d.precision) return fail(LEE_E_ARG, "mixed precision");
+        if ((v[k]->host.d.filter_sigma > 0.0) != (v[0]->host.d.filter_sigma > 0.0))
+            return fail(LEE_E_ARG, "mixed filter on/off");
+        if (v[k]->device != v[0]->device) return fail(LEE_E_ARG, "members on different devices");
+    }
+    const int prec = v[0]->host.d.precision;
+    const bool filt = v[0]->host.d.filter_sigma > 0.0;
+    const lee_tiling tl = tiling ? *tiling : default_tiling_for(prec, 4096, 4096);
+    if (!tiling_valid(prec, tl)) return fail(LEE_E_ARG, "unsupported tiling");
+    bool poles = false;
+    for (int k = 0; k < n; ++k) {
+        if (v[k]->host.d.radiation && tl.kind == LEE_SWEEP_MARCH)
+            return fail(LEE_E_ARG, "the march sweep has no radiation band");
+        poles = poles || v[k]->host.ade_kind == 3;
+    }
+    if (steps == 0) return LEE_OK;
+    hipStream_t s = v[0]->stream;
+    for (int k = 1; k < n; ++k)                  // their set-up ran on their own streams
+        if (v[k]->stream != s) HIPCHK(hipStreamSynchronize(v[k]->stream));
+    unsigned char *base = nullptr;
+    lee_status st = scratch_on(v[0]->device, &base);
+    if (st != LEE_OK) return st;
+
+    // the lists of a batch of these members (as batch_rebuild and
+    // batch_build_work1 make them, without padding)
+    NoAllocStaging &S = g_noalloc;
+    S.table.clear();
+    S.work2.clear();
+    S.pwork.clear();
+    S.items.clear();
+    S.patches.clear();
+    for (int k = 0; k < n; ++k) {
+        const lee_instance *I = v[k];
+        S.table.push_back(I->dev);
+        for (int g = 0; g < (int)I->host.gidx.size(); ++g)
+            S.work2.push_back(make_int4(k, g, I->host.cptr[g], I->host.cptr[g + 1]));
+        for (int p = 0; p < I->host.np; ++p) S.pwork.push_back(make_int2(k, p));
+        build_items(I->host, k, tl, S.items, &S.patches);
+    }
+    const int tile0 = order_work(S.items, S.patches, per_unit_of(tl), carriers_for(tl, S.work2.size()), true,
+                                 S.work1, S.aux, S.patch);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = (off + std::max<size_t>(bytes, 1) + 255) / 256 * 256;
+        return o;
+    };
+    const size_t o_table = take(S.table.size() * sizeof(DevInst));
+    const size_t o_work1 = take(S.work1.size() * sizeof(int4));
+    const size_t o_aux = take(S.aux.size() * sizeof(int2));
+    const size_t o_work2 = take(S.work2.size() * sizeof(int4));
+    const size_t o_patch = take(S.patch.size() * sizeof(int2));
+    const size_t o_pwork = take(S.pwork.size() * sizeof(int2));
+    const size_t o_sync = take(SYNC_INTS * sizeof(int));
+    if (off > LEE_NOALLOC_SCRATCH_BYTES)
+        return fail(LEE_E_ARG, "the members' table and work lists need " + std::to_string(off) +
+                                   " bytes; the no-alloc scratch holds " +
+                                   std::to_string((size_t)LEE_NOALLOC_SCRATCH_BYTES));
+    DevInst *d_table = (DevInst *)(base + o_table);
+    int4 *d_work1 = (int4 *)(base + o_work1);
+    int2 *d_aux = (int2 *)(base + o_aux);
+    int4 *d_work2 = (int4 *)(base + o_work2);
+    int2 *d_patch = (int2 *)(base + o_patch);
+    int2 *d_pwork = (int2 *)(base + o_pwork);
+    int *d_sync = (int *)(base + o_sync);
+    auto up = [&](void *dst, const void *src, size_t bytes) -> hipError_t {
+        return bytes ? hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s) : hipSuccess;
+    };
+    HIPCHK(up(d_table, S.table.data(), S.table.size() * sizeof(DevInst)));
+    HIPCHK(up(d_work1, S.work1.data(), S.work1.size() * sizeof(int4)));
+    HIPCHK(up(d_aux, S.aux.data(), S.aux.size() * sizeof(int2)));
+    HIPCHK(up(d_work2, S.work2.data(), S.work2.size() * sizeof(int4)));
+    HIPCHK(up(d_patch, S.patch.data(), S.patch.size() * sizeof(int2)));
+    HIPCHK(up(d_pwork, S.pwork.data(), S.pwork.size() * sizeof(int2)));
+    HIPCHK(launch_fill_bytes(d_sync, SYNC_INTS * sizeof(int), s));   // a fill kernel: the flag starts clear
+    HIPCHK(hipStreamSynchronize(s));             // the host staging is reused by the next call
+
+    const int nwork1 = (int)S.work1.size(), nwork2 = (int)S.work2.size(), npwork = (int)S.pwork.size();
+    for (int64_t done = 0; done < steps;) {
+        const int run = (int)std::min<int64_t>(steps - done, 1 << 20);
+        for (int j = 0; j < run; ++j)
+            for (int l = 0; l < 4; ++l)
+                HIPCHK(stage_launches(prec, filt, tl, d_table, 0, poles, d_work1, nwork1, d_aux, d_patch, tile0,
+                                      d_work2, nwork2, d_sync, l, j, probe_pass(d_pwork, npwork, l, j), 0, s));
+        HIPCHK(launch_probe(prec, d_table, ProbePass{d_pwork, npwork, run - 1}, s));
+        HIPCHK(launch_advance(d_table, n, run, s));
+        done += run;
+    }
+    HIPCHK(launch_merge_flag(d_sync, v[0]->d_sync, s));
+    for (int k = 0; k < n; ++k) v[k]->steps_issued += steps;
+    return LEE_OK;
+}

@@ -120,6 +120,8 @@ hipError_t launch_probe(int prec, const DevInst *insts, ProbePass pp, hipStream_
 // held at *stop.
 hipError_t launch_advance(const DevInst *insts, int ninst, int n, hipStream_t s);
 hipError_t launch_fill(int prec, void *p, size_t n, hipStream_t s);
+// sync words: dst[4] |= src[4] (the ghost-wait error flag)
+hipError_t launch_merge_flag(const int *src, int *dst, hipStream_t s);
 hipError_t launch_fill_bytes(void *p, size_t bytes, hipStream_t s);
 hipError_t launch_init_ic(int prec, const DevInst *insts, int nx, int ny, int kind, const double *c,
                           hipStream_t s);

@@ -1587,6 +1587,19 @@ hipError_t launch_advance(const DevInst *insts, int ninst, int n, hipStream_t s)
     return hipGetLastError();
 }
 
+// dst[4] |= src[4]: a ghost-wait error flag raised in one set of sync words
+// carried over to another
+__global__ void k_merge_flag(const int *__restrict__ src, int *__restrict__ dst)
+{
+    if (threadIdx.x == 0 && src[4] != 0) atomicOr(&dst[4], src[4]);
+}
+
+hipError_t launch_merge_flag(const int *src, int *dst, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_merge_flag, dim3(1), dim3(64), 0, s, src, dst);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill(int prec, void *p, size_t n, hipStream_t s)
 {
     const int nb = (int)((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096);

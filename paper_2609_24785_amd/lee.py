@@ -416,4 +416,13 @@ class Batch:
             pass
 
 
-__all__ = ["Instance", "Batch", "LeeError", "case_desc", "impedance_desc"]
+def step_members_noalloc(members: Sequence[Instance], steps: int, tiling: Optional[dict] = None):
+    """Advance bound instances together as a batch of them would, with the
+    library allocating nothing on the device (lee_step_members_noalloc)."""
+    lib = load()
+    arr = (c_void_p * len(members))(*[m._h.value for m in members])
+    t = ctypes.byref(make_tiling(**tiling)) if tiling is not None else None
+    check(lib.lee_step_members_noalloc(arr, len(members), t, int(steps)), "lee_step_members_noalloc")
+
+
+__all__ = ["Instance", "Batch", "LeeError", "case_desc", "impedance_desc", "step_members_noalloc"]
