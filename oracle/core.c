@@ -105,7 +105,8 @@ static long long pad_index(const oc_case *c, long long lin)
 
 /* steps 1-5 for every ghost; writes ghost values into (p, u, v) and the
  * stage value of the auxiliary states into psi_out; when watch is given, the
- * watched ghost's p_BP and u_n,BP go to watch[0], watch[1] (recording only) */
+ * watched ghost's p_BP, u_n,BP and fluid-side u_n go to watch[0..2]
+ * (recording only) */
 static void fill_ghosts(const oc_case *c, double *p, double *u, double *v,
                         const double *psi_in, const double *psi_n, double *psi_out,
                         double alpha, double *watch)
@@ -159,6 +160,11 @@ static void fill_ghosts(const oc_case *c, double *p, double *u, double *v,
         if (watch && g == c->watch_g) {
             watch[0] = pBP;
             watch[1] = U;
+            /* the fluid's own normal velocity at the boundary point: the
+             * least-squares read-out of u.n at P_0, unconstrained by the wall
+             * datum, counted positive into the wall like U (Sec. 4.3 compares
+             * the two) */
+            watch[2] = -un[0];
         }
         long long q = pad_index(c, c->gidx[g]);
         p[q] = pg;
@@ -278,8 +284,9 @@ static void sweep(const oc_case *c, const double *p, const double *u, const doub
  * Advance nsteps full steps from step counter step0.  After every step the
  * probes are sampled from q^{n+1}: trace[(s*np + k)*3 + {0,1,2}] = p, u, v at
  * probe k, with 4x4 interpolation weights probe_w[k*16 + b*4 + a] applied to
- * node (probe_ij[2k] + a, probe_ij[2k+1] + b).  watch (2 per step, may be
- * NULL) receives the watched ghost's p_BP and u_n,BP of the step's first stage.
+ * node (probe_ij[2k] + a, probe_ij[2k+1] + b).  watch (3 per step, may be
+ * NULL) receives the watched ghost's p_BP, u_n,BP of the ADE and u_n at the
+ * boundary point read out of the fluid, all of the step's first stage.
  */
 int oc_run(const oc_case *c, double *p, double *u, double *v, double *psi,
            long long step0, int nsteps, int np, const long long *probe_ij,
@@ -300,7 +307,7 @@ int oc_run(const oc_case *c, double *p, double *u, double *v, double *psi,
             double *ps = l == 0 ? p : S[0], *us = l == 0 ? u : S[1], *vs = l == 0 ? v : S[2];
             const double *psi_in = l == 0 ? psi : psS;
             double t = ((double)(step0 + s) + RK_C[l]) * c->dt;
-            fill_ghosts(c, ps, us, vs, psi_in, psi, psT, RK_ALPHA[l], (watch && l == 0) ? watch + 2 * s : NULL);
+            fill_ghosts(c, ps, us, vs, psi_in, psi, psT, RK_ALPHA[l], (watch && l == 0) ? watch + 3 * s : NULL);
             sweep(c, p, u, v, ps, us, vs, T[0], T[1], T[2], RK_ALPHA[l], t);
             for (k = 0; k < 3; ++k) { double *x = S[k]; S[k] = T[k]; T[k] = x; }
             { double *x = psS; psS = psT; psT = x; }

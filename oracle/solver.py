@@ -160,7 +160,7 @@ class OracleSolver:
         self.psi = np.zeros(max(self.ns * G, self.ns))
         self.step = 0
         self.watch_g = -1
-        self.watch_trace = np.zeros((0, 2))
+        self.watch_trace = np.zeros((0, 3))
         self._init_fields()
         self.probe_ij, self.probe_w = self._probes()
         # per node and axis, the half-width of its filter row (schemes, geometry)
@@ -255,8 +255,11 @@ class OracleSolver:
 
     # ---- stepping ---------------------------------------------------------
     def set_watch(self, x: float, y: float) -> int:
-        """Record, every step, p_BP and u_n,BP (first stage) of the ghost whose
-        boundary point is nearest (x, y) (ties: the lowest ghost index)."""
+        """Record, every step (first stage), p_BP, the ADE's wall velocity
+        u_n,BP and the normal velocity read out of the fluid at the boundary
+        point (the least-squares fit at P_0, u_n positive into the wall) of
+        the ghost whose boundary point is nearest (x, y) (ties: the lowest
+        ghost index)."""
         if len(self.gidx) == 0:
             raise ValueError("no ghost points")
         d2 = (self.bx - x) * (self.bx - x) + (self.by - y) * (self.by - y)
@@ -267,12 +270,12 @@ class OracleSolver:
 
     def run(self, nsteps: int) -> np.ndarray:
         """Advance nsteps; returns probe traces [nsteps, nprobes, 3].  With a
-        watched ghost, its (p_BP, u_n,BP) per step are appended to
+        watched ghost, its (p_BP, u_n,BP, fluid u_n) per step are appended to
         self.watch_trace."""
         lib = _load()
         npb = len(self.case.probes)
         trace = np.zeros((max(nsteps, 1), max(npb, 1), 3))
-        watch = np.zeros((max(nsteps, 1), 2))
+        watch = np.zeros((max(nsteps, 1), 3))
         rc = lib.oc_run(ctypes.byref(self._cs), _ptr(self.p), _ptr(self.u), _ptr(self.v),
                         _ptr(self.psi), self.step, nsteps, npb, _ptr(self.probe_ij),
                         _ptr(self.probe_w), _ptr(trace), _ptr(watch) if self.watch_g >= 0 else None)
