@@ -229,17 +229,22 @@ lee_status lee_probe_traces(lee_instance *inst, double *out, int64_t cap, int64_
 lee_status lee_probe_dft(lee_instance *inst, double *out);
 
 /*
- * Watched ghost (Coupling section, steps 1-3): before lee_bind, choose the
- * ghost whose boundary point is nearest (x, y) (ties: the lowest index;
- * *ghost receives its index, NULL allowed) and keep a ring of `capacity`
- * steps of its boundary pressure p_BP and wall normal velocity u_n,BP
- * (positive into the wall) at the first stage of each step, in FP64.  With
- * capacity 0 nothing is recorded.  LEE_E_ARG without ghosts.
+ * Watched ghost (Coupling section, steps 1-3; Sec. 4.3, cylinder scattering a
+ * harmonic monopole, for the comparison of the two normal velocities):
+ * before lee_bind, choose the ghost whose boundary point is nearest (x, y)
+ * (ties: the lowest index; *ghost receives its index, NULL allowed) and keep
+ * a ring of `capacity` steps of three values at the first stage of each step,
+ * in FP64: its boundary pressure p_BP, the ADE's wall normal velocity u_n,BP,
+ * and the normal velocity read out of the fluid at the boundary point (the
+ * least-squares fit's u.n at P_0, which the wall datum does not constrain),
+ * both velocities positive into the wall.  With capacity 0 nothing is
+ * recorded.  LEE_E_ARG without ghosts.
  */
 lee_status lee_set_watch(lee_instance *inst, double x, double y, int64_t capacity, int32_t *ghost);
 
-/* The last min(steps, capacity, cap) recorded (p_BP, u_n,BP) pairs, oldest
- * first, into out[2 * cap]; *n receives the count.  Synchronising. */
+/* The last min(steps, capacity, cap) recorded (p_BP, u_n,BP, fluid u_n)
+ * triples, oldest first, into out[3 * cap]; *n receives the count.
+ * Synchronising. */
 lee_status lee_watch_traces(lee_instance *inst, double *out, int64_t cap, int64_t *n);
 
 /* Synchronising: copy q^n at the domain nodes into caller arrays of

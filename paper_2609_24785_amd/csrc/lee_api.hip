@@ -147,7 +147,7 @@ Layout layout(const Host &h)
     L.pwork = take(std::max(h.np, 1) * sizeof(int2));
     L.trace = take(std::max<size_t>((size_t)h.trace_cap * h.np * 3, 1) * 8);
     L.dft = take(2 * std::max(h.np, 1) * 8);
-    L.watch = take(2 * std::max<size_t>((size_t)h.watch_cap, 1) * 8);
+    L.watch = take(3 * std::max<size_t>((size_t)h.watch_cap, 1) * 8);
     L.xg = take(xg_bytes(h));
     L.work1 = take(work1_capacity(h) * sizeof(int4));
     L.aux = take(work1_capacity(h) * sizeof(int2));
@@ -630,7 +630,7 @@ lee_status lee_watch_traces(lee_instance *I, double *out, int64_t cap, int64_t *
     if (h.watch_g < 0 || h.watch_cap == 0) return LEE_OK;
     long long done = 0;
     HIPCHK(hipMemcpyAsync(&done, I->dev.step, 8, hipMemcpyDeviceToHost, I->stream));
-    std::vector<double> ring(2 * (size_t)h.watch_cap);
+    std::vector<double> ring(3 * (size_t)h.watch_cap);
     HIPCHK(hipMemcpyAsync(ring.data(), I->dev.watch, ring.size() * 8, hipMemcpyDeviceToHost, I->stream));
     HIPCHK(hipStreamSynchronize(I->stream));
     int64_t m = std::min<int64_t>({(int64_t)done, (int64_t)h.watch_cap, cap});
@@ -638,8 +638,7 @@ lee_status lee_watch_traces(lee_instance *I, double *out, int64_t cap, int64_t *
     const int64_t first = done - m;
     for (int64_t s = 0; s < m; ++s) {
         const size_t r = (size_t)((first + s) % h.watch_cap);
-        out[2 * s] = ring[2 * r];
-        out[2 * s + 1] = ring[2 * r + 1];
+        for (int k = 0; k < 3; ++k) out[3 * s + k] = ring[3 * r + k];
     }
     *n = m;
     return LEE_OK;
@@ -854,7 +853,7 @@ lee_status lee_init_fields(lee_instance *I)
         HIPCHK(launch_fill(prec, I->base + L.psi[k], (size_t)h.ade_ns * std::max<size_t>(h.gidx.size(), 1), s));
     HIPCHK(launch_fill_bytes(I->base + L.trace, std::max<size_t>((size_t)h.trace_cap * h.np * 3, 1) * 8, s));
     HIPCHK(launch_fill_bytes(I->base + L.dft, 2 * std::max(h.np, 1) * 8, s));
-    HIPCHK(launch_fill_bytes(I->base + L.watch, 2 * std::max<size_t>((size_t)h.watch_cap, 1) * 8, s));
+    HIPCHK(launch_fill_bytes(I->base + L.watch, 3 * std::max<size_t>((size_t)h.watch_cap, 1) * 8, s));
     HIPCHK(launch_fill_bytes(I->base + L.xg, xg_bytes(h), s));
     HIPCHK(launch_fill_bytes(I->base + L.sync, SYNC_INTS * sizeof(int), s));
     I->up_counters[0] = 0;                       // first step of the next run

@@ -29,7 +29,7 @@ struct DevInst {
     const double *pw;       // probe weights, 16 per probe
     double *trace;          // ring of trace_cap steps x np x 3
     double *dft;            // 2 per probe: sum p exp(-i omega t)
-    double *watch;          // ring of watch_cap steps x (p_BP, u_n,BP) of ghost watch_g
+    double *watch;          // ring of watch_cap steps x (p_BP, u_n,BP, fluid u_n) of ghost watch_g
     unsigned long long *xg; // ghost values of the current stage for fused launches: per ghost
                             // and field, sizeof(T)/4 words of (32 value bits | stage epoch << 32)
     long long watch_cap;

@@ -47,7 +47,8 @@ struct Host {
     int64_t trace_cap = 0;
     double dft_omega = 0.0;
     int64_t dft_start = 0, dft_count = 0;
-    // watched ghost: p_BP and u_n,BP of every step's first stage
+    // watched ghost: p_BP, u_n,BP and the fluid's u_n at the boundary point,
+    // of every step's first stage
     int watch_g = -1;
     int64_t watch_cap = 0;
 };

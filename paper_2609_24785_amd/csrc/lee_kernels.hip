@@ -235,6 +235,34 @@ __device__ __forceinline__ void ghost_item(const DevInst *__restrict__ insts, co
         sN += __shfl_xor(sN, m, GL);
     }
     const T a0 = s0, aF = sF, aD = sD, aN = sN;
+    // the watched ghost also records the fluid's own normal velocity at its
+    // boundary point: the read-out of u.n at P_0 (weights w0), which the wall
+    // datum does not constrain (Sec. 4.3 compares it with the ADE's); one
+    // more pass over its cloud in the same lane layout, for that ghost only
+    const bool rec = stage == 0 && g == I.watch_g && I.watch_cap > 0;
+    T aW = 0;
+    if (rec) {
+        T cW[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) cW[r] = 0;
+        for (int base = e0; base < e1; base += 2 * VL) {
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int k = 0; k < 2; ++k) {
+                    const int e = base + sub + r * GL + k * VL;
+                    if (e >= e1) continue;
+                    const int o = coff[e];
+                    cW[r] += w4[4 * (size_t)e] * (nx * U[o] + ny * V[o]);
+                }
+        }
+        T sW = cW[0];
+        if constexpr (R == 2) sW = cW[0] + cW[1];
+        else sW += __shfl_xor(sW, 16, GL);
+#pragma unroll
+        for (int m = 8; m >= 1; m >>= 1) sW += __shfl_xor(sW, m, GL);
+        aW = sW;
+    }
     if (sub != 0 || !active) return;
     // steps 2-3: ADE derivative, wall normal velocity and its time derivative
     T d1 = 0, d2 = 0, Un = 0, Ud = 0;
@@ -272,10 +300,11 @@ __device__ __forceinline__ void ghost_item(const DevInst *__restrict__ insts, co
     }
     // steps 4-5: Neumann for p (dp/dn = +du_n/dt in the wall-to-fluid frame),
     // Dirichlet for u.n (= -u_n), free for u.t
-    if (stage == 0 && g == I.watch_g && I.watch_cap > 0) {   // recording only
-        double *wr = I.watch + 2 * (step % I.watch_cap);
+    if (rec) {                                               // recording only
+        double *wr = I.watch + 3 * (step % I.watch_cap);
         wr[0] = (double)a0;
         wr[1] = (double)Un;
+        wr[2] = (double)(-aW);                               // positive into the wall, like U
     }
     const T pg = aN + gdv.v[3] * ((T)I.h * Ud);
     const T un = aD + gdv.v[2] * (-Un);

@@ -100,8 +100,9 @@ class Instance:
     def __init__(self, case, precision: str = "f32", device: str = "cuda:0", stream=None,
                  trace_capacity: Optional[int] = None, dft: Optional[tuple] = None, bind: bool = True,
                  watch: Optional[tuple] = None):
-        """watch = (x, y, capacity): record p_BP and u_n,BP of the ghost whose
-        boundary point is nearest (x, y) for up to `capacity` steps."""
+        """watch = (x, y, capacity): record p_BP, the ADE's u_n,BP and the
+        fluid's u_n at the boundary point of the ghost whose boundary point is
+        nearest (x, y) for up to `capacity` steps."""
         self.lib = load()
         self.case = case
         self.precision = precision
@@ -230,9 +231,10 @@ class Instance:
         return out[:done.value]
 
     def watch_traces(self, cap: Optional[int] = None) -> np.ndarray:
-        """Recorded (p_BP, u_n,BP) per step of the watched ghost, oldest first."""
+        """Recorded (p_BP, u_n,BP of the ADE, u_n read out of the fluid) per
+        step of the watched ghost, oldest first."""
         cap = cap if cap is not None else max(self.step, 1)
-        out = np.zeros((max(cap, 1), 2))
+        out = np.zeros((max(cap, 1), 3))
         n = c_int64()
         check(self.lib.lee_watch_traces(self._h, _ptr(out), cap, ctypes.byref(n)), "lee_watch_traces")
         return out[:n.value]

@@ -18,15 +18,21 @@ boundary, and its work overlaps theirs in the same launches.
 
 Each result carries:
 - the probe traces;
-- the watched ghost's boundary pressure and wall normal velocity (the ghost
-  whose boundary point is nearest the pulse centre);
-- the reflection coefficient estimated from them;
+- the watched ghost's boundary pressure, the ADE's wall normal velocity and
+  the normal velocity read out of the fluid at the same boundary point (the
+  ghost whose boundary point is nearest the pulse centre);
+- the reflection coefficient estimated from the pressure and the fluid's
+  normal velocity;
 - the latency (completion - arrival) and the wait (admission - arrival).
 
-The reflection coefficient estimate: Z = P/U from the discrete Fourier
-transforms of p_BP and u_n,BP over the run, and R = (Z - 1)/(Z + 1), beside
-the exact (Z - 1)/(Z + 1) of the mass-spring-damper impedance
-Z = R + i (M w - K / w) (Single-resonance mass spring damper wall).
+The reflection coefficient estimate: Z = P/U_f from the discrete Fourier
+transforms of p_BP and of the fluid's normal velocity u_n at the boundary
+point (the least-squares read-out, not the ADE's own u_n,BP, which equals
+Y p_BP by construction), and R = (Z - 1)/(Z + 1), beside the exact
+(Z - 1)/(Z + 1) of the mass-spring-damper impedance Z = R + i (M w - K / w)
+(Single-resonance mass spring damper wall).  The ratio of the two normal
+velocities' transforms is reported too: the fluid realises the wall's
+velocity where it is close to 1 (Sec. 4.3).
 
 The scheduler is written against a small backend interface.  GpuBackend
 drives the library; tests drive the same scheduler with a simulated one.
@@ -73,24 +79,29 @@ class Result:
 
 
 def reflection(watch: np.ndarray, dt: float, impedance, omegas: Sequence[float]) -> Dict[str, Any]:
-    """R = (Z - 1)/(Z + 1) with Z = P/U from the transforms of the watched
-    ghost's p_BP and u_n,BP traces, at each angular frequency in omegas, beside
-    the exact value of the wall's impedance."""
+    """R = (Z - 1)/(Z + 1) with Z = P/U_f from the transforms of the watched
+    ghost's p_BP trace and of the fluid's normal velocity at its boundary
+    point (watch columns 0 and 2), at each angular frequency in omegas,
+    beside the exact value of the wall's impedance and the ratio U_f/U of the
+    fluid's and the ADE's normal velocity transforms."""
     if watch is None or len(watch) == 0:
         return {}
     t = dt * np.arange(len(watch))
-    out = {"omega": [], "R_est": [], "R_exact": []}
+    out = {"omega": [], "R_est": [], "R_exact": [], "un_fluid_over_ade": []}
     for w in omegas:
         e = np.exp(-1j * w * t) * dt
         P = np.sum(watch[:, 0] * e)
-        U = np.sum(watch[:, 1] * e)
+        Ua = np.sum(watch[:, 1] * e)
+        Uf = np.sum(watch[:, 2] * e)
         out["omega"].append(float(w))
-        if abs(U) > 0:
-            Z = P / U
+        if abs(Uf) > 0:
+            Z = P / Uf
             r = (Z - 1.0) / (Z + 1.0)
             out["R_est"].append([float(r.real), float(r.imag)])
         else:
             out["R_est"].append(None)
+        q = Uf / Ua if abs(Ua) > 0 else None
+        out["un_fluid_over_ade"].append(None if q is None else [float(q.real), float(q.imag)])
         if impedance.kind == "msd":
             Ze = impedance.R + 1j * (impedance.M * w - impedance.K / w)
             re = (Ze - 1.0) / (Ze + 1.0)

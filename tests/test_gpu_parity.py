@@ -59,8 +59,9 @@ def _compare(case, steps, prec, tol, tiling=None, graph_steps=None):
 
 @pytest.mark.parametrize("prec,tol", [("f64", 1e-9), ("f32", 1e-4)])
 def test_watched_ghost_traces_match_oracle(prec, tol):
-    """p_BP and u_n,BP of the ghost nearest the pulse, every step, against the
-    oracle's (the boundary read-out and the ADE wall velocity themselves)."""
+    """p_BP, the ADE's u_n,BP and the fluid's u_n at the boundary point of the
+    ghost nearest the pulse, every step, against the oracle's (the boundary
+    read-out, the ADE wall velocity and the unconstrained read-out of u.n)."""
     Instance, _ = _lee()
     case = lc.small_cylinder(160, 60)
     _say(f"[watch] {case.name} {prec}")
@@ -73,8 +74,8 @@ def test_watched_ghost_traces_match_oracle(prec, tol):
     assert g == inst.watch_g
     ora.run(60)
     ref = ora.watch_trace
-    assert got.shape == ref.shape == (60, 2)
-    for k in range(2):
+    assert got.shape == ref.shape == (60, 3)
+    for k in range(3):
         assert np.abs(ref[:, k]).max() > 0
         assert np.abs(got[:, k] - ref[:, k]).max() <= tol * np.abs(ref[:, k]).max()
 

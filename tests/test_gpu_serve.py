@@ -62,6 +62,7 @@ def test_served_result_matches_oracle():
     scale = np.abs(tr).max()
     assert np.abs(r.traces - tr).max() <= 1e-4 * scale
     w = ora.watch_trace
-    for k in range(2):
+    for k in range(3):
         assert np.abs(r.watch[:, k] - w[:, k]).max() <= 1e-4 * np.abs(w[:, k]).max()
     assert r.reflection and len(r.reflection["R_est"]) == 3
+    assert len(r.reflection["un_fluid_over_ade"]) == 3

@@ -90,12 +90,15 @@ def test_reflection_of_a_resistive_relation_is_exact():
     t = np.arange(400) * 0.01
     u = np.exp(-2.0 * t) * np.sin(9.0 * t)
     z0 = 3.0
-    w = np.stack([z0 * u, u], axis=1)
+    # columns: p_BP, the ADE's u_n and the fluid's u_n; the estimate reads
+    # the pressure and the fluid's velocity only
+    w = np.stack([z0 * u, 0.5 * u, u], axis=1)
     imp = lc.Impedance("msd", R=z0, M=0.1, K=8.1)      # resonance at sqrt(K/M) = 9
     out = reflection(w, 0.01, imp, [4.5, 9.0, 18.0])
-    for est in out["R_est"]:
+    for est, q in zip(out["R_est"], out["un_fluid_over_ade"]):
         assert est[0] == pytest.approx((z0 - 1) / (z0 + 1), abs=1e-12)
         assert est[1] == pytest.approx(0.0, abs=1e-12)
+        assert q[0] == pytest.approx(2.0, abs=1e-12) and q[1] == pytest.approx(0.0, abs=1e-12)
     # the exact value at resonance is (R - 1)/(R + 1)
     assert out["R_exact"][1][0] == pytest.approx((z0 - 1) / (z0 + 1), abs=1e-12)
     assert out["R_exact"][1][1] == pytest.approx(0.0, abs=1e-12)
