@@ -266,6 +266,24 @@ lee_status lee_get_ade_states(lee_instance *inst, double *out);
  * analysis of the step map needs. */
 lee_status lee_set_ade_states(lee_instance *inst, const double *in);
 
+/*
+ * The semi-discrete operator at the current state (abstract: the spectral
+ * analysis of the linearised operator; Sec. 3.2 steps 1-6 without the stage
+ * update): the ghost fill and ADE derivative from (q^n, Psi^n) and the
+ * right-hand side of the LEE at every fluid node, computed by the
+ * instance's own stage kernels (its first stage, run once with an update
+ * coefficient of one, then undone: q^n, Psi^n, the step counter and the
+ * stage sequence are unchanged).  p, u, v (ny * nx doubles, row-major, any
+ * may be NULL) receive the right-hand side at the fluid nodes and zero
+ * elsewhere; psi (NULL allowed; ns * G doubles in the layout of
+ * lee_get_ade_states) receives dPsi/dt (zero for a rigid wall).  The source
+ * term, if any, is included at the current step's time.  Each value is the
+ * difference of the stage output and q^n in the instance's precision, so an
+ * FP32 instance carries FP32 rounding.  Synchronising; LEE_E_STATE while a
+ * partial step is pending.
+ */
+lee_status lee_rhs(lee_instance *inst, double *p, double *u, double *v, double *psi);
+
 /* Completed steps: the device's step counter once the stream is idle
  * (synchronising; budgets of a batch may have idled the instance); before
  * lee_bind, 0.  Reports a spent fused-stage wait as lee_synchronize does. */

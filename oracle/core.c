@@ -109,7 +109,7 @@ static long long pad_index(const oc_case *c, long long lin)
  * (recording only) */
 static void fill_ghosts(const oc_case *c, double *p, double *u, double *v,
                         const double *psi_in, const double *psi_n, double *psi_out,
-                        double alpha, double *watch)
+                        double adt, double *watch)
 {
     int g;
 #pragma omp parallel for schedule(static)
@@ -171,7 +171,7 @@ static void fill_ghosts(const oc_case *c, double *p, double *u, double *v,
         u[q] = nx * ung - ny * utg;
         v[q] = ny * ung + nx * utg;
         for (i = 0; i < ns; ++i)
-            psi_out[(long long)ns * g + i] = psi_n[(long long)ns * g + i] + alpha * c->dt * d[i];
+            psi_out[(long long)ns * g + i] = psi_n[(long long)ns * g + i] + adt * d[i];
     }
 }
 
@@ -209,7 +209,7 @@ static double rad_deriv(const oc_case *c, const double *q, long long at, int i, 
 /* step 6: RHS at fluid nodes of the stage input (ps, us, vs) and the update */
 static void sweep(const oc_case *c, const double *p, const double *u, const double *v,
                   const double *ps, const double *us, const double *vs,
-                  double *po, double *uo, double *vo, double alpha, double t)
+                  double *po, double *uo, double *vo, double adt, double t)
 {
     const long long sy = c->nx + 2 * c->F;
     const double amp = c->has_src ? sin(c->src_omega * t) : 0.0;
@@ -273,9 +273,9 @@ static void sweep(const oc_case *c, const double *p, const double *u, const doub
                 double r2 = (x - c->src_x) * (x - c->src_x) + (y - c->src_y) * (y - c->src_y);
                 rp += c->src_a * exp(-c->src_b * r2) * amp;
             }
-            po[q] = p[q] + alpha * c->dt * rp;
-            uo[q] = u[q] + alpha * c->dt * ru;
-            vo[q] = v[q] + alpha * c->dt * rv;
+            po[q] = p[q] + adt * rp;
+            uo[q] = u[q] + adt * ru;
+            vo[q] = v[q] + adt * rv;
         }
     }
 }
@@ -307,8 +307,9 @@ int oc_run(const oc_case *c, double *p, double *u, double *v, double *psi,
             double *ps = l == 0 ? p : S[0], *us = l == 0 ? u : S[1], *vs = l == 0 ? v : S[2];
             const double *psi_in = l == 0 ? psi : psS;
             double t = ((double)(step0 + s) + RK_C[l]) * c->dt;
-            fill_ghosts(c, ps, us, vs, psi_in, psi, psT, RK_ALPHA[l], (watch && l == 0) ? watch + 3 * s : NULL);
-            sweep(c, p, u, v, ps, us, vs, T[0], T[1], T[2], RK_ALPHA[l], t);
+            const double adt = RK_ALPHA[l] * c->dt;
+            fill_ghosts(c, ps, us, vs, psi_in, psi, psT, adt, (watch && l == 0) ? watch + 3 * s : NULL);
+            sweep(c, p, u, v, ps, us, vs, T[0], T[1], T[2], adt, t);
             for (k = 0; k < 3; ++k) { double *x = S[k]; S[k] = T[k]; T[k] = x; }
             { double *x = psS; psS = psT; psT = x; }
         }
@@ -333,5 +334,34 @@ int oc_run(const oc_case *c, double *p, double *u, double *v, double *psi,
     }
     free(buf);
     free(psb);
+    return 0;
+}
+
+/*
+ * The semi-discrete operator at a state (the spectral analysis of the
+ * abstract): with the ghosts filled from (p, u, v) and psi as every stage
+ * fills them, (rp, ru, rv) receive the right-hand side of step 6 at the
+ * fluid nodes (zero elsewhere) and rpsi the auxiliary states' derivative
+ * dPsi/dt, at time t (the source, if any, at that time).  Each is the stage
+ * update with q^n = 0 and a step of 1, so it is the same arithmetic as a
+ * stage.  Arrays are (ny + 2F) x (nx + 2F); the inputs are not modified.
+ */
+int oc_rhs(const oc_case *c, const double *p, const double *u, const double *v, const double *psi, double t,
+           double *rp, double *ru, double *rv, double *rpsi)
+{
+    const long long sy = c->nx + 2 * c->F;
+    const long long n = sy * (long long)(c->ny + 2 * c->F);
+    const long long npsi = (long long)c->ade_ns * (c->G > 0 ? c->G : 1);
+    double *buf = (double *)calloc((size_t)(4 * n), sizeof(double));
+    double *z = (double *)calloc((size_t)npsi, sizeof(double));
+    if (!buf || !z) { free(buf); free(z); return -1; }
+    double *ps = buf, *us = buf + n, *vs = buf + 2 * n, *zero = buf + 3 * n;
+    memcpy(ps, p, (size_t)n * sizeof(double));
+    memcpy(us, u, (size_t)n * sizeof(double));
+    memcpy(vs, v, (size_t)n * sizeof(double));
+    fill_ghosts(c, ps, us, vs, psi, z, rpsi, 1.0, NULL);
+    sweep(c, zero, zero, zero, ps, us, vs, rp, ru, rv, 1.0, t);
+    free(buf);
+    free(z);
     return 0;
 }

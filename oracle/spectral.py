@@ -21,6 +21,10 @@ two-register scheme on a linear system).  The scheme is stable when the
 spectral radius of G does not exceed 1, and the growth per step of the worst
 mode is that spectral radius.
 
+The semi-discrete operator L itself (operator_matrix: the right-hand side
+at each unit state) gives the growth rates per unit time as the real parts
+of its eigenvalues; G = P4(dt L) ties the two assemblies together.
+
 Parity: pinned (tests) against an independent Kronecker-product
 construction of L and its Taylor polynomial on wall-free grids, and against
 the dissipativity that the central stencil, the selective filter and the
@@ -88,6 +92,47 @@ def step_matrix(case: Case, filter_rows=None) -> np.ndarray:
         G[:, k] = _get(s)
         e[k] = 0.0
     return G
+
+
+def operator_matrix(case: Case) -> np.ndarray:
+    """L[n, n], the semi-discrete operator of the scheme (the right-hand side
+    with the ghosts eliminated: every stage fills them linearly from the
+    stage value and the auxiliary states), in the state ordering of
+    step_matrix; column k is the right-hand side at the k-th unit state
+    (oc_rhs).  The step map is the fourth-order Taylor polynomial of dt L;
+    the eigenvalues of L are the growth rates per unit time, independent of
+    the time step."""
+    import ctypes
+    from .solver import _load, _ptr
+    s = _solver(case)
+    lib = _load()
+    lib.oc_rhs.restype = ctypes.c_int
+    lib.oc_rhs.argtypes = [ctypes.c_void_p] * 5 + [ctypes.c_double] + [ctypes.c_void_p] * 4
+    c = s.case
+    nf, naux, n = _layout(s)
+    sl = (slice(F, F + c.ny), slice(F, F + c.nx))
+    rp, ru, rv = (np.zeros(s.shape) for _ in range(3))
+    rpsi = np.zeros_like(s.psi)
+    L = np.empty((n, n))
+    e = np.zeros(n)
+    for k in range(n):
+        e[k] = 1.0
+        _put(s, e)
+        if lib.oc_rhs(ctypes.byref(s._cs), _ptr(s.p), _ptr(s.u), _ptr(s.v), _ptr(s.psi), 0.0,
+                      _ptr(rp), _ptr(ru), _ptr(rv), _ptr(rpsi)) != 0:
+            raise MemoryError("oracle core allocation failed")
+        for m, arr in enumerate((rp, ru, rv)):
+            L[m * nf:(m + 1) * nf, k] = arr[sl][s.fluid]
+        if naux:
+            L[3 * nf:, k] = rpsi[:naux]
+        e[k] = 0.0
+    return L
+
+
+def spectral_abscissa(L: np.ndarray) -> float:
+    """Largest real part of the eigenvalues of L: the growth rate per unit
+    time of the worst mode of the semi-discrete scheme (stable when <= 0)."""
+    return float(np.max(np.linalg.eigvals(L).real))
 
 
 def apply_steps(case: Case, x0: np.ndarray, steps: int) -> np.ndarray:

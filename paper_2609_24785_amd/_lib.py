@@ -81,6 +81,7 @@ SIGNATURES = {
     "lee_set_fields": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "lee_get_ade_states": (c_int32, [c_void_p, c_void_p]),
     "lee_set_ade_states": (c_int32, [c_void_p, c_void_p]),
+    "lee_rhs": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "lee_get_step": (c_int32, [c_void_p, ctypes.POINTER(c_int64)]),
     "lee_export_lists": (c_int32, [c_void_p] + [c_void_p] * 7),
     "lee_set_tiling": (c_int32, [c_void_p, ctypes.POINTER(Tiling)]),

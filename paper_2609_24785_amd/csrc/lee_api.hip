@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstddef>
 #include <climits>
 #include <cmath>
 #include <cstdio>
@@ -1038,6 +1039,58 @@ lee_status lee_set_ade_states(lee_instance *I, const double *in)
         HIPCHK(hipStreamSynchronize(I->stream));
     }
     return LEE_OK;
+}
+
+lee_status lee_rhs(lee_instance *I, double *p, double *u, double *v, double *psi)
+{
+    if (!I || !I->bound) return fail(LEE_E_STATE, "instance not bound");
+    if (I->next_stage != 0) return fail(LEE_E_STATE, "a partial step is pending");
+    const Host &h = I->host;
+    const Layout L = layout(h);
+    hipStream_t s = I->stream;
+    // the step's first stage with an update coefficient of one writes
+    // q^(1) = q^n + RHS(q^n) and Psi^(1) = Psi^n + dPsi/dt; the coefficient is
+    // put back before anything else runs on the stream
+    static const double one = 1.0;
+    char *adt0 = (char *)I->d_inst + offsetof(DevInst, alpha_dt);
+    HIPCHK(hipMemcpyAsync(adt0, &one, sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHK(issue_stage(I, 0, 0));
+    HIPCHK(hipMemcpyAsync(adt0, &I->dev.alpha_dt[0], sizeof(double), hipMemcpyHostToDevice, s));
+    // a fused launch published its ghost values with this step's first-stage
+    // epoch: clear them, so that the step itself cannot take them
+    HIPCHK(launch_fill_bytes(I->base + L.xg, xg_bytes(h), s));
+    const size_t nn = (size_t)h.d.nx * h.d.ny;
+    double *o[3] = {p, u, v};
+    std::vector<double> q1(nn), qn(nn);
+    for (int f = 0; f < 3; ++f) {
+        if (!o[f]) continue;
+        lee_status st = h.d.precision == LEE_F32 ? copy_plane_out<float>(I, 1, f, q1.data())
+                                                 : copy_plane_out<double>(I, 1, f, q1.data());
+        if (st == LEE_OK)
+            st = h.d.precision == LEE_F32 ? copy_plane_out<float>(I, 0, f, qn.data())
+                                          : copy_plane_out<double>(I, 0, f, qn.data());
+        if (st != LEE_OK) return st;
+        for (size_t k = 0; k < nn; ++k) o[f][k] = h.fluid[k] ? q1[k] - qn[k] : 0.0;
+    }
+    const size_t n = (size_t)h.ade_ns * h.gidx.size();
+    if (psi && n) {
+        if (h.ade_kind == 0) {
+            std::fill(psi, psi + n, 0.0);
+        } else if (h.d.precision == LEE_F32) {
+            std::vector<float> a(n), b(n);
+            HIPCHK(hipMemcpyAsync(a.data(), I->dev.psi[1], n * 4, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipMemcpyAsync(b.data(), I->dev.psi[0], n * 4, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            for (size_t k = 0; k < n; ++k) psi[k] = (double)a[k] - (double)b[k];
+        } else {
+            std::vector<double> a(n), b(n);
+            HIPCHK(hipMemcpyAsync(a.data(), I->dev.psi[1], n * 8, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipMemcpyAsync(b.data(), I->dev.psi[0], n * 8, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            for (size_t k = 0; k < n; ++k) psi[k] = a[k] - b[k];
+        }
+    }
+    return check_sync(I->d_sync, s);
 }
 
 lee_status lee_probe(lee_instance *I, int32_t np, const double *xy, double *out)

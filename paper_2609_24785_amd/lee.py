@@ -211,6 +211,17 @@ class Instance:
             raise ValueError(f"expected {ns * self.summary.G} auxiliary states, got {a.size}")
         check(self.lib.lee_set_ade_states(self._h, _ptr(a)), "lee_set_ade_states")
 
+    def rhs(self):
+        """The semi-discrete right-hand side at the current state (lee_rhs):
+        (p, u, v) planes and the auxiliary states' derivatives, one row per
+        ghost."""
+        c = self.case
+        planes = [np.zeros((c.ny, c.nx)) for _ in range(3)]
+        ns = max(int(self.summary.ade_states), 1)
+        psi = np.zeros(ns * self.summary.G)
+        check(self.lib.lee_rhs(self._h, *(_ptr(a) for a in planes), _ptr(psi) if psi.size else None), "lee_rhs")
+        return planes[0], planes[1], planes[2], psi.reshape(-1, ns)
+
     def probe(self, xy: Sequence[Sequence[float]]):
         xy = np.ascontiguousarray(np.asarray(xy, dtype=np.float64).reshape(-1, 2))
         out = np.zeros((len(xy), 3))

@@ -9,9 +9,13 @@ order, x fastest) followed, for an impedance wall, by the auxiliary states
 of every ghost.  The scheme is stable when the spectral radius of G is at
 most 1; above 1, the worst mode grows by that factor every step.
 
-Two tools, both stepping through the library's kernels:
+Three tools, all running the library's kernels:
 * step_matrix: G column by column on a small grid (one step from each unit
   state); its eigenvalues come from a dense host eigen-solve;
+* operator_matrix: the semi-discrete operator L (G is the fourth-order
+  Taylor polynomial of dt L) column by column, one right-hand-side
+  evaluation per unit state (lee_rhs); the real parts of its eigenvalues are
+  growth rates per unit time, free of the time step;
 * power_growth: the growth per step of the worst mode by power iteration,
   for grids far too large to assemble: run chunks of steps from a start
   state and renormalise between chunks.
@@ -93,6 +97,33 @@ def step_matrix(inst: Instance) -> np.ndarray:
         G[:, k] = sp.get()
         e[k] = 0.0
     return G
+
+
+def operator_matrix(inst: Instance) -> np.ndarray:
+    """L[n, n], the semi-discrete operator (the right-hand side with the
+    ghosts eliminated), column k the right-hand side at the k-th unit state
+    (lee_rhs, through the instance's stage kernels); same state ordering as
+    step_matrix.  Its eigenvalues are the growth rates per unit time."""
+    _check_homogeneous(inst)
+    sp = StatePacker(inst)
+    L = np.empty((sp.n, sp.n))
+    e = np.zeros(sp.n)
+    nf = sp.nf
+    for k in range(sp.n):
+        e[k] = 1.0
+        sp.put(e)
+        p, u, v, psi = inst.rhs()
+        for m, a in enumerate((p, u, v)):
+            L[m * nf:(m + 1) * nf, k] = a[sp.mask]
+        if sp.naux:
+            L[3 * nf:, k] = psi.reshape(-1)[:sp.naux]
+        e[k] = 0.0
+    return L
+
+
+def spectral_abscissa(L: np.ndarray) -> float:
+    """Largest real part of the eigenvalues of L (stable when <= 0)."""
+    return float(np.max(np.linalg.eigvals(L).real))
 
 
 def spectral_radius(G: np.ndarray) -> float:

@@ -124,3 +124,38 @@ def test_state_round_trip_at_full_size():
     back = sp.get()
     inst.close()
     assert np.array_equal(back, x)
+
+
+OPER_CASES = CASES + [("fused-two-launch", MSD, 5, 0.2)]
+
+
+@pytest.mark.parametrize("name,z,H,fs", OPER_CASES, ids=[c[0] for c in OPER_CASES])
+def test_semi_discrete_operator_matches_oracle(name, z, H, fs):
+    """The semi-discrete operator L through the C ABI (lee_rhs: one
+    right-hand-side evaluation of the library's stage kernels per unit state)
+    against the oracle's (oc_rhs), entry by entry in FP64, with the same
+    growth rate per unit time; the step map of the same instance afterwards
+    is still the oracle's (lee_rhs leaves the state and the step sequence as
+    they were, and a fused launch takes none of its exchange words)."""
+    Instance, stability = _mods()
+    case = _cyl(z, H=H, fs=fs)
+    _say(f"[stability] semi-discrete operator {case.name} {name} f64")
+    inst = Instance(case, "f64")
+    if name == "fused-two-launch":
+        inst.set_tiling(kind="tile", cols=64, rows=8, fused=0)
+    else:
+        inst.set_tiling(kind="tile", cols=64, rows=8, fused=1)
+    L = stability.operator_matrix(inst)
+    ref = osp.operator_matrix(case)
+    assert L.shape == ref.shape
+    scale = np.abs(ref).max()
+    err = np.abs(L - ref).max()
+    a_g, a_o = stability.spectral_abscissa(L), osp.spectral_abscissa(ref)
+    _say(f"[stability] n={L.shape[0]} max|dL|={err:.3e} (scale {scale:.3f}); abscissa gpu {a_g:.6e} oracle {a_o:.6e}")
+    assert err <= 1e-11 * scale
+    assert abs(a_g - a_o) <= 1e-9 * scale
+    # the instance steps on as if lee_rhs had not been called
+    G = stability.step_matrix(inst)
+    inst.close()
+    Gr = osp.step_matrix(case)
+    assert np.abs(G - Gr).max() <= 1e-11 * np.abs(Gr).max()

@@ -357,3 +357,50 @@ def test_peak_coupling_gain_limit(monkeypatch):
     monkeypatch.setattr(ade_mod, "PEAK_MAX", 100.0)
     bad = sp.spectral_radius(sp.step_matrix(_coarse(1, _resonant_wall(5.0, wh=0.5), 0.5)))
     assert bad > 1.002, bad
+
+
+# ---- the semi-discrete operator L (abstract: spectral analysis of the
+# linearised semi-discrete operator) ----------------------------------------
+
+@pytest.mark.parametrize("H,fs,sw", [(5, 0.2, 3), (3, 0.0, 0)])
+def test_wall_free_operator_is_the_kronecker_operator(H, fs, sw):
+    case = _wall_free(13, 11, H, fs, sponge_cells=sw, sponge_sigma=0.4 if sw else 0.0)
+    L = sp.operator_matrix(case)
+    ref = _operator(case)
+    assert L.shape == ref.shape
+    assert np.max(np.abs(L - ref)) < 1e-13 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("z", [lc.Impedance(), MSD_COARSE], ids=["rigid", "msd"])
+@pytest.mark.parametrize("H,fs", [(5, 0.2), (3, 0.0)], ids=["11pt-filter", "paper-scheme"])
+def test_step_map_is_taylor_polynomial_of_operator_with_a_wall(z, H, fs):
+    # one RHS evaluation per unit state against four stages per unit state:
+    # G = P4(dt L) holds with the ghost fill and the auxiliary states in both
+    c = lc.coarse_cylinder(20, 4.0, 0.31, 0.17, impedance=z, H=H, filter_sigma=fs)
+    G = sp.step_matrix(c)
+    L = sp.operator_matrix(c)
+    assert np.max(np.abs(G - _taylor4(c.dt * L))) < 1e-13 * max(1.0, np.max(np.abs(G)))
+    if z.kind != "rigid":                       # the auxiliary states couple both ways
+        nf = (L.shape[0] - 2 * len(sp._solver(c).gidx)) // 3
+        assert np.abs(L[3 * nf:, :3 * nf]).max() > 0 and np.abs(L[:3 * nf, 3 * nf:]).max() > 0
+
+
+def test_operator_does_not_depend_on_the_time_step_without_the_filter():
+    # without the filter's sigma_d / dt term the right-hand side has no dt in
+    # it (the ADE derivative and the Neumann datum are rates): growth rates
+    # per unit time are properties of the space discretisation alone
+    c = lc.coarse_cylinder(20, 4.0, 0.31, 0.17, impedance=MSD_COARSE, H=3, filter_sigma=0.0)
+    L1 = sp.operator_matrix(c.replace(cfl=0.5))
+    L2 = sp.operator_matrix(c.replace(cfl=0.25))
+    assert np.max(np.abs(L1 - L2)) <= 1e-15 * np.max(np.abs(L1))
+
+
+def test_paper_scheme_grows_at_the_wall_and_the_filter_rows_do_not():
+    # the semi-discrete growth rate of a coarse shifted cylinder: the paper's
+    # scheme (no filter) has growing modes; the filtered scheme with the
+    # near-wall rows has none beyond rounding of the eigen-solve
+    c = lc.coarse_cylinder(24, 4.0, 0.31, 0.17)
+    a_paper = sp.spectral_abscissa(sp.operator_matrix(c.replace(H=3, filter_sigma=0.0)))
+    a_filt = sp.spectral_abscissa(sp.operator_matrix(c))
+    assert a_paper > 5e-3, a_paper
+    assert a_filt < 2e-4, a_filt
