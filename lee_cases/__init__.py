@@ -350,6 +350,33 @@ def paper_cylinder_pulse(steps: int = 400) -> Case:
     )
 
 
+def paper_monopole(steps: int = 1500, h: float = 0.02) -> Case:
+    """The paper's harmonic-monopole configuration (Sec. 4.3): [-6, 6]^2 at
+    h = 0.02 (601^2 nodes), cylinder r_c = 0.5 at the origin, monopole of
+    amplitude 1 and half-width 0.2 at (4, 0) driven at omega = 8 pi, wall
+    (M, K, R) = (0.025, 15.79, 1) (resonance at 8 pi), CFL 0.5, the paper's
+    scheme (7-point DRP, no filter) and the non-reflecting condition on all
+    four sides; t_end = 15 and a running DFT over the last two time units
+    (eight periods, the paper's window [13, 15]) on rings r = 0.6 (the
+    nearest ring whose probe stencils stay in the fluid at this h; the
+    paper's is 0.55) and r = 5, 72 points each."""
+    n = int(round(12.0 / h)) + 1
+    omega = 8.0 * math.pi
+    rings = []
+    for r in (0.6, 5.0):
+        for j in range(72):
+            t = 2.0 * math.pi * (j + 0.5) / 72.0
+            rings.append((r * math.cos(t), r * math.sin(t)))
+    return Case(
+        nx=n, ny=n, x0=-6.0, y0=-6.0, h=h, H=3, cfl=0.5, filter_sigma=0.0,
+        wall=Wall("circle", 0.0, 0.0, rc=0.5),
+        impedance=Impedance("msd", R=1.0, M=0.025, K=15.79),
+        source=Monopole(4.0, 0.0, 1.0, 0.2, omega), steps=steps, probes=tuple(rings),
+        dft_steps=int(round(2.0 / (0.5 * h))), radiation=True, rad_center=(0.0, 0.0),
+        name="paper-monopole-601",
+    )
+
+
 def named(name: str) -> Case:
     table = {
         "flat-wall-201": flat_wall_201,

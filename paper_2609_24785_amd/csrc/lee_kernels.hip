@@ -1236,6 +1236,89 @@ __device__ __forceinline__ void band_row(const DevInst &I, const TileCtx<T> &c, 
     }
 }
 
+#ifndef BAND_PASS
+#define BAND_PASS 1
+#endif
+
+// The radiation band nodes of a tile in a pass of their own, one (node,
+// field) item per thread: the items of all the tile's band nodes in the
+// three fields are spread over the workgroup's threads, so no lane works
+// through a chain of band nodes while the rest of its wave waits (in a
+// left or right edge tile only the lanes of the first or last columns hold
+// band nodes, and the edge tiles of a launch that fills the device in one
+// wave are on its critical path).  Each item is band_row's arithmetic for
+// one field of one node; the stage input comes from the tile's LDS copy,
+// q^n from global memory.
+template <typename T, int TX, int TY>
+__device__ __forceinline__ void band_pass(const DevInst &I, const TileCtx<T> &c, const T (*reg)[TY + 10][TX + 16],
+                                          const T (*wt)[7], int stage)
+{
+    const int W = I.rad_w, nx = I.nx, ny = I.ny;
+    const int ncol = min(TX, nx - c.c0);         // tile columns inside the domain
+    const int nrow = c.r1 - c.r0;
+    // tile rows [0, lo) and [hi, nrow) lie wholly in the band (j < W or
+    // j >= ny - W); the rows between hold band nodes only in the columns
+    // [0, cl) and [cr, ncol) (col < W or col >= nx - W)
+    const int lo = max(0, min(nrow, W - c.r0));
+    const int hi = max(lo, min(nrow, ny - W - c.r0));
+    const int cl = max(0, min(ncol, W - c.c0));
+    const int cr = max(cl, min(ncol, nx - W - c.c0));
+    const int nbc = cl + (ncol - cr);
+    const int nfull = (lo + (nrow - hi)) * ncol;
+    const int items = 3 * (nfull + (hi - lo) * nbc);
+    for (int it = (int)threadIdx.x; it < items; it += 256) {
+        const int f = it % 3, nd = it / 3;
+        int i, tc;
+        if (nd < nfull) {
+            const int r = nd / ncol;
+            i = r < lo ? r : hi + (r - lo);
+            tc = nd - r * ncol;
+        } else {
+            const int m = nd - nfull;
+            const int r = m / nbc;
+            const int k = m - r * nbc;
+            i = lo + r;
+            tc = k < cl ? k : cr + (k - cl);
+        }
+        const int j = c.r0 + i, col = c.c0 + tc;
+        const int eg = min(min(col, j), min(nx - 1 - col, ny - 1 - j));
+        const int rx = rad_place(col, nx), ry = rad_place(j, ny);
+        const int lc = tc + 8;
+        const int y0 = j - ry - (c.r0 - 5);      // LDS row of the y window's first node
+        const bool ylds = y0 >= 0 && y0 + 6 < TY + 10;
+        const T x = (T)(I.x0 - I.rad_xc) + (T)col * (T)I.h, y = (T)(I.y0 - I.rad_yc) + (T)j * (T)I.h;
+        const T ir = (T)1 / sqrt(x * x + y * y);
+        const T ct = x * ir, st = y * ir, hr = (T)0.5 * ir;
+        T sg = 0;
+        if (c.in_sponge && eg < I.sponge_w) {
+            const T fr = (T)(I.sponge_w - eg) * c.sp_inv;
+            sg = c.sp_s * fr * fr;
+        }
+        const T *row = &reg[f][i + 5][0];
+        T dx = 0, dy = 0;
+#pragma unroll
+        for (int k = 0; k < 7; ++k) dx += wt[rx][k] * row[lc - rx + k];
+        if (ylds) {
+#pragma unroll
+            for (int k = 0; k < 7; ++k) dy += wt[ry][k] * reg[f][y0 + k][lc];
+        } else {
+            const GLOBAL T *q = gp<T>(I.f[c.ib][f]) + (I.org + (j - ry) * I.pitch + col);
+#pragma unroll 1
+            for (int k = 0; k < 7; ++k) dy += wt[ry][k] * q[k * I.pitch];
+        }
+        const T qc = row[lc];
+        T rq = -(ct * dx + st * dy + hr * qc) - sg * qc;
+        if (f == 0 && c.has_src) {
+            const T xx = (T)(col - I.src_ic) * (T)I.h - (T)I.src_fx;
+            const T yy = (T)(j - I.src_jc) * (T)I.h - (T)I.src_fy;
+            rq += c.amp * exp(-(T)I.src_b * (xx * xx + yy * yy));
+        }
+        const unsigned off = (unsigned)(I.org + j * I.pitch + col);
+        const T base = stage != 0 ? gp<T>(I.f[0][f])[off] : qc;
+        gp<T>(I.f[c.ob][f])[off] = c.adt * rq + base;
+    }
+}
+
 // One tile: wk = {instance, first column, first row, +-(end row)}.
 template <typename T, int VEC, bool FILT, int TX, int TY>
 __device__ __forceinline__ void tile_body(const DevInst *__restrict__ insts, const int4 wk, int stage, int slot,
@@ -1291,9 +1374,11 @@ __device__ __forceinline__ void tile_body(const DevInst *__restrict__ insts, con
         bool ok[VEC];
         bool all;
         tile_row<T, VEC, FILT, TX, TY>(I, c, lds, wfd, wiv, stage, i, tc, iv, pn, un, vn, po, uo, vo, ok, all);
-        if (c.in_band) band_row<T, VEC, TX, TY>(I, c, lds, wt, stage, i, tc, pn, un, vn, po, uo, vo, ok, all);
+        if (!BAND_PASS && c.in_band)
+            band_row<T, VEC, TX, TY>(I, c, lds, wt, stage, i, tc, pn, un, vn, po, uo, vo, ok, all);
         tile_store<T, VEC>(I, c.ob, (unsigned)(I.org + j * I.pitch + c.c0 + tc), po, uo, vo, ok, all);
     }
+    if (BAND_PASS && c.in_band) band_pass<T, TX, TY>(I, c, lds, wt, stage);
 
 }
 

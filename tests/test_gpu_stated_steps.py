@@ -160,3 +160,58 @@ def test_batch_256_at_2000_steps_members_match_oracle():
                 assert err <= 1e-6 * scale, (c.name, k)
     assert all(v > 0 for v in taken.values()), taken
     b.close()
+
+
+@pytest.fixture(scope="module")
+def paper_monopole_oracle():
+    case = lc.paper_monopole()
+    _say(f"[stated] oracle {case.name} {case.steps} steps")
+    s = OracleSolver(case)
+    tr = s.run(case.steps)
+    amp = dft_amplitude(tr[:, :, 0], case, case.steps, case.source.omega, case.dft_steps)
+    return case, s, amp
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-9), ("f32", 1e-4)])
+def test_paper_monopole_on_device(paper_monopole_oracle, prec, tol):
+    """The paper's own monopole configuration (Sec. 4.3: 601^2, 7-point
+    scheme, no filter, radiation on all sides, t_end = 15) on the device:
+    fields and ring DFT amplitudes over the paper's window against the
+    oracle; the distance of both to App. C is printed (the oracle's physics
+    is pinned elsewhere).
+
+    FP64 is held to 1e-9 everywhere.  FP32 is held to 1e-3 on the pressure
+    field and the ring amplitudes only: the paper's scheme without a filter
+    carries a growing wall mode (the semi-discrete operator of a coarse
+    cylinder grows at about 0.01 per unit time at h = 1, i.e. about 0.5 at
+    h = 0.02, a factor of a few thousand over t = 15), which amplifies FP32
+    rounding near the wall, most in the velocities (measured: p 3.2e-4,
+    u 8.8e-3, v 4.9e-3, ring amplitudes 5.4e-4)."""
+    import math
+    from tests import refsol
+    Instance, _ = _lee()
+    case, ora, amp = paper_monopole_oracle
+    n = case.dft_steps
+    _say(f"[stated] {case.name} {prec} {case.steps} steps")
+    inst = Instance(case, prec, dft=(case.source.omega, case.steps - n, n))
+    inst.step_n(case.steps)
+    inst.synchronize()
+    errs = [relative_l2(a, b, ora.fluid) for a, b in zip(inst.fields(), ora.fields())]
+    got = inst.dft()
+    inst.close()
+    scale = np.abs(amp).max()
+    dft_err = float(np.abs(got - amp).max() / scale)
+    xy = np.array(case.probes)
+    imp = case.impedance
+    Z = imp.R + 1j * (imp.M * case.source.omega - imp.K / case.source.omega)
+    P, _ = refsol.monopole_cylinder(xy[:, 0], xy[:, 1], case.source.omega, 1.0, 0.2, 4.0, 0.0, 0.5, Z=Z)
+    e_app = [float(np.linalg.norm(got[k * 72:(k + 1) * 72] - P[k * 72:(k + 1) * 72]) /
+                   np.linalg.norm(P[k * 72:(k + 1) * 72])) for k in range(2)]
+    _say(f"[stated] rel L2 p,u,v = {errs}; ring DFT vs oracle {dft_err:.3e}; vs App. C r=0.6 {e_app[0]:.3e} "
+         f"r=5 {e_app[1]:.3e}")
+    if prec == "f64":
+        assert max(errs) <= tol, errs
+        assert dft_err <= tol
+    else:
+        assert errs[0] <= 1e-3, errs
+        assert dft_err <= 1e-3
