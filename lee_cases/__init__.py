@@ -111,6 +111,7 @@ class Case:
     H: int = 5                     # DRP half-width: 5 (11-point) or 3 (7-point)
     cfl: float = 0.5               # dt = cfl * h  (c0 = 1)
     filter_sigma: float = 0.2      # selective-filter strength; 0 disables it
+    filter_explicit: bool = False  # the filter once per step (q -= sigma F q) instead of in each stage's RHS
     sponge_cells: int = 0          # width of the outer damping layer
     sponge_sigma: float = 0.0      # peak damping rate at the domain edge
     wall: Wall = Wall()

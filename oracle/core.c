@@ -92,6 +92,7 @@ typedef struct {
     double rad_b[3][7];         /* one-sided 7-point first derivative at point m of 0..6 */
     const unsigned char *fw;    /* per node, x then y: index of its filter row in frow */
     double frow[36][11];        /* filter rows: weights of nodes -5..5 */
+    int filter_explicit;        /* the filter once per step instead of in the RHS */
 } oc_case;
 
 static const double RK_ALPHA[4] = {0.25, 1.0 / 3.0, 0.5, 1.0};
@@ -248,7 +249,7 @@ static void sweep(const oc_case *c, const double *p, const double *u, const doub
             rp = -(dudx + dvdy);
             ru = -dpdx;
             rv = -dpdy;
-            if (c->sigma_d > 0.0) {
+            if (c->sigma_d > 0.0 && !c->filter_explicit) {
                 /* selective-filter damping -(sigma_d/dt)(F_x + F_y)q, each
                  * axis with the row of this node's half-width along it */
                 const long long lin = (long long)j * c->nx + i;
@@ -276,6 +277,60 @@ static void sweep(const oc_case *c, const double *p, const double *u, const doub
             po[q] = p[q] + adt * rp;
             uo[q] = u[q] + adt * ru;
             vo[q] = v[q] + adt * rv;
+        }
+    }
+}
+
+/*
+ * The explicit form of the filter (the alternative to the damping term in
+ * the right-hand side): after a full step, q <- q - sigma_d (F_x + F_y) q at
+ * every fluid node outside the radiation band, each axis with the row of the
+ * node's half-width along it (the rows of the damping term), from the step's
+ * result; other nodes are left as they are (ghost values are filled again by
+ * the next stage).
+ */
+static void filter_step(const oc_case *c, double *p, double *u, double *v, double *fp, double *fu, double *fv)
+{
+    const long long sy = c->nx + 2 * c->F;
+    int j;
+#pragma omp parallel for schedule(static)
+    for (j = 0; j < c->ny; ++j) {
+        int i, k;
+        for (i = 0; i < c->nx; ++i) {
+            const long long lin = (long long)j * c->nx + i;
+            if (!c->fluid[lin]) continue;
+            const long long q = (j + c->F) * sy + (i + c->F);
+            int e = i;
+            if (j < e) e = j;
+            if (c->nx - 1 - i < e) e = c->nx - 1 - i;
+            if (c->ny - 1 - j < e) e = c->ny - 1 - j;
+            if (e < c->rad_w) {                  /* the radiation band has no filter */
+                fp[q] = p[q]; fu[q] = u[q]; fv[q] = v[q];
+                continue;
+            }
+            const double *wx = c->frow[c->fw[2 * lin]];
+            const double *wy = c->frow[c->fw[2 * lin + 1]];
+            double a = 0.0, b = 0.0, d = 0.0;
+            for (k = -5; k <= 5; ++k) {
+                a += wx[k + 5] * p[q + k] + wy[k + 5] * p[q + k * sy];
+                b += wx[k + 5] * u[q + k] + wy[k + 5] * u[q + k * sy];
+                d += wx[k + 5] * v[q + k] + wy[k + 5] * v[q + k * sy];
+            }
+            fp[q] = p[q] - c->sigma_d * a;
+            fu[q] = u[q] - c->sigma_d * b;
+            fv[q] = v[q] - c->sigma_d * d;
+        }
+    }
+#pragma omp parallel for schedule(static)
+    for (j = 0; j < c->ny; ++j) {
+        int i;
+        for (i = 0; i < c->nx; ++i) {
+            const long long lin = (long long)j * c->nx + i;
+            if (!c->fluid[lin]) continue;
+            const long long q = (j + c->F) * sy + (i + c->F);
+            p[q] = fp[q];
+            u[q] = fu[q];
+            v[q] = fv[q];
         }
     }
 }
@@ -316,6 +371,7 @@ int oc_run(const oc_case *c, double *p, double *u, double *v, double *psi,
         memcpy(p, S[0], (size_t)n * sizeof(double));
         memcpy(u, S[1], (size_t)n * sizeof(double));
         memcpy(v, S[2], (size_t)n * sizeof(double));
+        if (c->filter_explicit && c->sigma_d > 0.0) filter_step(c, p, u, v, T[0], T[1], T[2]);
         if (c->G > 0) memcpy(psi, psS, (size_t)c->ade_ns * c->G * sizeof(double));
         for (k = 0; k < np; ++k) {
             double acc[3] = {0, 0, 0};

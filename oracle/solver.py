@@ -12,7 +12,9 @@ the reading is stated in core.c).
 
 Filter rows: per node and axis, the widest centred filter row that reads no
 non-fluid node of the domain (geometry.filter_widths, schemes.filter_rows;
-the reading is stated in core.c).
+the reading is stated in core.c).  The filter is the damping term of every
+stage's right-hand side, or, with case.filter_explicit, applied once after
+every step (q <- q - sigma_d (F_x + F_y) q at the fluid nodes).
 
 Sponge reading: sigma_s = sigma_max ((W - e) / W)^2 for a node e < W cells
 from the nearest domain edge, zero elsewhere.
@@ -55,6 +57,7 @@ class _OcCase(ctypes.Structure):
         ("rad_w", ctypes.c_int), ("rad_xc", ctypes.c_double), ("rad_yc", ctypes.c_double),
         ("rad_c", ctypes.c_double * 3), ("rad_b", ctypes.c_double * 21),
         ("fw", ctypes.c_void_p), ("frow", ctypes.c_double * 396),
+        ("filter_explicit", ctypes.c_int),
     ]
 
 
@@ -207,6 +210,7 @@ class OracleSolver:
         for k in range(5):
             s.a[k] = a[k] if k < len(a) else 0.0
         s.sigma_d = c.filter_sigma
+        s.filter_explicit = int(bool(c.filter_explicit))
         rows = self.filter_rows.ravel()
         for k in range(len(rows)):
             s.frow[k] = rows[k]

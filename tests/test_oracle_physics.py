@@ -203,6 +203,33 @@ def test_filter_removes_checkerboard_at_rk4_rate():
     assert abs(u[30, 30]) < 1e-15 and abs(v[30, 30]) < 1e-15
 
 
+def test_explicit_filter_removes_checkerboard_at_its_rate():
+    """The explicit form: the step itself leaves (-1)^(i+j) alone (its DRP
+    derivative vanishes), then q <- q - sigma (F_x + F_y) q multiplies it by
+    1 - 2 sigma (D(pi) = 1 per axis)."""
+    n = 61
+    case = lc.Case(nx=n, ny=n, x0=0.0, y0=0.0, h=1.0, H=5, filter_sigma=0.2, filter_explicit=True,
+                   probes=((30.0, 30.0),))
+    s = OracleSolver(case)
+    ii, jj = np.meshgrid(np.arange(n), np.arange(n))
+    s.p[5:5 + n, 5:5 + n] = 1e-3 * (-1.0) ** (ii + jj)
+    s.run(1)
+    p, u, v = s.fields()
+    assert abs(p[30, 30] / 1e-3 - (1.0 - 2 * 0.2)) < 1e-12
+    assert abs(u[30, 30]) < 1e-15 and abs(v[30, 30]) < 1e-15
+
+
+def test_explicit_filter_barely_touches_a_resolved_pulse():
+    w = 4.0
+    pts = ((0.0, 0.0), (10.0, 0.0), (14.0, 14.0), (-25.0, 3.0))
+    case = lc.Case(nx=121, ny=121, x0=-60.0, y0=-60.0, h=1.0, H=5, filter_sigma=0.2, filter_explicit=True,
+                   ic=lc.Pulse(0.0, 0.0, 1.0, w), probes=pts)
+    s, tr = _probe_series(case, 60)
+    r = np.array([math.hypot(*p) for p in pts])
+    ref = refsol.free_pulse(r, 30.0, 1.0, w)
+    assert np.max(np.abs(tr[-1, :, 0] - ref)) < 2e-3 * np.abs(ref).max()
+
+
 def test_sponge_absorbs():
     base = lc.Case(nx=81, ny=81, x0=-40.0, y0=-40.0, h=1.0, H=5, filter_sigma=0.0,
                    ic=lc.Pulse(0.0, 0.0, 1.0, 3.0))

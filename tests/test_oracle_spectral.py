@@ -404,3 +404,17 @@ def test_paper_scheme_grows_at_the_wall_and_the_filter_rows_do_not():
     a_filt = sp.spectral_abscissa(sp.operator_matrix(c))
     assert a_paper > 5e-3, a_paper
     assert a_filt < 2e-4, a_filt
+
+
+@pytest.mark.parametrize("z", [lc.Impedance(), MSD_COARSE], ids=["rigid", "msd"])
+def test_explicit_filter_form_does_not_grow(z):
+    # the filter once per step (q <- q - sigma F q after the step) with the
+    # same near-wall rows: no growing mode on the shifted coarse cylinder at
+    # either time step, and the step map is the filter after P4(dt L) with L
+    # free of the filter
+    for cfl in (0.5, 0.25):
+        c = _coarse(1, z, cfl).replace(filter_explicit=True)
+        G = sp.step_matrix(c)
+        assert sp.spectral_radius(G) <= 1.0 + 1e-9, cfl
+    L = sp.operator_matrix(c)
+    assert np.allclose(L, sp.operator_matrix(c.replace(filter_sigma=0.0)), rtol=0, atol=0)
