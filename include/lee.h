@@ -101,6 +101,15 @@ typedef struct {
      * (else LEE_E_ARG); the tile sweeps only (LEE_SWEEP_MARCH -> LEE_E_ARG). */
     int32_t radiation;
     double rad_xc, rad_yc;
+    /* Form of the selective filter (with filter_sigma > 0; Sec. 2.2 names
+     * none, the paper runs without one).  0: the damping term
+     * -(sigma/dt)(F_x + F_y)q in every stage's right-hand side.  1: the
+     * explicit form, q <- q - sigma (F_x + F_y)q at the fluid nodes outside
+     * the radiation band after every full step (one more launch per step),
+     * the stages then without the damping term.  Both take the narrower
+     * centred rows next to an immersed wall.  1 requires the tile sweep
+     * (LEE_SWEEP_MARCH -> LEE_E_ARG); other values -> LEE_E_ARG. */
+    int32_t filter_explicit;
 } lee_case_desc;
 
 typedef struct {

@@ -27,7 +27,8 @@ class CaseDesc(ctypes.Structure):
                 ("wall_kind", c_int32), ("wall_cx", c_double), ("wall_cy", c_double),
                 ("wall_nx", c_double), ("wall_ny", c_double), ("wall_rc", c_double),
                 ("ic_kind", c_int32), ("ic", c_double * 7), ("src_kind", c_int32), ("src", c_double * 5),
-                ("radiation", c_int32), ("rad_xc", c_double), ("rad_yc", c_double)]
+                ("radiation", c_int32), ("rad_xc", c_double), ("rad_yc", c_double),
+                ("filter_explicit", c_int32)]
 
 
 ADE_MAX_STATES = 8

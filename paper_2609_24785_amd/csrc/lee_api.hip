@@ -105,12 +105,18 @@ size_t plane_elems(const Host &h) { return (size_t)(h.d.ny + 2 * FRAME) * pitch_
 // and 2 column blocks (cols >= 64), with one entry per field.
 size_t patch_capacity(const Host &h) { return 24 * h.gidx.size() + 64; }
 
+// Relative cost of a sweep item whose nodes take the near-wall filter rows
+// (measured: about twice a plain tile's time).
+constexpr int WALL_ITEM_COST = 2;
+
 size_t work1_capacity(const Host &h)
 {
     const int ow_min = 64;                       // narrowest strip: 64-column tiles
     const size_t strips = (h.d.nx + ow_min - 1) / ow_min;
     const size_t tiles = (h.d.ny + 3) / 4;
-    return strips * tiles + 64;
+    // the slot order pads the list to at most WALL_ITEM_COST times the
+    // items plus 24 units of up to 4 items
+    return WALL_ITEM_COST * strips * tiles + 128;
 }
 
 struct Layout {
@@ -173,21 +179,58 @@ lee_status hip_fail(hipError_t e, const char *what)
         if (e_ != hipSuccess) return hip_fail(e_, #x); \
     } while (0)
 
-// Slot order of the work list: workgroup b (which the hardware places on XCD
-// b mod 8) takes unit (b mod 8) * per + b / 8, so each XCD gets a contiguous
-// run of neighbouring tiles and shares their halos in its own L2.  Returns,
-// per slot, the item index or -1 for an idle slot (they keep the pattern
-// when the count is not a multiple of 8).
-std::vector<int> xcd_slots(size_t n_items, int per_unit)
+// Slot order of the work list: the units (per_unit consecutive items) are cut
+// into 8 contiguous runs of about equal cost, and workgroup b (which the
+// hardware places on XCD b mod 8) takes unit b / 8 of run b mod 8.  Each XCD
+// thus gets neighbouring tiles and shares their halos in its own L2, the XCD
+// that holds the wall's tiles gets fewer of the others, and within a run the
+// costlier units go first, so that none of them starts last and finishes
+// after the rest of the launch.  Returns, per slot, the item index or -1 for
+// an idle slot.  Every run is padded to ceil(total cost / (8 per_unit)) + 2
+// units, a bound on the longest run, so the length depends on the multiset
+// of items alone (a batch whose members change order keeps its list length).
+std::vector<int> xcd_slots(const std::vector<int4> &items, int per_unit)
 {
-    std::vector<int> out;
+    const size_t n_items = items.size();
     const int units = (int)((n_items + per_unit - 1) / per_unit);
-    const int per = (units + 7) / 8;
+    std::vector<double> cost(units, 0.0);
+    double total = 0.0;
+    for (size_t k = 0; k < n_items; ++k) {
+        const int x = items[k].x;
+        const double c = (x >= 0 && (x & TILE_WALL_BIT)) ? WALL_ITEM_COST : 1;
+        cost[k / per_unit] += c;
+        total += c;
+    }
+    int start[9];
+    start[0] = 0;
+    int r = 1;
+    double acc = 0.0;
+    for (int u = 0; u < units && r < 8; ++u) {
+        // cut before unit u once its midpoint lies past r / 8 of the total
+        while (r < 8 && acc + 0.5 * cost[u] > total * r / 8.0) start[r++] = u;
+        acc += cost[u];
+    }
+    while (r < 8) start[r++] = units;
+    start[8] = units;
+    // a run's units have midpoints within an eighth of the total and cost
+    // per_unit at least (but the last), hence this bound
+    int per = units ? (int)std::ceil(total / (8.0 * per_unit)) + 2 : 0;
+    for (r = 0; r < 8; ++r) per = std::max(per, start[r + 1] - start[r]);
+    std::vector<int> order(units);
+    for (r = 0; r < 8; ++r) {
+        int q = start[r];
+        for (int u = start[r]; u < start[r + 1]; ++u)
+            if (cost[u] > per_unit) order[q++] = u;
+        for (int u = start[r]; u < start[r + 1]; ++u)
+            if (cost[u] <= per_unit) order[q++] = u;
+    }
+    std::vector<int> out;
     for (int b = 0; b < 8 * per; ++b) {
-        const int su = (b % 8) * per + b / 8;
+        const int t = b / 8, run = b % 8;
+        const int su = start[run] + t < start[run + 1] ? order[start[run] + t] : -1;
         for (int w = 0; w < per_unit; ++w) {
             const size_t k = (size_t)su * per_unit + w;
-            out.push_back(su < units && k < n_items ? (int)k : -1);
+            out.push_back(su >= 0 && k < n_items ? (int)k : -1);
         }
     }
     return out;
@@ -209,7 +252,7 @@ int order_work(const std::vector<int4> &items, const std::vector<std::vector<int
     out.clear();
     aux.clear();
     patch.clear();
-    std::vector<int> slots = xcd_slots(items.size(), per_unit);
+    std::vector<int> slots = xcd_slots(items, per_unit);
     auto dep = [&](int k) { return k >= 0 && (items[k].x & TILE_DEP_BIT); };
     int tile0 = dedicated && ncar > 0 ? (ncar + 7) / 8 * 8 : 0;
     if (ncar > 0 && tile0 == 0) {
@@ -226,7 +269,7 @@ int order_work(const std::vector<int4> &items, const std::vector<std::vector<int
             std::swap(slots[b], slots[c]);
             c += 8;
         }
-        if (tile0) slots = xcd_slots(items.size(), per_unit);
+        if (tile0) slots = xcd_slots(items, per_unit);
     }
     for (int k : slots) {
         if (k < 0) {
@@ -276,6 +319,10 @@ lee_tiling default_tiling_for(int prec, int nx, int ny)
     t.fused = 0;                                 // measured: fused wins only for FP64 on small grids
     return t;
 }
+
+// The filter's form: 0 none, 1 the damping term of every stage's right-hand
+// side, 2 once after every step (k_filter).
+int filter_form(const Host &h) { return h.d.filter_sigma > 0.0 ? (h.d.filter_explicit ? 2 : 1) : 0; }
 
 void default_tiling(lee_instance *I)
 {
@@ -468,7 +515,7 @@ ProbePass probe_pass(const int2 *pw, int np, int stage, int slot)
 hipError_t issue_stage(lee_instance *I, int stage, int slot)
 {
     const int prec = I->host.d.precision;
-    return stage_launches(prec, I->host.d.filter_sigma > 0.0, I->tl, I->d_inst, 1, I->host.ade_kind == 3,
+    return stage_launches(prec, filter_form(I->host) == 1, I->tl, I->d_inst, 1, I->host.ade_kind == 3,
                           I->d_work1, I->nwork1, I->d_aux,
                           I->d_patch, I->tile0, I->d_work2, I->nwork2, I->d_sync, stage, slot,
                           probe_pass(I->d_pwork, I->host.np, stage, slot), 0, I->stream, nullptr, I->spin);
@@ -483,11 +530,21 @@ hipError_t issue_tail(lee_instance *I, int n)
     return e;
 }
 
+// The explicit filter after step `slot` of the run (its form only).
+hipError_t issue_filter(lee_instance *I, int slot)
+{
+    if (filter_form(I->host) != 2) return hipSuccess;
+    return launch_filter(I->host.d.precision, I->tl.cols, I->tl.rows, I->d_inst, I->d_work1, I->nwork1, slot,
+                         I->stream);
+}
+
 hipError_t issue_run(lee_instance *I, int n)
 {
     hipError_t e = hipSuccess;
-    for (int j = 0; j < n && e == hipSuccess; ++j)
+    for (int j = 0; j < n && e == hipSuccess; ++j) {
         for (int l = 0; l < 4 && e == hipSuccess; ++l) e = issue_stage(I, l, j);
+        if (e == hipSuccess) e = issue_filter(I, j);
+    }
     if (e == hipSuccess) e = issue_tail(I, n);
     return e;
 }
@@ -712,7 +769,9 @@ lee_status lee_bind(lee_instance *I, void *dev_ptr, size_t bytes, void *hip_stre
         const double a = h.d.stencil_half == 5 ? A5[k] : (k < 3 ? A3[k] : 0.0);
         D.ax[k] = a / h.d.h;
     }
-    const double sd = h.d.filter_sigma / h.dt;
+    // the damping term carries sigma_d / dt; the explicit form, applied once
+    // per step, sigma_d itself
+    const double sd = h.d.filter_explicit ? h.d.filter_sigma : h.d.filter_sigma / h.dt;
     D.fd[0] = sd * 2.0 * FD[0];
     for (int k = 1; k < 6; ++k) D.fd[k] = sd * FD[k];
     for (int k = 0; k < 5; ++k) D.axf[k] = (float)D.ax[k];
@@ -742,6 +801,7 @@ lee_status lee_bind(lee_instance *I, void *dev_ptr, size_t bytes, void *hip_stre
         D.c_stage[l] = CST[l];
     }
     D.rad_w = h.d.radiation ? h.d.stencil_half : 0;
+    D.fx = filter_form(h) == 2 ? 1 : 0;
     D.rad_xc = h.d.rad_xc;
     D.rad_yc = h.d.rad_yc;
     // window weights: place 3 the central 7-node set (-a3, -a2, -a1, 0, a1,
@@ -872,6 +932,7 @@ lee_status lee_rk_stage(lee_instance *I, int32_t stage)
     if (stage < 0 || stage > 3) return fail(LEE_E_ARG, "stage must be 0..3");
     if (stage != I->next_stage) return fail(LEE_E_STATE, "stages must be issued in order 0, 1, 2, 3");
     HIPCHK(issue_stage(I, stage, 0));
+    if (stage == 3) HIPCHK(issue_filter(I, 0));
     if (stage == 3) HIPCHK(issue_tail(I, 1));
     I->next_stage = (stage + 1) & 3;
     if (stage == 3) ++I->steps_issued;
@@ -913,6 +974,8 @@ lee_status lee_set_tiling(lee_instance *I, const lee_tiling *t)
     if (!tiling_valid(I->host.d.precision, *t)) return fail(LEE_E_ARG, "unsupported tiling");
     if (t->kind == LEE_SWEEP_MARCH && I->host.d.radiation)
         return fail(LEE_E_ARG, "the march sweep has no radiation band; use a tile sweep");
+    if (t->kind == LEE_SWEEP_MARCH && filter_form(I->host) == 2)
+        return fail(LEE_E_ARG, "the explicit filter runs on the tile sweep's items; use a tile sweep");
     if (I->next_stage != 0) return fail(LEE_E_STATE, "a partial step is pending");
     I->tl = *t;
     drop_graph(I);
@@ -1181,7 +1244,7 @@ lee_status lee_time_kernels(lee_instance *I, int64_t n, double *sweep_us, double
     if (n <= 0) return fail(LEE_E_ARG, "n must be positive");
     if (I->next_stage != 0) return fail(LEE_E_STATE, "a partial step is pending");
     const int prec = I->host.d.precision;
-    const bool filt = I->host.d.filter_sigma > 0.0;
+    const bool filt = filter_form(I->host) == 1;
     auto ghosts = [&]() -> hipError_t {
         hipError_t e = hipSuccess;
         for (int64_t k = 0; k < 4 * n && e == hipSuccess; ++k)
@@ -1237,7 +1300,8 @@ void lee_destroy(lee_instance *I)
 struct lee_batch {
     std::vector<lee_instance *> members;
     int prec = LEE_F32;
-    bool filt = true;
+    bool filt = true;                            // the stages carry the filter's damping term
+    bool fx = false;                             // the filter runs once per step (k_filter)
     lee_tiling tl{};
     int pblocks = 0;
     hipStream_t stream = nullptr;
@@ -1315,8 +1379,11 @@ hipError_t batch_issue_stage(lee_batch *B, int stage, int slot)
 hipError_t batch_issue_run(lee_batch *B, int n)
 {
     hipError_t e = hipSuccess;
-    for (int j = 0; j < n && e == hipSuccess; ++j)
+    for (int j = 0; j < n && e == hipSuccess; ++j) {
         for (int l = 0; l < 4 && e == hipSuccess; ++l) e = batch_issue_stage(B, l, j);
+        if (e == hipSuccess && B->fx)
+            e = launch_filter(B->prec, B->tl.cols, B->tl.rows, B->d_table, B->d_work1, B->nwork1, j, B->stream);
+    }
     if (e == hipSuccess) e = launch_probe(B->prec, B->d_table, ProbePass{B->d_pwork, B->npwork, n - 1}, B->stream);
     if (e == hipSuccess) e = launch_advance(B->d_table, (int)B->table_cap, n, B->stream);
     return e;
@@ -1367,7 +1434,11 @@ lee_status batch_rebuild(lee_batch *B, bool drop = false)
             B->up_work2.push_back(make_int4((int)k, g, I->host.cptr[g], I->host.cptr[g + 1]));
         for (int p = 0; p < I->host.np; ++p) B->up_pwork.push_back(make_int2((int)k, p));
     }
+    // a list that grows drops the graphs (they launch the old capacities);
+    // the capacities are compared as well as the pointers, since a new
+    // allocation can come back at the address of the one it replaces
     const void *before[6] = {B->d_table, B->d_work1, B->d_work2, B->d_aux, B->d_patch, B->d_pwork};
+    const size_t caps_before[6] = {B->table_cap, B->work1_cap, B->work2_cap, B->aux_cap, B->patch_cap, B->pwork_cap};
     const int tile0_before = B->tile0;
     HIPCHK(grow(B->d_table, B->table_cap, n, B->stream));
     HIPCHK(grow(B->d_work2, B->work2_cap, B->up_work2.size(), B->stream));
@@ -1382,7 +1453,8 @@ lee_status batch_rebuild(lee_batch *B, bool drop = false)
     HIPCHK(grow(B->d_aux, B->aux_cap, B->work1_cap, B->stream));
     HIPCHK(grow(B->d_patch, B->patch_cap, B->up_patch.size(), B->stream));
     const void *after[6] = {B->d_table, B->d_work1, B->d_work2, B->d_aux, B->d_patch, B->d_pwork};
-    for (int k = 0; k < 6; ++k) drop = drop || before[k] != after[k];
+    const size_t caps_after[6] = {B->table_cap, B->work1_cap, B->work2_cap, B->aux_cap, B->patch_cap, B->pwork_cap};
+    for (int k = 0; k < 6; ++k) drop = drop || before[k] != after[k] || caps_before[k] != caps_after[k];
     bool poles = false;
     for (const auto *I : B->members) poles = poles || I->host.ade_kind == 3;
     drop = drop || poles != B->poles;               // another ghost-fill variant
@@ -1419,10 +1491,13 @@ lee_status member_ok(const lee_batch *B, const lee_instance *I)
     if (!I || !I->bound) return fail(LEE_E_STATE, "every member must be bound");
     if (I->next_stage != 0) return fail(LEE_E_STATE, "a member has a partial step pending");
     if (I->host.d.precision != B->prec) return fail(LEE_E_ARG, "mixed precision");
-    if ((I->host.d.filter_sigma > 0.0) != B->filt) return fail(LEE_E_ARG, "mixed filter on/off");
+    if ((filter_form(I->host) == 1) != B->filt || (filter_form(I->host) == 2) != B->fx)
+        return fail(LEE_E_ARG, "mixed filter forms");
     if (I->device != B->device) return fail(LEE_E_ARG, "members on different devices");
     if (I->host.d.radiation && B->tl.kind == LEE_SWEEP_MARCH)
         return fail(LEE_E_ARG, "the march sweep has no radiation band");
+    if (filter_form(I->host) == 2 && B->tl.kind == LEE_SWEEP_MARCH)
+        return fail(LEE_E_ARG, "the explicit filter needs a tile sweep");
     return LEE_OK;
 }
 
@@ -1448,15 +1523,15 @@ lee_status lee_batch_create(lee_instance *const *v, int32_t n, const lee_batch_o
         if (!v[k] || !v[k]->bound) return fail(LEE_E_STATE, "every member must be bound");
         if (v[k]->next_stage != 0) return fail(LEE_E_STATE, "a member has a partial step pending");
         if (v[k]->host.d.precision != v[0]->host.d.precision) return fail(LEE_E_ARG, "mixed precision");
-        if ((v[k]->host.d.filter_sigma > 0.0) != (v[0]->host.d.filter_sigma > 0.0))
-            return fail(LEE_E_ARG, "mixed filter on/off");
+        if (filter_form(v[k]->host) != filter_form(v[0]->host)) return fail(LEE_E_ARG, "mixed filter forms");
         if (v[k]->device != v[0]->device) return fail(LEE_E_ARG, "members on different devices");
     }
     lee_batch *B = new (std::nothrow) lee_batch();
     if (!B) return fail(LEE_E_NOMEM, "host allocation");
     B->members.assign(v, v + n);
     B->prec = v[0]->host.d.precision;
-    B->filt = v[0]->host.d.filter_sigma > 0.0;
+    B->filt = filter_form(v[0]->host) == 1;
+    B->fx = filter_form(v[0]->host) == 2;
     B->stream = v[0]->stream;
     B->device = v[0]->device;
     B->tl = default_tiling_for(B->prec, 4096, 4096);
@@ -1469,7 +1544,7 @@ lee_status lee_batch_create(lee_instance *const *v, int32_t n, const lee_batch_o
         }
         B->graphs.per = graph_steps_from(opts->graph_steps);
     }
-    if (!tiling_valid(B->prec, B->tl) || B->pblocks < 0) {
+    if (!tiling_valid(B->prec, B->tl) || B->pblocks < 0 || (B->fx && B->tl.kind == LEE_SWEEP_MARCH)) {
         delete B;
         return fail(LEE_E_ARG, "batch tiling options");
     }
@@ -1615,9 +1690,11 @@ lee_status lee_batch_set_tiling(lee_batch *B, const lee_tiling *t)
 {
     if (!B || !t) return fail(LEE_E_ARG, "null argument");
     if (!tiling_valid(B->prec, *t)) return fail(LEE_E_ARG, "unsupported tiling");
-    if (t->kind == LEE_SWEEP_MARCH)
+    if (t->kind == LEE_SWEEP_MARCH) {
+        if (B->fx) return fail(LEE_E_ARG, "the explicit filter needs a tile sweep");
         for (lee_instance *m : B->members)
             if (m->host.d.radiation) return fail(LEE_E_ARG, "the march sweep has no radiation band");
+    }
     HIPCHK(hipStreamSynchronize(B->stream));     // the old lists may still be read
     B->tl = *t;
     return batch_rebuild(B, true);
@@ -1702,18 +1779,19 @@ extern "C" lee_status lee_step_members_noalloc(lee_instance *const *v, int32_t n
         if (!v[k] || !v[k]->bound) return fail(LEE_E_STATE, "every member must be bound");
         if (v[k]->next_stage != 0) return fail(LEE_E_STATE, "a member has a partial step pending");
         if (v[k]->host.d.precision != v[0]->host.d.precision) return fail(LEE_E_ARG, "mixed precision");
-        if ((v[k]->host.d.filter_sigma > 0.0) != (v[0]->host.d.filter_sigma > 0.0))
-            return fail(LEE_E_ARG, "mixed filter on/off");
+        if (filter_form(v[k]->host) != filter_form(v[0]->host)) return fail(LEE_E_ARG, "mixed filter forms");
         if (v[k]->device != v[0]->device) return fail(LEE_E_ARG, "members on different devices");
     }
     const int prec = v[0]->host.d.precision;
-    const bool filt = v[0]->host.d.filter_sigma > 0.0;
+    const bool filt = filter_form(v[0]->host) == 1;
+    const bool fx = filter_form(v[0]->host) == 2;
     const lee_tiling tl = tiling ? *tiling : default_tiling_for(prec, 4096, 4096);
     if (!tiling_valid(prec, tl)) return fail(LEE_E_ARG, "unsupported tiling");
     bool poles = false;
     for (int k = 0; k < n; ++k) {
         if (v[k]->host.d.radiation && tl.kind == LEE_SWEEP_MARCH)
             return fail(LEE_E_ARG, "the march sweep has no radiation band");
+        if (fx && tl.kind == LEE_SWEEP_MARCH) return fail(LEE_E_ARG, "the explicit filter needs a tile sweep");
         poles = poles || v[k]->host.ade_kind == 3;
     }
     if (steps == 0) return LEE_OK;
@@ -1781,10 +1859,12 @@ extern "C" lee_status lee_step_members_noalloc(lee_instance *const *v, int32_t n
     const int nwork1 = (int)S.work1.size(), nwork2 = (int)S.work2.size(), npwork = (int)S.pwork.size();
     for (int64_t done = 0; done < steps;) {
         const int run = (int)std::min<int64_t>(steps - done, 1 << 20);
-        for (int j = 0; j < run; ++j)
+        for (int j = 0; j < run; ++j) {
             for (int l = 0; l < 4; ++l)
                 HIPCHK(stage_launches(prec, filt, tl, d_table, 0, poles, d_work1, nwork1, d_aux, d_patch, tile0,
                                       d_work2, nwork2, d_sync, l, j, probe_pass(d_pwork, npwork, l, j), 0, s));
+            if (fx) HIPCHK(launch_filter(prec, tl.cols, tl.rows, d_table, d_work1, nwork1, j, s));
+        }
         HIPCHK(launch_probe(prec, d_table, ProbePass{d_pwork, npwork, run - 1}, s));
         HIPCHK(launch_advance(d_table, n, run, s));
         done += run;

@@ -64,6 +64,8 @@ struct DevInst {
     double ade_st[8][5];    // kind 3: per state a, bn, bp, f, c of
                             // dX_k = a X_k + bn X_{k+1} + bp X_{k-1} + f p_BP, u_n = sum c X_k
     int rad_w;              // radiation band width (nodes closer than rad_w to an edge; 0 = none)
+    int fx;                 // the filter once per step (k_filter) instead of in the stages' RHS:
+                            // the last stage writes register set C and fd, fdw hold sigma_d times the rows
     double rad_xc, rad_yc;  // its centre
     double rad_w7[7][7];    // first-derivative weights / h on a 7-node window, node at place r:
                             // r = 3 the central set a_k, else the one-sided maximal-order set
@@ -84,6 +86,11 @@ struct ProbePass {
 hipError_t launch_sweep(int prec, int vec, bool filt, int waves, const DevInst *insts, const int4 *work,
                         int nwork, int stage, int slot, int blocks, hipStream_t s);
 bool tile_shape_supported(int prec, int tx, int ty);
+// The explicit filter after step `slot` of a run, one workgroup per tile
+// item of the tile sweep's list (shape tx x ty): members with fx set take
+// q <- q - sigma_d (F_x + F_y) q from register set C into register set A.
+hipError_t launch_filter(int prec, int tx, int ty, const DevInst *insts, const int4 *work, int nwork, int slot,
+                         hipStream_t s);
 hipError_t launch_tile(int prec, bool filt, int tx, int ty, const DevInst *insts, const int4 *work, int nwork,
                        int stage, int slot, int blocks, hipStream_t s);
 // One launch for a stage with the tile sweep: the first ceil(nwork2 / 8)

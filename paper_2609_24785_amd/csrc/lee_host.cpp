@@ -103,6 +103,7 @@ lee_status host_setup(const lee_case_desc *dp, Host *H)
     if (!(d.h > 0.0) || !(d.cfl > 0.0) || d.cfl > 1.0) return fail(LEE_E_ARG, "h > 0 and 0 < cfl <= 1 required");
     if (d.stencil_half != 3 && d.stencil_half != 5) return fail(LEE_E_ARG, "stencil_half must be 3 or 5");
     if (d.filter_sigma < 0.0 || d.filter_sigma > 0.5) return fail(LEE_E_ARG, "filter_sigma in [0, 0.5]");
+    if (d.filter_explicit != 0 && d.filter_explicit != 1) return fail(LEE_E_ARG, "filter_explicit must be 0 or 1");
     if (d.filter_sigma > 0.0 && d.stencil_half != 5)
         return fail(LEE_E_ARG, "the 11-point filter needs stencil_half = 5 (five ghost layers)");
     if (d.sponge_cells < 0 || d.sponge_sigma < 0.0) return fail(LEE_E_ARG, "negative sponge");

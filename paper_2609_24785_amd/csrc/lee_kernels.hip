@@ -33,6 +33,7 @@
 #include <cstdint>
 
 #include "lee_device.h"
+#include <type_traits>
 
 namespace lee {
 
@@ -450,6 +451,25 @@ __device__ __forceinline__ int y_width(const R &row, int col)
     for (int k = 5; k >= 1; --k)
         if (!in_iv(row(-k), col) || !in_iv(row(k), col)) w = k - 1;
     return w;
+}
+
+// Non-fluid rows of one tile column as bits (bit b: LDS row b of the tile's
+// copy, rows outside the domain open): wide enough for the copied rows.
+template <int R>
+using ColMask = typename std::conditional<(R <= 32), unsigned, unsigned long long>::type;
+
+// Half-width (0..5) of the filter row along y at LDS row y of a column whose
+// non-fluid rows are the bits of m: one less than the distance to the
+// nearest non-fluid row within five, 5 when there is none (the same as
+// y_width over the rows' intervals).
+template <typename M>
+__device__ __forceinline__ int y_width_bits(M m, int y)
+{
+    const unsigned win = (unsigned)(m >> (y - 5)) & 0x7ffu;  // rows y - 5 .. y + 5, bit 5 = row y
+    const unsigned up = win >> 6, down = win & 0x1fu;
+    const int du = up ? __builtin_ctz(up) + 1 : 6;          // nearest above
+    const int dd = down ? 5 - (31 - __builtin_clz(down)) : 6;   // nearest below
+    return min(du, dd) - 1;
 }
 
 // Change of one field's filter sum at a node whose rows have half-widths wx
@@ -920,7 +940,9 @@ __device__ __forceinline__ TileCtx<T> tile_ctx(const DevInst &I, const int4 wk, 
     c.r0 = wk.z;
     c.r1 = wk.w < 0 ? -wk.w : wk.w;
     c.ib = in_buf(stage);
-    c.ob = out_buf(stage);
+    // with the explicit filter the last stage leaves its result in register
+    // set C, from which k_filter writes q^{n+1} into A
+    c.ob = stage == 3 && I.fx ? 2 : out_buf(stage);
     coefs<T>(I, c.ax, c.fd);
     c.adt = (T)I.alpha_dt[stage];
     const int sw = I.sponge_w;
@@ -1029,14 +1051,53 @@ __device__ __forceinline__ void tile_patch(const DevInst &I, unsigned epoch, T (
     }
 }
 
+// Nodes within five of the wall along an axis (wall tiles): that axis takes
+// the narrower centred row, so each field's filter sum changes by the
+// difference of the rows (wfd; subtracted from rp, ru, rv).  The x
+// half-widths come from the row's intervals iv, the y ones from the column
+// masks wcm (a few bit operations per node).
+template <typename T, int VEC, int TX, int TY>
+__device__ __forceinline__ void wall_rows(const DevInst &I, const T (*reg)[TY + 10][TX + 16], const T (*wfd)[6],
+                                          const ColMask<TY + 10> *wcm, int y, int lc, int gc, int tc, const int4 iv,
+                                          T (&rp)[VEC], T (&ru)[VEC], T (&rv)[VEC])
+{
+    int wx[VEC], wy[VEC];
+    bool any = false;
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+        const int col = gc + e;
+        wx[e] = wy[e] = 5;
+        if (!in_iv(iv, col)) continue;
+        wx[e] = x_width(iv, col, I.nx);
+        wy[e] = y_width_bits(wcm[tc + e], y);
+        any = any || wx[e] < 5 || wy[e] < 5;
+    }
+    if (!any) return;
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+        if (wx[e] == 5 && wy[e] == 5) continue;
+        const int cx = lc + e;
+        T d[3];
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+            const T(*L)[TX + 16] = reg[f];
+            d[f] = wall_filter_delta<T>(wfd, wx[e], wy[e], [&](int k) { return L[y][cx + k]; },
+                                        [&](int k) { return L[y + k][cx]; });
+        }
+        rp[e] -= d[0];
+        ru[e] -= d[1];
+        rv[e] -= d[2];
+    }
+}
+
 // Right-hand side (Sec. 3.2 step 6) and RK stage update of row i of a tile
 // for the VEC nodes of columns tc .. tc + VEC - 1 of the tile: reg is the LDS
 // copy of the stage input, (pn, un, vn) the q^n values (unused in the first
 // stage, whose input is q^n), iv the row's fluid column ranges.  Returns the
 // new values and which of the nodes are fluid.
-template <typename T, int VEC, bool FILT, int TX, int TY>
+template <typename T, int VEC, bool FILT, int TX, int TY, bool WALL>
 __device__ __forceinline__ void tile_row(const DevInst &I, const TileCtx<T> &c, const T (*reg)[TY + 10][TX + 16],
-                                         const T (*wfd)[6], const int4 *wiv,
+                                         const T (*wfd)[6], const ColMask<TY + 10> *wcm,
                                          int stage, int i, int tc, const int4 iv, const VecT<T, VEC> &pn_,
                                          const VecT<T, VEC> &un_, const VecT<T, VEC> &vn_, VecT<T, VEC> &po,
                                          VecT<T, VEC> &uo, VecT<T, VEC> &vo, bool (&ok)[VEC], bool &all)
@@ -1055,31 +1116,9 @@ __device__ __forceinline__ void tile_row(const DevInst &I, const TileCtx<T> &c, 
     row_field<T, VEC, FILT, 1>(reg[1], y, lc, c.ax, c.fd, rp, ru, rv);
     pin_sums<T, VEC>(rp, ru, rv);
     row_field<T, VEC, FILT, 2>(reg[2], y, lc, c.ax, c.fd, rp, ru, rv);
-    if (FILT && c.wall) {
-        // nodes within five of the wall along an axis: that axis takes the
-        // narrower centred row (wfd: its difference from the 11-point one),
-        // wiv[y + k] the intervals of row j + k
+    if constexpr (FILT && WALL) {
         pin_sums<T, VEC>(rp, ru, rv);
-        const int4 own = wiv[y];
-#pragma unroll
-        for (int e = 0; e < VEC; ++e) {
-            const int col = gc + e;
-            if (!in_iv(own, col)) continue;
-            const int wx = x_width(own, col, I.nx);
-            const int wy = y_width([&](int k) { return wiv[y + k]; }, col);
-            if (wx == 5 && wy == 5) continue;
-            const int cx = lc + e;
-            T d[3];
-#pragma unroll
-            for (int f = 0; f < 3; ++f) {
-                const T(*L)[TX + 16] = reg[f];
-                d[f] = wall_filter_delta<T>(wfd, wx, wy, [&](int k) { return L[y][cx + k]; },
-                                            [&](int k) { return L[y + k][cx]; });
-            }
-            rp[e] -= d[0];
-            ru[e] -= d[1];
-            rv[e] -= d[2];
-        }
+        wall_rows<T, VEC, TX, TY>(I, reg, wfd, wcm, y, lc, gc, tc, iv, rp, ru, rv);
     }
     const VecT<T, VEC> pc = *(const VecT<T, VEC> *)&reg[0][y][lc];
     const VecT<T, VEC> uc = *(const VecT<T, VEC> *)&reg[1][y][lc];
@@ -1319,6 +1358,73 @@ __device__ __forceinline__ void band_pass(const DevInst &I, const TileCtx<T> &c,
     }
 }
 
+// Wall tiles, while the copy flies: the near-wall filter rows into LDS and
+// the fluid intervals of copied row threadIdx.x (rows outside the domain
+// are open) into a register.
+template <typename T, int VEC, int TX, int TY>
+__device__ __forceinline__ int4 wall_prefetch(const DevInst &I, const TileCtx<T> &c, T (*wfd)[6])
+{
+    using G = TileGeo<T, VEC, TX, TY>;
+    const int tid = threadIdx.x;
+    int4 r = make_int4(0, 0, 0, 0);
+    if (c.wall) {
+        if (tid < 36) wfd[tid / 6][tid % 6] = fdw_at<T>(I, tid / 6, tid % 6);
+        const int row = c.r0 - 5 + tid;
+        if (tid < G::R) r = row >= 0 && row < I.ny ? int4(gp<int4>(I.iv)[row]) : open_row();
+    }
+    return r;
+}
+
+// Wall tiles: the column masks of non-fluid copied rows from the rows'
+// intervals (each row's bit OR-ed into every column it is not fluid at,
+// after the masks are cleared); ordered before their use by the barrier
+// that follows the copy.
+template <typename T, int VEC, int TX, int TY>
+__device__ __forceinline__ void wall_masks(const TileCtx<T> &c, const int4 wivr, ColMask<TY + 10> *wcm)
+{
+    using G = TileGeo<T, VEC, TX, TY>;
+    __shared__ int4 wiv[G::R];
+    const int tid = threadIdx.x;
+    if (tid < TX) wcm[tid] = 0;
+    if (tid < G::R) wiv[tid] = wivr;
+    __syncthreads();
+    for (int q = tid; q < TX * G::R; q += G::NT) {
+        const int b = q / TX, col = q - (q / TX) * TX;
+        if (!in_iv(wiv[b], c.c0 + col)) atomicOr(&wcm[col], (ColMask<G::R>)1 << b);
+    }
+}
+
+// The row passes of a tile: each lane computes VEC nodes of rows i0,
+// i0 + RG, .. (the q^n values of a row in flight during its arithmetic).
+template <typename T, int VEC, bool FILT, int TX, int TY, bool WALL>
+__device__ __forceinline__ void tile_rows(const DevInst &I, const TileCtx<T> &c, const T (*lds)[TY + 10][TX + 16],
+                                          const T (*wt)[7], const T (*wfd)[6], const ColMask<TY + 10> *wcm,
+                                          int stage, int i0, int tc, int4 iv)
+{
+    using G = TileGeo<T, VEC, TX, TY>;
+#pragma unroll 1
+    for (int i = i0; i < TY; i += G::RG) {
+        const int j = c.r0 + i;
+        if (j >= c.r1) break;
+        if (i != i0) iv = gp<int4>(I.iv)[j];
+        VecT<T, VEC> pn{}, un{}, vn{};
+        if (stage != 0) {                        // in flight during the row's arithmetic
+            const unsigned qo = (unsigned)(I.org + j * I.pitch + c.c0 + tc);
+            pn = vld<T, VEC>(gp<T>(I.f[0][0]) + qo);
+            un = vld<T, VEC>(gp<T>(I.f[0][1]) + qo);
+            vn = vld<T, VEC>(gp<T>(I.f[0][2]) + qo);
+        }
+        VecT<T, VEC> po, uo, vo;
+        bool ok[VEC];
+        bool all;
+        tile_row<T, VEC, FILT, TX, TY, WALL>(I, c, lds, wfd, wcm, stage, i, tc, iv, pn, un, vn, po, uo, vo, ok,
+                                             all);
+        if (!BAND_PASS && c.in_band)
+            band_row<T, VEC, TX, TY>(I, c, lds, wt, stage, i, tc, pn, un, vn, po, uo, vo, ok, all);
+        tile_store<T, VEC>(I, c.ob, (unsigned)(I.org + j * I.pitch + c.c0 + tc), po, uo, vo, ok, all);
+    }
+}
+
 // One tile: wk = {instance, first column, first row, +-(end row)}.
 template <typename T, int VEC, bool FILT, int TX, int TY>
 __device__ __forceinline__ void tile_body(const DevInst *__restrict__ insts, const int4 wk, int stage, int slot,
@@ -1337,12 +1443,8 @@ __device__ __forceinline__ void tile_body(const DevInst *__restrict__ insts, con
     // wall tiles: the near-wall filter rows and the fluid intervals of the
     // copied rows (rows outside the domain are open)
     __shared__ T wfd[6][6];
-    __shared__ int4 wiv[G::R];
-    if (c.wall) {
-        if (tid < 36) wfd[tid / 6][tid % 6] = fdw_at<T>(I, tid / 6, tid % 6);
-        const int row = c.r0 - 5 + tid;
-        if (tid < G::R) wiv[tid] = row >= 0 && row < I.ny ? int4(gp<int4>(I.iv)[row]) : open_row();
-    }
+    __shared__ ColMask<G::R> wcm[TX];            // per tile column, its non-fluid copied rows
+    const int4 wivr = wall_prefetch<T, VEC, TX, TY>(I, c, wfd);
     // while the copy flies: this lane's first row ranges and its first patch
     // entries
     const int i0 = tid / G::NCX;
@@ -1350,36 +1452,21 @@ __device__ __forceinline__ void tile_body(const DevInst *__restrict__ insts, con
     if (i0 < TY && c.r0 + i0 < c.r1) iv = gp<int4>(I.iv)[c.r0 + i0];
     int2 pre[2];
     if (dep) patch_prefetch(dep->patch, dep->p0, dep->p1, pre);
+    if (c.wall) wall_masks<T, VEC, TX, TY>(c, wivr, wcm);
     __builtin_amdgcn_s_waitcnt(0);               // this wave's DMA has landed in LDS
     __syncthreads();                             // ... and every other wave's
     if (dep) {                                   // this stage's ghost values over the copied ones
         tile_patch<T, TX, TY>(I, stage_epoch(step, stage), lds, *dep, pre);
         __syncthreads();
     }
-    const int cg = tid % G::NCX;
-    const int tc = cg * VEC;
-#pragma unroll 1
-    for (int i = i0; i < TY; i += G::RG) {
-        const int j = c.r0 + i;
-        if (j >= c.r1) break;
-        if (i != i0) iv = gp<int4>(I.iv)[j];
-        VecT<T, VEC> pn{}, un{}, vn{};
-        if (stage != 0) {                        // in flight during the row's arithmetic
-            const unsigned qo = (unsigned)(I.org + j * I.pitch + c.c0 + tc);
-            pn = vld<T, VEC>(gp<T>(I.f[0][0]) + qo);
-            un = vld<T, VEC>(gp<T>(I.f[0][1]) + qo);
-            vn = vld<T, VEC>(gp<T>(I.f[0][2]) + qo);
-        }
-        VecT<T, VEC> po, uo, vo;
-        bool ok[VEC];
-        bool all;
-        tile_row<T, VEC, FILT, TX, TY>(I, c, lds, wfd, wiv, stage, i, tc, iv, pn, un, vn, po, uo, vo, ok, all);
-        if (!BAND_PASS && c.in_band)
-            band_row<T, VEC, TX, TY>(I, c, lds, wt, stage, i, tc, pn, un, vn, po, uo, vo, ok, all);
-        tile_store<T, VEC>(I, c.ob, (unsigned)(I.org + j * I.pitch + c.c0 + tc), po, uo, vo, ok, all);
-    }
+    const int tc = (tid % G::NCX) * VEC;
+    // wall tiles run a row loop of their own, so that the near-wall code
+    // takes nothing from the scheduling of the plain tiles' loop
+    if (FILT && c.wall)
+        tile_rows<T, VEC, FILT, TX, TY, true>(I, c, lds, wt, wfd, wcm, stage, i0, tc, iv);
+    else
+        tile_rows<T, VEC, FILT, TX, TY, false>(I, c, lds, wt, wfd, wcm, stage, i0, tc, iv);
     if (BAND_PASS && c.in_band) band_pass<T, TX, TY>(I, c, lds, wt, stage);
-
 }
 
 // Work items of the tile sweep: x = instance | DEP_BIT when a fused tile's
@@ -1441,6 +1528,144 @@ __global__ __launch_bounds__(256) void k_stage(const DevInst *__restrict__ insts
     } else {
         wk.x &= TILE_INST_MASK;
         tile_body<T, VEC, FILT, TX, TY>(insts, wk, stage, slot, nullptr, wall);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// the filter once per step (the explicit form)
+
+// One field's filter sum at the VEC nodes of one row of a tile's LDS copy:
+// fd[0] q_0 + sum_k fd[k] ((q_{x+k} + q_{x-k}) + (q_{y+k} + q_{y-k})), the sum
+// of row_field's damping term in the same order.
+template <typename T, int VEC, int LW>
+__device__ __forceinline__ void filt_field(const T (*lds)[LW], int y, int lc, const T (&fd)[6], T (&fl)[VEC])
+{
+    constexpr int KM = (5 + VEC - 1) / VEC;
+    constexpr int KP = (VEC + 4) / VEC;
+    constexpr int XW = (KM + 1 + KP) * VEC;
+    T yw[11][VEC];
+#pragma unroll
+    for (int k = 0; k < 11; ++k) {
+        const VecT<T, VEC> a = lds16<T, VEC>(&lds[y - 5 + k][lc]);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) yw[k][e] = a.v[e];
+    }
+    T xw[XW];
+#pragma unroll
+    for (int k = -KM; k <= KP; ++k) {
+        if (k == 0) {
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) xw[KM * VEC + e] = yw[5][e];
+            continue;
+        }
+        if (k == -KM) {
+            xw[VEC - 1] = lds[y][lc - KM * VEC + VEC - 1];
+            continue;
+        }
+        if (k == KP) {
+            xw[(KM + KP) * VEC] = lds[y][lc + KP * VEC];
+            continue;
+        }
+        const VecT<T, VEC> a = lds16<T, VEC>(&lds[y][lc + k * VEC]);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) xw[(k + KM) * VEC + e] = a.v[e];
+    }
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+        const int x = KM * VEC + e;
+        T f = fd[0] * yw[5][e];
+#pragma unroll
+        for (int k = 1; k <= 5; ++k) f += fd[k] * ((xw[x + k] + xw[x - k]) + (yw[5 + k][e] + yw[5 - k][e]));
+        fl[e] = f;
+    }
+}
+
+// The explicit filter after step `slot` of a run: in this form a step's
+// last stage leaves its result in register set C; each tile copies it with
+// its halo into LDS and every fluid node outside the radiation band takes
+// q - sigma_d (F_x + F_y) q into register set A (fd and fdw hold sigma_d
+// times the rows in this form; nodes within five of the wall take the
+// narrower rows as in the stages).  Other nodes of A are not written: the
+// next stage fills the ghosts again.  Members without the explicit filter,
+// or past their stop step, are skipped.
+template <typename T, int VEC, int TX, int TY>
+__global__ __launch_bounds__(256) void k_filter(const DevInst *__restrict__ insts, const int4 *__restrict__ work,
+                                                int nwork, int slot)
+{
+    using G = TileGeo<T, VEC, TX, TY>;
+    __shared__ alignas(16) T lds[3][G::R][G::LW];
+    const int w = blockIdx.x;
+    if (w >= nwork) return;
+    int4 wk = work[w];
+    if (wk.x < 0) return;
+    const bool wall = (wk.x & TILE_WALL_BIT) != 0;
+    wk.x &= TILE_INST_MASK;
+    const DevInst &I = insts[wk.x];
+    if (!I.fx) return;
+    const long long step = sload<long long>(I.step) + slot;
+    if (step >= sload<long long>(I.stop)) return;
+    const int tid = threadIdx.x;
+    TileCtx<T> c = tile_ctx<T, TX>(I, wk, 3, step, wall);
+    c.ib = 2;
+    c.ob = 0;
+    tile_copy<T, VEC, TX, TY>(I, c, lds);
+    __shared__ T wfd[6][6];
+    __shared__ ColMask<G::R> wcm[TX];
+    const int4 wivr = wall_prefetch<T, VEC, TX, TY>(I, c, wfd);
+    const int i0 = tid / G::NCX;
+    int4 iv = make_int4(0, 0, 0, 0);
+    if (i0 < TY && c.r0 + i0 < c.r1) iv = gp<int4>(I.iv)[c.r0 + i0];
+    if (c.wall) wall_masks<T, VEC, TX, TY>(c, wivr, wcm);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    const int tc = (tid % G::NCX) * VEC;
+#pragma unroll 1
+    for (int i = i0; i < TY; i += G::RG) {
+        const int j = c.r0 + i;
+        if (j >= c.r1) break;
+        if (i != i0) iv = gp<int4>(I.iv)[j];
+        const int y = i + 5, lc = tc + 8, gc = c.c0 + tc;
+        T rp[VEC], ru[VEC], rv[VEC];
+        filt_field<T, VEC, TX + 16>(lds[0], y, lc, c.fd, rp);
+        filt_field<T, VEC, TX + 16>(lds[1], y, lc, c.fd, ru);
+        filt_field<T, VEC, TX + 16>(lds[2], y, lc, c.fd, rv);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+            rp[e] = -rp[e];
+            ru[e] = -ru[e];
+            rv[e] = -rv[e];
+        }
+        if (c.wall) wall_rows<T, VEC, TX, TY>(I, lds, wfd, wcm, y, lc, gc, tc, iv, rp, ru, rv);
+        const VecT<T, VEC> pc = *(const VecT<T, VEC> *)&lds[0][y][lc];
+        const VecT<T, VEC> uc = *(const VecT<T, VEC> *)&lds[1][y][lc];
+        const VecT<T, VEC> vc = *(const VecT<T, VEC> *)&lds[2][y][lc];
+        VecT<T, VEC> po, uo, vo;
+        bool ok[VEC];
+        bool all = true;
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+            const int col = gc + e;
+            po.v[e] = pc.v[e] + rp[e];
+            uo.v[e] = uc.v[e] + ru[e];
+            vo.v[e] = vc.v[e] + rv[e];
+            ok[e] = in_iv(iv, col);
+            if (c.in_band && min(min(col, j), min(I.nx - 1 - col, I.ny - 1 - j)) < I.rad_w) ok[e] = false;
+            all = all && ok[e];
+        }
+        tile_store<T, VEC>(I, 0, (unsigned)(I.org + j * I.pitch + c.c0 + tc), po, uo, vo, ok, all);
+        if (c.in_band) {
+            // band nodes keep the step's value: copy it from C to A
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) {
+                const int col = gc + e;
+                if (in_iv(iv, col) && min(min(col, j), min(I.nx - 1 - col, I.ny - 1 - j)) < I.rad_w) {
+                    const unsigned off = (unsigned)(I.org + j * I.pitch + col);
+                    gp<T>(I.f[0][0])[off] = pc.v[e];
+                    gp<T>(I.f[0][1])[off] = uc.v[e];
+                    gp<T>(I.f[0][2])[off] = vc.v[e];
+                }
+            }
+        }
     }
 }
 
@@ -1631,6 +1856,43 @@ hipError_t launch_tile(int prec, bool filt, int tx, int ty, const DevInst *insts
                     : launch_tile_v<float, 4, false>(tx, ty, insts, work, nwork, stage, slot, nullptr, s);
     return filt ? launch_tile_v<double, 2, true>(tx, ty, insts, work, nwork, stage, slot, nullptr, s)
                 : launch_tile_v<double, 2, false>(tx, ty, insts, work, nwork, stage, slot, nullptr, s);
+}
+
+template <typename T, int VEC, int TX, int TY>
+static hipError_t launch_filter_t(const DevInst *insts, const int4 *work, int nwork, int slot, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_filter<T, VEC, TX, TY>), dim3(nwork), dim3(256), 0, s, insts, work, nwork, slot);
+    return hipGetLastError();
+}
+
+template <typename T, int VEC>
+static hipError_t launch_filter_v(int tx, int ty, const DevInst *insts, const int4 *work, int nwork, int slot,
+                                  hipStream_t s)
+{
+    constexpr bool F4 = sizeof(T) == 4;
+    if (tx == 128) {
+        if (ty == 4) return launch_filter_t<T, VEC, 128, 4>(insts, work, nwork, slot, s);
+        if (ty == 8) return launch_filter_t<T, VEC, 128, 8>(insts, work, nwork, slot, s);
+        if (ty == 16) return launch_filter_t<T, VEC, 128, 16>(insts, work, nwork, slot, s);
+        if (F4 && ty == 32) return launch_filter_t<T, VEC, 128, (F4 ? 32 : 16)>(insts, work, nwork, slot, s);
+    } else if (tx == 256) {
+        if (ty == 4) return launch_filter_t<T, VEC, 256, 4>(insts, work, nwork, slot, s);
+        if (F4 && ty == 8) return launch_filter_t<T, VEC, 256, (F4 ? 8 : 4)>(insts, work, nwork, slot, s);
+        if (F4 && ty == 16) return launch_filter_t<T, VEC, 256, (F4 ? 16 : 4)>(insts, work, nwork, slot, s);
+    } else if (tx == 64) {
+        if (ty == 8) return launch_filter_t<T, VEC, 64, 8>(insts, work, nwork, slot, s);
+        if (ty == 16) return launch_filter_t<T, VEC, 64, 16>(insts, work, nwork, slot, s);
+        if (ty == 32) return launch_filter_t<T, VEC, 64, 32>(insts, work, nwork, slot, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_filter(int prec, int tx, int ty, const DevInst *insts, const int4 *work, int nwork, int slot,
+                         hipStream_t s)
+{
+    if (nwork <= 0) return hipSuccess;
+    if (prec == LEE_F32) return launch_filter_v<float, 4>(tx, ty, insts, work, nwork, slot, s);
+    return launch_filter_v<double, 2>(tx, ty, insts, work, nwork, slot, s);
 }
 
 static int ghost_variant(int ninst, bool poles) { return (ninst == 1 ? GV_ONE : GV_TABLE) | (poles ? GV_POLES : 0); }

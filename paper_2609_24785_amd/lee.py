@@ -72,6 +72,7 @@ def case_desc(case, precision: str = "f32") -> CaseDesc:
     if getattr(case, "radiation", False):
         d.radiation = 1
         d.rad_xc, d.rad_yc = case.rad_center
+    d.filter_explicit = 1 if getattr(case, "filter_explicit", False) else 0
     return d
 
 

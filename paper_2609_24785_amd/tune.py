@@ -52,10 +52,12 @@ def size_class(fluid_nodes: int, ghosts: int, members: int = 1) -> str:
 
 def variant_of(case) -> str:
     """The parts of a case that select different kernel code or cost: the
-    stencil half-width, the filter, the radiation band and the wall kind
-    (rigid, mass-spring-damper, multi-pole)."""
+    stencil half-width, the filter (off, in the stages, once per step), the
+    radiation band and the wall kind (rigid, mass-spring-damper,
+    multi-pole)."""
     wall = case.impedance.kind if case.wall.kind != "none" else "none"
-    return f"H{case.H}-s{int(case.filter_sigma > 0.0)}-r{int(bool(case.radiation))}-{wall}"
+    form = 0 if case.filter_sigma <= 0.0 else (2 if getattr(case, "filter_explicit", False) else 1)
+    return f"H{case.H}-s{form}-r{int(bool(case.radiation))}-{wall}"
 
 
 def cache_key(arch: str, precision: str, cls: str, variant: str) -> str:

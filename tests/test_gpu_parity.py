@@ -324,3 +324,56 @@ def test_paper_cylinder_pulse_configuration(prec, tol):
     case = lc.paper_cylinder_pulse(200)
     cols = 128 if prec == "f32" else 64
     _compare(case, 200, prec, tol, tiling=dict(kind="tile", cols=cols, rows=8, fused=1))
+
+
+# the filter once per step (the explicit form, instead of the damping term
+# of every stage): the stages without the term, then k_filter from register
+# set C into A, with the near-wall rows; against the oracle's filter_step
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-9), ("f32", 1e-4)])
+@pytest.mark.parametrize("fused", [0, 1])
+def test_explicit_filter_matches_oracle(prec, tol, fused):
+    case = lc.small_cylinder(128, 80).replace(filter_explicit=True, name="small-cyl-explicit-filter")
+    cols = 128 if prec == "f32" else 64
+    _compare(case, 80, prec, tol, tiling=dict(kind="tile", cols=cols, rows=8, fused=fused))
+
+
+def test_explicit_filter_with_radiation_band_and_stage_by_stage():
+    # band nodes keep the step's value (no filter in the band); the same
+    # result from lee_rk_stage one stage at a time as from graph replay
+    case = lc.radiating_cylinder(96, 120).replace(filter_explicit=True, name="radiating-explicit-filter")
+    inst, _ = _compare(case, 120, "f64", 1e-9, tiling=dict(kind="tile", cols=64, rows=16, fused=1))
+    Instance, _ = _lee()
+    b = Instance(case, "f64")
+    b.set_tiling("tile", cols=64, rows=16, fused=1)
+    for _ in range(120):
+        for l in range(4):
+            b.rk_stage(l)
+    b.synchronize()
+    for x, y in zip(inst.fields(), b.fields()):
+        assert np.array_equal(x, y)
+
+
+def test_explicit_filter_batch_equals_solo_bitwise_and_forms_do_not_mix():
+    Instance, Batch = _lee()
+    from paper_2609_24785_amd._lib import LeeError
+    cases = [lc.small_cylinder(96, 60).replace(filter_explicit=True),
+             lc.small_cylinder(80, 60, impedance=lc.Impedance("rigid")).replace(filter_explicit=True)]
+    solo = []
+    for c in cases:
+        i = Instance(c, "f32")
+        i.set_tiling("tile", cols=128, rows=8, fused=0)
+        i.step_n(60)
+        i.synchronize()
+        solo.append(i.fields())
+        i.close()
+    mem = [Instance(c, "f32") for c in cases]
+    b = Batch(mem, tiling=dict(kind="tile", cols=128, rows=8, fused=1))
+    b.step_n(60)
+    b.synchronize()
+    for m, ref in zip(mem, solo):
+        for x, y in zip(m.fields(), ref):
+            assert np.array_equal(x, y)
+    other = Instance(lc.small_cylinder(96, 60), "f32")
+    with pytest.raises(LeeError):
+        b.add(other)
+    b.close()
