@@ -74,8 +74,13 @@ COPY_BYTES = 1 << 28                     # the profile run's calibration copy (2
 
 
 def _kernel_hash() -> str:
-    with open(os.path.join(HERE, "paper_2609_24785_amd", "csrc", "lee_kernels.hip"), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Hash of the kernels and of the code that orders their work (the tile
+    order sets which halos the L2s still hold, hence the HBM traffic)."""
+    h = hashlib.sha256()
+    for name in ("lee_kernels.hip", "lee_device.h", "lee_api.hip"):
+        with open(os.path.join(HERE, "paper_2609_24785_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def _traffic(kernel: str):
@@ -105,10 +110,12 @@ def _apply(inst, choice):
         inst.set_graph_steps(choice["graph_steps"])
 
 
-def _timed(case, prec: str, steps: int, warmup: int, choice=None, dft=None, trace_capacity=None):
+def _timed(case, prec: str, steps: int, warmup: int, choice=None, dft=None, trace_capacity=None, fresh=False):
     """Graph-replayed steps of one instance; returns the rate and the instance.
     The run of `steps` steps is issued once untimed first, so that its graphs
-    are captured before the timed run."""
+    are captured before the timed run; with fresh, the instance then goes
+    back to its initial state (the graphs stay), so that the timed run is
+    the case's own time span."""
     import torch
     from paper_2609_24785_amd.lee import Instance
 
@@ -118,6 +125,9 @@ def _timed(case, prec: str, steps: int, warmup: int, choice=None, dft=None, trac
     inst.step_n(warmup)
     inst.step_n(steps)
     inst.synchronize()
+    if fresh:
+        inst.init_fields()
+        inst.synchronize()
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
@@ -400,7 +410,7 @@ def extras(args):
     cres, flds = {}, {}
     for prec in ("f32", "f64"):
         ch = tune.tune_case(cp, prec, cache)
-        rc_ = _timed(cp, prec, cp.steps, 0, ch)
+        rc_ = _timed(cp, prec, cp.steps, 0, ch, fresh=True)
         k = _kernel_times(cp, prec, args.kernel_steps, ch)
         cres[prec] = {"value": rc_["value"], "ms_per_step": 1000.0 * rc_["wall"] / rc_["steps"],
                       "tiling": ch["tiling"], "graph_steps": ch["graph_steps"], "kernel": k["kernel"],
@@ -408,13 +418,12 @@ def extras(args):
                       "effective_GBs": k["alg_bytes"] / (k["sweep_us"] * 1e-6) / 1e9}
         flds[prec] = rc_["inst"].fields()
         rc_["inst"].close()
-    # each timed instance ran its 4000 steps twice (capture pass, timed pass)
-    cres["fp32_vs_fp64_rel_l2_after_8000_steps"] = _max_rel_l2(flds["f32"], flds["f64"], fluid_mask(cp))
+    cres["fp32_vs_fp64_rel_l2_after_4000_steps"] = _max_rel_l2(flds["f32"], flds["f64"], fluid_mask(cp))
     out["cylinder_pulse_1024"] = dict(steps=cp.steps, unit=UNIT, working_set="cache-resident", **cres)
 
     print("[extras] flat wall 201^2 FP64 against the oracle", file=sys.stderr, flush=True)
     flat = lc.flat_wall_201(500)
-    rf = _timed(flat, "f64", 500, 0)
+    rf = _timed(flat, "f64", 500, 0, fresh=True)
     s = osv.OracleSolver(flat)
     s.run(500)
     out["flat_wall_201_f64"] = {"value": rf["value"], "unit": UNIT, "steps": 500,
@@ -440,7 +449,7 @@ def extras(args):
     pres = {}
     for prec in ("f32", "f64"):
         ch = tune.tune_case(pm, prec, cache)
-        rp = _timed(pm, prec, pm_steps, 0, ch)
+        rp = _timed(pm, prec, pm_steps, 0, ch, fresh=True)
         pres[prec] = {"value": rp["value"], "ms_per_step": 1000.0 * rp["wall"] / rp["steps"],
                       "tiling": ch["tiling"]}
         if prec == "f64":
@@ -459,7 +468,7 @@ def extras(args):
     mres = {}
     for prec in ("f32", "f64"):
         ch = tune.tune_case(mp, prec, cache)
-        rp = _timed(mp, prec, pm_steps, 0, ch)
+        rp = _timed(mp, prec, pm_steps, 0, ch, fresh=True)
         mres[prec] = {"value": rp["value"], "ms_per_step": 1000.0 * rp["wall"] / rp["steps"],
                       "tiling": ch["tiling"]}
         if prec == "f64":
@@ -476,7 +485,7 @@ def extras(args):
     rres = {}
     for prec in ("f32", "f64"):
         ch = tune.tune_case(rc, prec, cache)
-        rp = _timed(rc, prec, pm_steps, 0, ch)
+        rp = _timed(rc, prec, pm_steps, 0, ch, fresh=True)
         rres[prec] = {"value": rp["value"], "ms_per_step": 1000.0 * rp["wall"] / rp["steps"],
                       "tiling": ch["tiling"]}
         if prec == "f64":
@@ -494,7 +503,7 @@ def extras(args):
     pres = {}
     for prec in ("f32", "f64"):
         ch = tune.tune_case(pc, prec, cache)
-        rp = _timed(pc, prec, pc_steps, 0, ch)
+        rp = _timed(pc, prec, pc_steps, 0, ch, fresh=True)
         pres[prec] = {"value": rp["value"], "ms_per_step": 1000.0 * rp["wall"] / rp["steps"],
                       "tiling": ch["tiling"]}
         if prec == "f64":
@@ -503,6 +512,42 @@ def extras(args):
             pres[prec]["rel_l2_vs_oracle"] = _max_rel_l2(rp["inst"].fields(), s.fields(), s.fluid)
         rp["inst"].close()
     out["paper_cylinder_pulse_301"] = dict(steps=pc_steps, unit=UNIT, **pres)
+
+    # the paper's own monopole configuration (Sec. 4.3), its whole time span,
+    # ring amplitudes over its window against App. C: the total field, and
+    # the scattered field (the run minus the same grid without the cylinder,
+    # against the exact total minus the free field), the paper's measure
+    print("[extras] paper monopole 601^2", file=sys.stderr, flush=True)
+    from tests import refsol
+    pmc = lc.paper_monopole()
+    xy = np.array(pmc.probes)
+    imp = pmc.impedance
+    om = pmc.source.omega
+    Z = imp.R + 1j * (imp.M * om - imp.K / om)
+    P, Pfree = refsol.monopole_cylinder(xy[:, 0], xy[:, 1], om, 1.0, 0.2, 4.0, 0.0, 0.5, Z=Z)
+    dft = (om, pmc.steps - pmc.dft_steps, pmc.dft_steps)
+    rings = {"r=0.6": slice(0, 72), "r=5": slice(72, 144)}
+
+    def ring_err(got, ref):
+        return {k: float(np.linalg.norm(got[sl] - ref[sl]) / np.linalg.norm(ref[sl])) for k, sl in rings.items()}
+
+    pres = {}
+    for prec in ("f32", "f64"):
+        ch = tune.tune_case(pmc, prec, cache)
+        rp = _timed(pmc, prec, pmc.steps, 0, ch, dft=dft, fresh=True)
+        got = rp["inst"].dft()
+        rp["inst"].close()
+        free = Instance(pmc.replace(wall=lc.Wall()), prec, dft=dft)
+        free.step_n(pmc.steps)
+        free.synchronize()
+        got_free = free.dft()
+        free.close()
+        pres[prec] = {"value": rp["value"], "ms_per_step": 1000.0 * rp["wall"] / rp["steps"],
+                      "tiling": ch["tiling"], "steps_timed": pmc.steps,
+                      "ring_error_vs_app_c": ring_err(got, P),
+                      "scattered_ring_error_vs_app_c": ring_err(got - got_free, P - Pfree),
+                      "free_field_ring_error": ring_err(got_free, Pfree)}
+    out["paper_monopole_601"] = dict(unit=UNIT, steps=pmc.steps, **pres)
 
     # spectral stability of the step map (abstract): assembled on the GPU for
     # coarse cylinders and checked against the oracle's assembly; the growth
@@ -527,6 +572,31 @@ def extras(args):
                      "spectral_radius_oracle": osp.spectral_radius(R),
                      "max_abs_diff_vs_oracle": float(np.abs(G - R).max()),
                      "gpu_columns_per_s": G.shape[0] / t_gpu, "oracle_columns_per_s": R.shape[0] / t_cpu})
+    # the semi-discrete operator L (growth rates per unit time, free of dt):
+    # the paper's scheme and the filtered one on the same coarse cylinders,
+    # through the library (lee_rhs) and the oracle
+    semi = []
+    for d in (0.0, 0.25, 0.49):
+        for name, H, fs in (("paper-scheme", 3, 0.0), ("11pt-filter", 5, 0.2)):
+            sc = lc.coarse_cylinder(28, 4.0, d, 0.5 * d, H=H, filter_sigma=fs)
+            inst = Instance(sc, "f64")
+            Lg = stability.operator_matrix(inst)
+            inst.close()
+            Lo = osp.operator_matrix(sc)
+            semi.append({"shift": [d, 0.5 * d], "scheme": name, "states": int(Lg.shape[0]),
+                         "abscissa_per_unit_time": stability.spectral_abscissa(Lg),
+                         "abscissa_oracle": osp.spectral_abscissa(Lo),
+                         "max_abs_diff_vs_oracle": float(np.abs(Lg - Lo).max())})
+    # flat walls through a 24^2 grid swept in angle (oracle; the wall meets
+    # the domain edges, whose cut clouds weigh on these small grids)
+    sweep = []
+    for ang in (0.0, 1.0, 2.0, 5.0, 10.0, 20.0, 30.0, 45.0):
+        nxw, nyw = lc.line_normal(ang)
+        for name, H, fs in (("paper-scheme", 3, 0.0), ("11pt-filter", 5, 0.2)):
+            fc = lc.Case(nx=24, ny=24, x0=-11.5, y0=-11.5, h=1.0, H=H, cfl=0.5, filter_sigma=fs,
+                         wall=lc.Wall("line", 0.13, 0.21, nxw, nyw), impedance=lc.Impedance())
+            sweep.append({"angle_deg": ang, "scheme": name,
+                          "abscissa_per_unit_time": osp.spectral_abscissa(osp.operator_matrix(fc))})
     bench_case = lc.cylinder_pulse_1024(10).replace(ic=None, probes=())
     power = {}
     for prec in ("f32", "f64"):
@@ -543,7 +613,9 @@ def extras(args):
         power[prec] = {"growth_per_step": est, "over_4000_steps": est ** 4000,
                        "last_chunk_growth": float(np.exp((logs[-1] - logs[-2]) / 100)),
                        "steps": args.power_steps, "wall_s": wall}
-    out["spectral"] = {"coarse_cylinder_28_rc4_f64": scan, "benchmark_grid_power_iteration": power}
+    out["spectral"] = {"coarse_cylinder_28_rc4_f64": scan, "benchmark_grid_power_iteration": power,
+                       "semi_discrete_operator_coarse_cylinder_28_rc4": semi,
+                       "semi_discrete_flat_wall_angle_sweep_24_oracle": sweep}
 
     print(f"[extras] batch of {args.batch_size} uneven instances", file=sys.stderr, flush=True)
     gen = lc.batch_candidates(steps=args.batch_steps)

@@ -1127,10 +1127,10 @@ __device__ __forceinline__ void tile_row(const DevInst &I, const TileCtx<T> &c, 
     const VecT<T, VEC> un = stage != 0 ? un_ : uc;
     const VecT<T, VEC> vn = stage != 0 ? vn_ : vc;
     all = true;
+    if (c.in_sponge) {
 #pragma unroll
-    for (int e = 0; e < VEC; ++e) {
-        const int col = gc + e;
-        if (c.in_sponge) {
+        for (int e = 0; e < VEC; ++e) {
+            const int col = gc + e;
             const int sw = I.sponge_w;
             const int eg = min(min(col, j), min(I.nx - 1 - col, I.ny - 1 - j));
             if (eg < sw) {
@@ -1141,11 +1141,22 @@ __device__ __forceinline__ void tile_row(const DevInst &I, const TileCtx<T> &c, 
                 rv[e] -= sg * vc.v[e];
             }
         }
-        if (c.has_src) {
-            const T xx = (T)(col - I.src_ic) * (T)I.h - (T)I.src_fx;
+    }
+    if (c.has_src) {
+        // the empty asm keeps the optimiser from evaluating the source term
+        // on every tile and selecting it away (its exp costs about 25
+        // instructions per node)
+        __asm__ volatile("");
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+            const T xx = (T)(gc + e - I.src_ic) * (T)I.h - (T)I.src_fx;
             const T yy = (T)(j - I.src_jc) * (T)I.h - (T)I.src_fy;
             rp[e] += c.amp * exp(-(T)I.src_b * (xx * xx + yy * yy));
         }
+    }
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+        const int col = gc + e;
         po.v[e] = pn.v[e] + c.adt * rp[e];
         uo.v[e] = un.v[e] + c.adt * ru[e];
         vo.v[e] = vn.v[e] + c.adt * rv[e];
