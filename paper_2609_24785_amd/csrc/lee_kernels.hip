@@ -805,9 +805,17 @@ __device__ __forceinline__ void dma16(const void *src, void *lds_wave_base)
 // damping of the field itself, (2 d_0) f_0 + sum_k d_k (f_{+k} + f_{-k})
 // summed over both directions (fd holds these coefficients times sigma/dt).
 // The pair sums and differences of each offset are formed once and shared.
-template <typename T, int VEC, bool FILT, int F, int LW>
+// Near-wall nodes (WALL, wall tiles): a node whose filter rows narrow (half-
+// widths wx[e], wy[e] below 5) takes its filter sum with the rows wb[wx] and
+// wb[wy] (the half-width-w centred rows times sigma_d / dt, k = 0..5; row 5
+// the 11-point one), from the window values already in registers; every
+// other node keeps the sum above, so a node's arithmetic does not depend on
+// the tiling.
+template <typename T, int VEC, bool FILT, int F, int LW, bool WALL = false>
 __device__ __forceinline__ void row_field(const T (*lds)[LW], int y, int lc, const T (&ax)[5], const T (&fd)[6],
-                                          T (&rp)[VEC], T (&ru)[VEC], T (&rv)[VEC])
+                                          T (&rp)[VEC], T (&ru)[VEC], T (&rv)[VEC],
+                                          const T (*wb)[8] = nullptr, const int *wx = nullptr,
+                                          const int *wy = nullptr)
 {
     constexpr int KM = (5 + VEC - 1) / VEC;
     constexpr int KP = (VEC + 4) / VEC;
@@ -856,6 +864,17 @@ __device__ __forceinline__ void row_field(const T (*lds)[LW], int y, int lc, con
             if (F != 1) dy += ax[k - 1] * (yp - ym);
             if (F != 2) dx += ax[k - 1] * (xp - xm);
             if (FILT) fl += fd[k] * ((xp + xm) + (yp + ym));
+        }
+        if constexpr (FILT && WALL) {
+            if (wx[e] < 5 || wy[e] < 5) {
+                const T *bx = wb[wx[e]];
+                const T *by = wb[wy[e]];
+                T g = bx[0] * yw[5][e] + by[0] * yw[5][e];
+#pragma unroll
+                for (int k = 1; k <= 5; ++k)
+                    g += bx[k] * (xw[x + k] + xw[x - k]) + by[k] * (yw[5 + k][e] + yw[5 - k][e]);
+                fl = g;
+            }
         }
         if (F == 0) {
             rv[e] -= dy;
@@ -1097,7 +1116,7 @@ __device__ __forceinline__ void wall_rows(const DevInst &I, const T (*reg)[TY + 
 // new values and which of the nodes are fluid.
 template <typename T, int VEC, bool FILT, int TX, int TY, bool WALL>
 __device__ __forceinline__ void tile_row(const DevInst &I, const TileCtx<T> &c, const T (*reg)[TY + 10][TX + 16],
-                                         const T (*wfd)[6], const ColMask<TY + 10> *wcm,
+                                         const T (*wb)[8], const ColMask<TY + 10> *wcm,
                                          int stage, int i, int tc, const int4 iv, const VecT<T, VEC> &pn_,
                                          const VecT<T, VEC> &un_, const VecT<T, VEC> &vn_, VecT<T, VEC> &po,
                                          VecT<T, VEC> &uo, VecT<T, VEC> &vo, bool (&ok)[VEC], bool &all)
@@ -1109,17 +1128,24 @@ __device__ __forceinline__ void tile_row(const DevInst &I, const TileCtx<T> &c, 
     T rp[VEC], ru[VEC], rv[VEC];
 #pragma unroll
     for (int e = 0; e < VEC; ++e) rp[e] = ru[e] = rv[e] = 0;
+    // near-wall half-widths of this lane's nodes (wall tiles): along x from
+    // the row's intervals, along y from the column masks
+    int wx[VEC], wy[VEC];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+        wx[e] = wy[e] = 5;
+        if (FILT && WALL && in_iv(iv, gc + e)) {
+            wx[e] = x_width(iv, gc + e, I.nx);
+            wy[e] = y_width_bits(wcm[tc + e], y);
+        }
+    }
     // one field's windows live at a time: each field's sums are pinned
     // (empty asm, no instructions) before the next field's LDS reads
-    row_field<T, VEC, FILT, 0>(reg[0], y, lc, c.ax, c.fd, rp, ru, rv);
+    row_field<T, VEC, FILT, 0, TX + 16, WALL>(reg[0], y, lc, c.ax, c.fd, rp, ru, rv, wb, wx, wy);
     pin_sums<T, VEC>(rp, ru, rv);
-    row_field<T, VEC, FILT, 1>(reg[1], y, lc, c.ax, c.fd, rp, ru, rv);
+    row_field<T, VEC, FILT, 1, TX + 16, WALL>(reg[1], y, lc, c.ax, c.fd, rp, ru, rv, wb, wx, wy);
     pin_sums<T, VEC>(rp, ru, rv);
-    row_field<T, VEC, FILT, 2>(reg[2], y, lc, c.ax, c.fd, rp, ru, rv);
-    if constexpr (FILT && WALL) {
-        pin_sums<T, VEC>(rp, ru, rv);
-        wall_rows<T, VEC, TX, TY>(I, reg, wfd, wcm, y, lc, gc, tc, iv, rp, ru, rv);
-    }
+    row_field<T, VEC, FILT, 2, TX + 16, WALL>(reg[2], y, lc, c.ax, c.fd, rp, ru, rv, wb, wx, wy);
     const VecT<T, VEC> pc = *(const VecT<T, VEC> *)&reg[0][y][lc];
     const VecT<T, VEC> uc = *(const VecT<T, VEC> *)&reg[1][y][lc];
     const VecT<T, VEC> vc = *(const VecT<T, VEC> *)&reg[2][y][lc];
@@ -1409,7 +1435,7 @@ __device__ __forceinline__ void wall_masks(const TileCtx<T> &c, const int4 wivr,
 // i0 + RG, .. (the q^n values of a row in flight during its arithmetic).
 template <typename T, int VEC, bool FILT, int TX, int TY, bool WALL>
 __device__ __forceinline__ void tile_rows(const DevInst &I, const TileCtx<T> &c, const T (*lds)[TY + 10][TX + 16],
-                                          const T (*wt)[7], const T (*wfd)[6], const ColMask<TY + 10> *wcm,
+                                          const T (*wt)[7], const T (*wb)[8], const ColMask<TY + 10> *wcm,
                                           int stage, int i0, int tc, int4 iv)
 {
     using G = TileGeo<T, VEC, TX, TY>;
@@ -1428,7 +1454,7 @@ __device__ __forceinline__ void tile_rows(const DevInst &I, const TileCtx<T> &c,
         VecT<T, VEC> po, uo, vo;
         bool ok[VEC];
         bool all;
-        tile_row<T, VEC, FILT, TX, TY, WALL>(I, c, lds, wfd, wcm, stage, i, tc, iv, pn, un, vn, po, uo, vo, ok,
+        tile_row<T, VEC, FILT, TX, TY, WALL>(I, c, lds, wb, wcm, stage, i, tc, iv, pn, un, vn, po, uo, vo, ok,
                                              all);
         if (!BAND_PASS && c.in_band)
             band_row<T, VEC, TX, TY>(I, c, lds, wt, stage, i, tc, pn, un, vn, po, uo, vo, ok, all);
@@ -1454,8 +1480,13 @@ __device__ __forceinline__ void tile_body(const DevInst *__restrict__ insts, con
     // wall tiles: the near-wall filter rows and the fluid intervals of the
     // copied rows (rows outside the domain are open)
     __shared__ T wfd[6][6];
+    __shared__ alignas(16) T wb[6][8];           // near-wall filter rows, half-width w = 0..5
     __shared__ ColMask<G::R> wcm[TX];            // per tile column, its non-fluid copied rows
     const int4 wivr = wall_prefetch<T, VEC, TX, TY>(I, c, wfd);
+    if (c.wall && tid < 48) {
+        const int w = tid / 8, k = tid % 8;
+        wb[w][k] = k < 6 ? (T)((k == 0 ? 0.5 * I.fd[0] : I.fd[k]) + I.fdw[w][k]) : (T)0;
+    }
     // while the copy flies: this lane's first row ranges and its first patch
     // entries
     const int i0 = tid / G::NCX;
@@ -1474,9 +1505,9 @@ __device__ __forceinline__ void tile_body(const DevInst *__restrict__ insts, con
     // wall tiles run a row loop of their own, so that the near-wall code
     // takes nothing from the scheduling of the plain tiles' loop
     if (FILT && c.wall)
-        tile_rows<T, VEC, FILT, TX, TY, true>(I, c, lds, wt, wfd, wcm, stage, i0, tc, iv);
+        tile_rows<T, VEC, FILT, TX, TY, true>(I, c, lds, wt, wb, wcm, stage, i0, tc, iv);
     else
-        tile_rows<T, VEC, FILT, TX, TY, false>(I, c, lds, wt, wfd, wcm, stage, i0, tc, iv);
+        tile_rows<T, VEC, FILT, TX, TY, false>(I, c, lds, wt, wb, wcm, stage, i0, tc, iv);
     if (BAND_PASS && c.in_band) band_pass<T, TX, TY>(I, c, lds, wt, stage);
 }
 
