@@ -38,8 +38,9 @@
  * closed forms, the walls by the image solution, the plane-wave reflection of
  * the impedance and the convergence orders (tests).  The outer sponge is a
  * reading (the paper truncates its domains with radiation conditions instead):
- * its profile sigma(d) = sigma_max ((W - d) / W)^2 is parity unpinned; a test
- * checks only that it removes energy.
+ * its profile sigma(d) = sigma_max ((W - d) / W)^2 is pinned through the
+ * right-hand side of a uniform field, which is exactly -sigma(d) away from
+ * the frame (tests).
  *
  * Radiation condition (optional; Sec. 2.2 names one-sided stencils at the
  * outer boundary, Sec. 4.1-4.2 the non-reflecting condition of Tam and Webb

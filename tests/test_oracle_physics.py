@@ -279,6 +279,40 @@ def test_explicit_filter_barely_touches_a_resolved_pulse():
     assert np.max(np.abs(tr[-1, :, 0] - ref)) < 2e-3 * np.abs(ref).max()
 
 
+def test_sponge_profile_is_the_damping_rate():
+    """Reading R17 (the sponge): sigma(d) = sigma_max ((W - d) / W)^2 with d the
+    node's distance in cells to the nearest edge.  For a uniform pressure
+    field the DRP derivatives vanish and the filter gives D(0) = 0 wherever
+    the stencils stay off the zero frame (d >= 5), so the semi-discrete
+    right-hand side there is exactly -sigma(d) for p and 0 for u and v."""
+    import ctypes
+    from oracle import spectral as sp
+    from oracle.solver import F as FRAME, _load, _ptr
+    n, W, smax = 61, 20, 0.3
+    case = lc.Case(nx=n, ny=n, x0=0.0, y0=0.0, h=1.0, H=5, filter_sigma=0.2,
+                   sponge_cells=W, sponge_sigma=smax)
+    s = sp._solver(case)
+    lib = _load()
+    lib.oc_rhs.restype = ctypes.c_int
+    lib.oc_rhs.argtypes = [ctypes.c_void_p] * 5 + [ctypes.c_double] + [ctypes.c_void_p] * 4
+    inner = (slice(FRAME, FRAME + n), slice(FRAME, FRAME + n))
+    s.p[...] = 0.0
+    s.p[inner] = 1.0
+    s.u[...] = 0.0
+    s.v[...] = 0.0
+    rp, ru, rv = (np.zeros(s.shape) for _ in range(3))
+    rpsi = np.zeros_like(s.psi)
+    assert lib.oc_rhs(ctypes.byref(s._cs), _ptr(s.p), _ptr(s.u), _ptr(s.v), _ptr(s.psi), 0.0,
+                      _ptr(rp), _ptr(ru), _ptr(rv), _ptr(rpsi)) == 0
+    jj, ii = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    d = np.minimum(np.minimum(ii, jj), np.minimum(n - 1 - ii, n - 1 - jj))
+    sig = np.where(d < W, smax * ((W - d) / W) ** 2, 0.0)
+    away = d >= 5
+    assert np.max(np.abs(rp[inner][away] + sig[away])) < 1e-12
+    assert np.max(np.abs(ru[inner][away])) < 1e-12 and np.max(np.abs(rv[inner][away])) < 1e-12
+    assert sig[away].max() > 0.1 and np.all(sig[d >= W] == 0.0)
+
+
 def test_sponge_absorbs():
     base = lc.Case(nx=81, ny=81, x0=-40.0, y0=-40.0, h=1.0, H=5, filter_sigma=0.0,
                    ic=lc.Pulse(0.0, 0.0, 1.0, 3.0))
