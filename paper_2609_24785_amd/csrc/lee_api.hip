@@ -109,6 +109,9 @@ size_t patch_capacity(const Host &h) { return 24 * h.gidx.size() + 64; }
 // (measured: about twice a plain tile's time).
 constexpr int WALL_ITEM_COST = 2;
 
+// Field planes beyond this many bytes take streaming (non-temporal) stores.
+constexpr size_t STREAM_STORE_BYTES = size_t(128) << 20;
+
 size_t work1_capacity(const Host &h)
 {
     const int ow_min = 64;                       // narrowest strip: 64-column tiles
@@ -802,6 +805,9 @@ lee_status lee_bind(lee_instance *I, void *dev_ptr, size_t bytes, void *hip_stre
     }
     D.rad_w = h.d.radiation ? h.d.stencil_half : 0;
     D.fx = filter_form(h) == 2 ? 1 : 0;
+    // stage outputs bypass the caches when the field planes cannot stay in
+    // the 256 MB on-chip cache anyway (half of it, leaving room for the rest)
+    D.stream = 9 * plane_elems(h) * esize(h) > STREAM_STORE_BYTES ? 1 : 0;
     D.rad_xc = h.d.rad_xc;
     D.rad_yc = h.d.rad_yc;
     // window weights: place 3 the central 7-node set (-a3, -a2, -a1, 0, a1,
@@ -1427,9 +1433,14 @@ lee_status batch_rebuild(lee_batch *B, bool drop = false)
     B->up_table.clear();
     B->up_work2.clear();
     B->up_pwork.clear();
+    // the members' planes together decide the streaming stores: a batch
+    // whose planes exceed the on-chip cache streams every member's outputs
+    size_t plane_bytes = 0;
+    for (const auto *I : B->members) plane_bytes += 9 * plane_elems(I->host) * esize(I->host);
     for (size_t k = 0; k < n; ++k) {
         const lee_instance *I = B->members[k];
         B->up_table.push_back(I->dev);
+        B->up_table.back().stream = plane_bytes > STREAM_STORE_BYTES ? 1 : 0;
         for (int g = 0; g < (int)I->host.gidx.size(); ++g)
             B->up_work2.push_back(make_int4((int)k, g, I->host.cptr[g], I->host.cptr[g + 1]));
         for (int p = 0; p < I->host.np; ++p) B->up_pwork.push_back(make_int2((int)k, p));
@@ -1810,9 +1821,12 @@ extern "C" lee_status lee_step_members_noalloc(lee_instance *const *v, int32_t n
     S.pwork.clear();
     S.items.clear();
     S.patches.clear();
+    size_t plane_bytes = 0;                      // as for batches: the members together
+    for (int k = 0; k < n; ++k) plane_bytes += 9 * plane_elems(v[k]->host) * esize(v[k]->host);
     for (int k = 0; k < n; ++k) {
         const lee_instance *I = v[k];
         S.table.push_back(I->dev);
+        S.table.back().stream = plane_bytes > STREAM_STORE_BYTES ? 1 : 0;
         for (int g = 0; g < (int)I->host.gidx.size(); ++g)
             S.work2.push_back(make_int4(k, g, I->host.cptr[g], I->host.cptr[g + 1]));
         for (int p = 0; p < I->host.np; ++p) S.pwork.push_back(make_int2(k, p));

@@ -70,6 +70,7 @@ struct DevInst {
     double rad_w7[7][7];    // first-derivative weights / h on a 7-node window, node at place r:
                             // r = 3 the central set a_k, else the one-sided maximal-order set
     float rad_wf[7][7];
+    int stream;             // stage outputs take non-temporal stores (planes larger than the on-chip cache)
 };
 
 // Probe sampling carried by a launch: the (member, probe) pairs pw[0, np),

@@ -71,6 +71,30 @@ __device__ __forceinline__ void vst(GLOBAL T *p, const VecT<T, N> &v)
     *(GLOBAL VecT<T, N> *)p = v;
 }
 
+// An 8- or 16-byte store marked non-temporal: a stage's output is read back only by
+// the next launch, so where the planes do not fit the on-chip cache it need not
+// claim L2 lines that the tiles' halo reads share (measured: the 4096^2 step 5%
+// shorter in FP32 and FP64; the 1024^2 FP64 step, whose planes fit, 3-10% longer;
+// non-temporal loads of q^n were slower).
+template <int B>
+struct StreamWord;
+template <>
+struct StreamWord<8> {
+    typedef unsigned type __attribute__((ext_vector_type(2)));
+};
+template <>
+struct StreamWord<16> {
+    typedef unsigned type __attribute__((ext_vector_type(4)));
+};
+template <typename T, int N>
+__device__ __forceinline__ void vst_stream(GLOBAL T *p, const VecT<T, N> &v)
+{
+    using W = typename StreamWord<sizeof(VecT<T, N>)>::type;
+    W w;
+    __builtin_memcpy(&w, &v, sizeof(W));
+    __builtin_nontemporal_store(w, (GLOBAL W *)p);
+}
+
 // Orders this wave's LDS writes before its following LDS reads.  Each wave owns
 // its LDS rows, so no workgroup barrier is needed (and waves of one workgroup
 // may march tiles of different lengths).
@@ -718,9 +742,17 @@ __global__ __launch_bounds__(64 * WPB) void k_sweep(const DevInst *__restrict__ 
                         b.v[e] = ro[1][e];
                         c.v[e] = ro[2][e];
                     }
-                    vst<T, VEC>(Po + off, a);
-                    vst<T, VEC>(Uo + off, b);
-                    vst<T, VEC>(Vo + off, c);
+                    if (I.stream) {
+                        __asm__ volatile("");
+                        vst_stream<T, VEC>(Po + off, a);
+                        vst_stream<T, VEC>(Uo + off, b);
+                        vst_stream<T, VEC>(Vo + off, c);
+                        __asm__ volatile("");
+                    } else {
+                        vst<T, VEC>(Po + off, a);
+                        vst<T, VEC>(Uo + off, b);
+                        vst<T, VEC>(Vo + off, c);
+                    }
                 } else {
 #pragma unroll
                     for (int e = 0; e < VEC; ++e)
@@ -1204,9 +1236,19 @@ __device__ __forceinline__ void tile_store(const DevInst &I, int ob, unsigned of
     GLOBAL T *Uo = gp<T>(I.f[ob][1]);
     GLOBAL T *Vo = gp<T>(I.f[ob][2]);
     if (all) {
-        vst<T, VEC>(Po + off, po);
-        vst<T, VEC>(Uo + off, uo);
-        vst<T, VEC>(Vo + off, vo);
+        if (I.stream) {
+            // the empty asm statements keep the optimiser from merging these
+            // stores with the plain ones below (which drops the hint)
+            __asm__ volatile("");
+            vst_stream<T, VEC>(Po + off, po);
+            vst_stream<T, VEC>(Uo + off, uo);
+            vst_stream<T, VEC>(Vo + off, vo);
+            __asm__ volatile("");
+        } else {
+            vst<T, VEC>(Po + off, po);
+            vst<T, VEC>(Uo + off, uo);
+            vst<T, VEC>(Vo + off, vo);
+        }
     } else {
 #pragma unroll
         for (int e = 0; e < VEC; ++e)
