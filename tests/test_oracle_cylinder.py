@@ -38,8 +38,9 @@ import pytest
 import lee_cases as lc
 from oracle.solver import OracleSolver, dft_amplitude
 from tests import refsol
+from tests.golden import paper
 
-PAPER_MSD = lc.Impedance("msd", R=0.2, M=0.025, K=1.6)
+PAPER_MSD = lc.Impedance("msd", R=paper("pulse_R"), M=paper("pulse_M"), K=paper("pulse_K"))
 
 
 def _pulse_case(h, imp):
@@ -60,7 +61,8 @@ def _pulse_error(h, imp):
     return float(np.sqrt(np.mean((tr[win, 0, 0] - ref) ** 2)) / np.sqrt(np.mean(ref ** 2)))
 
 
-@pytest.mark.parametrize("imp,paper_order,tol", [(lc.Impedance("rigid"), 4.0, 5e-4), (PAPER_MSD, 3.0, 1e-3)],
+@pytest.mark.parametrize("imp,paper_order,tol", [(lc.Impedance("rigid"), paper("order_pulse_rigid"), 5e-4),
+                                                  (PAPER_MSD, paper("order_pulse_impedance"), 1e-3)],
                          ids=["rigid", "impedance"])
 def test_cylinder_pulse_converges_to_app_b(imp, paper_order, tol):
     e1, e2 = _pulse_error(0.04, imp), _pulse_error(0.02, imp)
@@ -70,7 +72,8 @@ def test_cylinder_pulse_converges_to_app_b(imp, paper_order, tol):
 
 
 OMEGA = 4.0 * math.pi
-MONO_WALL = lc.Impedance("msd", R=1.0, M=0.025, K=15.79)      # Sec. 4.3 (resonance at 8 pi)
+# Sec. 4.3 (resonance at 8 pi)
+MONO_WALL = lc.Impedance("msd", R=paper("monopole_R"), M=paper("monopole_M"), K=paper("monopole_K"))
 RINGS = (0.75, 2.0)
 
 
@@ -123,7 +126,7 @@ def test_monopole_scattering_converges_to_app_c(monopole_runs):
     for k in range(len(RINGS)):
         order = math.log(errs[0.04][k] / errs[0.02][k], 2.0)
         assert errs[0.02][k] < 1.5e-2, errs
-        assert order > 2.5, (errs, order)            # the paper: about 3
+        assert order > paper("order_monopole") - 0.5, (errs, order)
 
 
 def test_wall_velocity_of_ade_and_fluid_coincide(monopole_runs):

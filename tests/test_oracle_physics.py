@@ -18,6 +18,7 @@ import pytest
 import lee_cases as lc
 from oracle.solver import OracleSolver
 from tests import refsol
+from tests.golden import paper
 
 
 def _probe_series(case, nsteps):
@@ -117,7 +118,7 @@ def test_rigid_wall_convergence_order(H):
         ref = _image_ref(case, steps * case.dt)
         errs.append(np.max(np.abs(tr[-1, :, 0] - ref)))
     order = np.polyfit(np.log(hs), np.log(errs), 1)[0]
-    assert order > 3.3, (errs, order)
+    assert order > paper("order_flat") - 0.7, (errs, order)
 
 
 def _packet_case(imp, h=0.5, ang=30.0):
@@ -232,7 +233,7 @@ def test_impedance_flat_wall_convergence_order(imp):
     errs = [_packet_error_fixed_scale(imp, h) for h in hs]
     order = np.polyfit(np.log(hs), np.log(errs), 1)[0]
     assert errs[-1] < 1e-3, errs
-    assert order > 4.0, (errs, order)
+    assert order > paper("order_flat_conclusion") - 0.5, (errs, order)
 
 
 def test_filter_removes_checkerboard_at_rk4_rate():
