@@ -220,7 +220,8 @@ def _serve_short(args):
             enumerate(lc.request_stream(seed=26091, rate=args.serve_rate, duration=args.serve_duration))]
     be = GpuBackend("f32")
     try:
-        srv = Server(be, budget_bytes=args.serve_budget_gb * 1e9, chunk=args.serve_chunk)
+        srv = Server(be, budget_bytes=args.serve_budget_gb * 1e9, chunk=args.serve_chunk,
+                     report=lambda st: print(f"[serve] {json.dumps(st)}", file=sys.stderr, flush=True))
         res = srv.run(reqs)
     finally:
         be.close()
@@ -671,7 +672,8 @@ def serve(args):
           flush=True)
     be = GpuBackend("f32")
     try:
-        srv = Server(be, budget_bytes=args.serve_budget_gb * 1e9, chunk=args.serve_chunk)
+        srv = Server(be, budget_bytes=args.serve_budget_gb * 1e9, chunk=args.serve_chunk,
+                     report=lambda st: print(f"[serve] {json.dumps(st)}", file=sys.stderr, flush=True))
         res = srv.run(reqs)
     finally:
         be.close()

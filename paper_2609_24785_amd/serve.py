@@ -236,7 +236,8 @@ class Server:
 
     def __init__(self, backend, budget_bytes: float = 200e9, chunk: int = 100, max_members: int = 512,
                  clock: Callable[[], float] = time.monotonic, sleep: Callable[[float], None] = time.sleep,
-                 dt_of: Optional[Callable[[Any], float]] = None):
+                 dt_of: Optional[Callable[[Any], float]] = None,
+                 report: Optional[Callable[[Dict[str, Any]], None]] = None, report_every: float = 20.0):
         self.backend = backend
         self.budget = budget_bytes
         self.chunk = chunk
@@ -244,6 +245,8 @@ class Server:
         self.clock = clock
         self.sleep = sleep
         self.dt_of = dt_of or (lambda case: case.dt)
+        self.report = report                     # called with a state summary after a chunk,
+        self.report_every = report_every         # at most once per report_every seconds
         self.stats: Dict[str, Any] = {}
 
     def run(self, requests: Iterable[Request]) -> List[Result]:
@@ -259,6 +262,7 @@ class Server:
         peak_members = 0
         node_steps = 0
         busy = 0.0
+        last_report = 0.0
         while nxt < len(reqs) or preparing or active:
             t = now()
             while nxt < len(reqs) and reqs[nxt].arrival <= t:
@@ -317,6 +321,10 @@ class Server:
                                                 _omegas(req.case))
                 results.append(res)
             active = still
+            if self.report is not None and now() - last_report >= self.report_every:
+                last_report = now()
+                self.report({"t_s": last_report, "arrived": nxt, "finished": len(results),
+                             "active": len(active), "waiting": len(preparing), "bytes_in_use": in_use})
         wall = now()
         ok = [r for r in results if r.error is None]
         lat = np.array([r.latency for r in ok]) if ok else np.zeros(1)

@@ -125,3 +125,19 @@ def test_rejected_set_up_is_reported_not_raised():
     res = srv.run(reqs)
     assert "LEE_E_ADE_STIFF" in res[0].error
     assert res[1].error is None and int(res[1].traces[0]) == 20
+
+
+def test_progress_reports_follow_the_work():
+    # the report callback sees the state after chunks, at most once per
+    # report_every seconds of the server's clock, and its counts add up
+    reqs = [_req(k, 96, 50, 0.001 * k) for k in range(6)]
+    clk = VClock()
+    be = SimBackend(clk, 1e-6)
+    seen = []
+    srv = Server(be, chunk=10, clock=clk, sleep=clk.sleep, report=seen.append, report_every=0.01)
+    res = srv.run(reqs)
+    assert seen and len(res) == 6
+    ts = [r["t_s"] for r in seen]
+    assert all(b - a >= 0.01 for a, b in zip(ts, ts[1:]))
+    for r in seen:
+        assert r["finished"] + r["active"] + r["waiting"] <= r["arrived"] <= 6
