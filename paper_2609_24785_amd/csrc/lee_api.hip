@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cstddef>
 #include <climits>
 #include <cmath>
@@ -103,7 +104,11 @@ size_t plane_elems(const Host &h) { return (size_t)(h.d.ny + 2 * FRAME) * pitch_
 
 // A ghost node lies in the stencil region of at most 4 row tiles (rows >= 4)
 // and 2 column blocks (cols >= 64), with one entry per field.
-size_t patch_capacity(const Host &h) { return 24 * h.gidx.size() + 64; }
+// Band rows cut into one-row tiles (radiation band on) add at most 2 rw row
+// ranges to a ghost's reach.
+size_t band_rows(const Host &h) { return h.d.radiation ? 2 * (size_t)h.d.stencil_half : 0; }
+
+size_t patch_capacity(const Host &h) { return (24 + 6 * band_rows(h)) * h.gidx.size() + 64; }
 
 // Relative cost of a sweep item whose nodes take the near-wall filter rows
 // (measured: about twice a plain tile's time).
@@ -116,7 +121,7 @@ size_t work1_capacity(const Host &h)
 {
     const int ow_min = 64;                       // narrowest strip: 64-column tiles
     const size_t strips = (h.d.nx + ow_min - 1) / ow_min;
-    const size_t tiles = (h.d.ny + 3) / 4;
+    const size_t tiles = (h.d.ny + 3) / 4 + band_rows(h);
     // the slot order pads the list to at most WALL_ITEM_COST times the
     // items plus 24 units of up to 4 items
     return WALL_ITEM_COST * strips * tiles + 128;
@@ -364,8 +369,27 @@ void build_items(const Host &h, int inst_id, const lee_tiling &t, std::vector<in
         }
     }
     const int LW = ow + 16;
+    // row ranges of the tiles: with the radiation band on, a tile row that
+    // meets the band's top or bottom rows (wholly band nodes, computed by the
+    // band pass, one item per node and field) is cut into one-row tiles there
+    // and one tile for the rest, so that no edge tile works through a chain of
+    // band rows while the other tiles of its launch have finished
+    const int rw = h.d.radiation ? h.d.stencil_half : 0;
+    std::vector<std::array<int, 3>> ranges;      // r0, r1, tile row
     for (int r = 0; r < tiles; ++r) {
         const int r0 = r * rows, r1 = std::min(r0 + rows, h.d.ny);
+        const int b0 = std::min(std::max(r0, rw), r1);            // [r0, b0): top band rows
+        const int b1 = std::max(std::min(r1, h.d.ny - rw), b0);   // [b1, r1): bottom band rows
+        if (rw == 0 || (b0 == r0 && b1 == r1)) {
+            ranges.push_back({r0, r1, r});
+            continue;
+        }
+        for (int j = r0; j < b0; ++j) ranges.push_back({j, j + 1, r});
+        if (b0 < b1) ranges.push_back({b0, b1, r});
+        for (int j = b1; j < r1; ++j) ranges.push_back({j, j + 1, r});
+    }
+    for (const auto &rg : ranges) {
+        const int r0 = rg[0], r1 = rg[1], r = rg[2];
         for (int s = 0; s < strips; ++s) {
             const int c0 = s * ow, c1 = std::min(c0 + ow, h.d.nx);
             bool any = false;
@@ -378,8 +402,8 @@ void build_items(const Host &h, int inst_id, const lee_tiling &t, std::vector<in
             std::vector<int2> pl;
             bool wall = false;
             if (fused || walls) {
-                for (int j = std::max(0, r0 - 5); j < std::min(h.d.ny, r0 + rows + 5); ++j) {
-                    const bool own = j >= r0 && j < r0 + rows;
+                for (int j = std::max(0, r0 - 5); j < std::min(h.d.ny, r1 + 5); ++j) {
+                    const bool own = j >= r0 && j < r1;
                     const int lo = own ? c0 - 5 : c0, hi = own ? c0 + ow + 5 : c0 + ow;
                     const std::vector<int> &gc = grow_cols[j];
                     for (auto it = std::lower_bound(gc.begin(), gc.end(), lo); it != gc.end() && *it < hi; ++it) {

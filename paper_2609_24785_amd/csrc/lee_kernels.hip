@@ -1399,6 +1399,9 @@ __device__ __forceinline__ void band_pass(const DevInst &I, const TileCtx<T> &c,
             tc = k < cl ? k : cr + (k - cl);
         }
         const int j = c.r0 + i, col = c.c0 + tc;
+        const unsigned off = (unsigned)(I.org + j * I.pitch + col);
+        // q^n first, in flight during the arithmetic
+        const T qn = stage != 0 ? gp<T>(I.f[0][f])[off] : (T)0;
         const int eg = min(min(col, j), min(nx - 1 - col, ny - 1 - j));
         const int rx = rad_place(col, nx), ry = rad_place(j, ny);
         const int lc = tc + 8;
@@ -1431,9 +1434,7 @@ __device__ __forceinline__ void band_pass(const DevInst &I, const TileCtx<T> &c,
             const T yy = (T)(j - I.src_jc) * (T)I.h - (T)I.src_fy;
             rq += c.amp * exp(-(T)I.src_b * (xx * xx + yy * yy));
         }
-        const unsigned off = (unsigned)(I.org + j * I.pitch + col);
-        const T base = stage != 0 ? gp<T>(I.f[0][f])[off] : qc;
-        gp<T>(I.f[c.ob][f])[off] = c.adt * rq + base;
+        gp<T>(I.f[c.ob][f])[off] = c.adt * rq + (stage != 0 ? qn : qc);
     }
 }
 
@@ -1485,6 +1486,7 @@ __device__ __forceinline__ void tile_rows(const DevInst &I, const TileCtx<T> &c,
     for (int i = i0; i < TY; i += G::RG) {
         const int j = c.r0 + i;
         if (j >= c.r1) break;
+        if (c.in_band && (j < I.rad_w || j >= I.ny - I.rad_w)) continue;   // wholly band nodes
         if (i != i0) iv = gp<int4>(I.iv)[j];
         VecT<T, VEC> pn{}, un{}, vn{};
         if (stage != 0) {                        // in flight during the row's arithmetic
