@@ -687,7 +687,7 @@ def serve(args):
     out = {"serve": True, "metric": "served solves: throughput and p50/p99 latency", "unit": UNIT,
            "arrival_rate": args.serve_rate, "window_s": args.serve_duration, "chunk_steps": args.serve_chunk,
            "budget_gb": args.serve_budget_gb, "dtype": "f32",
-           "value": srv.stats["throughput"], **srv.stats,
+           "value": srv.stats["throughput"], **srv.stats, "gpu_s": be.gpu_s,
            "mean_steps": float(np.mean([r.steps for r in ok])) if ok else 0.0,
            "mean_fluid_nodes": float(np.mean([r.nodes for r in ok])) if ok else 0.0,
            "rejected_reasons": sorted({(r.error or "")[:60] for r in res if r.error}),

@@ -425,6 +425,22 @@ lee_status lee_batch_add(lee_batch *b, lee_instance *inst);
 lee_status lee_batch_remove(lee_batch *b, lee_instance *inst);
 lee_status lee_batch_size(const lee_batch *b, int32_t *n);
 
+/* Several membership changes with one rebuild of the device table and work
+ * lists: the nremove instances in `remove` (each a member, no repeats) leave
+ * the batch, then the nadd instances in `add` (each bound, not a member
+ * after the removals, no repeats, checked as lee_batch_add checks them)
+ * join it at the end, in that order.  The result is the batch that the same
+ * lee_batch_remove calls followed by the same lee_batch_add calls give, and
+ * its graphs are kept or dropped by the same rule (applied once, to the
+ * final membership); it costs one rebuild
+ * instead of one per change (the rebuild covers every member, so a served
+ * stream that retires and admits several requests between chunks of a
+ * large batch pays it once).  The batch's stream and the added instances'
+ * streams are synchronised first.  The arrays are the caller's; nothing is
+ * changed when an argument is refused (LEE_E_ARG, LEE_E_STATE). */
+lee_status lee_batch_update(lee_batch *b, lee_instance *const *add, int32_t nadd, lee_instance *const *remove,
+                            int32_t nremove);
+
 /* Number of step graphs the batch has captured so far (each run length
  * captured counts once); it grows only when graphs had to be dropped. */
 lee_status lee_batch_graph_captures(const lee_batch *b, int64_t *n);

@@ -98,6 +98,7 @@ SIGNATURES = {
     "lee_batch_synchronize": (c_int32, [c_void_p]),
     "lee_batch_add": (c_int32, [c_void_p, c_void_p]),
     "lee_batch_remove": (c_int32, [c_void_p, c_void_p]),
+    "lee_batch_update": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_int32]),
     "lee_batch_size": (c_int32, [c_void_p, ctypes.POINTER(c_int32)]),
     "lee_batch_graph_captures": (c_int32, [c_void_p, ctypes.POINTER(c_int64)]),
     "lee_batch_set_tiling": (c_int32, [c_void_p, ctypes.POINTER(Tiling)]),

@@ -1629,6 +1629,32 @@ lee_status lee_batch_remove(lee_batch *B, lee_instance *I)
     return batch_rebuild(B);
 }
 
+lee_status lee_batch_update(lee_batch *B, lee_instance *const *add, int32_t nadd, lee_instance *const *remove,
+                            int32_t nremove)
+{
+    if (!B || nadd < 0 || nremove < 0 || (nadd > 0 && !add) || (nremove > 0 && !remove))
+        return fail(LEE_E_ARG, "batch update arguments");
+    std::vector<lee_instance *> next = B->members;
+    for (int32_t k = 0; k < nremove; ++k) {
+        auto it = std::find(next.begin(), next.end(), remove[k]);
+        if (!remove[k] || it == next.end()) return fail(LEE_E_ARG, "not a member");
+        next.erase(it);
+    }
+    for (int32_t k = 0; k < nadd; ++k) {
+        lee_status st = member_ok(B, add[k]);
+        if (st != LEE_OK) return st;
+        if (std::find(next.begin(), next.end(), add[k]) != next.end()) return fail(LEE_E_ARG, "already a member");
+        next.push_back(add[k]);
+    }
+    HIPCHK(hipStreamSynchronize(B->stream));      // no queued step may still use a removed member
+    for (int32_t k = 0; k < nadd; ++k) HIPCHK(hipStreamSynchronize(add[k]->stream));   // their set-up
+    std::vector<lee_instance *> before = B->members;
+    B->members = std::move(next);
+    lee_status st = batch_rebuild(B);
+    if (st != LEE_OK) B->members = std::move(before);
+    return st;
+}
+
 lee_status lee_batch_graph_captures(const lee_batch *B, int64_t *n)
 {
     if (!B || !n) return fail(LEE_E_ARG, "null argument");

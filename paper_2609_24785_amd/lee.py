@@ -369,6 +369,16 @@ class Batch:
         check(self.lib.lee_batch_remove(self._h, inst._h), "lee_batch_remove")
         self.members.remove(inst)
 
+    def update(self, add: Sequence[Instance] = (), remove: Sequence[Instance] = ()):
+        """Removals, then additions at the end, with one rebuild (lee_batch_update)."""
+        add, remove = list(add), list(remove)
+        a = (c_void_p * max(len(add), 1))(*[m._h.value for m in add])
+        r = (c_void_p * max(len(remove), 1))(*[m._h.value for m in remove])
+        check(self.lib.lee_batch_update(self._h, a, len(add), r, len(remove)), "lee_batch_update")
+        for m in remove:
+            self.members.remove(m)
+        self.members.extend(add)
+
     def __len__(self) -> int:
         n = ctypes.c_int32()
         check(self.lib.lee_batch_size(self._h, ctypes.byref(n)), "lee_batch_size")

@@ -135,6 +135,11 @@ class GpuBackend:
         self.graph_steps = graph_steps
         self.batch = None
         self.pool = ThreadPoolExecutor(max_workers=prepare_threads)
+        self.gpu_s = 0.0                         # device time of the chunks (events on the stream)
+        # membership changes since the last chunk, applied together before the
+        # next one (one rebuild of the batch's lists instead of one per change)
+        self._add: List[Any] = []
+        self._remove: List[Any] = []
 
     # host side, in worker threads: the library releases the GIL in its calls
     def prepare(self, case):
@@ -153,28 +158,50 @@ class GpuBackend:
         return int(inst.summary.fluid_nodes)
 
     def admit(self, inst) -> None:
-        from .lee import Batch
         inst.bind(self.device, self.stream)
+        self._add.append(inst)
+
+    def _flush(self) -> None:
+        """The pending removals and additions in one lee_batch_update; the
+        removed instances are closed after it."""
+        from .lee import Batch
+        if not self._add and not self._remove:
+            return
         if self.batch is None:
-            self.batch = Batch([inst], tiling=self.tiling, graph_steps=self.graph_steps)
+            self.batch = Batch(self._add, tiling=self.tiling, graph_steps=self.graph_steps)
         else:
-            self.batch.add(inst)
+            self.batch.update(add=self._add, remove=self._remove)
+        for inst in self._remove:
+            inst.close()
+            inst.buf = None                  # the device memory returns to torch's cache
+        self._add, self._remove = [], []
 
     def step(self, insts: Sequence, budgets: Sequence[int], n: int) -> None:
+        self._flush()
+        # budgets are per position: the batch holds the scheduler's members in its order
+        assert [id(m) for m in self.batch.members] == [id(m) for m in insts]
         self.batch.set_budget(budgets)
+        ev = [self.torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        with self.torch.cuda.stream(self.stream):
+            ev[0].record()
         self.batch.step_n(n)
+        with self.torch.cuda.stream(self.stream):
+            ev[1].record()
         self.batch.synchronize()
+        ev[1].synchronize()
+        self.gpu_s += ev[0].elapsed_time(ev[1]) * 1e-3
 
     def retire(self, inst) -> Dict[str, Any]:
         out = {"traces": inst.traces(), "watch": inst.watch_traces() if inst.watch_g >= 0 else None}
-        self.batch.remove(inst)
-        inst.close()
-        inst.buf = None                      # the device memory returns to torch's cache
+        self._remove.append(inst)            # leaves the batch before the next chunk
         return out
 
     def close(self):
         if self.batch is not None:
             self.batch.close()
+        for inst in self._remove + self._add:
+            inst.close()
+        self._add, self._remove = [], []
         self.pool.shutdown(wait=True)
 
 
@@ -262,6 +289,7 @@ class Server:
         peak_members = 0
         node_steps = 0
         busy = 0.0
+        spent = {"admit_s": 0.0, "retire_s": 0.0, "setup_wait_s": 0.0}   # host phases between chunks
         last_report = 0.0
         while nxt < len(reqs) or preparing or active:
             t = now()
@@ -269,6 +297,7 @@ class Server:
                 preparing.append((reqs[nxt], self.backend.prepare_async(reqs[nxt].case)))
                 nxt += 1
             # admission in arrival order while memory and slots allow
+            ta = now()
             while preparing and preparing[0][1].done() and len(active) < self.max_members:
                 req, fut = preparing[0]
                 try:
@@ -290,14 +319,17 @@ class Server:
                 in_use += need
                 active.append({"req": req, "h": h, "left": req.case.steps, "admitted": now(), "need": need,
                                "nodes": self.backend.nodes(h)})
+            spent["admit_s"] += now() - ta
             peak_mem = max(peak_mem, in_use)
             peak_members = max(peak_members, len(active))
             if not active:
                 # idle: wait for the next arrival or a preparation to finish
+                tw = now()
                 if preparing:
                     wait_futures([preparing[0][1]])      # its outcome is handled at admission
                 elif nxt < len(reqs):
                     self.sleep(max(0.0, reqs[nxt].arrival - now()))
+                spent["setup_wait_s"] += now() - tw
                 continue
             budgets = [min(a["left"], self.chunk) for a in active]
             n = max(budgets)
@@ -306,6 +338,7 @@ class Server:
             busy += now() - ts
             node_steps += sum(a["nodes"] * b for a, b in zip(active, budgets))
             still = []
+            tr = now()
             for a, b in zip(active, budgets):
                 a["left"] -= b
                 if a["left"] > 0:
@@ -321,6 +354,7 @@ class Server:
                                                 _omegas(req.case))
                 results.append(res)
             active = still
+            spent["retire_s"] += now() - tr
             if self.report is not None and now() - last_report >= self.report_every:
                 last_report = now()
                 self.report({"t_s": last_report, "arrived": nxt, "finished": len(results),
@@ -334,7 +368,7 @@ class Server:
             "throughput": 4 * node_steps / wall if wall > 0 else 0.0,
             "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
             "mean_wait_s": float(np.mean([r.wait for r in ok])) if ok else 0.0,
-            "peak_members": peak_members, "peak_bytes": peak_mem,
+            "peak_members": peak_members, "peak_bytes": peak_mem, **spent,
         }
         return sorted(results, key=lambda r: r.rid)
 

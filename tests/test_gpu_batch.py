@@ -153,3 +153,64 @@ def test_batch_capacity_growth_and_trim_recapture():
         assert m.step == n
         for x, y in zip(m.fields(), ref):
             assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("prec,fused", [("f32", 1), ("f64", 0)])
+def test_update_applies_removals_and_additions_in_one_rebuild(prec, fused):
+    """lee_batch_update: two members leave and one joins in one call, then the
+    two come back in a second call; every member matches a solo run of the
+    same number of steps bit for bit and the same changes made one call at
+    a time, and arguments the library refuses (a non-member to remove, a
+    member to add) change nothing."""
+    from paper_2609_24785_amd._lib import LeeError
+    Instance, Batch = _lee()
+    cases = _members()[:5]
+    rows = 16 if prec == "f32" else 8
+    steps = [24, 16, 24, 16, 16]             # 1 and 3 sit out the middle run, 4 joins for it
+    print(f"[batch] update {prec} fused={fused}", flush=True)
+    solo = []
+    for c, n in zip(cases, steps):
+        i = Instance(c, prec)
+        i.set_tiling("tile", cols=64, rows=rows, fused=0)
+        i.step_n(n)
+        i.synchronize()
+        solo.append(i.fields())
+    mem = [Instance(c, prec) for c in cases]
+    b = Batch(mem[:4], tiling=dict(kind="tile", cols=64, rows=rows, fused=fused), graph_steps=4)
+    b.step_n(8)
+    b.synchronize()
+    captured = b.graph_captures()
+    b.update(add=[mem[4]], remove=[mem[1], mem[3]])
+    assert [id(m) for m in b.members] == [id(mem[0]), id(mem[2]), id(mem[4])] and len(b) == 3
+    b.step_n(8)
+    with pytest.raises(LeeError):
+        b.update(remove=[mem[1]])            # not a member
+    with pytest.raises(LeeError):
+        b.update(add=[mem[0]])               # already a member
+    assert len(b) == 3
+    b.update(add=[mem[1], mem[3]])
+    b.step_n(8)
+    b.synchronize()
+    assert len(b) == 5
+    for m, ref in zip(mem, solo):
+        m.synchronize()
+        for x, y in zip(m.fields(), ref):
+            assert np.array_equal(x, y)
+    # the same changes one call at a time give the same fields
+    mem2 = [Instance(c, prec) for c in cases]
+    b2 = Batch(mem2[:4], tiling=dict(kind="tile", cols=64, rows=rows, fused=fused), graph_steps=4)
+    b2.step_n(8)
+    b2.remove(mem2[1])
+    b2.remove(mem2[3])
+    b2.add(mem2[4])
+    b2.step_n(8)
+    b2.add(mem2[1])
+    b2.add(mem2[3])
+    b2.step_n(8)
+    b2.synchronize()
+    assert b.graph_captures() >= captured and b2.graph_captures() >= captured
+    for m, m2 in zip(mem, mem2):
+        for x, y in zip(m.fields(), m2.fields()):
+            assert np.array_equal(x, y)
+    b.close()
+    b2.close()
