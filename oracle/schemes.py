@@ -11,7 +11,8 @@
   symmetric stencil D f_i = d_0 f_i + sum_j d_j (f_{i+j} + f_{i-j}).  It is
   applied inside every stage as the damping term -(sigma_d/dt)(D_x + D_y) q.
   Pinned by D(0) = 0 (no damping of a constant) and D(pi) = 1 (full removal
-  of the grid-scale mode).
+  of the grid-scale mode); beyond these two the coefficient values are
+  parity unpinned (recalled from the reference, which is not at hand).
 * centred_filter(w): near an immersed wall, where fewer than five fluid
   nodes lie on one side of a node along an axis, that axis takes the
   standard centred filter of the largest half-width w that fits in the fluid
