@@ -11,10 +11,15 @@ an arrival time.  The server:
   per-member budgets on the device stop a request mid-chunk when its steps
   are done.
 
-After every chunk the finished requests are retired (results copied out,
-memory released) and waiting ones admitted.  A request that arrives while
-others are on the GPU therefore joins the running batch at the next chunk
-boundary, and its work overlaps theirs in the same launches.
+After every chunk the finished requests are retired (results copied out)
+and waiting ones admitted; the batch takes the chunk's removals and
+additions in one membership update before the next chunk, and the retired
+requests' device memory is released then.  The budget counts a retired
+request's bytes as free from its retirement, so the device can hold up to
+one chunk's retirements beyond the budget until that update.  A request
+that arrives while others are on the GPU therefore joins the running batch
+at the next chunk boundary, and its work overlaps theirs in the same
+launches.
 
 Each result carries:
 - the probe traces;
@@ -178,8 +183,9 @@ class GpuBackend:
 
     def step(self, insts: Sequence, budgets: Sequence[int], n: int) -> None:
         self._flush()
-        # budgets are per position: the batch holds the scheduler's members in its order
-        assert [id(m) for m in self.batch.members] == [id(m) for m in insts]
+        # budgets are per position: the batch must hold the scheduler's members in its order
+        if [id(m) for m in self.batch.members] != [id(m) for m in insts]:
+            raise RuntimeError("batch members and scheduler order differ")
         self.batch.set_budget(budgets)
         ev = [self.torch.cuda.Event(enable_timing=True) for _ in range(2)]
         with self.torch.cuda.stream(self.stream):
@@ -188,7 +194,6 @@ class GpuBackend:
         with self.torch.cuda.stream(self.stream):
             ev[1].record()
         self.batch.synchronize()
-        ev[1].synchronize()
         self.gpu_s += ev[0].elapsed_time(ev[1]) * 1e-3
 
     def retire(self, inst) -> Dict[str, Any]:
