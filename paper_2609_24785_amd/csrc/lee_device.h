@@ -71,6 +71,8 @@ struct DevInst {
                             // r = 3 the central set a_k, else the one-sided maximal-order set
     float rad_wf[7][7];
     int stream;             // stage outputs take non-temporal stores (planes larger than the on-chip cache)
+    int stream_in;          // the halo copy of a stage input other than q^n takes non-temporal loads
+                            // (planes larger than the on-chip cache, the q^n planes not)
 };
 
 // Probe sampling carried by a launch: the (member, probe) pairs pw[0, np),

@@ -830,6 +830,11 @@ __device__ __forceinline__ void dma16(const void *src, void *lds_wave_base)
 {
     __builtin_amdgcn_global_load_lds((const GLOBAL void *)src, (LOCAL void *)lds_wave_base, 16, 0, 0);
 }
+// The same with the non-temporal hint (cache policy NT).
+__device__ __forceinline__ void dma16_nt(const void *src, void *lds_wave_base)
+{
+    __builtin_amdgcn_global_load_lds((const GLOBAL void *)src, (LOCAL void *)lds_wave_base, 16, 0, 2);
+}
 
 // One field's contribution to the right-hand sides of VEC nodes of one row
 // (LDS row y, first LDS column lc): F = 0 (p): -dp/dx -> u, -dp/dy -> v;
@@ -1023,6 +1028,9 @@ __device__ __forceinline__ void tile_copy(const DevInst &I, const TileCtx<T> &c,
     const int lane = tid & 63, wave = tid >> 6;
     const int pitch = I.pitch, org = I.org;
     const int rowmax = I.ny + 4;                 // last allocated frame row
+    // a stage input other than q^n streams through the caches where q^n
+    // is to stay in them (stream_in)
+    const bool nt = I.stream_in && c.ib != 0;
 #pragma unroll
     for (int f = 0; f < 3; ++f) {
         const T *src = (const T *)I.f[c.ib][f];
@@ -1032,7 +1040,12 @@ __device__ __forceinline__ void tile_copy(const DevInst &I, const TileCtx<T> &c,
             const int gr = c.r0 - 5 + row;
             const bool halo_row = row < 5 || row >= TY + 5;
             const bool ok = q < G::NCH && !(halo_row && (cc < G::HC || cc >= G::CW - G::HC)) && gr <= rowmax;
-            if (ok) dma16(src + (unsigned)(org + gr * pitch + (c.c0 - 8 + cc * VEC)), &reg[f][0][0] + base * VEC);
+            if (!ok) continue;
+            const T *at = src + (unsigned)(org + gr * pitch + (c.c0 - 8 + cc * VEC));
+            if (nt)
+                dma16_nt(at, &reg[f][0][0] + base * VEC);
+            else
+                dma16(at, &reg[f][0][0] + base * VEC);
         }
     }
 }
