@@ -141,3 +141,26 @@ def test_progress_reports_follow_the_work():
     assert all(b - a >= 0.01 for a, b in zip(ts, ts[1:]))
     for r in seen:
         assert r["finished"] + r["active"] + r["waiting"] <= r["arrived"] <= 6
+
+
+def test_reflection_estimate_on_the_flat_wall_matches_the_impedance():
+    """The served reflection estimate from the oracle's watched ghost (p_BP and
+    the normal velocity read out of the fluid at its boundary point) on the
+    201^2 flat wall at 30 deg, 500 steps: a locally-reacting wall relates p
+    and u_n by Z at every frequency (single-resonance mass-spring-damper
+    wall, Z = R + i (M w - K / w)), so (Z_est - 1)/(Z_est + 1) must reproduce
+    (Z - 1)/(Z + 1) wherever the pulse carries energy.  Measured: 0.007 at
+    w0/2 and 0.003 at the resonance w0 (40 and 20 points per wavelength),
+    0.15 at 2 w0 (10 points per wavelength, where the 11-point scheme with
+    its filter no longer resolves the wave)."""
+    from oracle.solver import OracleSolver
+    from paper_2609_24785_amd.serve import _omegas
+    c = lc.flat_wall_201(500)
+    o = OracleSolver(c)
+    o.set_watch(c.ic.xs, c.ic.ys)
+    o.run(c.steps)
+    r = reflection(o.watch_trace, c.dt, c.impedance, _omegas(c))
+    dev = [math.hypot(a[0] - b[0], a[1] - b[1]) for a, b in zip(r["R_est"], r["R_exact"])]
+    assert dev[0] < 0.02 and dev[1] < 0.01, dev
+    assert dev[2] < 0.25, dev
+    assert abs(complex(*r["R_exact"][1])) < 1e-12      # R = 1: no reflection at resonance
