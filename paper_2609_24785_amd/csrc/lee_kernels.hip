@@ -1029,7 +1029,8 @@ __device__ __forceinline__ void tile_copy(const DevInst &I, const TileCtx<T> &c,
     const int pitch = I.pitch, org = I.org;
     const int rowmax = I.ny + 4;                 // last allocated frame row
     // a stage input other than q^n streams through the caches where q^n
-    // is to stay in them (stream_in)
+    // is to stay in them (stream_in), except the last ten copied rows: the
+    // tile below, next in its XCD's row-major run, reads them again
     const bool nt = I.stream_in && c.ib != 0;
 #pragma unroll
     for (int f = 0; f < 3; ++f) {
@@ -1042,7 +1043,7 @@ __device__ __forceinline__ void tile_copy(const DevInst &I, const TileCtx<T> &c,
             const bool ok = q < G::NCH && !(halo_row && (cc < G::HC || cc >= G::CW - G::HC)) && gr <= rowmax;
             if (!ok) continue;
             const T *at = src + (unsigned)(org + gr * pitch + (c.c0 - 8 + cc * VEC));
-            if (nt)
+            if (nt && row < TY)
                 dma16_nt(at, &reg[f][0][0] + base * VEC);
             else
                 dma16(at, &reg[f][0][0] + base * VEC);
